@@ -1,0 +1,317 @@
+"""Pins of the reference oracle against what the paper and plain mathematics fix.
+
+Every check here is independent of the oracle's own code path: closed forms
+printed in the paper, exact symbolic traces, dense linear algebra, brute
+force and invariants.  No GPU is used.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+# Example 1 (Sec. 3.1): an aperiodic irreducible 4-state chain.
+P4 = np.array([[0, .5, .5, 0], [0, 0, 1, 0], [0, 0, 0, 1], [1, 0, 0, 0]], dtype=np.float64)
+PI4 = np.array([2, 1, 2, 2], dtype=np.float64) / 7.0
+
+
+def chain_from_dense(P, c=1.0):
+    n = P.shape[0]
+    rows, cols = np.nonzero(P)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rowptr, rows + 1, 1)
+    rowptr = np.cumsum(rowptr)
+    return oracle.Chain(rowptr, cols.astype(np.int32), P[rows, cols], c)
+
+
+def random_chain(n, seed, c=0.85, dangling=0.0, deg=4.0):
+    g = workloads.random_small(n, deg, c, seed, dangling)
+    return oracle.Chain(g.rowptr, g.col, None, c), g
+
+
+# ---------------------------------------------------------------- dense solves
+
+def test_four_state_stationary_exact():
+    assert np.allclose(oracle.stationary_dense(P4), PI4, atol=1e-15, rtol=0)
+    assert np.allclose(oracle.stationary_gth(P4), PI4, atol=1e-15, rtol=0)
+
+
+def test_dense_solvers_agree_and_fix_point():
+    for seed in range(5):
+        ch, _ = random_chain(40, seed, c=0.85, dangling=0.1)
+        P = oracle.dense_P(ch)
+        assert np.allclose(P.sum(1), 1.0, atol=1e-14)
+        a = oracle.stationary_dense(P)
+        b = oracle.stationary_gth(P)
+        assert np.abs(a - b).sum() < 1e-13
+        assert np.abs(a - a @ P).sum() < 1e-14
+        w, v = np.linalg.eig(P.T)  # eigenvector of eigenvalue 1, a different library route
+        k = np.argmin(np.abs(w - 1.0))
+        e = np.real(v[:, k])
+        e = e / e.sum()
+        assert np.abs(a - e).sum() < 1e-12
+
+
+def test_route_matches_dense_product():
+    """route(M) is M P for the Google matrix with dangling rows uniform and
+    duplicate links adding up (the chain the oracle documents)."""
+    for seed in range(4):
+        ch, g = random_chain(60, seed, c=0.7, dangling=0.15, deg=3.0)
+        assert len(set(zip(np.repeat(np.arange(g.n), g.outdeg), g.col))) < g.nnz or seed > 0
+        P = oracle.dense_P(ch)
+        rng = np.random.default_rng(seed)
+        M = rng.standard_normal(ch.n)
+        assert np.abs(oracle.route(ch, M) - M @ P).max() < 1e-14
+
+
+# ------------------------------------------------------------- Examples 1, 2
+
+def test_example1_zero_history():
+    """M_0 = e_1, G_1 = {1} gives H_2 = C_2 = 0 exactly (Example 1)."""
+    ch = chain_from_dense(P4)
+    s = oracle.State(ch, M0=np.array([1.0, 0, 0, 0]))
+    assert np.array_equal(s.C, [-1.0, .5, .5, 0.0])
+    assert np.array_equal(s.H, [1.0, 0, 0, 0])
+    s.step_mask([1, 0, 0, 0])
+    assert np.array_equal(s.H, np.zeros(4)) and np.array_equal(s.C, np.zeros(4))
+    assert s.hsum == 0.0
+    # the same start under RLGL_MaxC greens node 1 first: the solver reports it
+    st, _, info = oracle.solve(ch, oracle.MAXC, eps=1e-12, M0=np.array([1.0, 0, 0, 0]))
+    assert st == oracle.EZERO_HISTORY and info["t"] == 2
+
+
+def _parse_trace(path):
+    rows = []
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        t, h, c, g = [x.strip() for x in line.split("|")]
+        rows.append((int(t), [x.strip() for x in h.split(",")], [x.strip() for x in c.split(",")], int(g)))
+    return rows
+
+
+def _eval_cells(cells, m):
+    env = {"M1": m[0], "M2": m[1], "M3": m[2], "M4": m[3], "__builtins__": {}}
+    return np.array([eval(x, env) for x in cells], dtype=np.float64)
+
+
+@pytest.mark.parametrize("fname", ["example2_cycle_a.txt", "example2_cycle_b.txt"])
+def test_example2_symbolic_traces(fname):
+    """The H_t, C_t tables of Example 2, checked exactly with dyadic M_0."""
+    rows = _parse_trace(os.path.join(GOLDEN, fname))
+    ch = chain_from_dense(P4)
+    rng = np.random.default_rng(7)
+    for _ in range(5):
+        m = rng.integers(1, 64, size=4).astype(np.float64) / 64.0
+        s = oracle.State(ch, M0=m)
+        for t, hc, cc, g in rows:
+            assert s.t == t
+            assert np.array_equal(s.H, _eval_cells(hc, m)), (fname, t, s.H)
+            assert np.array_equal(s.C, _eval_cells(cc, m)), (fname, t, s.C)
+            mask = np.zeros(4, dtype=bool)
+            mask[g - 1] = True
+            s.step_mask(mask)
+
+
+def test_example2_first_cycle_converges_uniform():
+    """With uniform M_0 the first cycle converges: C_t -> 0 and pi_hat -> pi*."""
+    ch = chain_from_dense(P4)
+    s = oracle.State(ch)
+    cyc = [1, 0, 2, 3]
+    for k in range(400):
+        mask = np.zeros(4, dtype=bool)
+        mask[cyc[k % 4]] = True
+        s.step_mask(mask)
+    assert s.l1 < 1e-15
+    assert np.abs(s.pi_hat - PI4).sum() < 1e-14
+
+
+def test_example2_second_cycle_never_converges():
+    """Second cycle: ||C_t||_1 stays at 2|M3-M4| forever unless M3 = M4, in
+    which case C_3 = 0 and pi_hat_3 = pi* exactly."""
+    ch = chain_from_dense(P4)
+    cyc = [0, 1, 3, 2]
+    m = np.array([0.25, 0.25, 0.375, 0.125])
+    s = oracle.State(ch, M0=m)
+    for k in range(200):
+        mask = np.zeros(4, dtype=bool)
+        mask[cyc[k % 4]] = True
+        s.step_mask(mask)
+        if s.t >= 3:
+            assert s.l1 == pytest.approx(2 * abs(m[2] - m[3]), abs=1e-15)
+    m = np.full(4, 0.25)
+    s = oracle.State(ch, M0=m)
+    for k in range(2):
+        mask = np.zeros(4, dtype=bool)
+        mask[cyc[k]] = True
+        s.step_mask(mask)
+    assert s.t == 3 and s.l1 == 0.0
+    assert np.abs(s.pi_hat - PI4).max() < 1e-15
+
+
+def test_single_node_forever_stalls():
+    """G_t = {1} for all t stops decreasing ||C_t||_1 after one step (Sec. 2.2)."""
+    ch = chain_from_dense(P4)
+    s = oracle.State(ch)
+    l1 = []
+    for _ in range(6):
+        s.step_mask([1, 0, 0, 0])
+        l1.append(s.l1)
+    assert l1[0] > 0 and all(x == l1[0] for x in l1)
+
+
+# ------------------------------------------------- power iteration special case
+
+def test_all_green_equals_power_iteration():
+    """G_t = [N] gives H_t = M_0 P^(t-1) and H_t 1 = 1 (Sec. 2.3.1)."""
+    for seed in range(3):
+        ch, _ = random_chain(50, seed, c=0.8, dangling=0.1)
+        P = oracle.dense_P(ch)
+        M0 = np.full(ch.n, 1.0 / ch.n)
+        s = oracle.State(ch)
+        for t in range(1, 25):
+            ref = M0 @ np.linalg.matrix_power(P, t - 1)
+            assert np.abs(s.H - ref).max() < 1e-15 * t + 1e-16
+            assert abs(s.hsum - 1.0) < 1e-14
+            s.step(oracle.ALL)
+
+
+def test_power_iteration_reference_accuracy():
+    for seed in range(3):
+        ch, _ = random_chain(80, seed, c=0.85, dangling=0.05)
+        pistar = oracle.stationary_dense(oracle.dense_P(ch))
+        x, _ = oracle.reference_pagerank(ch, 1e-13)
+        assert np.abs(x - pistar).sum() <= 1e-13
+
+
+# ------------------------------------------------------------------ invariants
+
+@pytest.mark.parametrize("sched", [oracle.ALL, oracle.THRESHOLD, oracle.TOPK, oracle.MAXC])
+def test_invariants_every_step(sched):
+    """sum C_t = 0 (Sec. 2.1), H_t + C_t = H_t P (eq. (7) with C_0 = 0),
+    ||C_t||_1 non-increasing (proof of Theorem 2), and for G_t = [N] the
+    Dobrushin bound ||C_t||_1 <= 2 c^(t-1) (Theorem 3 with m = 1)."""
+    for seed in range(3):
+        c = 0.85
+        ch, _ = random_chain(70, seed, c=c, dangling=0.1)
+        P = oracle.dense_P(ch)
+        s = oracle.State(ch)
+        prev = s.l1
+        for _ in range(40):
+            assert abs(s.C.sum()) < 1e-15
+            assert np.abs(s.H + s.C - s.H @ P).max() < 1e-15
+            assert s.l1 <= prev * (1 + 1e-13) + 1e-16
+            if sched == oracle.ALL:
+                assert s.l1 <= 2 * c ** (s.t - 1) + 1e-15
+            prev = s.l1
+            s.step(sched, k=5)
+
+
+def test_residual_equals_cash_over_history():
+    """||pi_hat - pi_hat P||_1 = ||C_t||_1 / |H_t 1| (Algorithm 1, step (7))."""
+    ch, _ = random_chain(200, 3, c=0.85, dangling=0.1)
+    st, pi, info, C, H = oracle.solve(ch, oracle.THRESHOLD, eps=1e-9, want_state=True)
+    assert st == oracle.OK
+    assert oracle.residual(ch, pi) == pytest.approx(info["resid"], rel=1e-6)
+
+
+def test_pagerank_error_bound():
+    """With c < 1: ||pi_hat - pi*||_1 <= resid / (1 - c) (eq. (9) with the
+    contraction of Theorem 3); the stopping rule at (1-c)*tol certifies tol."""
+    for seed in range(4):
+        for sched in (oracle.ALL, oracle.THRESHOLD, oracle.MAXC, oracle.TOPK):
+            c = 0.85
+            ch, _ = random_chain(120, seed, c=c, dangling=0.1)
+            pistar = oracle.stationary_dense(oracle.dense_P(ch))
+            st, pi, info = oracle.solve(ch, sched, eps=(1 - c) * 1e-8, k=7)
+            assert st == oracle.OK
+            err = np.abs(pi - pistar).sum()
+            assert err <= info["resid"] / (1 - c) + 1e-14
+            assert err <= 1e-8
+
+
+# ------------------------------------------------------------- closed forms
+
+def test_two_wheels_degree_law():
+    """Two-wheels graph (Sec. 6), simple random walk: pi_i = deg_i / 42."""
+    edges = np.loadtxt(os.path.join(GOLDEN, "two_wheels_edges.txt"), dtype=np.int64) - 1
+    assert edges.shape == (21, 2)
+    src = np.concatenate([edges[:, 0], edges[:, 1]])
+    dst = np.concatenate([edges[:, 1], edges[:, 0]])
+    g = workloads.from_edges(12, src, dst, 1.0)
+    deg = g.outdeg.astype(np.float64)
+    assert list(deg) == [3, 3, 4, 3, 3, 3, 6, 4, 3, 3, 3, 4]
+    pi_ref = deg / 42.0
+    ch = oracle.Chain(g.rowptr, g.col, None, 1.0)
+    assert np.abs(oracle.stationary_dense(oracle.dense_P(ch)) - pi_ref).max() < 1e-15
+    assert np.abs(oracle.stationary_gth(oracle.dense_P(ch)) - pi_ref).max() < 1e-15
+    for sched in (oracle.ALL, oracle.THRESHOLD, oracle.MAXC, oracle.TOPK):
+        st, pi, info = oracle.solve(ch, sched, eps=1e-13, k=3)
+        assert st == oracle.OK, sched
+        assert np.abs(pi - pi_ref).sum() < 1e-11, (sched, info)
+
+
+def _mf_sbm(K, n, p, q):
+    N1, N2 = K * n, n
+    N = N1 + N2
+    A = np.full((N, N), q)
+    A[:N1, :N1] = p
+    A[N1:, N1:] = p
+    return A / A.sum(1, keepdims=True), N1
+
+
+def test_two_block_mean_field_rates():
+    """Sec. 4: lambda_2 = (p^2-q^2)K/((pK+q)(qK+p)); one-block schedules
+    contract ||C_t||_1 by pK/(pK+q) (G = B_1) and p/(qK+p) (G = B_2)."""
+    for K, n, p, q in [(3, 4, 0.5, 0.1), (5, 3, 0.3, 0.02), (2, 6, 0.9, 0.4)]:
+        P, N1 = _mf_sbm(K, n, p, q)
+        lam = sorted(np.abs(np.linalg.eigvals(P)))[-2]
+        assert lam == pytest.approx((p * p - q * q) * K / ((p * K + q) * (q * K + p)), rel=1e-12)
+        ch = chain_from_dense(P)
+        for block, factor in ((np.arange(P.shape[0]) < N1, p * K / (p * K + q)),
+                              (np.arange(P.shape[0]) >= N1, p / (q * K + p))):
+            s = oracle.State(ch)
+            for _ in range(8):
+                before = s.l1
+                s.step_mask(block)
+                assert s.l1 == pytest.approx(factor * before, rel=1e-10)
+
+
+# ------------------------------------------------------------------ selection
+
+def test_selection_brute_force():
+    rng = np.random.default_rng(11)
+    for trial in range(30):
+        n = int(rng.integers(1, 300))
+        C = rng.standard_normal(n) * 10.0 ** rng.integers(-12, 0)
+        if n > 4:  # plant ties, including ties in |C| with opposite signs
+            C[1] = -C[0]
+            C[3] = C[2]
+        th = oracle.theta(C, 1.0)
+        assert th == pytest.approx(math.fsum(np.abs(C)) / n, rel=1e-14)
+        assert np.array_equal(oracle.select(C, oracle.THRESHOLD, th), np.abs(C) >= th)
+        mx = np.abs(C).max()
+        assert np.array_equal(oracle.select(C, oracle.MAXC), np.abs(C) == mx)
+        k = int(rng.integers(1, n + 1))
+        order = sorted(range(n), key=lambda i: (-abs(C[i]), i))
+        want = np.zeros(n, dtype=bool)
+        want[order[:k]] = True
+        assert np.array_equal(oracle.select(C, oracle.TOPK, k=k), want)
+        assert oracle.select(C, oracle.ALL).all()
+        r = 2.0
+        assert oracle.theta(C, r) == pytest.approx(math.sqrt(math.fsum(C * C) / n), rel=1e-13)
+
+
+def test_zero_cash_green_nodes_push_nothing():
+    """A green node with C_i = 0 moves nothing and uses no link."""
+    ch = chain_from_dense(P4)
+    s = oracle.State.from_arrays(ch, C=[0.0, 0.5, -0.5, 0.0], H=[0.25] * 4, hsum=1.0)
+    s.step_mask([1, 0, 0, 1])
+    assert s.edges == 0 and np.array_equal(s.C, [0.0, 0.5, -0.5, 0.0])
+    s.step_mask([0, 1, 0, 0])
+    assert s.edges == 1
