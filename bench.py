@@ -1,0 +1,234 @@
+"""Benchmark of the MI355X RLGL solver.
+
+A "step" of this benchmark is one whole solve: step 0 of Algorithm 1, the
+green-light steps, the stop test and the normalisation pi_hat = H / (H 1),
+on a graph already resident in HBM.  The default workload is the Chung-Lu
+power-law digraph with 2^20 nodes (exponent 2.1, mean degree 16, 5% forced
+dangling nodes, damping 0.85), threshold schedule (r = 1), FP32 cash with
+FP64 history, push/pull chosen per step.
+
+The solve stops at ||C_t||_1 / |H_t 1| < (1 - c) * 1e-6, which bounds the L1
+distance to pi* by 1e-6 (contraction of the Google matrix); the result is
+then checked against the FP64 reference (power iteration of the oracle) and
+by the FP64 residual of the returned vector.
+
+Printed: one JSON line (the contract of the build driver).
+"""
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "edge-pushes/s (GTEPS) to L1≤1e-6 vs FP64; batched solves/s + p99 latency"
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("rlgl_kernels.hip", "rlgl_api.hip", "rlgl_device.h"):
+        with open(os.path.join(ROOT, "paper_2008_02710_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def make_workload(name: str):
+    import workloads
+    if name == "chung_lu_2p20":
+        g = workloads.chung_lu(1 << 20, 2.1, 16.0, 0.05, 0.85, seed=0, name=name)
+        return g, dict(sched="threshold", r=1.0)
+    if name == "rmat_s24":
+        g = workloads.rmat(24, 16, 0.57, 0.19, 0.19, 0.85, seed=0)
+        g.name = name
+        return g, dict(sched="threshold", r=1.0)
+    if name == "poisson_1e4":
+        g = workloads.poisson_uniform(10000, 8.0, 0.85, seed=0)
+        g.name = name
+        return g, dict(sched="all", r=1.0)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10, help="timed solves")
+    ap.add_argument("--warmup", type=int, default=3, help="untimed solves")
+    ap.add_argument("--workload", default="chung_lu_2p20")
+    ap.add_argument("--route", default="auto", choices=["auto", "push", "pull"])
+    ap.add_argument("--precision", default="fp32c_fp64h", choices=["fp64", "fp32c_fp64h", "fp32c_kahanh"])
+    ap.add_argument("--tol", type=float, default=1e-6, help="certified L1 target")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--no-ref", action="store_true", help="skip the FP64 power-iteration reference")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2008_02710_amd as rl
+
+    prec = {"fp64": rl.FP64, "fp32c_fp64h": rl.FP32C_FP64H, "fp32c_kahanh": rl.FP32C_KAHANH}[args.precision]
+    route = {"auto": rl.ROUTE_AUTO, "push": rl.ROUTE_PUSH, "pull": rl.ROUTE_PULL}[args.route]
+    t0 = time.time()
+    g, wl = make_workload(args.workload)
+    sched = {"threshold": rl.SCHED_THRESHOLD, "all": rl.SCHED_ALL}[wl["sched"]]
+    print(f"# workload {g.name}: n={g.n} nnz={g.nnz} dangling={g.n_dangling} gen={time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    dg = rl.DeviceGraph.from_workload(g, precision=prec, with_csc=True, explicit_val=True, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    s = rl.Solver(dg, stream=stream, sched=sched, r=wl["r"], route=route, precision=prec)
+    eps = (1.0 - g.c) * args.tol
+    max_steps = 100000
+
+    def one_solve():
+        s.reset()
+        st, info = s.solve(eps, max_steps)
+        return info
+
+    for _ in range(args.warmup):
+        one_solve()
+    torch.cuda.synchronize()
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    infos = []
+    wall = []
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        a = time.perf_counter()
+        infos.append(one_solve())
+        wall.append(time.perf_counter() - a)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    ev_ms = ev0.elapsed_time(ev1)
+    pushes = sum(i["edges_pushed"] for i in infos)
+    gteps = pushes / t_total / 1e9
+    ms_per_solve = 1000.0 * t_total / args.steps
+    last = infos[-1]
+    pi = s.pi.detach().cpu().numpy()
+    print(f"# timed {args.steps} solves: {ms_per_solve:.3f} ms/solve (events {ev_ms / args.steps:.3f}), "
+          f"steps={last['t'] - 1} pushes/solve={last['edges_pushed']} GTEPS={gteps:.1f}",
+          file=sys.stderr, flush=True)
+
+    # ---- roofline of the dominant kernel: same solve, events around each launch
+    rl.rlgl_profile_enable(s.ctx, True)
+    one_solve()
+    torch.cuda.synchronize()
+    prof = rl.rlgl_profile_read(s.ctx)
+    rl.rlgl_profile_enable(s.ctx, False)
+    dom = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    dom_name, dom_stat = dom
+    achieved = dom_stat["bytes"] / (dom_stat["ms"] * 1e-3) / 1e9
+    per_launch_bytes = dom_stat["bytes"] / max(dom_stat["launches"], 1)
+    traffic = read_traffic(dom_name, g.name)
+    roofline = {"bound": "hbm", "kernel": f"k_{dom_name}", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "algorithmic_bytes_per_launch": round(per_launch_bytes),
+                "avg_launch_us": round(1000.0 * dom_stat["ms"] / max(dom_stat["launches"], 1), 2),
+                "launches_per_solve": dom_stat["launches"],
+                "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 4),
+                                "GBps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)} for k, v in prof.items()}}
+    print(f"# profile: {json.dumps(roofline['kernels'])}", file=sys.stderr, flush=True)
+
+    # ---- accuracy against FP64
+    import oracle
+    ch = oracle.Chain(g.rowptr, g.col, g.val(), g.c)
+    t_res = time.time()
+    true_resid = oracle.residual(ch, pi)
+    l1_bound = true_resid / (1.0 - g.c)
+    print(f"# FP64 residual of pi_hat {true_resid:.3e} -> certified L1 <= {l1_bound:.3e} "
+          f"({time.time() - t_res:.1f}s)", file=sys.stderr, flush=True)
+    l1_ref = None
+    if not args.no_ref:
+        t_ref = time.time()
+        x, it = oracle.reference_pagerank(ch, 1e-10)
+        l1_ref = float(np.abs(pi - x).sum())
+        print(f"# L1 vs FP64 power iteration ({it} iterations, {time.time() - t_ref:.1f}s): {l1_ref:.3e}",
+              file=sys.stderr, flush=True)
+
+    # ---- CPU baseline: the oracle's own solve, same graph, same schedule and eps
+    cpu = None
+    if not args.no_cpu:
+        osched = {rl.SCHED_THRESHOLD: oracle.THRESHOLD, rl.SCHED_ALL: oracle.ALL}[sched]
+        done, opushes, tcpu = 0, 0, 0.0
+        while tcpu < args.cpu_seconds or done == 0:
+            a = time.perf_counter()
+            ost, opi, oinfo = oracle.solve(ch, osched, eps=eps, max_steps=max_steps, r=wl["r"])
+            tcpu += time.perf_counter() - a
+            opushes += oinfo["edges_pushed"]
+            done += 1
+        cpu = {"value": round(opushes / tcpu / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+               "sample": f"{done} full serial FP64 oracle solves of the same graph to the same eps "
+                         f"({tcpu:.1f} s, {oinfo['t'] - 1} steps each)",
+               "ms_per_solve": round(1000.0 * tcpu / done, 1), "host": platform.processor() or platform.machine()}
+        print(f"# cpu oracle: {cpu}", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC,
+        "value": round(gteps, 3),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_solve, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec != rl.FP64 else "f64",
+        "data": "synthetic",
+        "config": {"workload": g.name, "n": g.n, "nnz": g.nnz, "dangling": g.n_dangling, "damping": g.c,
+                   "schedule": wl["sched"], "r": wl["r"], "precision": args.precision, "route": args.route,
+                   "eps_resid": eps, "tol_l1": args.tol, "generator": g.params.get("generator"),
+                   "seed": g.params.get("seed")},
+        "steps_per_solve": last["t"] - 1,
+        "edge_pushes_per_solve": last["edges_pushed"],
+        "normalized_iterations": round(last["edges_pushed"] / g.nnz, 3),
+        "solve_ms_min": round(1000 * min(wall), 4),
+        "solve_ms_max": round(1000 * max(wall), 4),
+        "l1_vs_fp64_power_iteration": l1_ref,
+        "fp64_residual": true_resid,
+        "l1_certified_bound": l1_bound,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

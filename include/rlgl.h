@@ -1,0 +1,198 @@
+/*
+ * rlgl.h - C ABI of the MI355X (gfx950) Red-Light-Green-Light solver.
+ *
+ * The method is the one of Avrachenkov, Brown and Litvak, "Red Light Green
+ * Light Method for Solving Large Markov Chains" (J. Sci. Comput. 93:18, 2022):
+ * every state i holds cash C_i; at step t a green-light set G_t moves its
+ * cash along the transition matrix P, the moved cash accumulates in the
+ * history H, and pi_hat_t = H_t / (H_t 1) estimates the stationary
+ * distribution pi* = pi* P (Sec. 2.1, eqs. (1)-(6), Algorithm 1).
+ *
+ * Conventions for every call
+ *   - Graph arrays, the workspace and the output vector are DEVICE pointers
+ *     owned by the caller; they must stay alive until rlgl_destroy.  The
+ *     library allocates no device memory and frees nothing it did not create.
+ *     It allocates a small host-side context only.
+ *   - All device work is enqueued on the caller's hipStream_t given to
+ *     rlgl_create.  rlgl_step/rlgl_solve/rlgl_get_state return after the work
+ *     they enqueued has finished and the host-visible results are final.
+ *   - Calls on one context must not overlap (one host thread at a time).
+ *     Distinct contexts are independent.
+ *   - Errors are reported through the return code; rlgl_last_error() gives a
+ *     human-readable message for the calling thread.  No C++ exception
+ *     crosses this interface.
+ */
+#ifndef RLGL_H
+#define RLGL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rlgl_ctx rlgl_ctx;
+
+typedef enum {
+  RLGL_OK = 0,
+  RLGL_EINVAL = -1,          /* bad argument; nothing was enqueued */
+  RLGL_ENOMEM = -2,          /* workspace smaller than rlgl_workspace_bytes() or host allocation failed */
+  RLGL_EHIP = -3,            /* a HIP runtime call failed */
+  RLGL_EZERO_HISTORY = -4,   /* |H_t 1| <= 1e-300 or <= 1e-12 ||H_t||_1: the "restart" case of Sec. 2.1 / Example 1 */
+  RLGL_ENOT_CONVERGED = -5,  /* max_steps reached before the stop test; pi is still written */
+  RLGL_ENONFINITE = -6       /* ||C_t||_1 or H_t 1 is not finite */
+} rlgl_status;
+
+/* Green-light rules (Sec. 6, "cash-dependent heuristics"; G_t is chosen from
+ * the cash snapshot C_t and all green nodes move at once, eq. (4)). */
+typedef enum {
+  RLGL_SCHED_ALL = 0,        /* G_t = [N]: power iteration (Sec. 2.3.1) */
+  RLGL_SCHED_THRESHOLD = 1,  /* |C_t,i| >= theta_t, theta_t = (sum_j |C_t,j|^r / N)^(1/r) (RLGL_Theta, all nodes at once) */
+  RLGL_SCHED_TOPK = 2,       /* the k largest |C_t,i|, ties broken by smaller node id (Gauss-Southwell style) */
+  RLGL_SCHED_MAXC = 3        /* every node with |C_t,i| = max_j |C_t,j| (RLGL_MaxC) */
+} rlgl_sched;
+
+/* Arithmetic.  Cash routing runs in the cash type; H_t 1, ||C_t||_1, theta
+ * and all other reductions run in FP64. */
+typedef enum {
+  RLGL_FP64 = 0,             /* C, P values and H in double */
+  RLGL_FP32C_FP64H = 1,      /* C and P values in float, H in double */
+  RLGL_FP32C_KAHANH = 2      /* C and P values in float, H as a compensated (Neumaier) float pair */
+} rlgl_precision;
+
+/* How the moved cash M_t reaches the destinations (the product M_t P of eq. (6)). */
+typedef enum {
+  RLGL_ROUTE_PUSH = 0,       /* scatter along the CSR rows of the green nodes (atomic adds) */
+  RLGL_ROUTE_PULL = 1,       /* gather along the CSC columns of every node (needs the CSC arrays) */
+  RLGL_ROUTE_AUTO = 2        /* per step: pull when the previous step's green links >= pull_alpha * nnz */
+} rlgl_route;
+
+/* The chain.  W is given in CSR (out-links) and optionally in CSC (in-links,
+ * the transpose of the same matrix).  The transition matrix is
+ *   P_ij = c * W_ij + (1 - c) / N   for a row i with at least one stored link,
+ *   P_ij = 1 / N                    for a row with none (dangling),
+ * i.e. the Google matrix of Sec. 3.2 with uniform restart; duplicate (i,j)
+ * entries add up.  Rows of W must sum to 1 (the caller's contract).
+ * Value arrays hold double for RLGL_FP64 and float otherwise; a NULL value
+ * array means 1/outdeg(i) for every stored link of row i. */
+typedef struct {
+  int32_t n;                  /* number of states N >= 1 */
+  int64_t nnz;                /* stored links, must equal csr_rowptr[n] and be < 2^31 */
+  const int32_t *csr_rowptr;  /* [n+1], non-decreasing, csr_rowptr[0] = 0 */
+  const int32_t *csr_col;     /* [nnz], each in [0, n) */
+  const void *csr_val;        /* [nnz] or NULL */
+  const int32_t *csc_colptr;  /* [n+1] or NULL: then only push routing is possible */
+  const int32_t *csc_row;     /* [nnz] source of each in-link */
+  const void *csc_val;        /* [nnz] or NULL (1/outdeg of the source) */
+  double damping;             /* c in (0, 1] */
+} rlgl_graph;
+
+typedef struct {
+  int32_t sched;              /* rlgl_sched */
+  double r;                   /* power-mean order of the threshold, r >= 1 (default 1) */
+  int64_t k;                  /* top-k size, >= 1 */
+  int32_t theta_period;       /* recompute theta every theta_period steps (>= 1, default 1) */
+  int32_t precision;          /* rlgl_precision */
+  int32_t route;              /* rlgl_route */
+  double pull_alpha;          /* AUTO switch point as a fraction of nnz (default 0.5) */
+  int32_t check_period;       /* rlgl_solve: steps enqueued between host reads of the stop flag; 0 = adaptive */
+  int32_t record_green;       /* non-zero: keep the green mask of the last step for rlgl_get_green */
+  int32_t refresh;            /* rebuild C_t = H_t P - H_t in FP64 (needs the CSC; see rlgl_refresh):
+                                 0 never; 1 in rlgl_solve before a stop is accepted and whenever |C_t 1| exceeds
+                                 ||C_t||_1 / 2 (rounding drift); k > 1 also every k steps of rlgl_solve */
+} rlgl_options;
+
+/* Snapshot of the solver after the last enqueued step. */
+typedef struct {
+  int64_t t;                  /* index of the current state C_t, H_t (t = 1 after rlgl_create) */
+  int64_t green;              /* |G| of the last step */
+  int64_t green_total;        /* sum of |G_t| over the steps t >= 1 */
+  int64_t edges_pushed;       /* stored links of green nodes that moved non-zero cash, step 0 included */
+  double l1_cash;             /* ||C_t||_1 */
+  double h_sum;               /* H_t 1 */
+  double resid;               /* ||C_t||_1 / |H_t 1| = ||pi_hat_t - pi_hat_t P||_1 (Algorithm 1, step (7)) */
+  double theta;               /* threshold used by the last step (THRESHOLD), else 0 */
+  double cash_sum;            /* C_t 1 (zero in exact arithmetic) */
+  int32_t status;             /* rlgl_status of the last call */
+  int32_t last_route;         /* rlgl_route used by the last step (PUSH or PULL) */
+} rlgl_step_info;
+
+/* Fills *opt with the defaults: THRESHOLD, r = 1, k = 1, theta_period = 1,
+ * FP32C_FP64H, AUTO, pull_alpha = 0.5, check_period = 0, record_green = 0,
+ * refresh = 1. */
+void rlgl_default_options(rlgl_options *opt);
+
+/* Device workspace the context needs, in bytes (0 on a bad argument).  Depends
+ * on n, nnz, the precision and whether the CSC is given. */
+size_t rlgl_workspace_bytes(const rlgl_graph *g, const rlgl_options *opt);
+
+/* Checks the arguments, lays out the workspace, builds the static pull plan
+ * from the CSC column pointers (setup: one device-to-host copy of csc_colptr)
+ * and performs step 0 of Algorithm 1 (eq. (3) with uniform M_0 = (1/N) 1), so
+ * the context holds C_1, H_1 and t = 1.  `stream` is a hipStream_t (NULL =
+ * the default stream).  *out is set only on RLGL_OK. */
+rlgl_status rlgl_create(const rlgl_graph *g, const rlgl_options *opt, void *dev_workspace, size_t ws_bytes,
+                        void *stream, rlgl_ctx **out);
+
+/* Performs nsteps >= 0 green-light steps (eqs. (4)-(6)) without any stop test
+ * on the residual; stops early only on RLGL_EZERO_HISTORY or RLGL_ENONFINITE.
+ * info (host pointer, may be NULL) receives the state after the last step. */
+rlgl_status rlgl_step(rlgl_ctx *ctx, int32_t nsteps, rlgl_step_info *info);
+
+/* Runs Algorithm 1 from the current state until ||C_t||_1 / |H_t 1| < eps for
+ * some t >= 2 (step (7)), or until max_steps more steps were taken
+ * (RLGL_ENOT_CONVERGED).  Then writes pi_hat_t = H_t / (H_t 1) as n doubles
+ * into dev_pi (device pointer, may be NULL).  For c < 1 the L1 distance of
+ * pi_hat to pi* is at most resid / (1 - c). */
+rlgl_status rlgl_solve(rlgl_ctx *ctx, double eps, int64_t max_steps, double *dev_pi, rlgl_step_info *info);
+
+/* Releases the host context.  Does not touch the caller's device memory. */
+void rlgl_destroy(rlgl_ctx *ctx);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *rlgl_last_error(void);
+
+/* ---- extensions ------------------------------------------------------- */
+
+/* Re-runs step 0: the context is back at t = 1 (same as right after create). */
+rlgl_status rlgl_reset(rlgl_ctx *ctx);
+
+/* Copies C_t and H_t out as n doubles each (device pointers, either may be
+ * NULL).  A compensated history is returned as hi + lo. */
+rlgl_status rlgl_get_state(rlgl_ctx *ctx, double *dev_C, double *dev_H, rlgl_step_info *info);
+
+/* Replaces the state by (C, H, H 1 = h_sum) at index t >= 1.  C is rounded to
+ * the cash type; h_sum NaN means "sum of H".  The checkpoint of eq. (7): any
+ * (C, H) with H + C = H P continues the method exactly. */
+rlgl_status rlgl_set_state(rlgl_ctx *ctx, const double *dev_C, const double *dev_H, double h_sum, int64_t t);
+
+/* Rebuilds the cash of the current state from its history with the balance
+ * identity of Sec. 2.2 (eq. (7), C_0 = 0): C_t = H_t P - H_t, evaluated in FP64
+ * along the CSC columns and rounded once to the cash type.  Needs the CSC
+ * arrays (RLGL_EINVAL otherwise).  The method's state is unchanged in exact
+ * arithmetic; the rounding accumulated by FP32 routing is removed. */
+rlgl_status rlgl_refresh(rlgl_ctx *ctx, rlgl_step_info *info);
+
+/* Green mask of the last step as n bytes (1 = green), device pointer.  Needs
+ * record_green in the options; RLGL_EINVAL otherwise. */
+rlgl_status rlgl_get_green(rlgl_ctx *ctx, uint8_t *dev_mask);
+
+/* Per-kernel timing of the steps enqueued since the last call (HIP events on
+ * the context's stream around every launch while enabled).  Fills up to 8
+ * entries: name, launches, total milliseconds, algorithmic bytes moved.  The
+ * return value is the number of entries (or a negative rlgl_status). */
+typedef struct {
+  char name[24];
+  int64_t launches;
+  double ms;
+  double bytes;
+} rlgl_kernel_stat;
+rlgl_status rlgl_profile_enable(rlgl_ctx *ctx, int32_t on);
+int32_t rlgl_profile_read(rlgl_ctx *ctx, rlgl_kernel_stat *out, int32_t max_entries);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RLGL_H */

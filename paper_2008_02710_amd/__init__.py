@@ -1,0 +1,311 @@
+"""Python binding of the MI355X Red-Light-Green-Light library (``librlgl.so``).
+
+The functions below carry the names of the C ABI in ``include/rlgl.h`` and do
+argument marshalling only; every step of the method runs in the HIP kernels.
+PyTorch provides device memory (the graph arrays, the workspace, the output)
+and the stream.  There is no fallback: importing this package fails when the
+built library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loads the HIP runtime that the library then shares
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librlgl.so")
+
+RLGL_OK, RLGL_EINVAL, RLGL_ENOMEM, RLGL_EHIP = 0, -1, -2, -3
+RLGL_EZERO_HISTORY, RLGL_ENOT_CONVERGED, RLGL_ENONFINITE = -4, -5, -6
+SCHED_ALL, SCHED_THRESHOLD, SCHED_TOPK, SCHED_MAXC = 0, 1, 2, 3
+FP64, FP32C_FP64H, FP32C_KAHANH = 0, 1, 2
+ROUTE_PUSH, ROUTE_PULL, ROUTE_AUTO = 0, 1, 2
+
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EZERO_HISTORY", -5: "ENOT_CONVERGED",
+                -6: "ENONFINITE"}
+
+
+class rlgl_graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("csr_rowptr", ctypes.c_void_p), ("csr_col", ctypes.c_void_p), ("csr_val", ctypes.c_void_p),
+                ("csc_colptr", ctypes.c_void_p), ("csc_row", ctypes.c_void_p), ("csc_val", ctypes.c_void_p),
+                ("damping", ctypes.c_double)]
+
+
+class rlgl_options(ctypes.Structure):
+    _fields_ = [("sched", ctypes.c_int32), ("r", ctypes.c_double), ("k", ctypes.c_int64),
+                ("theta_period", ctypes.c_int32), ("precision", ctypes.c_int32), ("route", ctypes.c_int32),
+                ("pull_alpha", ctypes.c_double), ("check_period", ctypes.c_int32),
+                ("record_green", ctypes.c_int32), ("refresh", ctypes.c_int32)]
+
+
+class rlgl_step_info(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int64), ("green", ctypes.c_int64), ("green_total", ctypes.c_int64),
+                ("edges_pushed", ctypes.c_int64), ("l1_cash", ctypes.c_double), ("h_sum", ctypes.c_double),
+                ("resid", ctypes.c_double), ("theta", ctypes.c_double), ("cash_sum", ctypes.c_double),
+                ("status", ctypes.c_int32), ("last_route", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class rlgl_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
+EXPORTED = ["rlgl_default_options", "rlgl_workspace_bytes", "rlgl_create", "rlgl_step", "rlgl_solve",
+            "rlgl_destroy", "rlgl_last_error", "rlgl_reset", "rlgl_get_state", "rlgl_set_state",
+            "rlgl_get_green", "rlgl_refresh", "rlgl_profile_enable", "rlgl_profile_read"]
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"the HIP library {path} is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    G, O, I = ctypes.POINTER(rlgl_graph), ctypes.POINTER(rlgl_options), ctypes.POINTER(rlgl_step_info)
+    lib.rlgl_default_options.argtypes = [O]
+    lib.rlgl_default_options.restype = None
+    lib.rlgl_workspace_bytes.argtypes = [G, O]
+    lib.rlgl_workspace_bytes.restype = ctypes.c_size_t
+    lib.rlgl_create.argtypes = [G, O, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    lib.rlgl_create.restype = i32
+    lib.rlgl_step.argtypes = [vp, i32, I]
+    lib.rlgl_step.restype = i32
+    lib.rlgl_solve.argtypes = [vp, f64, i64, vp, I]
+    lib.rlgl_solve.restype = i32
+    lib.rlgl_destroy.argtypes = [vp]
+    lib.rlgl_destroy.restype = None
+    lib.rlgl_last_error.argtypes = []
+    lib.rlgl_last_error.restype = ctypes.c_char_p
+    lib.rlgl_reset.argtypes = [vp]
+    lib.rlgl_reset.restype = i32
+    lib.rlgl_get_state.argtypes = [vp, vp, vp, I]
+    lib.rlgl_get_state.restype = i32
+    lib.rlgl_set_state.argtypes = [vp, vp, vp, f64, i64]
+    lib.rlgl_set_state.restype = i32
+    lib.rlgl_refresh.argtypes = [vp, I]
+    lib.rlgl_refresh.restype = i32
+    lib.rlgl_get_green.argtypes = [vp, vp]
+    lib.rlgl_get_green.restype = i32
+    lib.rlgl_profile_enable.argtypes = [vp, i32]
+    lib.rlgl_profile_enable.restype = i32
+    lib.rlgl_profile_read.argtypes = [vp, ctypes.POINTER(rlgl_kernel_stat), i32]
+    lib.rlgl_profile_read.restype = i32
+    return lib
+
+
+_lib = load_library()
+
+
+class RlglError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {STATUS_NAMES.get(status, status)}: {rlgl_last_error()}")
+
+
+def _check(st: int, what: str, allow=()):
+    if st != RLGL_OK and st not in allow:
+        raise RlglError(st, what)
+    return st
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+# ---------------------------------------------------------------- C names
+
+def rlgl_default_options(**overrides) -> rlgl_options:
+    o = rlgl_options()
+    _lib.rlgl_default_options(ctypes.byref(o))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def rlgl_last_error() -> str:
+    return _lib.rlgl_last_error().decode()
+
+
+def rlgl_workspace_bytes(graph: rlgl_graph, opt: rlgl_options) -> int:
+    return int(_lib.rlgl_workspace_bytes(ctypes.byref(graph), ctypes.byref(opt)))
+
+
+def rlgl_create(graph: rlgl_graph, opt: rlgl_options, workspace, ws_bytes: int, stream=None):
+    ctx = ctypes.c_void_p()
+    st = _lib.rlgl_create(ctypes.byref(graph), ctypes.byref(opt), _ptr(workspace), int(ws_bytes),
+                          _stream_handle(stream), ctypes.byref(ctx))
+    _check(st, "rlgl_create")
+    return ctx
+
+
+def rlgl_step(ctx, nsteps: int) -> rlgl_step_info:
+    info = rlgl_step_info()
+    _check(_lib.rlgl_step(ctx, int(nsteps), ctypes.byref(info)), "rlgl_step")
+    return info
+
+
+def rlgl_solve(ctx, eps: float, max_steps: int, pi_out=None, raise_on_error: bool = True):
+    info = rlgl_step_info()
+    st = _lib.rlgl_solve(ctx, float(eps), int(max_steps), _ptr(pi_out), ctypes.byref(info))
+    if raise_on_error:
+        _check(st, "rlgl_solve")
+    return st, info
+
+
+def rlgl_destroy(ctx) -> None:
+    _lib.rlgl_destroy(ctx)
+
+
+def rlgl_reset(ctx) -> None:
+    _check(_lib.rlgl_reset(ctx), "rlgl_reset")
+
+
+def rlgl_get_state(ctx, C_out=None, H_out=None) -> rlgl_step_info:
+    info = rlgl_step_info()
+    _check(_lib.rlgl_get_state(ctx, _ptr(C_out), _ptr(H_out), ctypes.byref(info)), "rlgl_get_state")
+    return info
+
+
+def rlgl_set_state(ctx, C, H, h_sum: float, t: int) -> None:
+    _check(_lib.rlgl_set_state(ctx, _ptr(C), _ptr(H), float(h_sum), int(t)), "rlgl_set_state")
+
+
+def rlgl_refresh(ctx) -> rlgl_step_info:
+    info = rlgl_step_info()
+    _check(_lib.rlgl_refresh(ctx, ctypes.byref(info)), "rlgl_refresh")
+    return info
+
+
+def rlgl_get_green(ctx, mask_out) -> None:
+    _check(_lib.rlgl_get_green(ctx, _ptr(mask_out)), "rlgl_get_green")
+
+
+def rlgl_profile_enable(ctx, on: bool) -> None:
+    _check(_lib.rlgl_profile_enable(ctx, 1 if on else 0), "rlgl_profile_enable")
+
+
+def rlgl_profile_read(ctx):
+    buf = (rlgl_kernel_stat * 8)()
+    m = _lib.rlgl_profile_read(ctx, buf, 8)
+    if m < 0:
+        raise RlglError(m, "rlgl_profile_read")
+    return {buf[i].name.decode(): {"launches": buf[i].launches, "ms": buf[i].ms, "bytes": buf[i].bytes}
+            for i in range(m)}
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ------------------------------------------------------ convenience layer
+
+class DeviceGraph:
+    """Device copies (torch tensors) of a chain's CSR and CSC arrays.
+
+    ``rowptr``/``col`` (and optionally ``colptr``/``row``/``perm``) are host
+    arrays; ``val`` is 1/outdeg per stored link as float64 (or None for the
+    implicit form).  Values are stored as float64 for FP64 and float32
+    otherwise.
+    """
+
+    def __init__(self, n, rowptr, col, damping, val=None, colptr=None, row=None, perm=None, precision=FP32C_FP64H,
+                 device="cuda"):
+        import numpy as np
+        vdt = torch.float64 if precision == FP64 else torch.float32
+        self.n = int(n)
+        self.nnz = int(rowptr[-1])
+        self.damping = float(damping)
+        self.precision = precision
+        self.rowptr = torch.from_numpy(np.ascontiguousarray(rowptr, dtype=np.int32)).to(device)
+        self.col = torch.from_numpy(np.ascontiguousarray(col, dtype=np.int32)).to(device)
+        self.val = None if val is None else torch.from_numpy(np.ascontiguousarray(val, dtype=np.float64)).to(
+            device=device, dtype=vdt)
+        self.colptr = self.row = self.cval = None
+        if colptr is not None:
+            self.colptr = torch.from_numpy(np.ascontiguousarray(colptr, dtype=np.int32)).to(device)
+            self.row = torch.from_numpy(np.ascontiguousarray(row, dtype=np.int32)).to(device)
+            if val is not None:
+                cv = np.ascontiguousarray(np.asarray(val, dtype=np.float64)[perm])
+                self.cval = torch.from_numpy(cv).to(device=device, dtype=vdt)
+
+    @classmethod
+    def from_workload(cls, g, precision=FP32C_FP64H, with_csc=True, explicit_val=True, device="cuda"):
+        val = g.val() if explicit_val else None
+        if with_csc:
+            colptr, row, perm = g.csc()
+        else:
+            colptr = row = perm = None
+        return cls(g.n, g.rowptr, g.col, g.c, val, colptr, row, perm, precision, device)
+
+    def struct(self) -> rlgl_graph:
+        return rlgl_graph(self.n, self.nnz, _ptr(self.rowptr), _ptr(self.col), _ptr(self.val),
+                          _ptr(self.colptr), _ptr(self.row), _ptr(self.cval), self.damping)
+
+
+class Solver:
+    """Owns one context, its workspace tensor and an output buffer."""
+
+    def __init__(self, dg: DeviceGraph, stream=None, **options):
+        options.setdefault("precision", dg.precision)
+        self.dg = dg
+        self.graph = dg.struct()
+        self.opt = rlgl_default_options(**options)
+        self.ws_bytes = rlgl_workspace_bytes(self.graph, self.opt)
+        if self.ws_bytes == 0:
+            raise RlglError(RLGL_EINVAL, "rlgl_workspace_bytes")
+        dev = dg.rowptr.device
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        self.stream = stream
+        self.ctx = rlgl_create(self.graph, self.opt, self.workspace, self.ws_bytes, stream)
+        self.pi = torch.empty(dg.n, dtype=torch.float64, device=dev)
+
+    def step(self, nsteps: int = 1) -> dict:
+        return rlgl_step(self.ctx, nsteps).as_dict()
+
+    def solve(self, eps: float, max_steps: int = 1_000_000, raise_on_error: bool = True):
+        st, info = rlgl_solve(self.ctx, eps, max_steps, self.pi, raise_on_error)
+        return st, info.as_dict()
+
+    def reset(self):
+        rlgl_reset(self.ctx)
+
+    def refresh(self) -> dict:
+        return rlgl_refresh(self.ctx).as_dict()
+
+    def state(self):
+        dev = self.dg.rowptr.device
+        C = torch.empty(self.dg.n, dtype=torch.float64, device=dev)
+        H = torch.empty(self.dg.n, dtype=torch.float64, device=dev)
+        info = rlgl_get_state(self.ctx, C, H)
+        return C, H, info.as_dict()
+
+    def set_state(self, C, H, h_sum=float("nan"), t: int = 2):
+        rlgl_set_state(self.ctx, C, H, h_sum, t)
+
+    def green(self):
+        m = torch.empty(self.dg.n, dtype=torch.uint8, device=self.dg.rowptr.device)
+        rlgl_get_green(self.ctx, m)
+        return m
+
+    def close(self):
+        if self.ctx is not None:
+            rlgl_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,32 @@
+"""Builds the HIP library librlgl.so in-tree for gfx950 with hipcc."""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "csrc", "rlgl_api.hip")
+OUT = os.path.join(HERE, "librlgl.so")
+DEPS = [os.path.join(HERE, "csrc", f) for f in ("rlgl_api.hip", "rlgl_kernels.hip", "rlgl_device.h")] + [
+    os.path.join(os.path.dirname(HERE), "include", "rlgl.h")]
+
+FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared", "-Wall",
+         # no packed FP32 instructions are emitted
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-fno-fast-math", "-ffp-contract=on"]
+
+
+def build(force: bool = True, verbose: bool = False) -> str:
+    if not force and os.path.exists(OUT) and all(os.path.getmtime(OUT) >= os.path.getmtime(p) for p in DEPS):
+        return OUT
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    tmp = OUT + ".tmp"
+    cmd = [hipcc, *FLAGS, "-o", tmp, SRC]
+    if verbose:
+        print(" ".join(cmd), file=sys.stderr)
+    subprocess.check_call(cmd)
+    os.replace(tmp, OUT)
+    return OUT
+
+
+if __name__ == "__main__":
+    print(build(force=True, verbose=True))

@@ -1,0 +1,623 @@
+// Host side of the C ABI declared in include/rlgl.h.
+//
+// The context owns no device memory: the caller's workspace is carved into
+// the cash buffers, the history, the frontier, the per-step record ring and
+// the static pull plan.  A step is three launches (select, push, complete);
+// rlgl_solve enqueues a batch of steps, reads the device status word once per
+// batch and sizes the next batch from the observed contraction of the
+// residual, so that the host synchronises a handful of times per solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/rlgl.h"
+#include "rlgl_device.h"
+#include "rlgl_kernels.hip"
+
+using namespace rlgl;
+
+namespace {
+
+thread_local std::string g_err;
+
+rlgl_status fail(rlgl_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) return fail(RLGL_EHIP, "%s: %s", #expr, hipGetErrorString(e_));     \
+  } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Layout {
+  size_t cash0, cash1, hist, hist_lo, fr_rowstart, fr_eoff, fr_id, fr_scale, chunk_first, green_mask, rec, glob,
+      log, items, med_cols, long_cols, long_acc, total;
+  size_t max_items, max_med, max_long;
+};
+
+Layout make_layout(long long n, long long nnz, int prec, bool has_csc) {
+  Layout L{};
+  const size_t cs = (prec == RLGL_FP64) ? 8 : 4;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes, 256);
+    return at;
+  };
+  L.cash0 = take(cs * n);
+  L.cash1 = has_csc ? take(cs * n) : L.cash0;
+  L.hist = take(8 * n);  // double, or the float hi part
+  L.hist_lo = (prec == RLGL_FP32C_KAHANH) ? take(4 * n) : 0;
+  L.fr_rowstart = take(4 * n);
+  L.fr_eoff = take(4 * n);
+  L.fr_id = take(4 * n);
+  L.fr_scale = take(cs * n);
+  L.chunk_first = take(4 * (nnz / CH + 2));
+  L.green_mask = take(n);
+  L.rec = take(sizeof(Rec) * 3);
+  L.glob = take(sizeof(Glob));
+  L.log = take(sizeof(StepLog) * LOG_STEPS);
+  if (has_csc) {
+    // upper bounds of the plan built in rlgl_create
+    L.max_med = (size_t)(nnz / (SHORT_MAX + 1) + 1);
+    L.max_long = (size_t)(nnz / (LONG_COL_MIN + 1) + 1);
+    L.max_items = (size_t)(nnz / CH + 2) + (size_t)(n / 1024 + 2) + 2 * L.max_med + L.max_med / NWAVE + 2 +
+                  (size_t)(nnz / LONG_COL_MIN + 2) + L.max_long;
+    L.items = take(sizeof(int4) * L.max_items);
+    L.med_cols = take(4 * L.max_med);
+    L.long_cols = take(4 * L.max_long);
+    L.long_acc = take(8 * L.max_long);
+  }
+  L.total = off + 256;
+  return L;
+}
+
+bool valid_options(const rlgl_options *o, std::string &why) {
+  if (o->sched < 0 || o->sched > 3) { why = "sched out of range"; return false; }
+  if (!(o->r >= 1.0) || !std::isfinite(o->r)) { why = "r must be >= 1"; return false; }
+  if (o->sched == RLGL_SCHED_TOPK && o->k < 1) { why = "k must be >= 1"; return false; }
+  if (o->theta_period < 1) { why = "theta_period must be >= 1"; return false; }
+  if (o->precision < 0 || o->precision > 2) { why = "precision out of range"; return false; }
+  if (o->route < 0 || o->route > 2) { why = "route out of range"; return false; }
+  if (!(o->pull_alpha >= 0.0)) { why = "pull_alpha must be >= 0"; return false; }
+  if (o->check_period < 0) { why = "check_period must be >= 0"; return false; }
+  if (o->refresh < 0) { why = "refresh must be >= 0"; return false; }
+  return true;
+}
+
+const char *kernel_names[] = {"select", "push", "complete", "topk"};
+enum { KS_SELECT = 0, KS_PUSH = 1, KS_COMPLETE = 2, KS_TOPK = 3, KS_N = 4 };
+
+struct Launch {
+  int kind;
+  long long s;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct rlgl_ctx {
+  Dev d;
+  hipStream_t stream;
+  int prec;
+  int hk;  // compensated history
+  long long t;
+  int grid_sel, grid_push, grid_cmp, grid_misc;
+  Glob *host_glob;  // pinned
+  Rec *host_rec;    // pinned, 3 records
+  StepLog *host_log;
+  bool prof;
+  std::vector<Launch> launches;
+  std::vector<hipEvent_t> free_events;
+  int has_mask;
+  int check_period;
+  int refresh;
+  long long refreshes;
+};
+
+namespace {
+
+hipEvent_t get_event(rlgl_ctx *c) {
+  if (!c->free_events.empty()) {
+    hipEvent_t e = c->free_events.back();
+    c->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+template <class F>
+hipError_t timed(rlgl_ctx *c, int kind, long long s, F launch) {
+  if (!c->prof) {
+    launch();
+    return hipGetLastError();
+  }
+  Launch L{kind, s, get_event(c), get_event(c)};
+  (void)hipEventRecord(L.a, c->stream);
+  launch();
+  hipError_t e = hipGetLastError();
+  (void)hipEventRecord(L.b, c->stream);
+  c->launches.push_back(L);
+  return e;
+}
+
+hipError_t enqueue_step(rlgl_ctx *c, long long s, double eps, long long s_limit, int force_all) {
+  const dim3 blk(BLOCK);
+  const Dev &d = c->d;
+  hipError_t e = hipSuccess;
+  if (!force_all && d.sched == SCHED_TOPK) {
+    e = timed(c, KS_TOPK, s, [&] {
+      if (c->prec == RLGL_FP64) k_topk<double><<<1, 1024, 0, c->stream>>>(d, s);
+      else k_topk<float><<<1, 1024, 0, c->stream>>>(d, s);
+    });
+    if (e != hipSuccess) return e;
+  }
+  e = timed(c, KS_SELECT, s, [&] {
+    if (c->prec == RLGL_FP64) k_select<double, 0><<<c->grid_sel, blk, 0, c->stream>>>(d, s, eps, s_limit, force_all);
+    else if (c->hk) k_select<float, 1><<<c->grid_sel, blk, 0, c->stream>>>(d, s, eps, s_limit, force_all);
+    else k_select<float, 0><<<c->grid_sel, blk, 0, c->stream>>>(d, s, eps, s_limit, force_all);
+  });
+  if (e != hipSuccess) return e;
+  if (!(d.route == ROUTE_PULL && d.colptr)) {
+    e = timed(c, KS_PUSH, s, [&] {
+      if (c->prec == RLGL_FP64) k_push<double><<<c->grid_push, blk, 0, c->stream>>>(d, s);
+      else k_push<float><<<c->grid_push, blk, 0, c->stream>>>(d, s);
+    });
+    if (e != hipSuccess) return e;
+  }
+  e = timed(c, KS_COMPLETE, s, [&] {
+    if (c->prec == RLGL_FP64) k_complete<double><<<c->grid_cmp, blk, 0, c->stream>>>(d, s, force_all);
+    else k_complete<float><<<c->grid_cmp, blk, 0, c->stream>>>(d, s, force_all);
+  });
+  return e;
+}
+
+rlgl_status read_back(rlgl_ctx *c) {
+  HIP_TRY(hipMemcpyAsync(c->host_glob, c->d.glob, sizeof(Glob), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->host_rec, c->d.rec, sizeof(Rec) * 3, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->t = c->host_glob->t;
+  return RLGL_OK;
+}
+
+void fill_info(rlgl_ctx *c, rlgl_step_info *info, int status) {
+  if (!info) return;
+  const long long t = c->t;
+  const Rec &cur = c->host_rec[t % 3];
+  const Rec &prv = c->host_rec[(t + 2) % 3];
+  info->t = t;
+  info->green = prv.green;
+  info->green_total = cur.green_total;
+  info->edges_pushed = cur.edges_total;
+  info->l1_cash = cur.l1;
+  info->h_sum = cur.hsum;
+  info->resid = cur.hsum != 0.0 ? cur.l1 / std::fabs(cur.hsum) : INFINITY;
+  info->theta = prv.theta;
+  info->cash_sum = cur.csum;
+  info->status = status;
+  info->last_route = prv.mode;
+}
+
+rlgl_status reset_device(rlgl_ctx *c) {
+  const Dev &d = c->d;
+  if (c->prec == RLGL_FP64) k_reset<double, 0><<<c->grid_misc, BLOCK, 0, c->stream>>>(d);
+  else if (c->hk) k_reset<float, 1><<<c->grid_misc, BLOCK, 0, c->stream>>>(d);
+  else k_reset<float, 0><<<c->grid_misc, BLOCK, 0, c->stream>>>(d);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(enqueue_step(c, 0, -1.0, 1, 1));  // step 0: all green, M_0 = (1/N) 1
+  return read_back(c);
+}
+
+rlgl_status do_refresh(rlgl_ctx *c) {
+  if (!c->d.colptr) return fail(RLGL_EINVAL, "refresh needs the CSC arrays");
+  const long long t = c->t;
+  const int out = c->host_rec[t % 3].buf ^ 1;
+  const Dev &d = c->d;
+  k_refresh_prep<<<1, 64, 0, c->stream>>>(d, t);
+  if (c->hk) k_refresh_pool<1><<<c->grid_misc, BLOCK, 0, c->stream>>>(d);
+  else k_refresh_pool<0><<<c->grid_misc, BLOCK, 0, c->stream>>>(d);
+  if (c->prec == RLGL_FP64) k_refresh<double, 0><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, t, out);
+  else if (c->hk) k_refresh<float, 1><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, t, out);
+  else k_refresh<float, 0><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, t, out);
+  k_refresh_done<<<1, 64, 0, c->stream>>>(d, t, out);
+  HIP_TRY(hipGetLastError());
+  ++c->refreshes;
+  return read_back(c);
+}
+
+rlgl_status status_of(int dev_status) {
+  switch (dev_status) {
+    case ST_ZERO_HISTORY: return RLGL_EZERO_HISTORY;
+    case ST_NONFINITE: return RLGL_ENONFINITE;
+    case ST_LIMIT: return RLGL_ENOT_CONVERGED;
+    default: return RLGL_OK;
+  }
+}
+
+// Host-side construction of the static pull plan from the CSC column pointers.
+rlgl_status build_plan(rlgl_ctx *c, const rlgl_graph *g, const Layout &L, char *ws) {
+  const int n = g->n;
+  std::vector<int> cp((size_t)n + 1);
+  HIP_TRY(hipMemcpyAsync(cp.data(), g->csc_colptr, sizeof(int) * ((size_t)n + 1), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (cp[0] != 0 || (long long)cp[n] != g->nnz) return fail(RLGL_EINVAL, "csc_colptr[0] must be 0 and csc_colptr[n] = nnz");
+  std::vector<int4> items;
+  std::vector<int> med, lng;
+  int run0 = -1, run_e = 0;
+  auto flush = [&](int end) {
+    if (run0 >= 0 && end > run0) items.push_back(make_int4(ITEM_SHORT, run0, end, 0));
+    run0 = -1;
+    run_e = 0;
+  };
+  for (int k = 0; k < n; ++k) {
+    const int dg = cp[k + 1] - cp[k];
+    if (dg < 0) return fail(RLGL_EINVAL, "csc_colptr is not non-decreasing at %d", k);
+    if (dg > SHORT_MAX) {
+      flush(k);
+      if (dg >= LONG_COL_MIN) lng.push_back(k);
+      else med.push_back(k);
+      continue;
+    }
+    if (run0 >= 0 && (run_e + dg > CH || k - run0 >= 1024)) flush(k);
+    if (run0 < 0) run0 = k;
+    run_e += dg;
+  }
+  flush(n);
+  for (size_t q = 0; q < med.size(); q += NWAVE)
+    items.push_back(make_int4(ITEM_MEDIUM, (int)q, (int)std::min<size_t>(NWAVE, med.size() - q), 0));
+  for (size_t q = 0; q < lng.size(); ++q) {
+    const int k = lng[q];
+    for (int p = cp[k]; p < cp[k + 1]; p += LONG_COL_MIN) items.push_back(make_int4(ITEM_LONG, (int)q, p, p + LONG_COL_MIN));
+  }
+  // long pieces first: their partial sums are the longest dependency chain
+  std::stable_partition(items.begin(), items.end(), [](const int4 &a) { return a.x == ITEM_LONG; });
+  if (items.size() > L.max_items || med.size() > L.max_med || lng.size() > L.max_long)
+    return fail(RLGL_EINVAL, "pull plan exceeds its bound (internal)");
+  if (!items.empty())
+    HIP_TRY(hipMemcpyAsync(ws + L.items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, c->stream));
+  if (!med.empty())
+    HIP_TRY(hipMemcpyAsync(ws + L.med_cols, med.data(), sizeof(int) * med.size(), hipMemcpyHostToDevice, c->stream));
+  if (!lng.empty())
+    HIP_TRY(hipMemcpyAsync(ws + L.long_cols, lng.data(), sizeof(int) * lng.size(), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->d.items = (const int4 *)(ws + L.items);
+  c->d.n_items = (int)items.size();
+  c->d.med_cols = (const int *)(ws + L.med_cols);
+  c->d.long_cols = (const int *)(ws + L.long_cols);
+  c->d.long_acc = (double *)(ws + L.long_acc);
+  c->d.n_long = (int)lng.size();
+  return RLGL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void rlgl_default_options(rlgl_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->sched = RLGL_SCHED_THRESHOLD;
+  o->r = 1.0;
+  o->k = 1;
+  o->theta_period = 1;
+  o->precision = RLGL_FP32C_FP64H;
+  o->route = RLGL_ROUTE_AUTO;
+  o->pull_alpha = 0.5;
+  o->check_period = 0;
+  o->record_green = 0;
+  o->refresh = 1;
+}
+
+const char *rlgl_last_error(void) { return g_err.c_str(); }
+
+size_t rlgl_workspace_bytes(const rlgl_graph *g, const rlgl_options *o) {
+  if (!g || !o || g->n < 1 || g->nnz < 0 || o->precision < 0 || o->precision > 2) return 0;
+  return make_layout(g->n, g->nnz, o->precision, g->csc_colptr != nullptr).total;
+}
+
+rlgl_status rlgl_create(const rlgl_graph *g, const rlgl_options *o, void *ws, size_t ws_bytes, void *stream,
+                        rlgl_ctx **out) {
+  if (!g || !o || !out) return fail(RLGL_EINVAL, "null argument");
+  *out = nullptr;
+  std::string why;
+  if (!valid_options(o, why)) return fail(RLGL_EINVAL, "options: %s", why.c_str());
+  if (g->n < 1) return fail(RLGL_EINVAL, "n must be >= 1");
+  if (g->nnz < 0 || g->nnz >= (1ll << 31)) return fail(RLGL_EINVAL, "nnz must be in [0, 2^31)");
+  if (!(g->damping > 0.0 && g->damping <= 1.0)) return fail(RLGL_EINVAL, "damping must be in (0, 1]");
+  if (!g->csr_rowptr || (g->nnz > 0 && !g->csr_col)) return fail(RLGL_EINVAL, "CSR arrays missing");
+  if (g->csc_colptr && (g->nnz > 0 && !g->csc_row)) return fail(RLGL_EINVAL, "csc_row missing");
+  if (o->route == RLGL_ROUTE_PULL && !g->csc_colptr) return fail(RLGL_EINVAL, "pull routing needs the CSC arrays");
+  if ((g->csr_val == nullptr) != (g->csc_colptr ? g->csc_val == nullptr : g->csr_val == nullptr))
+    return fail(RLGL_EINVAL, "csr_val and csc_val must both be given or both be NULL");
+  if (!ws) return fail(RLGL_EINVAL, "workspace is NULL");
+  const Layout L = make_layout(g->n, g->nnz, o->precision, g->csc_colptr != nullptr);
+  if (ws_bytes < L.total) return fail(RLGL_ENOMEM, "workspace too small: %zu < %zu", ws_bytes, L.total);
+
+  rlgl_ctx *c = new (std::nothrow) rlgl_ctx();
+  if (!c) return fail(RLGL_ENOMEM, "host allocation failed");
+  c->stream = (hipStream_t)stream;
+  c->prec = o->precision;
+  c->hk = (o->precision == RLGL_FP32C_KAHANH);
+  c->prof = false;
+  char *w = (char *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+  Dev &d = c->d;
+  d.n = g->n;
+  d.nnz = g->nnz;
+  d.c = g->damping;
+  d.rowptr = g->csr_rowptr;
+  d.col = g->csr_col;
+  d.val = g->csr_val;
+  d.colptr = g->csc_colptr;
+  d.crow = g->csc_row;
+  d.cval = g->csc_val;
+  d.sched = o->sched;
+  d.r = o->r;
+  d.k = o->k;
+  d.theta_period = o->theta_period;
+  d.route = g->csc_colptr ? o->route : RLGL_ROUTE_PUSH;
+  d.pull_alpha = o->pull_alpha;
+  d.cash[0] = w + L.cash0;
+  d.cash[1] = w + L.cash1;
+  d.hist = w + L.hist;
+  d.hist_lo = c->hk ? (float *)(w + L.hist_lo) : nullptr;
+  d.fr_rowstart = (int *)(w + L.fr_rowstart);
+  d.fr_eoff = (int *)(w + L.fr_eoff);
+  d.fr_id = (int *)(w + L.fr_id);
+  d.fr_scale = w + L.fr_scale;
+  d.chunk_first = (int *)(w + L.chunk_first);
+  d.green_mask = o->record_green ? (unsigned char *)(w + L.green_mask) : nullptr;
+  c->has_mask = o->record_green != 0;
+  c->check_period = o->check_period;
+  c->refresh = g->csc_colptr ? o->refresh : 0;
+  d.rec = (Rec *)(w + L.rec);
+  d.glob = (Glob *)(w + L.glob);
+  d.log = (StepLog *)(w + L.log);
+  d.items = nullptr;
+  d.n_items = 0;
+  d.med_cols = nullptr;
+  d.long_cols = nullptr;
+  d.long_acc = nullptr;
+  d.n_long = 0;
+
+  const int tiles = (g->n + TILE - 1) / TILE;
+  c->grid_sel = std::max(1, std::min(tiles, MAX_GRID));
+  c->grid_push = (int)std::max<long long>(1, std::min<long long>((g->nnz + CH - 1) / CH, MAX_GRID));
+  c->grid_misc = std::max(1, std::min((g->n + BLOCK - 1) / BLOCK, MAX_GRID));
+
+  rlgl_status st = RLGL_OK;
+  if (hipHostMalloc((void **)&c->host_glob, sizeof(Glob), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&c->host_rec, sizeof(Rec) * 3, hipHostMallocDefault) != hipSuccess) {
+    st = fail(RLGL_EHIP, "pinned host allocation failed");
+  }
+  if (st == RLGL_OK) {
+    int last = 0;
+    if (hipMemcpyAsync(&last, g->csr_rowptr + g->n, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+      st = fail(RLGL_EHIP, "reading csr_rowptr[n] failed");
+    else if ((long long)last != g->nnz)
+      st = fail(RLGL_EINVAL, "csr_rowptr[n] = %d differs from nnz = %lld", last, (long long)g->nnz);
+  }
+  if (st == RLGL_OK && g->csc_colptr) st = build_plan(c, g, L, w);
+  if (st == RLGL_OK) {
+    c->grid_cmp = std::max(1, std::min(std::max(tiles, d.n_items), MAX_GRID));
+    st = reset_device(c);
+  }
+  if (st != RLGL_OK) {
+    rlgl_destroy(c);
+    return st;
+  }
+  *out = c;
+  return RLGL_OK;
+}
+
+void rlgl_destroy(rlgl_ctx *c) {
+  if (!c) return;
+  for (auto &L : c->launches) {
+    (void)hipEventDestroy(L.a);
+    (void)hipEventDestroy(L.b);
+  }
+  for (auto e : c->free_events) (void)hipEventDestroy(e);
+  if (c->host_glob) (void)hipHostFree(c->host_glob);
+  if (c->host_rec) (void)hipHostFree(c->host_rec);
+  delete c;
+}
+
+rlgl_status rlgl_reset(rlgl_ctx *c) {
+  if (!c) return fail(RLGL_EINVAL, "null context");
+  return reset_device(c);
+}
+
+rlgl_status rlgl_step(rlgl_ctx *c, int32_t nsteps, rlgl_step_info *info) {
+  if (!c || nsteps < 0) return fail(RLGL_EINVAL, "bad argument");
+  k_set_status<<<1, 64, 0, c->stream>>>(c->d.glob, 0);
+  HIP_TRY(hipGetLastError());
+  const long long s0 = c->t;
+  for (long long s = s0; s < s0 + nsteps; ++s) HIP_TRY(enqueue_step(c, s, -1.0, s0 + nsteps, 0));
+  rlgl_status st = read_back(c);
+  if (st != RLGL_OK) return st;
+  const int ds = c->host_glob->status;
+  const rlgl_status rs = (ds == ST_ZERO_HISTORY || ds == ST_NONFINITE) ? status_of(ds) : RLGL_OK;
+  fill_info(c, info, rs);
+  if (rs != RLGL_OK) return fail(rs, "stopped at t = %lld (device status %d)", c->t, ds);
+  return RLGL_OK;
+}
+
+rlgl_status rlgl_solve(rlgl_ctx *c, double eps, int64_t max_steps, double *dev_pi, rlgl_step_info *info) {
+  if (!c || max_steps < 0 || !(eps >= 0.0)) return fail(RLGL_EINVAL, "bad argument");
+  k_set_status<<<1, 64, 0, c->stream>>>(c->d.glob, 0);
+  HIP_TRY(hipGetLastError());
+  const long long s_limit = c->t + max_steps;
+  long long batch = c->check_period > 0 ? c->check_period : (c->d.sched == SCHED_MAXC ? 64 : 4);
+  double prev_resid = -1.0;
+  long long prev_t = c->t, refreshed_at = -1, last_refresh = c->t;
+  int ds = 0;
+  for (;;) {
+    const long long s = c->t;
+    long long nb = batch;
+    if (s + nb > s_limit + 1) nb = s_limit + 1 - s;
+    if (nb < 1) nb = 1;
+    for (long long q = 0; q < nb; ++q) HIP_TRY(enqueue_step(c, s + q, eps, s_limit, 0));
+    rlgl_status st = read_back(c);
+    if (st != RLGL_OK) return st;
+    ds = c->host_glob->status;
+    if (ds == ST_CONVERGED && c->refresh > 0 && refreshed_at != c->t) {
+      // accept the stop only on the cash rebuilt from the history
+      st = do_refresh(c);
+      if (st != RLGL_OK) return st;
+      refreshed_at = last_refresh = c->t;
+      continue;
+    }
+    if (ds != 0) break;
+    const Rec &cur = c->host_rec[c->t % 3];
+    const bool drift = std::fabs(cur.csum) > 0.5 * cur.l1;
+    const bool periodic = c->refresh > 1 && c->t - last_refresh >= c->refresh;
+    if (c->refresh > 0 && (drift || periodic) && refreshed_at != c->t) {
+      st = do_refresh(c);
+      if (st != RLGL_OK) return st;
+      refreshed_at = last_refresh = c->t;
+    }
+    // size the next batch from the contraction seen so far
+    const Rec &now = c->host_rec[c->t % 3];
+    const double resid = now.hsum != 0.0 ? now.l1 / std::fabs(now.hsum) : INFINITY;
+    long long next = batch * 2;
+    if (prev_resid > 0.0 && resid > 0.0 && resid < prev_resid && c->t > prev_t) {
+      const double rate = std::pow(resid / prev_resid, 1.0 / (double)(c->t - prev_t));
+      if (rate < 1.0 && resid > eps) next = (long long)std::ceil(std::log(eps / resid) / std::log(rate)) + 1;
+    }
+    if (c->d.sched == SCHED_MAXC) next = std::max(next, (long long)256);
+    batch = std::max(1ll, std::min(next, 4096ll));
+    if (c->check_period > 0) batch = c->check_period;
+    prev_resid = resid;
+    prev_t = c->t;
+  }
+  if (dev_pi) {
+    if (c->hk) k_normalize<1><<<c->grid_misc, BLOCK, 0, c->stream>>>(c->d, dev_pi);
+    else k_normalize<0><<<c->grid_misc, BLOCK, 0, c->stream>>>(c->d, dev_pi);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  const rlgl_status rs = (ds == ST_CONVERGED) ? RLGL_OK : status_of(ds);
+  fill_info(c, info, rs);
+  if (rs != RLGL_OK) return fail(rs, "solve stopped at t = %lld (device status %d)", c->t, ds);
+  return RLGL_OK;
+}
+
+rlgl_status rlgl_refresh(rlgl_ctx *c, rlgl_step_info *info) {
+  if (!c) return fail(RLGL_EINVAL, "null context");
+  rlgl_status st = do_refresh(c);
+  if (st != RLGL_OK) return st;
+  fill_info(c, info, RLGL_OK);
+  return RLGL_OK;
+}
+
+rlgl_status rlgl_get_state(rlgl_ctx *c, double *dC, double *dH, rlgl_step_info *info) {
+  if (!c) return fail(RLGL_EINVAL, "null context");
+  if (dC || dH) {
+    if (c->prec == RLGL_FP64) k_export<double, 0><<<c->grid_misc, BLOCK, 0, c->stream>>>(c->d, dC, dH);
+    else if (c->hk) k_export<float, 1><<<c->grid_misc, BLOCK, 0, c->stream>>>(c->d, dC, dH);
+    else k_export<float, 0><<<c->grid_misc, BLOCK, 0, c->stream>>>(c->d, dC, dH);
+    HIP_TRY(hipGetLastError());
+  }
+  rlgl_status st = read_back(c);
+  if (st != RLGL_OK) return st;
+  fill_info(c, info, RLGL_OK);
+  return RLGL_OK;
+}
+
+rlgl_status rlgl_set_state(rlgl_ctx *c, const double *dC, const double *dH, double h_sum, int64_t t) {
+  if (!c || !dC || !dH || t < 1) return fail(RLGL_EINVAL, "bad argument");
+  const int buf = 0;
+  k_prepare_import<<<1, 64, 0, c->stream>>>(c->d, t, buf);
+  if (c->prec == RLGL_FP64) k_import<double, 0><<<c->grid_misc, BLOCK, 0, c->stream>>>(c->d, dC, dH, t, buf);
+  else if (c->hk) k_import<float, 1><<<c->grid_misc, BLOCK, 0, c->stream>>>(c->d, dC, dH, t, buf);
+  else k_import<float, 0><<<c->grid_misc, BLOCK, 0, c->stream>>>(c->d, dC, dH, t, buf);
+  k_finish_import<<<1, 64, 0, c->stream>>>(c->d, t, h_sum);
+  HIP_TRY(hipGetLastError());
+  return read_back(c);
+}
+
+rlgl_status rlgl_get_green(rlgl_ctx *c, uint8_t *dmask) {
+  if (!c || !dmask) return fail(RLGL_EINVAL, "bad argument");
+  if (!c->has_mask) return fail(RLGL_EINVAL, "the context was created without record_green");
+  HIP_TRY(hipMemcpyAsync(dmask, c->d.green_mask, (size_t)c->d.n, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return RLGL_OK;
+}
+
+rlgl_status rlgl_profile_enable(rlgl_ctx *c, int32_t on) {
+  if (!c) return fail(RLGL_EINVAL, "null context");
+  c->prof = on != 0;
+  return RLGL_OK;
+}
+
+int32_t rlgl_profile_read(rlgl_ctx *c, rlgl_kernel_stat *out, int32_t max_entries) {
+  if (!c || !out || max_entries < 0) return fail(RLGL_EINVAL, "bad argument");
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(RLGL_EHIP, "synchronize failed");
+  std::vector<StepLog> log(LOG_STEPS);
+  if (hipMemcpy(log.data(), c->d.log, sizeof(StepLog) * LOG_STEPS, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(RLGL_EHIP, "reading the step log failed");
+  const double cs = (c->prec == RLGL_FP64) ? 8.0 : 4.0;
+  const double vs = c->d.val ? cs : 0.0;
+  const double hb = 16.0;  // history read-modify-write per green node
+  const double n = (double)c->d.n, nnz = (double)c->d.nnz;
+  double ms[KS_N] = {0}, bytes[KS_N] = {0};
+  long long cnt[KS_N] = {0};
+  for (auto &L : c->launches) {
+    const StepLog &lg = log[L.s % LOG_STEPS];
+    if (lg.s != L.s) continue;  // launch of a step that never ran (after the stop) or fell off the ring
+    const bool push = lg.mode == 0;
+    double b = 0.0;
+    if (L.kind == KS_SELECT) {
+      b = cs * n + (double)lg.green * (8.0 + hb);
+      if (push) b += (double)lg.nfront * (4 + 4 + 4 + cs) + (double)lg.green * cs;
+    } else if (L.kind == KS_PUSH) {
+      if (!push) continue;
+      b = (double)lg.gedges * (4.0 + vs + 2.0 * cs) + (double)lg.nfront * (8.0 + cs);
+    } else if (L.kind == KS_COMPLETE) {
+      b = push ? 2.0 * cs * n : (4.0 * n + nnz * (4.0 + vs + cs) + 2.0 * cs * n);
+    } else {
+      b = 0.0;
+    }
+    float e = 0.f;
+    (void)hipEventElapsedTime(&e, L.a, L.b);
+    ms[L.kind] += e;
+    bytes[L.kind] += b;
+    cnt[L.kind] += 1;
+  }
+  for (auto &L : c->launches) {
+    c->free_events.push_back(L.a);
+    c->free_events.push_back(L.b);
+  }
+  c->launches.clear();
+  int m = 0;
+  for (int k = 0; k < KS_N && m < max_entries; ++k) {
+    if (!cnt[k]) continue;
+    std::memset(&out[m], 0, sizeof out[m]);
+    std::snprintf(out[m].name, sizeof out[m].name, "%s", kernel_names[k]);
+    out[m].launches = cnt[k];
+    out[m].ms = ms[k];
+    out[m].bytes = bytes[k];
+    ++m;
+  }
+  return m;
+}
+
+}  // extern "C"

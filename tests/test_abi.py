@@ -1,0 +1,91 @@
+"""The C-ABI library loads, exports every symbol the header declares, and
+rejects bad arguments on the host before any device work (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rlgl.h")
+LIB = os.path.join(ROOT, "paper_2008_02710_amd", "librlgl.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rlgl_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        import paper_2008_02710_amd.build as b
+        b.build(force=True)
+    return ctypes.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert "rlgl_create" in names and "rlgl_solve" in names and "rlgl_step" in names and "rlgl_destroy" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_binding_names_match_header():
+    import paper_2008_02710_amd as rl
+    for name in declared_functions():
+        assert hasattr(rl, name), name
+
+
+def test_struct_sizes_match_header():
+    """The ctypes mirrors have the C layout (checked against offsets the
+    compiler computes for the header)."""
+    import paper_2008_02710_amd as rl
+    src = os.path.join(ROOT, "_sizes_probe.c")
+    exe = os.path.join(ROOT, "_sizes_probe")
+    open(src, "w").write(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "rlgl.h"\n'
+        'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(rlgl_graph), sizeof(rlgl_options),'
+        ' sizeof(rlgl_step_info), sizeof(rlgl_kernel_stat), offsetof(rlgl_options, record_green),'
+        ' offsetof(rlgl_step_info, last_route));return 0;}\n')
+    try:
+        import subprocess
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", exe, src])
+        out = subprocess.check_output([exe]).decode().split()
+    finally:
+        for p in (src, exe):
+            if os.path.exists(p):
+                os.remove(p)
+    got = [ctypes.sizeof(rl.rlgl_graph), ctypes.sizeof(rl.rlgl_options), ctypes.sizeof(rl.rlgl_step_info),
+           ctypes.sizeof(rl.rlgl_kernel_stat), rl.rlgl_options.record_green.offset,
+           rl.rlgl_step_info.last_route.offset]
+    assert [int(x) for x in out] == got
+
+
+def test_host_side_argument_checks():
+    import paper_2008_02710_amd as rl
+    g = rl.rlgl_graph(10, 0, 1, 0, None, None, None, None, 0.85)
+    opt = rl.rlgl_default_options()
+    assert opt.sched == rl.SCHED_THRESHOLD and opt.r == 1.0 and opt.theta_period == 1
+    assert rl.rlgl_workspace_bytes(g, opt) > 0
+    bad = rl.rlgl_graph(0, 0, 1, 0, None, None, None, None, 0.85)
+    assert rl.rlgl_workspace_bytes(bad, opt) == 0
+    ctx = ctypes.c_void_p()
+    lib = rl._lib
+    # damping outside (0, 1]
+    g0 = rl.rlgl_graph(10, 0, 1, 0, None, None, None, None, 0.0)
+    assert lib.rlgl_create(ctypes.byref(g0), ctypes.byref(opt), 4096, 1 << 20, None, ctypes.byref(ctx)) == rl.RLGL_EINVAL
+    assert "damping" in rl.rlgl_last_error()
+    # workspace too small
+    assert lib.rlgl_create(ctypes.byref(g), ctypes.byref(opt), 4096, 16, None, ctypes.byref(ctx)) == rl.RLGL_ENOMEM
+    # bad options
+    for field, value in (("sched", 9), ("r", 0.5), ("theta_period", 0), ("precision", 7), ("route", 5)):
+        o = rl.rlgl_default_options(**{field: value})
+        assert lib.rlgl_create(ctypes.byref(g), ctypes.byref(o), 4096, 1 << 30, None, ctypes.byref(ctx)) == rl.RLGL_EINVAL
+    o = rl.rlgl_default_options(sched=rl.SCHED_TOPK, k=0)
+    assert lib.rlgl_create(ctypes.byref(g), ctypes.byref(o), 4096, 1 << 30, None, ctypes.byref(ctx)) == rl.RLGL_EINVAL
+    # pull routing without the CSC
+    o = rl.rlgl_default_options(route=rl.ROUTE_PULL)
+    assert lib.rlgl_create(ctypes.byref(g), ctypes.byref(o), 4096, 1 << 30, None, ctypes.byref(ctx)) == rl.RLGL_EINVAL
+    assert ctx.value is None

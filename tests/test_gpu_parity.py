@@ -1,0 +1,297 @@
+"""Parity of the HIP path (through the C ABI) with the reference oracle.
+
+Tolerances:
+  * FP64 cash: single steps agree to 1e-14 of the moved mass; solves reach
+    L1 <= 1e-10 against the FP64 power-iteration reference.
+  * FP32 cash (FP64 or compensated history): single steps agree to 2e-6 of
+    the moved mass (one float rounding per stored link plus one per atomic
+    add, at most ~2^-23 relative each); solves reach L1 <= 1e-6.
+  * The green set is compared bit for bit: the oracle selects on the very
+    cash vector the device holds, with the threshold the device reports.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import l1, oracle_chain, say, solver, to_np
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2008_02710_amd as rl  # noqa: E402
+
+PRECS = [rl.FP64, rl.FP32C_FP64H, rl.FP32C_KAHANH]
+PREC_NAMES = {rl.FP64: "fp64", rl.FP32C_FP64H: "fp32c_fp64h", rl.FP32C_KAHANH: "fp32c_kahanh"}
+SCHEDS = {"all": rl.SCHED_ALL, "threshold": rl.SCHED_THRESHOLD, "topk": rl.SCHED_TOPK, "maxc": rl.SCHED_MAXC}
+ORC_SCHED = {rl.SCHED_ALL: oracle.ALL, rl.SCHED_THRESHOLD: oracle.THRESHOLD, rl.SCHED_TOPK: oracle.TOPK,
+             rl.SCHED_MAXC: oracle.MAXC}
+ROUTES = {"push": rl.ROUTE_PUSH, "pull": rl.ROUTE_PULL, "auto": rl.ROUTE_AUTO}
+
+
+def tol_step(prec):
+    return 1e-14 if prec == rl.FP64 else 2e-6
+
+
+def tol_solve(prec):
+    return 1e-10 if prec == rl.FP64 else 1e-6
+
+
+_cache = {}
+
+
+def small_graph():
+    # 3 tiles of 1024 nodes with a ragged tail, 10% dangling, duplicates and self-loops
+    if "small" not in _cache:
+        _cache["small"] = workloads.chung_lu(2500, 2.5, 6.0, 0.1, 0.85, seed=3, name="small")
+    return _cache["small"]
+
+
+def hub_graph():
+    # power-law exponent 2.1: out- and in-hubs with more than 4096 links
+    if "hub" not in _cache:
+        g = workloads.chung_lu(20000, 2.1, 16.0, 0.05, 0.85, seed=5, name="hub")
+        assert g.outdeg.max() > 4096 and np.diff(g.csc()[0]).max() > 4096
+        _cache["hub"] = g
+    return _cache["hub"]
+
+
+def reference(g):
+    key = ("ref", g.name, g.n)
+    if key not in _cache:
+        _cache[key] = oracle.reference_pagerank(oracle_chain(g), 1e-13)[0]
+    return _cache[key]
+
+
+# ------------------------------------------------------------------- step 0
+
+@pytest.mark.parametrize("prec", PRECS, ids=PREC_NAMES.get)
+@pytest.mark.parametrize("route", ["push", "pull"])
+def test_step0_matches_oracle(prec, route):
+    g = small_graph()
+    say("case step0", PREC_NAMES[prec], route)
+    s = solver(g, prec, route=ROUTES[route], sched=rl.SCHED_ALL)
+    C, H, info = s.state()
+    st = oracle.State(oracle_chain(g))
+    assert info["t"] == 1
+    assert l1(to_np(C), st.C) <= tol_step(prec)
+    assert l1(to_np(H), st.H) <= (1e-15 if prec == rl.FP64 else 1e-6)
+    # M_0 = (1/N) 1 rounded to the cash type
+    assert abs(info["h_sum"] - 1.0) <= (1e-12 if prec == rl.FP64 else 1e-7)
+    assert info["edges_pushed"] == st.edges == int(g.outdeg[g.outdeg > 0].sum())
+    s.close()
+
+
+# ------------------------------------------------------------ one step
+
+def _nontrivial_state(g, prec, steps=3):
+    st = oracle.State(oracle_chain(g))
+    for _ in range(steps):
+        st.step(oracle.ALL)
+    C = st.C.copy()
+    if prec != rl.FP64:
+        C = C.astype(np.float32).astype(np.float64)
+    return C, st.H.copy(), st.hsum
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=PREC_NAMES.get)
+@pytest.mark.parametrize("route", ["push", "pull", "auto"])
+@pytest.mark.parametrize("sched", ["all", "threshold", "topk", "maxc"])
+@pytest.mark.parametrize("which", ["small", "hub"])
+def test_single_step_parity(prec, route, sched, which):
+    g = small_graph() if which == "small" else hub_graph()
+    say("case single_step", which, PREC_NAMES[prec], route, sched)
+    k = 97
+    s = solver(g, prec, route=ROUTES[route], sched=SCHEDS[sched], k=k, record_green=1)
+    C0, H0, hs0 = _nontrivial_state(g, prec)
+    s.set_state(torch.from_numpy(C0).cuda(), torch.from_numpy(H0).cuda(), hs0, t=4)
+    Cg, Hg, info0 = s.state()
+    Cg, Hg = to_np(Cg), to_np(Hg)
+    assert np.array_equal(Cg, C0)  # the state is representable in the cash type
+    assert l1(Hg, H0) <= (0.0 if prec != rl.FP32C_KAHANH else 1e-13)
+    assert info0["h_sum"] == hs0 and info0["t"] == 4
+    info1 = s.step(1)
+    mask = to_np(s.green()).astype(bool)
+    theta = info1["theta"]
+    osch = ORC_SCHED[SCHEDS[sched]]
+    if osch == oracle.THRESHOLD:
+        assert theta == pytest.approx(oracle.theta(Cg), rel=1e-12)
+    want = oracle.select(Cg, osch, theta, k)
+    assert np.array_equal(mask, want), (int(mask.sum()), int(want.sum()))
+    assert info1["green"] == int(want.sum())
+    ost = oracle.State.from_arrays(oracle_chain(g), Cg, Hg, info0["h_sum"], t=4)
+    moved = float(np.abs(Cg[want]).sum())
+    ost.step_mask(want)
+    C1, H1, info2 = s.state()
+    assert info2["t"] == 5
+    assert l1(to_np(C1), ost.C) <= tol_step(prec) * moved + 1e-300
+    assert l1(to_np(H1), ost.H) <= (1e-15 * moved if prec == rl.FP64 else 1e-13 + 1e-7 * moved)
+    assert abs(info2["h_sum"] - ost.hsum) <= 1e-14
+    assert info2["l1_cash"] == pytest.approx(float(np.abs(to_np(C1)).sum()), rel=1e-12, abs=1e-300)
+    s.close()
+
+
+# --------------------------------------------------------------- solves
+
+@pytest.mark.parametrize("prec", PRECS, ids=PREC_NAMES.get)
+@pytest.mark.parametrize("sched", ["all", "threshold", "topk", "maxc"])
+def test_solve_small(prec, sched):
+    g = small_graph()
+    say("case solve_small", PREC_NAMES[prec], sched)
+    tol = tol_solve(prec)
+    eps = (1 - g.c) * tol * 0.5
+    s = solver(g, prec, sched=SCHEDS[sched], k=50)
+    st, info = s.solve(eps)
+    assert st == rl.RLGL_OK and info["resid"] < eps and info["t"] >= 2
+    pi = to_np(s.pi)
+    x = reference(g)
+    assert l1(pi, x) <= tol, info
+    assert abs(pi.sum() - 1.0) <= 1e-12
+    ost, opi, oinfo = oracle.solve(oracle_chain(g), ORC_SCHED[SCHEDS[sched]], eps=eps, k=50)
+    assert ost == oracle.OK
+    if prec == rl.FP64 and sched == "all":
+        assert abs(info["t"] - oinfo["t"]) <= 1
+    else:
+        assert info["t"] <= 2 * oinfo["t"] + 5
+    s.close()
+
+
+@pytest.mark.parametrize("route", ["push", "pull"])
+def test_all_green_trajectory_is_power_iteration(route):
+    """G_t = [N]: H_t = M_0 P^(t-1) and H_t 1 = 1, step by step (FP64)."""
+    g = small_graph()
+    say("case all_green_trajectory", route)
+    s = solver(g, rl.FP64, sched=rl.SCHED_ALL, route=ROUTES[route])
+    ost = oracle.State(oracle_chain(g))
+    for t in range(1, 30):
+        C, H, info = s.state()
+        assert info["t"] == t
+        # summation order differs (CSC gather or atomics vs the oracle's CSR
+        # scatter): ~sqrt(in-degree) ulps on the hub nodes per step
+        assert l1(to_np(H), ost.H) <= 2e-14 * t
+        assert abs(info["h_sum"] - 1.0) <= 1e-13
+        s.step(1)
+        ost.step(oracle.ALL)
+    s.close()
+
+
+@pytest.mark.parametrize("route", ["push", "pull", "auto"])
+@pytest.mark.parametrize("prec", [rl.FP32C_FP64H, rl.FP32C_KAHANH], ids=PREC_NAMES.get)
+def test_solve_hub_graph(route, prec):
+    g = hub_graph()
+    say("case solve_hub", route, PREC_NAMES[prec])
+    s = solver(g, prec, sched=rl.SCHED_THRESHOLD, route=ROUTES[route])
+    st, info = s.solve((1 - g.c) * 0.5e-6)
+    assert st == rl.RLGL_OK
+    assert l1(to_np(s.pi), reference(g)) <= 1e-6
+    s.close()
+
+
+def test_implicit_values_match_explicit():
+    g = hub_graph()
+    say("case implicit_values")
+    a = solver(g, rl.FP32C_FP64H, explicit_val=False, route=rl.ROUTE_AUTO)
+    st, info = a.solve((1 - g.c) * 0.5e-6)
+    assert st == rl.RLGL_OK
+    assert l1(to_np(a.pi), reference(g)) <= 1e-6
+    a.close()
+
+
+def test_reset_repeats_the_solve():
+    g = small_graph()
+    say("case reset")
+    s = solver(g, rl.FP64, sched=rl.SCHED_THRESHOLD, route=rl.ROUTE_PULL)
+    st, a = s.solve(1e-12)
+    pa = to_np(s.pi).copy()
+    s.reset()
+    st, b = s.solve(1e-12)
+    assert a["t"] == b["t"] and a["edges_pushed"] == b["edges_pushed"]
+    assert l1(pa, to_np(s.pi)) <= 1e-13
+    s.close()
+
+
+def test_push_and_pull_agree():
+    g = hub_graph()
+    say("case push_pull_agree")
+    out = []
+    for route in (rl.ROUTE_PUSH, rl.ROUTE_PULL):
+        s = solver(g, rl.FP64, sched=rl.SCHED_ALL, route=route)
+        s.step(12)
+        C, H, info = s.state()
+        out.append((to_np(C), to_np(H)))
+        s.close()
+    assert l1(out[0][0], out[1][0]) <= 1e-13
+    assert l1(out[0][1], out[1][1]) <= 2e-13
+
+
+# ---------------------------------------------------------- edge cases
+
+def test_error_zero_history():
+    """Example 1: C_1 = (-1, .5, .5, 0), H_1 = (1, 0, 0, 0); MaxC greens node 1
+    and the history vanishes."""
+    P = workloads.from_edges(4, [0, 0, 1, 2, 3], [1, 2, 2, 3, 0], 1.0)
+    say("case zero_history")
+    s = solver(P, rl.FP64, sched=rl.SCHED_MAXC)
+    s.set_state(torch.tensor([-1.0, .5, .5, 0.0], dtype=torch.float64).cuda(),
+                torch.tensor([1.0, 0, 0, 0], dtype=torch.float64).cuda(), 1.0, t=1)
+    st, info = s.solve(1e-12, raise_on_error=False)
+    assert st == rl.RLGL_EZERO_HISTORY and info["t"] == 2
+    s.close()
+
+
+def test_error_not_converged_and_nonfinite():
+    g = small_graph()
+    say("case not_converged")
+    s = solver(g, rl.FP32C_FP64H, sched=rl.SCHED_THRESHOLD)
+    st, info = s.solve(1e-30, max_steps=5, raise_on_error=False)
+    assert st == rl.RLGL_ENOT_CONVERGED and info["t"] == 6
+    assert abs(to_np(s.pi).sum() - 1.0) < 1e-9  # pi is still written
+    say("case nonfinite")
+    C = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    C[7] = float("nan")
+    H = torch.full((g.n,), 1.0 / g.n, dtype=torch.float64, device="cuda")
+    s.set_state(C, H, 1.0, t=3)
+    st, info = s.solve(1e-9, raise_on_error=False)
+    assert st == rl.RLGL_ENONFINITE
+    s.close()
+
+
+@pytest.mark.parametrize("prec", [rl.FP64, rl.FP32C_FP64H], ids=PREC_NAMES.get)
+def test_degenerate_graphs(prec):
+    say("case degenerate", PREC_NAMES[prec])
+    # a single dangling node; an empty link set (every row dangling: uniform pi)
+    for n in (1, 5, 1500):
+        g = workloads.from_edges(n, np.zeros(0, np.int32), np.zeros(0, np.int32), 0.85)
+        s = solver(g, prec, sched=rl.SCHED_THRESHOLD)
+        st, info = s.solve(1e-12)
+        assert st == rl.RLGL_OK
+        assert np.abs(to_np(s.pi) - 1.0 / n).max() <= 1e-7
+        s.close()
+    # two nodes pointing at each other, c = 1 (periodic chain, but the
+    # all-green step lands exactly on pi* from the uniform start)
+    g = workloads.from_edges(2, [0, 1], [1, 0], 1.0)
+    s = solver(g, prec, sched=rl.SCHED_ALL)
+    st, info = s.solve(1e-12)
+    assert st == rl.RLGL_OK and np.allclose(to_np(s.pi), 0.5)
+    s.close()
+
+
+def test_two_wheels_closed_form():
+    """Two-wheels graph, c = 1: pi = deg / 42."""
+    import os
+    say("case two_wheels")
+    edges = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "two_wheels_edges.txt"),
+                       dtype=np.int64) - 1
+    g = workloads.from_edges(12, np.r_[edges[:, 0], edges[:, 1]], np.r_[edges[:, 1], edges[:, 0]], 1.0)
+    ref = g.outdeg / 42.0
+    for sched in (rl.SCHED_ALL, rl.SCHED_THRESHOLD, rl.SCHED_MAXC, rl.SCHED_TOPK):
+        s = solver(g, rl.FP64, sched=sched, k=3)
+        st, info = s.solve(1e-13)
+        assert st == rl.RLGL_OK
+        assert l1(to_np(s.pi), ref) <= 1e-11
+        s.close()
