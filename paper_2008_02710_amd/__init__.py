@@ -97,7 +97,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     return lib
 
 
-_lib = load_library()
+_lib = load_library(os.environ.get("RLGL_LIBRARY", LIB_PATH))
 
 
 class RlglError(RuntimeError):

@@ -46,9 +46,10 @@ rlgl_status fail(rlgl_status st, const char *fmt, ...) {
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-  size_t cash0, cash1, hist, hist_lo, fr_rowstart, fr_eoff, fr_id, fr_scale, chunk_first, green_mask, rec, glob,
-      log, items, med_cols, long_cols, long_acc, total;
-  size_t max_items, max_med, max_long;
+  size_t cash0, cash1, hist, hist_lo, fr_rowstart, fr_eoff, fr_id, fr_scale, chunk_first, green_mask, delta, colt,
+      hot_nodes, rec, glob,
+      log, items, long_cols, long_acc, total;
+  size_t max_items, max_long;
 };
 
 Layout make_layout(long long n, long long nnz, int prec, bool has_csc) {
@@ -70,17 +71,20 @@ Layout make_layout(long long n, long long nnz, int prec, bool has_csc) {
   L.fr_scale = take(cs * n);
   L.chunk_first = take(4 * (nnz / CH + 2));
   L.green_mask = take(n);
+  L.delta = (prec == RLGL_FP64) ? 0 : take(8 * n);
+  L.colt = take(4 * (size_t)nnz);
+  L.hot_nodes = take(4 * (size_t)HOT_MAX);
   L.rec = take(sizeof(Rec) * 3);
   L.glob = take(sizeof(Glob));
   L.log = take(sizeof(StepLog) * LOG_STEPS);
   if (has_csc) {
-    // upper bounds of the plan built in rlgl_create
-    L.max_med = (size_t)(nnz / (SHORT_MAX + 1) + 1);
-    L.max_long = (size_t)(nnz / (LONG_COL_MIN + 1) + 1);
-    L.max_items = (size_t)(nnz / CH + 2) + (size_t)(n / 1024 + 2) + 2 * L.max_med + L.max_med / NWAVE + 2 +
-                  (size_t)(nnz / LONG_COL_MIN + 2) + L.max_long;
+    // upper bounds of the plan built in rlgl_create: a run ends because it is
+    // full (CH links or RUN_MAX_COLS columns) or because a long column follows
+    L.max_long = (size_t)(nnz / (CH + 1) + 1);
+    // runs: two consecutive runs hold more than CH links unless a column-count
+    // or long-column break separates them; pieces: nnz / CH + one per long column
+    L.max_items = 3 * (size_t)(nnz / CH + 2) + (size_t)(n / RUN_MAX_COLS + 2) + 2 * L.max_long + 2;
     L.items = take(sizeof(int4) * L.max_items);
-    L.med_cols = take(4 * L.max_med);
     L.long_cols = take(4 * L.max_long);
     L.long_acc = take(8 * L.max_long);
   }
@@ -101,8 +105,8 @@ bool valid_options(const rlgl_options *o, std::string &why) {
   return true;
 }
 
-const char *kernel_names[] = {"select", "push", "complete", "topk"};
-enum { KS_SELECT = 0, KS_PUSH = 1, KS_COMPLETE = 2, KS_TOPK = 3, KS_N = 4 };
+const char *kernel_names[] = {"select", "push", "complete", "topk", "complete_long"};
+enum { KS_SELECT = 0, KS_PUSH = 1, KS_COMPLETE = 2, KS_TOPK = 3, KS_LONG = 4, KS_N = 5 };
 
 struct Launch {
   int kind;
@@ -187,6 +191,12 @@ hipError_t enqueue_step(rlgl_ctx *c, long long s, double eps, long long s_limit,
     if (c->prec == RLGL_FP64) k_complete<double><<<c->grid_cmp, blk, 0, c->stream>>>(d, s, force_all);
     else k_complete<float><<<c->grid_cmp, blk, 0, c->stream>>>(d, s, force_all);
   });
+  if (e != hipSuccess || d.n_long == 0) return e;
+  const int gl = std::max(1, std::min((d.n_long + BLOCK - 1) / BLOCK, NODE_GRID));
+  e = timed(c, KS_LONG, s, [&] {
+    if (c->prec == RLGL_FP64) k_complete_long<double><<<gl, blk, 0, c->stream>>>(d, s, force_all);
+    else k_complete_long<float><<<gl, blk, 0, c->stream>>>(d, s, force_all);
+  });
   return e;
 }
 
@@ -203,24 +213,26 @@ void fill_info(rlgl_ctx *c, rlgl_step_info *info, int status) {
   const long long t = c->t;
   const Rec &cur = c->host_rec[t % 3];
   const Rec &prv = c->host_rec[(t + 2) % 3];
+  const Tot ct = host_totals(cur), pt = host_totals(prv);
   info->t = t;
-  info->green = prv.green;
+  info->green = pt.green;
   info->green_total = cur.green_total;
   info->edges_pushed = cur.edges_total;
-  info->l1_cash = cur.l1;
+  info->l1_cash = ct.l1;
   info->h_sum = cur.hsum;
-  info->resid = cur.hsum != 0.0 ? cur.l1 / std::fabs(cur.hsum) : INFINITY;
+  info->resid = cur.hsum != 0.0 ? ct.l1 / std::fabs(cur.hsum) : INFINITY;
   info->theta = prv.theta;
-  info->cash_sum = cur.csum;
+  info->cash_sum = ct.csum;
   info->status = status;
   info->last_route = prv.mode;
 }
 
 rlgl_status reset_device(rlgl_ctx *c) {
   const Dev &d = c->d;
-  if (c->prec == RLGL_FP64) k_reset<double, 0><<<c->grid_misc, BLOCK, 0, c->stream>>>(d);
-  else if (c->hk) k_reset<float, 1><<<c->grid_misc, BLOCK, 0, c->stream>>>(d);
-  else k_reset<float, 0><<<c->grid_misc, BLOCK, 0, c->stream>>>(d);
+  const int gr = std::max(3, c->grid_misc);  // blocks 0..2 clear the three records
+  if (c->prec == RLGL_FP64) k_reset<double, 0><<<gr, BLOCK, 0, c->stream>>>(d);
+  else if (c->hk) k_reset<float, 1><<<gr, BLOCK, 0, c->stream>>>(d);
+  else k_reset<float, 0><<<gr, BLOCK, 0, c->stream>>>(d);
   HIP_TRY(hipGetLastError());
   HIP_TRY(enqueue_step(c, 0, -1.0, 1, 1));  // step 0: all green, M_0 = (1/N) 1
   return read_back(c);
@@ -237,6 +249,12 @@ rlgl_status do_refresh(rlgl_ctx *c) {
   if (c->prec == RLGL_FP64) k_refresh<double, 0><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, t, out);
   else if (c->hk) k_refresh<float, 1><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, t, out);
   else k_refresh<float, 0><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, t, out);
+  if (d.n_long > 0) {
+    const int gl = std::max(1, std::min((d.n_long + BLOCK - 1) / BLOCK, NODE_GRID));
+    if (c->prec == RLGL_FP64) k_refresh_long<double, 0><<<gl, BLOCK, 0, c->stream>>>(d, t, out);
+    else if (c->hk) k_refresh_long<float, 1><<<gl, BLOCK, 0, c->stream>>>(d, t, out);
+    else k_refresh_long<float, 0><<<gl, BLOCK, 0, c->stream>>>(d, t, out);
+  }
   k_refresh_done<<<1, 64, 0, c->stream>>>(d, t, out);
   HIP_TRY(hipGetLastError());
   ++c->refreshes;
@@ -260,50 +278,88 @@ rlgl_status build_plan(rlgl_ctx *c, const rlgl_graph *g, const Layout &L, char *
   HIP_TRY(hipStreamSynchronize(c->stream));
   if (cp[0] != 0 || (long long)cp[n] != g->nnz) return fail(RLGL_EINVAL, "csc_colptr[0] must be 0 and csc_colptr[n] = nnz");
   std::vector<int4> items;
-  std::vector<int> med, lng;
+  std::vector<int> lng;
   int run0 = -1, run_e = 0;
+  // RUN {k0, k1, p0, p1} with k0 >= 0; PIECE {-1 - slot, k, p0, p1}
   auto flush = [&](int end) {
-    if (run0 >= 0 && end > run0) items.push_back(make_int4(ITEM_SHORT, run0, end, 0));
+    if (run0 >= 0 && end > run0) items.push_back(make_int4(run0, end, cp[run0], cp[end]));
     run0 = -1;
     run_e = 0;
   };
   for (int k = 0; k < n; ++k) {
     const int dg = cp[k + 1] - cp[k];
     if (dg < 0) return fail(RLGL_EINVAL, "csc_colptr is not non-decreasing at %d", k);
-    if (dg > SHORT_MAX) {
+    if (dg > CH) {
+      // a long column: pieces of CH links, completed by the last workgroup
       flush(k);
-      if (dg >= LONG_COL_MIN) lng.push_back(k);
-      else med.push_back(k);
+      const int slot = (int)lng.size();
+      lng.push_back(k);
+      for (int p = cp[k]; p < cp[k + 1]; p += CH)
+        items.push_back(make_int4(-1 - slot, k, p, std::min(p + CH, cp[k + 1])));
       continue;
     }
-    if (run0 >= 0 && (run_e + dg > CH || k - run0 >= 1024)) flush(k);
+    if (run0 >= 0 && (run_e + dg > CH || k - run0 >= RUN_MAX_COLS)) flush(k);
     if (run0 < 0) run0 = k;
     run_e += dg;
   }
   flush(n);
-  for (size_t q = 0; q < med.size(); q += NWAVE)
-    items.push_back(make_int4(ITEM_MEDIUM, (int)q, (int)std::min<size_t>(NWAVE, med.size() - q), 0));
-  for (size_t q = 0; q < lng.size(); ++q) {
-    const int k = lng[q];
-    for (int p = cp[k]; p < cp[k + 1]; p += LONG_COL_MIN) items.push_back(make_int4(ITEM_LONG, (int)q, p, p + LONG_COL_MIN));
-  }
   // long pieces first: their partial sums are the longest dependency chain
-  std::stable_partition(items.begin(), items.end(), [](const int4 &a) { return a.x == ITEM_LONG; });
-  if (items.size() > L.max_items || med.size() > L.max_med || lng.size() > L.max_long)
+  std::stable_partition(items.begin(), items.end(), [](const int4 &a) { return a.x < 0; });
+  if (items.size() > L.max_items || lng.size() > L.max_long)
     return fail(RLGL_EINVAL, "pull plan exceeds its bound (internal)");
   if (!items.empty())
     HIP_TRY(hipMemcpyAsync(ws + L.items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, c->stream));
-  if (!med.empty())
-    HIP_TRY(hipMemcpyAsync(ws + L.med_cols, med.data(), sizeof(int) * med.size(), hipMemcpyHostToDevice, c->stream));
   if (!lng.empty())
     HIP_TRY(hipMemcpyAsync(ws + L.long_cols, lng.data(), sizeof(int) * lng.size(), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->d.items = (const int4 *)(ws + L.items);
   c->d.n_items = (int)items.size();
-  c->d.med_cols = (const int *)(ws + L.med_cols);
   c->d.long_cols = (const int *)(ws + L.long_cols);
   c->d.long_acc = (double *)(ws + L.long_acc);
   c->d.n_long = (int)lng.size();
+  return RLGL_OK;
+}
+
+// Setup of the push route: the HOT_MAX destinations with the largest
+// in-degrees (at least HOT_MIN_INDEG) get LDS accumulators, and a copy of
+// the CSR columns tags them as -1 - slot.  In-degrees come from the CSC
+// column pointers when given, else from a histogram of the CSR columns.
+rlgl_status build_hot(rlgl_ctx *c, const rlgl_graph *g, const Layout &L, char *ws) {
+  const int n = g->n;
+  Dev &d = c->d;
+  int *colt = (int *)(ws + L.colt);
+  int *tmp = d.fr_id;  // n ints, free until the first push step
+  std::vector<int> indeg((size_t)n);
+  if (g->csc_colptr) {
+    std::vector<int> cp((size_t)n + 1);
+    HIP_TRY(hipMemcpyAsync(cp.data(), g->csc_colptr, sizeof(int) * ((size_t)n + 1), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < n; ++k) indeg[k] = cp[k + 1] - cp[k];
+  } else {
+    k_fill_int<<<c->grid_misc, BLOCK, 0, c->stream>>>(tmp, n, 0);
+    if (g->nnz > 0) k_indegree<<<MAX_GRID, BLOCK, 0, c->stream>>>(d, tmp);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(indeg.data(), tmp, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  std::vector<int> hot;
+  for (int k = 0; k < n; ++k)
+    if (indeg[k] >= HOT_MIN_INDEG) hot.push_back(k);
+  std::sort(hot.begin(), hot.end(), [&](int a, int b) { return indeg[a] != indeg[b] ? indeg[a] > indeg[b] : a < b; });
+  if ((int)hot.size() > HOT_MAX) hot.resize(HOT_MAX);
+  d.n_hot = (int)hot.size();
+  if (g->nnz > 0) {
+    k_fill_int<<<c->grid_misc, BLOCK, 0, c->stream>>>(tmp, n, -1);
+    if (!hot.empty()) {
+      HIP_TRY(hipMemcpyAsync((void *)d.hot_nodes, hot.data(), sizeof(int) * hot.size(), hipMemcpyHostToDevice,
+                             c->stream));
+      k_scatter_slots<<<1, BLOCK, 0, c->stream>>>(d.hot_nodes, d.n_hot, tmp);
+    }
+    k_tag_columns<<<MAX_GRID, BLOCK, 0, c->stream>>>(d, colt, tmp);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    d.colt = colt;
+  }
   return RLGL_OK;
 }
 
@@ -320,7 +376,7 @@ void rlgl_default_options(rlgl_options *o) {
   o->theta_period = 1;
   o->precision = RLGL_FP32C_FP64H;
   o->route = RLGL_ROUTE_AUTO;
-  o->pull_alpha = 0.5;
+  o->pull_alpha = 0.05;
   o->check_period = 0;
   o->record_green = 0;
   o->refresh = 1;
@@ -384,6 +440,10 @@ rlgl_status rlgl_create(const rlgl_graph *g, const rlgl_options *o, void *ws, si
   d.fr_scale = w + L.fr_scale;
   d.chunk_first = (int *)(w + L.chunk_first);
   d.green_mask = o->record_green ? (unsigned char *)(w + L.green_mask) : nullptr;
+  d.delta = (o->precision == RLGL_FP64) ? nullptr : (double *)(w + L.delta);
+  d.colt = nullptr;
+  d.hot_nodes = (const int *)(w + L.hot_nodes);
+  d.n_hot = 0;
   c->has_mask = o->record_green != 0;
   c->check_period = o->check_period;
   c->refresh = g->csc_colptr ? o->refresh : 0;
@@ -392,15 +452,14 @@ rlgl_status rlgl_create(const rlgl_graph *g, const rlgl_options *o, void *ws, si
   d.log = (StepLog *)(w + L.log);
   d.items = nullptr;
   d.n_items = 0;
-  d.med_cols = nullptr;
   d.long_cols = nullptr;
   d.long_acc = nullptr;
   d.n_long = 0;
 
   const int tiles = (g->n + TILE - 1) / TILE;
-  c->grid_sel = std::max(1, std::min(tiles, MAX_GRID));
-  c->grid_push = (int)std::max<long long>(1, std::min<long long>((g->nnz + CH - 1) / CH, MAX_GRID));
-  c->grid_misc = std::max(1, std::min((g->n + BLOCK - 1) / BLOCK, MAX_GRID));
+  c->grid_sel = std::max(1, std::min(tiles, NODE_GRID));
+  c->grid_push = (int)std::max<long long>(1, std::min<long long>((g->nnz + CH - 1) / CH, PUSH_GRID));
+  c->grid_misc = std::max(1, std::min((g->n + BLOCK - 1) / BLOCK, NODE_GRID));
 
   rlgl_status st = RLGL_OK;
   if (hipHostMalloc((void **)&c->host_glob, sizeof(Glob), hipHostMallocDefault) != hipSuccess ||
@@ -416,8 +475,9 @@ rlgl_status rlgl_create(const rlgl_graph *g, const rlgl_options *o, void *ws, si
       st = fail(RLGL_EINVAL, "csr_rowptr[n] = %d differs from nnz = %lld", last, (long long)g->nnz);
   }
   if (st == RLGL_OK && g->csc_colptr) st = build_plan(c, g, L, w);
+  if (st == RLGL_OK) st = build_hot(c, g, L, w);
   if (st == RLGL_OK) {
-    c->grid_cmp = std::max(1, std::min(std::max(tiles, d.n_items), MAX_GRID));
+    c->grid_cmp = std::max({1, std::min(tiles, NODE_GRID), std::min(d.n_items, MAX_GRID)});
     st = reset_device(c);
   }
   if (st != RLGL_OK) {
@@ -486,7 +546,7 @@ rlgl_status rlgl_solve(rlgl_ctx *c, double eps, int64_t max_steps, double *dev_p
       continue;
     }
     if (ds != 0) break;
-    const Rec &cur = c->host_rec[c->t % 3];
+    const Tot cur = host_totals(c->host_rec[c->t % 3]);
     const bool drift = std::fabs(cur.csum) > 0.5 * cur.l1;
     const bool periodic = c->refresh > 1 && c->t - last_refresh >= c->refresh;
     if (c->refresh > 0 && (drift || periodic) && refreshed_at != c->t) {
@@ -496,7 +556,7 @@ rlgl_status rlgl_solve(rlgl_ctx *c, double eps, int64_t max_steps, double *dev_p
     }
     // size the next batch from the contraction seen so far
     const Rec &now = c->host_rec[c->t % 3];
-    const double resid = now.hsum != 0.0 ? now.l1 / std::fabs(now.hsum) : INFINITY;
+    const double resid = now.hsum != 0.0 ? host_totals(now).l1 / std::fabs(now.hsum) : INFINITY;
     long long next = batch * 2;
     if (prev_resid > 0.0 && resid > 0.0 && resid < prev_resid && c->t > prev_t) {
       const double rate = std::pow(resid / prev_resid, 1.0 / (double)(c->t - prev_t));
@@ -545,7 +605,7 @@ rlgl_status rlgl_get_state(rlgl_ctx *c, double *dC, double *dH, rlgl_step_info *
 rlgl_status rlgl_set_state(rlgl_ctx *c, const double *dC, const double *dH, double h_sum, int64_t t) {
   if (!c || !dC || !dH || t < 1) return fail(RLGL_EINVAL, "bad argument");
   const int buf = 0;
-  k_prepare_import<<<1, 64, 0, c->stream>>>(c->d, t, buf);
+  k_prepare_import<<<3, 64, 0, c->stream>>>(c->d, t, buf);
   if (c->prec == RLGL_FP64) k_import<double, 0><<<c->grid_misc, BLOCK, 0, c->stream>>>(c->d, dC, dH, t, buf);
   else if (c->hk) k_import<float, 1><<<c->grid_misc, BLOCK, 0, c->stream>>>(c->d, dC, dH, t, buf);
   else k_import<float, 0><<<c->grid_misc, BLOCK, 0, c->stream>>>(c->d, dC, dH, t, buf);
@@ -593,6 +653,9 @@ int32_t rlgl_profile_read(rlgl_ctx *c, rlgl_kernel_stat *out, int32_t max_entrie
       b = (double)lg.gedges * (4.0 + vs + 2.0 * cs) + (double)lg.nfront * (8.0 + cs);
     } else if (L.kind == KS_COMPLETE) {
       b = push ? 2.0 * cs * n : (4.0 * n + nnz * (4.0 + vs + cs) + 2.0 * cs * n);
+    } else if (L.kind == KS_LONG) {
+      if (push) continue;
+      b = (double)c->d.n_long * (4.0 + 8.0 + 8.0 + 2.0 * cs);
     } else {
       b = 0.0;
     }

@@ -10,49 +10,67 @@ constexpr int NWAVE = BLOCK / 64;
 constexpr int VPT = 4;              // nodes per thread in node-parallel passes
 constexpr int TILE = BLOCK * VPT;   // nodes per tile
 constexpr int CH = 2048;            // links per push/pull chunk
-constexpr int SHORT_MAX = 64;       // pull: in-degree handled by the thread-per-column path
-constexpr int LONG_COL_MIN = 4096;      // pull: in-degree split across several workgroups
+constexpr int RUN_MAX_COLS = 1024; // pull: columns per run item (4 per thread)
 constexpr int LOG_STEPS = 4096;     // ring of per-step records kept for profiling
-constexpr int MAX_GRID = 2048;
+constexpr int MAX_GRID = 2048;      // edge-parallel launches
+constexpr int NODE_GRID = 512;      // node-parallel launches (2 workgroups per CU)
+constexpr int HOT_MAX = 2048;       // push: destinations privatised in LDS (FP64) per workgroup
+constexpr int HOT_MIN_INDEG = 256;  // push: in-degree from which a destination is privatised
+constexpr int PUSH_GRID = 512;      // push launches (hot partials flushed once per workgroup)
+// Same-address atomics serialise (~13 ns each on MI355X), so every block
+// folds its partial sums into one of NSTRIPE cache-line-sized stripes
+// (block b -> stripe b mod NSTRIPE); readers add the stripes up.
+constexpr int NSTRIPE = 32;
 
 enum { SCHED_ALL = 0, SCHED_THRESHOLD = 1, SCHED_TOPK = 2, SCHED_MAXC = 3 };
 enum { ROUTE_PUSH = 0, ROUTE_PULL = 1, ROUTE_AUTO = 2 };
 enum { ST_RUNNING = 0, ST_CONVERGED = 1, ST_LIMIT = 2, ST_ZERO_HISTORY = -4, ST_NONFINITE = -6 };
-enum { ITEM_SHORT = 0, ITEM_MEDIUM = 1, ITEM_LONG = 2 };
 
-// Scalars of step t (record t mod 3).  The statistics describe C_t and are
-// folded in by step t-1; the accumulators are folded in by step t itself.
+// One stripe of the FP64 accumulators of a record.
+struct alignas(128) Acc {
+  // statistics of C_t (folded in by the step that produced C_t)
+  double l1;                        // ||C_t||_1
+  double csum;                      // C_t 1
+  double sumr;                      // sum |C_t|^r (r != 1)
+  unsigned long long maxabs_bits;   // max |C_t| as the bits of a non-negative double
+  // accumulators of step t (folded in by select of step t)
+  double T;                         // restart pool: sum_G M_i (1 - c [outdeg_i > 0])
+  double msum;                      // sum_G M_i
+  double dhnorm;                    // change of ||H||_1
+  long long green;                  // |G_t|
+  long long gedges;                 // links of green nodes with non-zero cash
+  // sums of an imported state
+  double hsum_import;
+  double hnorm_import;
+};
+
+// Totals of the stripes.
+struct Tot {
+  double l1, csum, sumr, maxabs, T, msum, dhnorm, hsum_import, hnorm_import;
+  long long green, gedges;
+};
+
+// Scalars of step t (record t mod 3).
 struct alignas(256) Rec {
-  // statistics of C_t and H_t
-  double l1;                 // ||C_t||_1
-  double csum;               // C_t 1
-  double sumr;               // sum |C_t|^r (r != 1)
-  unsigned long long maxabs_bits;  // max |C_t| as double bits
-  double hsum;               // H_t 1
-  double hsum_import;        // sum of an imported H
-  double hnorm;              // ||H_t||_1
-  long long edges_total;     // edge-pushes of steps 0..t-1
-  long long green_total;     // |G| summed over steps 1..t-1
-  int buf;                   // cash buffer that holds C_t
-  int mode;                  // 0 push, 1 pull (set by select of step t)
-  double theta;              // threshold used by step t
-  double topk_tau;           // top-k: k-th largest |C_t|
-  int topk_tie_id;           // top-k: largest id taken among ties at tau
-  unsigned int ticket;       // last-block detection in k_complete
-  // accumulators of step t
-  double T;                  // restart pool: sum_G M_i (1 - c [outdeg_i > 0])
-  double msum;               // sum_G M_i
-  double dhnorm;             // change of ||H||_1
-  unsigned long long fr_pack;  // frontier rows << 32 | frontier links
-  long long green;           // |G_t|
-  long long gedges;          // links of green nodes with non-zero cash
+  double hsum;                // H_t 1
+  double hnorm;               // ||H_t||_1
+  long long edges_total;      // edge-pushes of steps 0..t-1
+  long long green_total;      // |G| summed over steps 1..t-1
+  int buf;                    // cash buffer that holds C_t
+  int mode;                   // 0 push, 1 pull (set by select of step t)
+  double theta;               // threshold used by step t
+  double topk_tau;            // top-k: k-th largest |C_t|
+  int topk_tie_id;            // top-k: largest id taken among ties at tau
+  unsigned int ticket;        // last-block detection in k_complete
+  unsigned long long fr_pack; // frontier rows << 32 | frontier links (one reservation per tile)
+  Acc acc[NSTRIPE];
 };
 
 struct Glob {
   int status;
-  unsigned int ticket;       // last-block detection in k_refresh
-  long long t;               // index of the current state
-  double rpool;              // refresh: sum_j H_j (1 - c [outdeg_j > 0])
+  unsigned int ticket;        // last-block detection in k_refresh
+  long long t;                // index of the current state
+  double rpool;               // refresh: sum_j H_j (1 - c [outdeg_j > 0])
 };
 
 struct StepLog {
@@ -88,16 +106,41 @@ struct Dev {
   void *fr_scale;
   int *chunk_first;
   unsigned char *green_mask;
+  double *delta;         // push with FP32 cash: FP64 sums of the routed cash, folded into C by complete
+  const int *colt;       // push: CSR columns with hot destinations tagged as -1 - slot
+  const int *hot_nodes;  // push: node of each hot slot
+  int n_hot;
   Rec *rec;
   Glob *glob;
   StepLog *log;
   // static pull plan
   const int4 *items;
   int n_items;
-  const int *med_cols;
   const int *long_cols;
   double *long_acc;
   int n_long;
 };
+
+// Host-side sum of the stripes (same order as the device).
+inline Tot host_totals(const Rec &r) {
+  Tot t{};
+  for (int q = 0; q < NSTRIPE; ++q) {
+    const Acc &a = r.acc[q];
+    t.l1 += a.l1;
+    t.csum += a.csum;
+    t.sumr += a.sumr;
+    double m;
+    __builtin_memcpy(&m, &a.maxabs_bits, sizeof m);
+    t.maxabs = m > t.maxabs ? m : t.maxabs;
+    t.T += a.T;
+    t.msum += a.msum;
+    t.dhnorm += a.dhnorm;
+    t.hsum_import += a.hsum_import;
+    t.hnorm_import += a.hnorm_import;
+    t.green += a.green;
+    t.gedges += a.gedges;
+  }
+  return t;
+}
 
 }  // namespace rlgl

@@ -13,13 +13,16 @@
 //                each link found by a search in LDS).  Pull steps skip it.
 //   k_complete - push: adds the uniform restart share T/N to every node;
 //                pull: gathers sum_j M_j c P_jk along the CSC columns into
-//                the other cash buffer.  Both fold ||C_{t+1}||_1, sum C,
-//                sum |C|^r and max |C| into the record of step t+1.
+//                the other cash buffer, M_j recomputed from the snapshot.
+//                Both fold ||C_{t+1}||_1, sum C, sum |C|^r and max |C| into
+//                the record of step t+1.
 //
 // All reductions are FP64.  Per-step scalars live in a ring of three device
-// records indexed by t mod 3, so the host never has to touch them between
-// steps: the kernels of step t read record t, accumulate into record t (select)
-// or t+1 (complete), and select clears record t+1 before anyone uses it.
+// records indexed by t mod 3, so the host never touches them between steps:
+// the kernels of step t read record t, accumulate into record t (select) or
+// t+1 (complete), and select clears record t+1 before anyone uses it.  Block
+// partial sums go to one of NSTRIPE stripes of a record (same-address atomics
+// serialise), and readers add the stripes up with one wave.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -46,7 +49,8 @@ __device__ __forceinline__ long long wave_sum_ll(long long x) {
 struct Red4 {
   double a, b, c, d;
 };
-__device__ __forceinline__ Red4 block_sum4(Red4 v, double *sh /* 4*NWAVE */) {
+template <int NW = NWAVE>
+__device__ __forceinline__ Red4 block_sum4(Red4 v, double *sh /* 4*NW */) {
   v.a = wave_sum(v.a);
   v.b = wave_sum(v.b);
   v.c = wave_sum(v.c);
@@ -54,22 +58,23 @@ __device__ __forceinline__ Red4 block_sum4(Red4 v, double *sh /* 4*NWAVE */) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   if (l == 0) {
     sh[w] = v.a;
-    sh[NWAVE + w] = v.b;
-    sh[2 * NWAVE + w] = v.c;
-    sh[3 * NWAVE + w] = v.d;
+    sh[NW + w] = v.b;
+    sh[2 * NW + w] = v.c;
+    sh[3 * NW + w] = v.d;
   }
   __syncthreads();
   Red4 r{0, 0, 0, 0};
 #pragma unroll
-  for (int i = 0; i < NWAVE; ++i) {
+  for (int i = 0; i < NW; ++i) {
     r.a += sh[i];
-    r.b += sh[NWAVE + i];
-    r.c += sh[2 * NWAVE + i];
-    r.d += sh[3 * NWAVE + i];
+    r.b += sh[NW + i];
+    r.c += sh[2 * NW + i];
+    r.d += sh[3 * NW + i];
   }
   __syncthreads();
   return r;
 }
+template <int NW = NWAVE>
 __device__ __forceinline__ double block_max(double v, double *sh) {
   v = wave_max(v);
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -77,7 +82,7 @@ __device__ __forceinline__ double block_max(double v, double *sh) {
   __syncthreads();
   double r = sh[0];
 #pragma unroll
-  for (int i = 1; i < NWAVE; ++i) r = fmax(r, sh[i]);
+  for (int i = 1; i < NW; ++i) r = fmax(r, sh[i]);
   __syncthreads();
   return r;
 }
@@ -125,38 +130,129 @@ __device__ __forceinline__ double load_agent(const double *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Green test of node i with cash v on the snapshot of step t.
+__device__ __forceinline__ Acc *my_stripe(Rec *r) { return &r->acc[blockIdx.x % NSTRIPE]; }
+
+// Totals of a record's stripes, computed by the first wave and broadcast.
+__device__ Tot read_totals(const Rec *r, Tot *sh) {
+  if (threadIdx.x < 64) {
+    const int q = threadIdx.x;
+    double l1 = 0, cs = 0, sr = 0, mx = 0, T = 0, ms = 0, dh = 0, hi = 0, hn = 0;
+    long long gr = 0, ge = 0;
+    if (q < NSTRIPE) {
+      const Acc &a = r->acc[q];
+      l1 = a.l1;
+      cs = a.csum;
+      sr = a.sumr;
+      mx = __longlong_as_double((long long)a.maxabs_bits);
+      T = a.T;
+      ms = a.msum;
+      dh = a.dhnorm;
+      hi = a.hsum_import;
+      hn = a.hnorm_import;
+      gr = a.green;
+      ge = a.gedges;
+    }
+    l1 = wave_sum(l1);
+    cs = wave_sum(cs);
+    sr = wave_sum(sr);
+    mx = wave_max(mx);
+    T = wave_sum(T);
+    ms = wave_sum(ms);
+    dh = wave_sum(dh);
+    hi = wave_sum(hi);
+    hn = wave_sum(hn);
+    gr = wave_sum_ll(gr);
+    ge = wave_sum_ll(ge);
+    if (q == 0) *sh = Tot{l1, cs, sr, mx, T, ms, dh, hi, hn, gr, ge};
+  }
+  __syncthreads();
+  const Tot t = *sh;
+  __syncthreads();
+  return t;
+}
+
+// Clears every stripe of a record (threads 0..NSTRIPE-1 of one block).
+__device__ __forceinline__ void clear_stripes(Rec *r) {
+  if (threadIdx.x < NSTRIPE) {
+    Acc &a = r->acc[threadIdx.x];
+    a.l1 = 0.0;
+    a.csum = 0.0;
+    a.sumr = 0.0;
+    a.maxabs_bits = 0ull;
+    a.T = 0.0;
+    a.msum = 0.0;
+    a.dhnorm = 0.0;
+    a.green = 0;
+    a.gedges = 0;
+    a.hsum_import = 0.0;
+    a.hnorm_import = 0.0;
+  }
+}
+
+// Adds a block's statistics of a cash vector to its stripe of record r.
+template <int NW = NWAVE>
+__device__ __forceinline__ void fold_block_stats(Rec *r, double l1, double cs, double sr, double mx, double *sh) {
+  const Red4 t4 = block_sum4<NW>(Red4{l1, cs, sr, 0.0}, sh);
+  const double bm = block_max<NW>(mx, sh);
+  if (threadIdx.x == 0) {
+    Acc *a = my_stripe(r);
+    if (t4.a != 0.0) atomic_add_f64(&a->l1, t4.a);
+    if (t4.b != 0.0) atomic_add_f64(&a->csum, t4.b);
+    if (t4.c != 0.0) atomic_add_f64(&a->sumr, t4.c);
+    if (bm > 0.0) atomic_max_nonneg(&a->maxabs_bits, bm);
+  }
+}
+
+__device__ __forceinline__ void fold_stats(double x, double r, double &l1, double &cs, double &sr, double &mx) {
+  const double a = fabs(x);
+  l1 += a;
+  cs += x;
+  if (r != 1.0) sr += pow(a, r);
+  mx = fmax(mx, a);
+}
+
+// Green test of a node with cash v on the snapshot of step t.
 template <class T>
-__device__ __forceinline__ bool is_green(T v, int sched, double theta, double maxabs) {
+__device__ __forceinline__ bool is_green(T v, int id, int sched, double theta, double maxabs, double tau, int tie_id) {
   const double a = fabs((double)v);
   if (sched == SCHED_ALL) return true;
   if (sched == SCHED_THRESHOLD) return a >= theta;
   if (sched == SCHED_MAXC) return a == maxabs;
-  return a > theta;  // top-k: resolved into a strict bound plus explicit ties by the caller
+  return a > tau || (a == tau && id <= tie_id);  // top-k: k-th largest |C| and the id bound among its ties
 }
 
-// Top-k keys: |C| as the bits of a non-negative double, ties by smaller id.
-template <class T>
-__device__ __forceinline__ bool topk_green(T v, int i, double tau, int tie_limit_id) {
-  const double a = fabs((double)v);
-  return a > tau || (a == tau && i <= tie_limit_id);
+__device__ __forceinline__ double inv_outdeg(const Dev &d, int j) {
+  if ((unsigned)j >= (unsigned)d.n) return 0.0;
+  const int dg = d.rowptr[j + 1] - d.rowptr[j];
+  return dg > 0 ? 1.0 / (double)dg : 0.0;
 }
 
-__device__ __forceinline__ double pow_r(double a, double r) { return r == 1.0 ? a : pow(a, r); }
+template <int HK>
+__device__ __forceinline__ double hist_at(const Dev &d, int j) {
+  if (HK == 0) return ((const double *)d.hist)[j];
+  return (double)((const float *)d.hist)[j] + (double)d.hist_lo[j];
+}
 
 // ------------------------------------------------------------------ select
 
 template <class T, int HK>
-__global__ __launch_bounds__(BLOCK) void k_select(Dev d, long long s, double eps, long long s_limit, int force_all) {
+__global__ __launch_bounds__(BLOCK) void k_select(Dev d, long long s, double eps, long long s_limit, int init) {
   Glob *g = d.glob;
   if (g->status != 0) return;
   Rec *cur = &d.rec[s % 3];
   Rec *prv = &d.rec[(s + 2) % 3];
   Rec *nxt = &d.rec[(s + 1) % 3];
 
-  const double l1 = cur->l1, hsum = cur->hsum, hnorm = cur->hnorm;
+  __shared__ Tot sh_tot;
+  __shared__ unsigned long long sh_scan[NWAVE];
+  __shared__ double sh_red[4 * NWAVE];
+  __shared__ long long sh_ll[NWAVE];
+  __shared__ unsigned long long sh_base;
+
+  const Tot tot = read_totals(cur, &sh_tot);
+  const double l1 = tot.l1, hsum = cur->hsum, hnorm = cur->hnorm;
   int st = 0;
-  if (s >= 1) {
+  if (!init) {
     if (!isfinite(l1) || !isfinite(hsum)) st = ST_NONFINITE;
     else if (fabs(hsum) <= 1e-300 || fabs(hsum) <= 1e-12 * hnorm) st = ST_ZERO_HISTORY;
     else if (s >= 2 && l1 / fabs(hsum) < eps) st = ST_CONVERGED;
@@ -170,52 +266,39 @@ __global__ __launch_bounds__(BLOCK) void k_select(Dev d, long long s, double eps
     return;
   }
 
-  const int sched = force_all ? SCHED_ALL : d.sched;
+  const int sched = init ? SCHED_ALL : d.sched;
   double theta = 0.0;
   if (sched == SCHED_THRESHOLD) {
     if ((s - 1) % d.theta_period == 0)
-      theta = (d.r == 1.0) ? l1 / (double)d.n : pow(cur->sumr / (double)d.n, 1.0 / d.r);
+      theta = (d.r == 1.0) ? l1 / (double)d.n : pow(tot.sumr / (double)d.n, 1.0 / d.r);
     else
       theta = prv->theta;
   }
-  const double maxabs = __longlong_as_double((long long)cur->maxabs_bits);
-  double tau = 0.0;
-  int tie_id = -1;
-  if (sched == SCHED_TOPK) {
-    tau = cur->topk_tau;
-    tie_id = cur->topk_tie_id;
-  }
+  const double maxabs = tot.maxabs;
+  const double tau = cur->topk_tau;
+  const int tie_id = cur->topk_tie_id;
+  // route: AUTO pulls when the previous step moved cash along at least
+  // pull_alpha * nnz links (the log entry of step s-1)
   int mode;
   if (d.route == ROUTE_PUSH || d.colptr == nullptr) mode = 0;
   else if (d.route == ROUTE_PULL) mode = 1;
   else if (sched == SCHED_ALL) mode = 1;
-  else mode = ((double)prv->gedges >= d.pull_alpha * (double)d.nnz) ? 1 : 0;
+  else mode = ((double)d.log[(s + LOG_STEPS - 1) % LOG_STEPS].gedges >= d.pull_alpha * (double)d.nnz) ? 1 : 0;
 
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    cur->theta = theta;
-    cur->mode = mode;
-    nxt->l1 = 0.0;
-    nxt->csum = 0.0;
-    nxt->sumr = 0.0;
-    nxt->maxabs_bits = 0ull;
-    nxt->T = 0.0;
-    nxt->msum = 0.0;
-    nxt->dhnorm = 0.0;
-    nxt->fr_pack = 0ull;
-    nxt->green = 0;
-    nxt->gedges = 0;
-    nxt->ticket = 0u;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) {
+      cur->theta = theta;
+      cur->mode = mode;
+      nxt->fr_pack = 0ull;
+      nxt->ticket = 0u;
+    }
+    clear_stripes(nxt);
   }
 
   T *C = (T *)d.cash[cur->buf];
   const int n = d.n;
   const double c = d.c;
   const int ntiles = (n + TILE - 1) / TILE;
-
-  __shared__ unsigned long long sh_scan[NWAVE];
-  __shared__ double sh_red[4 * NWAVE];
-  __shared__ long long sh_ll[NWAVE];
-  __shared__ unsigned long long sh_base;
 
   double accT = 0.0, accM = 0.0, accDH = 0.0;
   long long accG = 0, accE = 0;
@@ -233,9 +316,9 @@ __global__ __launch_bounds__(BLOCK) void k_select(Dev d, long long s, double eps
       deg[q] = 0;
       rs[q] = 0;
       v[q] = T(0);
+      const T x = (i < n) ? C[i] : T(0);
+      const bool gr = (i < n) && is_green(x, i, sched, theta, maxabs, tau, tie_id);
       if (i < n) {
-        const T x = C[i];
-        const bool gr = (sched == SCHED_TOPK) ? topk_green(x, i, tau, tie_id) : is_green(x, sched, theta, maxabs);
         if (d.green_mask) d.green_mask[i] = gr ? 1 : 0;
         if (gr) {
           ++accG;
@@ -266,7 +349,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(Dev d, long long s, double eps
             if (mode == 0) {
               // C_t - M_t; the routed part arrives in k_push.  Step 0 starts
               // from C_0 = 0 while moving M_0 (held in C by k_reset): C_0 - M_0 = -M_0.
-              C[i] = force_all ? -x : T(0);
+              C[i] = init ? -x : T(0);
               if (dg > 0) {
                 fr[q] = true;
                 v[q] = x;
@@ -283,10 +366,10 @@ __global__ __launch_bounds__(BLOCK) void k_select(Dev d, long long s, double eps
     if (mode == 0) {
       // frontier compaction: one 64-bit atomic per tile reserves both the
       // slots and the link range, so slot order and link order agree.
-      unsigned long long tot;
+      unsigned long long tot2;
       const unsigned long long mine = ((unsigned long long)cnt << 32) | edges;
-      const unsigned long long ex = block_excl_scan(mine, sh_scan, &tot);
-      if (threadIdx.x == 0) sh_base = tot ? atomicAdd(&cur->fr_pack, tot) : 0ull;
+      const unsigned long long ex = block_excl_scan(mine, sh_scan, &tot2);
+      if (threadIdx.x == 0) sh_base = tot2 ? atomicAdd(&cur->fr_pack, tot2) : 0ull;
       __syncthreads();
       const unsigned long long b = sh_base + ex;
       unsigned int slot = (unsigned int)(b >> 32);
@@ -317,16 +400,22 @@ __global__ __launch_bounds__(BLOCK) void k_select(Dev d, long long s, double eps
   const long long gsum = block_sum_ll(accG, sh_ll);
   const long long esum = block_sum_ll(accE, sh_ll);
   if (threadIdx.x == 0) {
-    if (r.a != 0.0) atomic_add_f64(&cur->T, r.a);
-    if (r.b != 0.0) atomic_add_f64(&cur->msum, r.b);
-    if (r.c != 0.0) atomic_add_f64(&cur->dhnorm, r.c);
-    if (gsum) atomicAdd((unsigned long long *)&cur->green, (unsigned long long)gsum);
-    if (esum) atomicAdd((unsigned long long *)&cur->gedges, (unsigned long long)esum);
+    Acc *a = my_stripe(cur);
+    if (r.a != 0.0) atomic_add_f64(&a->T, r.a);
+    if (r.b != 0.0) atomic_add_f64(&a->msum, r.b);
+    if (r.c != 0.0) atomic_add_f64(&a->dhnorm, r.c);
+    if (gsum) atomicAdd((unsigned long long *)&a->green, (unsigned long long)gsum);
+    if (esum) atomicAdd((unsigned long long *)&a->gedges, (unsigned long long)esum);
   }
 }
 
 // -------------------------------------------------------------------- push
 
+// The routed cash is summed in FP64: into C itself for FP64 cash, else into
+// the delta array that complete folds into C with one rounding (adding many
+// small amounts to a large FP32 value, as at an in-hub, loses them).  The
+// destinations with the largest in-degrees are accumulated per workgroup in
+// LDS and flushed once per workgroup: same-address global atomics serialise.
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_push(Dev d, long long s) {
   if (d.glob->status != 0) return;
@@ -336,14 +425,17 @@ __global__ __launch_bounds__(BLOCK) void k_push(Dev d, long long s) {
   const int nent = (int)(pk >> 32);
   const int tot = (int)(pk & 0xffffffffu);
   if (tot == 0) return;
-  T *C = (T *)d.cash[cur->buf];
-  const int *__restrict__ col = d.col;
+  double *__restrict__ D = d.delta ? d.delta : (double *)d.cash[cur->buf];
+  const int *__restrict__ col = d.colt ? d.colt : d.col;
   const T *__restrict__ val = (const T *)d.val;
   const int nchunks = (tot + CH - 1) / CH;
+  const int n_hot = d.n_hot;
 
   __shared__ int s_eoff[CH + 1];
   __shared__ int s_rs[CH + 1];
   __shared__ T s_sc[CH + 1];
+  __shared__ double s_hot[HOT_MAX];
+  for (int q = threadIdx.x; q < n_hot; q += BLOCK) s_hot[q] = 0.0;
 
   for (int b = blockIdx.x; b < nchunks; b += gridDim.x) {
     const int e0 = b * CH;
@@ -370,183 +462,304 @@ __global__ __launch_bounds__(BLOCK) void k_push(Dev d, long long s) {
       const int idx = s_rs[lo] + (e - s_eoff[lo]);
       if ((unsigned long long)idx >= (unsigned long long)d.nnz) continue;
       const int dst = col[idx];
-      if ((unsigned)dst >= (unsigned)d.n) continue;  // links outside [0, N) are ignored
-      const T amt = val ? s_sc[lo] * val[idx] : s_sc[lo];
-      atomic_add_cash(&C[dst], amt);
+      const double amt = val ? (double)s_sc[lo] * (double)val[idx] : (double)s_sc[lo];
+      if (dst >= 0) {
+        if (dst < d.n) atomic_add_f64(&D[dst], amt);  // links outside [0, N) are ignored
+      } else if (-1 - dst < n_hot) {
+        atomicAdd(&s_hot[-1 - dst], amt);
+      }
     }
   }
+  __syncthreads();
+  for (int q = threadIdx.x; q < n_hot; q += BLOCK)
+    if (s_hot[q] != 0.0) atomic_add_f64(&D[d.hot_nodes[q]], s_hot[q]);
+}
+
+// Setup: CSR columns with the hot destinations tagged (slot map in fr_id).
+__global__ void k_tag_columns(Dev d, int *colt, const int *slot_of) {
+  for (long long e = blockIdx.x * (long long)BLOCK + threadIdx.x; e < d.nnz; e += (long long)gridDim.x * BLOCK) {
+    const int j = d.col[e];
+    const int sl = ((unsigned)j < (unsigned)d.n) ? slot_of[j] : -1;
+    colt[e] = sl >= 0 ? -1 - sl : j;
+  }
+}
+__global__ void k_fill_int(int *p, int n, int v) {
+  for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) p[i] = v;
+}
+__global__ void k_scatter_slots(const int *hot, int n_hot, int *slot_of) {
+  for (int q = blockIdx.x * BLOCK + threadIdx.x; q < n_hot; q += gridDim.x * BLOCK) slot_of[hot[q]] = q;
+}
+__global__ void k_indegree(Dev d, int *indeg) {
+  for (long long e = blockIdx.x * (long long)BLOCK + threadIdx.x; e < d.nnz; e += (long long)gridDim.x * BLOCK) {
+    const int j = d.col[e];
+    if ((unsigned)j < (unsigned)d.n) atomicAdd(&indeg[j], 1);
+  }
+}
+
+// ------------------------------------------------------- column gather pass
+//
+// Evaluates x_k = kept(k) + c * sum_{j in in(k)} moved(j) * P'_jk + off for
+// every column k along the static plan and writes x_k to out, folding its
+// statistics into record r.  P'_jk is the stored link value (or 1/outdeg(j)).
+//
+// Plan items: a RUN is a range of consecutive columns whose in-links (at most
+// CH of them) are contiguous in the CSC arrays; one workgroup stages the CH
+// contributions in LDS (coalesced index/value loads, 8 independent gathers
+// per thread) and adds them up per column with a block-wide segmented scan,
+// so every workgroup moves the same number of links whatever the degrees.
+// A column with more than CH in-links is cut into PIECEs of CH links whose
+// sums meet in long_acc; k_long_finish completes those columns afterwards
+// (a last-workgroup ticket would cost every workgroup a device-scope fence).
+
+struct Seg {
+  double v;
+  int f;  // a column starts inside the span
+};
+__device__ __forceinline__ Seg seg_op(Seg a, Seg b) { return Seg{b.f ? b.v : a.v + b.v, a.f | b.f}; }
+
+template <class T, int NT, class Moved, class Kept>
+__device__ __forceinline__ void column_pass(const Dev &d, Moved moved, Kept kept, double off, T *__restrict__ out,
+                                            Rec *r) {
+  const double c = d.c;
+  const double rr = d.r;
+  const int *__restrict__ colptr = d.colptr;
+  const int *__restrict__ crow = d.crow;
+  const T *__restrict__ cval = (const T *)d.cval;
+  double l1 = 0.0, cs = 0.0, sr = 0.0, mx = 0.0;
+  constexpr int NW = NT / 64;
+  constexpr int U = CH / NT;                 // links per thread
+  constexpr int KC = RUN_MAX_COLS / NT;      // columns per thread
+  __shared__ double sh_red[4 * NW];
+  __shared__ double s_con[CH];               // contributions, then inclusive segmented sums
+  __shared__ unsigned char s_head[CH];
+  __shared__ int s_cp[RUN_MAX_COLS + 1];     // column pointers of the run, relative to p0
+  __shared__ Seg s_wave[NW];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+
+  const int nitems = d.n_items;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int4 item = d.items[it];
+    if (item.x >= 0) {
+      // RUN {k0, k1, p0, p1}: every load below depends on the item alone
+      const int k0 = item.x, k1 = item.y, p0 = item.z, p1 = item.w;
+      const int ne = p1 - p0, ncol = k1 - k0;
+      if (ne > CH || ne < 0 || ncol > RUN_MAX_COLS || ncol < 0) continue;  // the plan never builds such an item
+      __syncthreads();
+      int jj[U];
+      double ww[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = u * NT + tid;
+        jj[u] = (e < ne) ? crow[p0 + e] : -1;
+        ww[u] = (e < ne && cval) ? (double)cval[p0 + e] : 0.0;
+      }
+      double kv[KC];
+#pragma unroll
+      for (int m = 0; m < KC; ++m) {
+        const int q = m * NT + tid;
+        kv[m] = (q < ncol) ? kept(k0 + q) : 0.0;
+      }
+      for (int q = tid; q <= ncol; q += NT) s_cp[q] = colptr[k0 + q] - p0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = u * NT + tid;
+        if (e < ne) {
+          const double w = cval ? ww[u] : inv_outdeg(d, jj[u]);
+          s_con[e] = moved(jj[u]) * w;
+          s_head[e] = 0;
+        }
+      }
+      __syncthreads();
+      for (int q = tid; q < ncol; q += NT) {
+        const int a = s_cp[q];
+        if (a < s_cp[q + 1]) s_head[a] = 1;
+      }
+      __syncthreads();
+      // segmented inclusive scan: thread t owns elements [t*U, t*U+U)
+      double loc[U];
+      int first_head = U;
+      Seg run{0.0, 0};
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = tid * U + u;
+        const double x = (e < ne) ? s_con[e] : 0.0;
+        const int h = (e < ne) ? s_head[e] : 0;
+        if (h && first_head == U) first_head = u;
+        run = h ? Seg{x, 1} : Seg{run.v + x, run.f};
+        loc[u] = run.v;
+      }
+      Seg inc = run;
+      for (int o = 1; o < 64; o <<= 1) {
+        Seg y;
+        y.v = __shfl_up(inc.v, o, 64);
+        y.f = __shfl_up(inc.f, o, 64);
+        if (lane >= o) inc = seg_op(y, inc);
+      }
+      if (lane == 63) s_wave[wv] = inc;
+      Seg ex;
+      ex.v = __shfl_up(inc.v, 1, 64);
+      ex.f = __shfl_up(inc.f, 1, 64);
+      if (lane == 0) ex = Seg{0.0, 0};
+      __syncthreads();
+      Seg wbase{0.0, 0};
+      for (int q = 0; q < wv; ++q) wbase = seg_op(wbase, s_wave[q]);
+      const Seg carry = seg_op(wbase, ex);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = tid * U + u;
+        if (e < ne) s_con[e] = (u < first_head) ? carry.v + loc[u] : loc[u];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < KC; ++m) {
+        const int q = m * NT + tid;
+        if (q < ncol) {
+          const int a = s_cp[q], b = s_cp[q + 1];
+          const double acc = (b > a) ? s_con[b - 1] : 0.0;
+          const T x = (T)(kv[m] + c * acc + off);
+          out[k0 + q] = x;
+          fold_stats((double)x, rr, l1, cs, sr, mx);
+        }
+      }
+    } else {  // PIECE {-1-slot, k, p0, p1}: partial sum of one long column
+      const int slot = -1 - item.x;
+      const int pb = item.z, pe = item.w;
+      double acc = 0.0;
+      int jj[U];
+      double ww[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int p = pb + u * NT + tid;
+        jj[u] = (p < pe) ? crow[p] : -1;
+        ww[u] = (p < pe) ? (cval ? (double)cval[p] : inv_outdeg(d, jj[u])) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (jj[u] >= 0) acc += moved(jj[u]) * ww[u];
+      const Red4 t4 = block_sum4<NW>(Red4{acc, 0, 0, 0}, sh_red);
+      if (tid == 0) atomic_add_f64(&d.long_acc[slot], t4.a);
+    }
+  }
+  fold_block_stats<NW>(r, l1, cs, sr, mx, sh_red);
 }
 
 // ----------------------------------------------------------------- complete
 
 template <class T>
-__device__ __forceinline__ void fold_stats(double x, double r, double &l1, double &cs, double &sr, double &mx) {
-  const double a = fabs(x);
-  l1 += a;
-  cs += x;
-  if (r != 1.0) sr += pow(a, r);
-  mx = fmax(mx, a);
-}
-
-template <class T>
-__device__ __forceinline__ double inv_outdeg(const Dev &d, int j) {
-  if ((unsigned)j >= (unsigned)d.n) return 0.0;
-  const int dg = d.rowptr[j + 1] - d.rowptr[j];
-  return dg > 0 ? 1.0 / (double)dg : 0.0;
-}
-
-template <class T>
-__global__ __launch_bounds__(BLOCK) void k_complete(Dev d, long long s, int force_all) {
+__global__ __launch_bounds__(BLOCK) void k_complete(Dev d, long long s, int init) {
   Glob *g = d.glob;
   if (g->status != 0) return;
   Rec *cur = &d.rec[s % 3];
   Rec *nxt = &d.rec[(s + 1) % 3];
+  __shared__ Tot sh_tot;
+  __shared__ double sh_red[4 * NWAVE];
+  const Tot tot = read_totals(cur, &sh_tot);
   const int n = d.n;
-  const double c = d.c;
-  const double off = cur->T / (double)n;  // uniform restart share of eq. (6)
+  const double off = tot.T / (double)n;  // uniform restart share of eq. (6)
   const int mode = cur->mode;
   const double r = d.r;
-  double l1 = 0.0, cs = 0.0, sr = 0.0, mx = 0.0;
-
-  __shared__ double sh_red[4 * NWAVE];
-  __shared__ double s_con[CH];
-  __shared__ int s_last;
 
   if (mode == 0) {
+    double l1 = 0.0, cs = 0.0, sr = 0.0, mx = 0.0;
     T *C = (T *)d.cash[cur->buf];
+    double *D = d.delta;
     const int ntiles = (n + TILE - 1) / TILE;
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
 #pragma unroll
       for (int q = 0; q < VPT; ++q) {
         const int i = tile * TILE + q * BLOCK + threadIdx.x;
         if (i < n) {
-          const T x = (T)((double)C[i] + off);
-          C[i] = x;
-          fold_stats<T>((double)x, r, l1, cs, sr, mx);
+          double x = (double)C[i] + off;
+          if (D) {
+            x += D[i];
+            D[i] = 0.0;
+          }
+          const T y = (T)x;
+          C[i] = y;
+          fold_stats((double)y, r, l1, cs, sr, mx);
         }
       }
     }
+    fold_block_stats(nxt, l1, cs, sr, mx, sh_red);
   } else {
-    const int sched = force_all ? SCHED_ALL : d.sched;
+    const int sched = init ? SCHED_ALL : d.sched;
     const double theta = cur->theta;
-    const double maxabs = __longlong_as_double((long long)cur->maxabs_bits);
+    const double maxabs = tot.maxabs;
     const double tau = cur->topk_tau;
     const int tie_id = cur->topk_tie_id;
     const T *__restrict__ Cc = (const T *)d.cash[cur->buf];
     T *__restrict__ Cn = (T *)d.cash[cur->buf ^ 1];
-    const int *__restrict__ colptr = d.colptr;
-    const int *__restrict__ crow = d.crow;
-    const T *__restrict__ cval = (const T *)d.cval;
     auto moved = [&](int j) -> double {
       if ((unsigned)j >= (unsigned)n) return 0.0;  // links outside [0, N) are ignored
       const T v = Cc[j];
-      const bool gr = (sched == SCHED_TOPK) ? topk_green(v, j, tau, tie_id) : is_green(v, sched, theta, maxabs);
-      return gr ? (double)v : 0.0;
+      return is_green(v, j, sched, theta, maxabs, tau, tie_id) ? (double)v : 0.0;
     };
     auto kept = [&](int k) -> double {
       const T v = Cc[k];
-      if (force_all) return -(double)v;  // step 0: C_0 - M_0 with C_0 = 0
-      const bool gr = (sched == SCHED_TOPK) ? topk_green(v, k, tau, tie_id) : is_green(v, sched, theta, maxabs);
-      return gr ? 0.0 : (double)v;
+      if (init) return -(double)v;  // step 0: C_0 - M_0 with C_0 = 0
+      return is_green(v, k, sched, theta, maxabs, tau, tie_id) ? 0.0 : (double)v;
     };
-    const int nitems = d.n_items;
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-      const int4 item = d.items[it];
-      if (item.x == ITEM_SHORT) {
-        const int k0 = item.y, k1 = item.z;
-        const int p0 = colptr[k0], p1 = colptr[k1];
-        if (p1 - p0 > CH || p1 < p0) continue;  // the plan never builds such an item
-        __syncthreads();
-        for (int p = p0 + threadIdx.x; p < p1; p += BLOCK) {
-          const int j = crow[p];
-          const double m = moved(j);
-          const double w = cval ? (double)cval[p] : inv_outdeg<T>(d, j);
-          s_con[p - p0] = m * w;
-        }
-        __syncthreads();
-        for (int k = k0 + threadIdx.x; k < k1; k += BLOCK) {
-          const int a = colptr[k] - p0, b = colptr[k + 1] - p0;
-          double acc = 0.0;
-          for (int q = a; q < b; ++q) acc += s_con[q];
-          const T x = (T)(kept(k) + c * acc + off);
-          Cn[k] = x;
-          fold_stats<T>((double)x, r, l1, cs, sr, mx);
-        }
-      } else if (item.x == ITEM_MEDIUM) {
-        const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-        if (w < item.z) {
-          const int k = d.med_cols[item.y + w];
-          const int p0 = colptr[k], p1 = colptr[k + 1];
-          double acc = 0.0;
-          for (int p = p0 + lane; p < p1; p += 64) {
-            const int j = crow[p];
-            const double wgt = cval ? (double)cval[p] : inv_outdeg<T>(d, j);
-            acc += moved(j) * wgt;
-          }
-          acc = wave_sum(acc);
-          if (lane == 0) {
-            const T x = (T)(kept(k) + c * acc + off);
-            Cn[k] = x;
-            fold_stats<T>((double)x, r, l1, cs, sr, mx);
-          }
-        }
-      } else {  // ITEM_LONG piece: partial sum of one long column
-        const int slot = item.y;
-        const int k = d.long_cols[slot];
-        const int p0 = item.z;
-        const int p1 = min(item.w, colptr[k + 1]);
-        double acc = 0.0;
-        for (int p = p0 + threadIdx.x; p < p1; p += BLOCK) {
-          const int j = crow[p];
-          const double wgt = cval ? (double)cval[p] : inv_outdeg<T>(d, j);
-          acc += moved(j) * wgt;
-        }
-        const Red4 t4 = block_sum4(Red4{acc, 0, 0, 0}, sh_red);
-        if (threadIdx.x == 0) atomic_add_f64(&d.long_acc[slot], t4.a);
-      }
-    }
-    // The last block to finish completes the long columns.
-    if (d.n_long > 0) {
-      __threadfence();
-      __syncthreads();
-      if (threadIdx.x == 0) s_last = (atomicAdd(&cur->ticket, 1u) == gridDim.x - 1);
-      __syncthreads();
-      if (s_last) {
-        __threadfence();
-        for (int q = threadIdx.x; q < d.n_long; q += BLOCK) {
-          const int k = d.long_cols[q];
-          const double acc = load_agent(&d.long_acc[q]);
-          d.long_acc[q] = 0.0;
-          const T x = (T)(kept(k) + c * acc + off);
-          Cn[k] = x;
-          fold_stats<T>((double)x, r, l1, cs, sr, mx);
-        }
-      }
-    }
+    column_pass<T, BLOCK>(d, moved, kept, off, Cn, nxt);
   }
 
-  const Red4 t4 = block_sum4(Red4{l1, cs, sr, 0.0}, sh_red);
-  const double bm = block_max(mx, sh_red);
-  if (threadIdx.x == 0) {
-    if (t4.a != 0.0) atomic_add_f64(&nxt->l1, t4.a);
-    if (t4.b != 0.0) atomic_add_f64(&nxt->csum, t4.b);
-    if (t4.c != 0.0) atomic_add_f64(&nxt->sumr, t4.c);
-    if (bm > 0.0) atomic_max_nonneg(&nxt->maxabs_bits, bm);
-    if (blockIdx.x == 0) {
-      nxt->hsum = cur->hsum + cur->msum;
-      nxt->hnorm = cur->hnorm + cur->dhnorm;
-      nxt->edges_total = cur->edges_total + cur->gedges;
-      nxt->green_total = cur->green_total + (s >= 1 ? cur->green : 0);
-      nxt->buf = (mode == 0) ? cur->buf : (cur->buf ^ 1);
-      g->t = s + 1;
-      StepLog *lg = &d.log[s % LOG_STEPS];
-      lg->s = s;
-      lg->mode = mode;
-      lg->green = cur->green;
-      lg->gedges = cur->gedges;
-      lg->nfront = (long long)(cur->fr_pack >> 32);
-    }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    nxt->hsum = cur->hsum + tot.msum;
+    nxt->hnorm = cur->hnorm + tot.dhnorm;
+    nxt->edges_total = cur->edges_total + tot.gedges;
+    nxt->green_total = cur->green_total + (init ? 0 : tot.green);
+    nxt->buf = (mode == 0) ? cur->buf : (cur->buf ^ 1);
+    g->t = s + 1;
+    StepLog *lg = &d.log[s % LOG_STEPS];
+    lg->s = s;
+    lg->mode = mode;
+    lg->green = tot.green;
+    lg->gedges = tot.gedges;
+    lg->nfront = (long long)(cur->fr_pack >> 32);
   }
+}
+
+// Completes the columns with more than CH in-links once all their pieces
+// have been added to long_acc: x_k = kept(k) + c * acc + off, then resets
+// long_acc for the next pass and folds the statistics of the x_k.
+template <class T, class Kept>
+__device__ __forceinline__ void long_finish(const Dev &d, Kept kept, double off, T *__restrict__ out, Rec *r) {
+  __shared__ double sh_red[4 * NWAVE];
+  double l1 = 0.0, cs = 0.0, sr = 0.0, mx = 0.0;
+  for (int q = blockIdx.x * BLOCK + threadIdx.x; q < d.n_long; q += gridDim.x * BLOCK) {
+    const int k = d.long_cols[q];
+    const double acc = d.long_acc[q];
+    d.long_acc[q] = 0.0;
+    const T x = (T)(kept(k) + d.c * acc + off);
+    out[k] = x;
+    fold_stats((double)x, d.r, l1, cs, sr, mx);
+  }
+  fold_block_stats(r, l1, cs, sr, mx, sh_red);
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_complete_long(Dev d, long long s, int init) {
+  if (d.glob->status != 0) return;
+  Rec *cur = &d.rec[s % 3];
+  if (cur->mode != 1) return;
+  Rec *nxt = &d.rec[(s + 1) % 3];
+  __shared__ Tot sh_tot;
+  const Tot tot = read_totals(cur, &sh_tot);
+  const int sched = init ? SCHED_ALL : d.sched;
+  const double theta = cur->theta, tau = cur->topk_tau, maxabs = tot.maxabs;
+  const int tie_id = cur->topk_tie_id;
+  const T *__restrict__ Cc = (const T *)d.cash[cur->buf];
+  auto kept = [&](int k) -> double {
+    const T v = Cc[k];
+    if (init) return -(double)v;
+    return is_green(v, k, sched, theta, maxabs, tau, tie_id) ? 0.0 : (double)v;
+  };
+  long_finish<T>(d, kept, tot.T / (double)d.n, (T *)d.cash[cur->buf ^ 1], nxt);
+}
+
+template <class T, int HK>
+__global__ __launch_bounds__(BLOCK) void k_refresh_long(Dev d, long long t, int out_buf) {
+  auto kept = [&](int k) -> double { return -hist_at<HK>(d, k); };
+  long_finish<T>(d, kept, d.glob->rpool / (double)d.n, (T *)d.cash[out_buf], &d.rec[t % 3]);
 }
 
 // -------------------------------------------------- top-k threshold search
@@ -592,15 +805,12 @@ __global__ __launch_bounds__(1024) void k_topk(Dev d, long long s) {
   const unsigned long long above = block_count([&](int i) { return keyof(i) > tau_bits; });
   const long long need = k - (long long)above;  // >= 1 ties to take
   // smallest id bound I such that #(key == tau, id <= I) >= need
-  if (threadIdx.x == 0) sh_prefix = 0ull;
-  __syncthreads();
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = lo + (hi - lo) / 2;
     const unsigned long long c = block_count([&](int i) { return i <= mid && keyof(i) == tau_bits; });
     if (c >= (unsigned long long)need) hi = mid;
     else lo = mid + 1;
-    __syncthreads();
   }
   if (threadIdx.x == 0) {
     cur->topk_tau = __longlong_as_double((long long)tau_bits);
@@ -617,20 +827,19 @@ __global__ __launch_bounds__(1024) void k_topk(Dev d, long long s) {
 // in C (whose exact sum is zero) without changing the method's trajectory.
 
 __global__ void k_refresh_prep(Dev d, long long t) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (blockIdx.x != 0) return;
   Rec *cur = &d.rec[t % 3];
-  cur->l1 = 0.0;
-  cur->csum = 0.0;
-  cur->sumr = 0.0;
-  cur->maxabs_bits = 0ull;
-  d.glob->rpool = 0.0;
-  d.glob->ticket = 0u;
-}
-
-template <int HK>
-__device__ __forceinline__ double hist_at(const Dev &d, int j) {
-  if (HK == 0) return ((const double *)d.hist)[j];
-  return (double)((const float *)d.hist)[j] + (double)d.hist_lo[j];
+  if (threadIdx.x < NSTRIPE) {
+    Acc &a = cur->acc[threadIdx.x];
+    a.l1 = 0.0;
+    a.csum = 0.0;
+    a.sumr = 0.0;
+    a.maxabs_bits = 0ull;
+  }
+  if (threadIdx.x == 0) {
+    d.glob->rpool = 0.0;
+    d.glob->ticket = 0u;
+  }
 }
 
 template <int HK>
@@ -651,94 +860,10 @@ template <class T, int HK>
 __global__ __launch_bounds__(BLOCK) void k_refresh(Dev d, long long t, int out_buf) {
   Rec *cur = &d.rec[t % 3];
   const int n = d.n;
-  const double c = d.c;
   const double off = d.glob->rpool / (double)n;
-  const double r = d.r;
-  T *__restrict__ Cn = (T *)d.cash[out_buf];
-  const int *__restrict__ colptr = d.colptr;
-  const int *__restrict__ crow = d.crow;
-  const T *__restrict__ cval = (const T *)d.cval;
-  double l1 = 0.0, cs = 0.0, sr = 0.0, mx = 0.0;
-  __shared__ double sh_red[4 * NWAVE];
-  __shared__ double s_con[CH];
-  __shared__ int s_last;
-  auto hin = [&](int j) -> double { return ((unsigned)j < (unsigned)n) ? hist_at<HK>(d, j) : 0.0; };
-  const int nitems = d.n_items;
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const int4 item = d.items[it];
-    if (item.x == ITEM_SHORT) {
-      const int k0 = item.y, k1 = item.z;
-      const int p0 = colptr[k0], p1 = colptr[k1];
-      if (p1 - p0 > CH || p1 < p0) continue;
-      __syncthreads();
-      for (int p = p0 + threadIdx.x; p < p1; p += BLOCK) {
-        const int j = crow[p];
-        const double w = cval ? (double)cval[p] : inv_outdeg<T>(d, j);
-        s_con[p - p0] = hin(j) * w;
-      }
-      __syncthreads();
-      for (int k = k0 + threadIdx.x; k < k1; k += BLOCK) {
-        const int a = colptr[k] - p0, b = colptr[k + 1] - p0;
-        double acc = 0.0;
-        for (int q = a; q < b; ++q) acc += s_con[q];
-        const T x = (T)(c * acc + off - hin(k));
-        Cn[k] = x;
-        fold_stats<T>((double)x, r, l1, cs, sr, mx);
-      }
-    } else if (item.x == ITEM_MEDIUM) {
-      const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-      if (w < item.z) {
-        const int k = d.med_cols[item.y + w];
-        double acc = 0.0;
-        for (int p = colptr[k] + lane; p < colptr[k + 1]; p += 64) {
-          const int j = crow[p];
-          acc += hin(j) * (cval ? (double)cval[p] : inv_outdeg<T>(d, j));
-        }
-        acc = wave_sum(acc);
-        if (lane == 0) {
-          const T x = (T)(c * acc + off - hin(k));
-          Cn[k] = x;
-          fold_stats<T>((double)x, r, l1, cs, sr, mx);
-        }
-      }
-    } else {
-      const int slot = item.y;
-      const int k = d.long_cols[slot];
-      const int p1 = min(item.w, colptr[k + 1]);
-      double acc = 0.0;
-      for (int p = item.z + threadIdx.x; p < p1; p += BLOCK) {
-        const int j = crow[p];
-        acc += hin(j) * (cval ? (double)cval[p] : inv_outdeg<T>(d, j));
-      }
-      const Red4 t4 = block_sum4(Red4{acc, 0, 0, 0}, sh_red);
-      if (threadIdx.x == 0) atomic_add_f64(&d.long_acc[slot], t4.a);
-    }
-  }
-  if (d.n_long > 0) {
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) s_last = (atomicAdd(&d.glob->ticket, 1u) == gridDim.x - 1);
-    __syncthreads();
-    if (s_last) {
-      __threadfence();
-      for (int q = threadIdx.x; q < d.n_long; q += BLOCK) {
-        const int k = d.long_cols[q];
-        const double acc = load_agent(&d.long_acc[q]);
-        d.long_acc[q] = 0.0;
-        const T x = (T)(c * acc + off - hin(k));
-        Cn[k] = x;
-        fold_stats<T>((double)x, r, l1, cs, sr, mx);
-      }
-    }
-  }
-  const Red4 t4 = block_sum4(Red4{l1, cs, sr, 0.0}, sh_red);
-  const double bm = block_max(mx, sh_red);
-  if (threadIdx.x == 0) {
-    if (t4.a != 0.0) atomic_add_f64(&cur->l1, t4.a);
-    if (t4.b != 0.0) atomic_add_f64(&cur->csum, t4.b);
-    if (t4.c != 0.0) atomic_add_f64(&cur->sumr, t4.c);
-    if (bm > 0.0) atomic_max_nonneg(&cur->maxabs_bits, bm);
-  }
+  auto moved = [&](int j) -> double { return ((unsigned)j < (unsigned)n) ? hist_at<HK>(d, j) : 0.0; };
+  auto kept = [&](int k) -> double { return -hist_at<HK>(d, k); };
+  column_pass<T, BLOCK>(d, moved, kept, off, (T *)d.cash[out_buf], cur);
 }
 
 __global__ void k_refresh_done(Dev d, long long t, int out_buf) {
@@ -755,6 +880,7 @@ __global__ __launch_bounds__(BLOCK) void k_reset(Dev d) {
   const T m0 = (T)(1.0 / (double)n);
   T *C = (T *)d.cash[0];
   for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
+    if (d.delta) d.delta[i] = 0.0;
     C[i] = m0;  // holds M_0 = (1/N) 1 until step 0 moves it
     if (HK == 0) {
       ((double *)d.hist)[i] = 0.0;
@@ -763,28 +889,22 @@ __global__ __launch_bounds__(BLOCK) void k_reset(Dev d) {
       d.hist_lo[i] = 0.0f;
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x < 3) {
-    Rec *r = &d.rec[threadIdx.x];
-    r->l1 = threadIdx.x == 0 ? 1.0 : 0.0;
-    r->csum = 0.0;
-    r->sumr = 0.0;
-    r->maxabs_bits = 0ull;
-    r->hsum = 0.0;
-    r->hnorm = 0.0;
-    r->edges_total = 0;
-    r->green_total = 0;
-    r->buf = 0;
-    r->mode = 0;
-    r->theta = 0.0;
-    r->T = 0.0;
-    r->msum = 0.0;
-    r->dhnorm = 0.0;
-    r->fr_pack = 0ull;
-    r->green = 0;
-    r->gedges = 0;
-    r->ticket = 0u;
-    r->topk_tau = 0.0;
-    r->topk_tie_id = -1;
+  if (blockIdx.x < 3) {
+    Rec *r = &d.rec[blockIdx.x];
+    clear_stripes(r);
+    if (threadIdx.x == 0) {
+      r->hsum = 0.0;
+      r->hnorm = 0.0;
+      r->edges_total = 0;
+      r->green_total = 0;
+      r->buf = 0;
+      r->mode = 0;
+      r->theta = 0.0;
+      r->fr_pack = 0ull;
+      r->ticket = 0u;
+      r->topk_tau = 0.0;
+      r->topk_tie_id = -1;
+    }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     d.glob->status = 0;
@@ -793,7 +913,10 @@ __global__ __launch_bounds__(BLOCK) void k_reset(Dev d) {
     d.glob->rpool = 0.0;
   }
   for (int q = blockIdx.x * BLOCK + threadIdx.x; q < d.n_long; q += gridDim.x * BLOCK) d.long_acc[q] = 0.0;
-  for (int q = blockIdx.x * BLOCK + threadIdx.x; q < LOG_STEPS; q += gridDim.x * BLOCK) d.log[q].s = -1;
+  for (int q = blockIdx.x * BLOCK + threadIdx.x; q < LOG_STEPS; q += gridDim.x * BLOCK) {
+    d.log[q].s = -1;
+    d.log[q].gedges = 0;
+  }
 }
 
 __global__ void k_set_status(Glob *g, int st) {
@@ -806,10 +929,7 @@ __global__ __launch_bounds__(BLOCK) void k_normalize(Dev d, double *pi) {
   const double hs = d.rec[t % 3].hsum;
   const int n = d.n;
   for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
-    double h;
-    if (HK == 0) h = ((const double *)d.hist)[i];
-    else h = (double)((const float *)d.hist)[i] + (double)d.hist_lo[i];
-    pi[i] = h / hs;  // pi_hat_t = H_t / (H_t 1), eq. (2)
+    pi[i] = hist_at<HK>(d, i) / hs;  // pi_hat_t = H_t / (H_t 1), eq. (2)
   }
 }
 
@@ -820,10 +940,7 @@ __global__ __launch_bounds__(BLOCK) void k_export(Dev d, double *Cout, double *H
   const int n = d.n;
   for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
     if (Cout) Cout[i] = (double)C[i];
-    if (Hout) {
-      if (HK == 0) Hout[i] = ((const double *)d.hist)[i];
-      else Hout[i] = (double)((const float *)d.hist)[i] + (double)d.hist_lo[i];
-    }
+    if (Hout) Hout[i] = hist_at<HK>(d, i);
   }
 }
 
@@ -838,9 +955,10 @@ __global__ __launch_bounds__(BLOCK) void k_import(Dev d, const double *Cin, cons
   double l1 = 0, cs = 0, sr = 0, mx = 0, hs = 0, hn = 0;
   __shared__ double sh_red[4 * NWAVE];
   for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
+    if (d.delta) d.delta[i] = 0.0;
     const T x = (T)Cin[i];
     C[i] = x;
-    fold_stats<T>((double)x, r, l1, cs, sr, mx);
+    fold_stats((double)x, r, l1, cs, sr, mx);
     const double h = Hin[i];
     if (HK == 0) {
       ((double *)d.hist)[i] = h;
@@ -855,55 +973,47 @@ __global__ __launch_bounds__(BLOCK) void k_import(Dev d, const double *Cin, cons
       hn += fabs((double)hi + (double)lo);
     }
   }
-  const Red4 a = block_sum4(Red4{l1, cs, sr, hs}, sh_red);
-  const Red4 b = block_sum4(Red4{hn, 0, 0, 0}, sh_red);
-  const double bm = block_max(mx, sh_red);
+  const Red4 b = block_sum4(Red4{hs, hn, 0, 0}, sh_red);
   if (threadIdx.x == 0) {
-    atomic_add_f64(&cur->l1, a.a);
-    atomic_add_f64(&cur->csum, a.b);
-    atomic_add_f64(&cur->sumr, a.c);
-    atomic_add_f64(&cur->hsum_import, a.d);
-    atomic_add_f64(&cur->hnorm, b.a);
-    if (bm > 0.0) atomic_max_nonneg(&cur->maxabs_bits, bm);
+    Acc *a = my_stripe(cur);
+    atomic_add_f64(&a->hsum_import, b.a);
+    atomic_add_f64(&a->hnorm_import, b.b);
   }
+  fold_block_stats(cur, l1, cs, sr, mx, sh_red);
 }
 
 __global__ void k_prepare_import(Dev d, long long t, int buf) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  for (int q = 0; q < 3; ++q) {
-    Rec *r = &d.rec[q];
-    r->l1 = 0.0;
-    r->csum = 0.0;
-    r->sumr = 0.0;
-    r->maxabs_bits = 0ull;
+  if (blockIdx.x >= 3) return;
+  Rec *r = &d.rec[blockIdx.x];
+  clear_stripes(r);
+  if (threadIdx.x == 0) {
     r->hsum = 0.0;
-    r->hsum_import = 0.0;
     r->hnorm = 0.0;
-    r->T = 0.0;
-    r->msum = 0.0;
-    r->dhnorm = 0.0;
+    r->edges_total = 0;
+    r->green_total = 0;
     r->fr_pack = 0ull;
-    r->green = 0;
-    r->gedges = 0;
     r->ticket = 0u;
     r->mode = 0;
     r->theta = 0.0;
     r->topk_tau = 0.0;
     r->topk_tie_id = -1;
+    r->buf = buf;
   }
-  Rec *cur = &d.rec[t % 3];
-  cur->buf = buf;
-  cur->edges_total = 0;
-  cur->green_total = 0;
-  d.rec[(t + 2) % 3].gedges = d.nnz;  // the AUTO router sees a dense previous step
-  d.glob->status = 0;
-  d.glob->t = t;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    d.log[(t + LOG_STEPS - 1) % LOG_STEPS].gedges = d.nnz;  // the AUTO router sees a dense previous step
+    d.glob->status = 0;
+    d.glob->t = t;
+  }
 }
 
 __global__ void k_finish_import(Dev d, long long t, double h_sum) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  __shared__ Tot sh_tot;
   Rec *cur = &d.rec[t % 3];
-  cur->hsum = isnan(h_sum) ? cur->hsum_import : h_sum;
+  const Tot tot = read_totals(cur, &sh_tot);
+  if (threadIdx.x == 0) {
+    cur->hsum = isnan(h_sum) ? tot.hsum_import : h_sum;
+    cur->hnorm = tot.hnorm_import;
+  }
 }
 
 // ------------------------------------------------------- explicit instances
@@ -915,16 +1025,21 @@ template __global__ void k_push<float>(Dev, long long);
 template __global__ void k_push<double>(Dev, long long);
 template __global__ void k_complete<float>(Dev, long long, int);
 template __global__ void k_complete<double>(Dev, long long, int);
+template __global__ void k_complete_long<float>(Dev, long long, int);
+template __global__ void k_complete_long<double>(Dev, long long, int);
+template __global__ void k_refresh_long<float, 0>(Dev, long long, int);
+template __global__ void k_refresh_long<float, 1>(Dev, long long, int);
+template __global__ void k_refresh_long<double, 0>(Dev, long long, int);
 template __global__ void k_topk<float>(Dev, long long);
 template __global__ void k_topk<double>(Dev, long long);
-template __global__ void k_reset<float, 0>(Dev);
-template __global__ void k_reset<float, 1>(Dev);
-template __global__ void k_reset<double, 0>(Dev);
 template __global__ void k_refresh_pool<0>(Dev);
 template __global__ void k_refresh_pool<1>(Dev);
 template __global__ void k_refresh<float, 0>(Dev, long long, int);
 template __global__ void k_refresh<float, 1>(Dev, long long, int);
 template __global__ void k_refresh<double, 0>(Dev, long long, int);
+template __global__ void k_reset<float, 0>(Dev);
+template __global__ void k_reset<float, 1>(Dev);
+template __global__ void k_reset<double, 0>(Dev);
 template __global__ void k_normalize<0>(Dev, double *);
 template __global__ void k_normalize<1>(Dev, double *);
 template __global__ void k_export<float, 0>(Dev, double *, double *);
