@@ -30,8 +30,9 @@ METRIC = "edge-pushes/s (GTEPS) to L1≤1e-6 vs FP64; batched solves/s + p99 lat
 
 
 def source_hash():
+    """Hash of the device code (kernels and their shared definitions)."""
     h = hashlib.sha256()
-    for f in ("rlgl_kernels.hip", "rlgl_api.hip", "rlgl_device.h"):
+    for f in ("rlgl_kernels.hip", "rlgl_device.h"):
         with open(os.path.join(ROOT, "paper_2008_02710_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -84,7 +85,19 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-ref", action="store_true", help="skip the FP64 power-iteration reference")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
+
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4, "launches": 3}))
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

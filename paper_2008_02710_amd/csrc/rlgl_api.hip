@@ -539,10 +539,12 @@ rlgl_status rlgl_solve(rlgl_ctx *c, double eps, int64_t max_steps, double *dev_p
     if (st != RLGL_OK) return st;
     ds = c->host_glob->status;
     if (ds == ST_CONVERGED && c->refresh > 0 && refreshed_at != c->t) {
-      // accept the stop only on the cash rebuilt from the history
+      // accept the stop only on the cash rebuilt from the history; one step
+      // is enqueued to re-run the stop test on it
       st = do_refresh(c);
       if (st != RLGL_OK) return st;
       refreshed_at = last_refresh = c->t;
+      batch = 1;
       continue;
     }
     if (ds != 0) break;
@@ -560,6 +562,7 @@ rlgl_status rlgl_solve(rlgl_ctx *c, double eps, int64_t max_steps, double *dev_p
     long long next = batch * 2;
     if (prev_resid > 0.0 && resid > 0.0 && resid < prev_resid && c->t > prev_t) {
       const double rate = std::pow(resid / prev_resid, 1.0 / (double)(c->t - prev_t));
+      // steps until the stop test passes, plus the step that runs the test
       if (rate < 1.0 && resid > eps) next = (long long)std::ceil(std::log(eps / resid) / std::log(rate)) + 1;
     }
     if (c->d.sched == SCHED_MAXC) next = std::max(next, (long long)256);
