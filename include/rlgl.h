@@ -191,6 +191,81 @@ typedef struct {
 rlgl_status rlgl_profile_enable(rlgl_ctx *ctx, int32_t on);
 int32_t rlgl_profile_read(rlgl_ctx *ctx, rlgl_kernel_stat *out, int32_t max_entries);
 
+/* ---- batched solves ----------------------------------------------------
+ *
+ * Many independent chains solved in one persistent launch (the north-star
+ * batched workload).  Each chain is the chain of rlgl_graph with its own
+ * damping; the method, readings and stop test are those of rlgl_solve
+ * (Algorithm 1 from uniform M_0, stop at ||C_t||_1 / |H_t 1| < eps, t >= 2,
+ * confirmed on C_t = H_t P - H_t when refresh is set).  The arrays of all
+ * chains are concatenated; node ids inside a chain are local (0-based).  The
+ * CSC is required (the batched route is the CSC gather).  Same conventions as
+ * above: device arrays and workspace belong to the caller and must outlive
+ * the batch; the library allocates no device memory. */
+typedef struct rlgl_batch rlgl_batch;
+
+typedef struct {
+  int32_t n_chains;           /* >= 1 */
+  const int64_t *node_off;    /* host [n_chains+1], non-decreasing, node_off[0] = 0: chain k owns entries
+                                 node_off[k] .. node_off[k+1]-1 of every per-node vector (n_k >= 1) */
+  const int64_t *edge_off;    /* host [n_chains+1]: chain k owns links edge_off[k] .. edge_off[k+1]-1 */
+  const double *damping;      /* host [n_chains], each in (0, 1] */
+  const int32_t *csr_rowptr;  /* device: chain k's n_k+1 local row pointers start at node_off[k] + k */
+  const int32_t *csr_col;     /* device [total links]: local target ids */
+  const void *csr_val;        /* device [total links] or NULL (1/outdeg); float, or double for RLGL_FP64 */
+  const int32_t *csc_colptr;  /* device, laid out like csr_rowptr */
+  const int32_t *csc_row;     /* device [total links]: local source ids */
+  const void *csc_val;        /* device or NULL, as csr_val */
+} rlgl_batch_graphs;
+
+typedef struct {
+  int32_t sched;              /* RLGL_SCHED_ALL, _THRESHOLD or _MAXC */
+  double r;                   /* threshold power-mean order, >= 1 */
+  int32_t precision;          /* rlgl_precision */
+  double eps;                 /* stop test on ||C_t||_1 / |H_t 1| */
+  int64_t max_steps;          /* per chain */
+  int32_t refresh;            /* confirm the stop on the cash rebuilt from the history (0/1) */
+  int32_t wg_size;            /* threads per workgroup: 256, 512 or 1024 */
+  int32_t wg_per_cu;          /* resident workgroups per CU: 1..8 */
+} rlgl_batch_options;
+
+/* Outcome of one chain. */
+typedef struct {
+  int64_t t;                  /* final state index */
+  int64_t edges_pushed;       /* as in rlgl_step_info */
+  double resid;               /* ||C_t||_1 / |H_t 1| at the stop */
+  double h_sum;               /* H_t 1 */
+  int32_t status;             /* rlgl_status of the chain */
+  int32_t green_steps;        /* green-light steps taken after step 0 */
+  double start_us, end_us;    /* device wall clock, microseconds since the launch began */
+} rlgl_chain_result;
+
+/* Defaults: THRESHOLD, r = 1, FP32C_KAHANH, eps = 1e-7, max_steps = 100000,
+ * refresh = 1, wg_size = 512, wg_per_cu = 2. */
+void rlgl_batch_default_options(rlgl_batch_options *opt);
+
+size_t rlgl_batch_workspace_bytes(const rlgl_batch_graphs *g, const rlgl_batch_options *opt);
+
+/* Checks the arguments, copies the column pointers to the host once to build
+ * each chain's static plan, and orders the chains by decreasing link count. */
+rlgl_status rlgl_batch_create(const rlgl_batch_graphs *g, const rlgl_batch_options *opt, void *dev_workspace,
+                              size_t ws_bytes, void *stream, rlgl_batch **out);
+
+/* Solves every chain in one persistent launch.  dev_pi (device, total nodes
+ * doubles) receives pi_hat of every chain in the concatenated layout; results
+ * (host, n_chains entries, may be NULL) the per-chain outcome; *elapsed_ms
+ * (may be NULL) the launch time.  Returns RLGL_OK when every chain stopped on
+ * its test, else the first failing chain's status. */
+rlgl_status rlgl_batch_solve(rlgl_batch *b, double *dev_pi, rlgl_chain_result *results, double *elapsed_ms);
+
+/* Autotuner: times one batch solve for every (wg_size, wg_per_cu) candidate
+ * with HIP events and keeps the fastest in the batch; *best (may be NULL)
+ * receives the chosen options.  Candidates whose LDS or register needs do not
+ * fit are skipped. */
+rlgl_status rlgl_batch_autotune(rlgl_batch *b, double *dev_pi, rlgl_batch_options *best);
+
+void rlgl_batch_destroy(rlgl_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -55,9 +55,33 @@ class rlgl_kernel_stat(ctypes.Structure):
                 ("bytes", ctypes.c_double)]
 
 
+class rlgl_batch_graphs(ctypes.Structure):
+    _fields_ = [("n_chains", ctypes.c_int32), ("node_off", ctypes.c_void_p), ("edge_off", ctypes.c_void_p),
+                ("damping", ctypes.c_void_p), ("csr_rowptr", ctypes.c_void_p), ("csr_col", ctypes.c_void_p),
+                ("csr_val", ctypes.c_void_p), ("csc_colptr", ctypes.c_void_p), ("csc_row", ctypes.c_void_p),
+                ("csc_val", ctypes.c_void_p)]
+
+
+class rlgl_batch_options(ctypes.Structure):
+    _fields_ = [("sched", ctypes.c_int32), ("r", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("eps", ctypes.c_double), ("max_steps", ctypes.c_int64), ("refresh", ctypes.c_int32),
+                ("wg_size", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32)]
+
+
+class rlgl_chain_result(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int64), ("edges_pushed", ctypes.c_int64), ("resid", ctypes.c_double),
+                ("h_sum", ctypes.c_double), ("status", ctypes.c_int32), ("green_steps", ctypes.c_int32),
+                ("start_us", ctypes.c_double), ("end_us", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 EXPORTED = ["rlgl_default_options", "rlgl_workspace_bytes", "rlgl_create", "rlgl_step", "rlgl_solve",
             "rlgl_destroy", "rlgl_last_error", "rlgl_reset", "rlgl_get_state", "rlgl_set_state",
-            "rlgl_get_green", "rlgl_refresh", "rlgl_profile_enable", "rlgl_profile_read"]
+            "rlgl_get_green", "rlgl_refresh", "rlgl_profile_enable", "rlgl_profile_read",
+            "rlgl_batch_default_options", "rlgl_batch_workspace_bytes", "rlgl_batch_create", "rlgl_batch_solve",
+            "rlgl_batch_autotune", "rlgl_batch_destroy"]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -94,6 +118,19 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rlgl_profile_enable.restype = i32
     lib.rlgl_profile_read.argtypes = [vp, ctypes.POINTER(rlgl_kernel_stat), i32]
     lib.rlgl_profile_read.restype = i32
+    BG, BO = ctypes.POINTER(rlgl_batch_graphs), ctypes.POINTER(rlgl_batch_options)
+    lib.rlgl_batch_default_options.argtypes = [BO]
+    lib.rlgl_batch_default_options.restype = None
+    lib.rlgl_batch_workspace_bytes.argtypes = [BG, BO]
+    lib.rlgl_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.rlgl_batch_create.argtypes = [BG, BO, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    lib.rlgl_batch_create.restype = i32
+    lib.rlgl_batch_solve.argtypes = [vp, vp, ctypes.POINTER(rlgl_chain_result), ctypes.POINTER(f64)]
+    lib.rlgl_batch_solve.restype = i32
+    lib.rlgl_batch_autotune.argtypes = [vp, vp, BO]
+    lib.rlgl_batch_autotune.restype = i32
+    lib.rlgl_batch_destroy.argtypes = [vp]
+    lib.rlgl_batch_destroy.restype = None
     return lib
 
 
@@ -201,6 +238,44 @@ def rlgl_profile_read(ctx):
             for i in range(m)}
 
 
+def rlgl_batch_default_options(**overrides) -> rlgl_batch_options:
+    o = rlgl_batch_options()
+    _lib.rlgl_batch_default_options(ctypes.byref(o))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def rlgl_batch_workspace_bytes(graphs: rlgl_batch_graphs, opt: rlgl_batch_options) -> int:
+    return int(_lib.rlgl_batch_workspace_bytes(ctypes.byref(graphs), ctypes.byref(opt)))
+
+
+def rlgl_batch_create(graphs: rlgl_batch_graphs, opt: rlgl_batch_options, workspace, ws_bytes: int, stream=None):
+    h = ctypes.c_void_p()
+    _check(_lib.rlgl_batch_create(ctypes.byref(graphs), ctypes.byref(opt), _ptr(workspace), int(ws_bytes),
+                                  _stream_handle(stream), ctypes.byref(h)), "rlgl_batch_create")
+    return h
+
+
+def rlgl_batch_solve(handle, pi_out, n_chains: int, raise_on_error: bool = True):
+    res = (rlgl_chain_result * n_chains)()
+    ms = ctypes.c_double(0.0)
+    st = _lib.rlgl_batch_solve(handle, _ptr(pi_out), res, ctypes.byref(ms))
+    if raise_on_error:
+        _check(st, "rlgl_batch_solve")
+    return st, [r.as_dict() for r in res], ms.value
+
+
+def rlgl_batch_autotune(handle, pi_out) -> rlgl_batch_options:
+    best = rlgl_batch_options()
+    _check(_lib.rlgl_batch_autotune(handle, _ptr(pi_out), ctypes.byref(best)), "rlgl_batch_autotune")
+    return best
+
+
+def rlgl_batch_destroy(handle) -> None:
+    _lib.rlgl_batch_destroy(handle)
+
+
 def _stream_handle(stream):
     if stream is None:
         return torch.cuda.current_stream().cuda_stream
@@ -303,6 +378,90 @@ class Solver:
         if self.ctx is not None:
             rlgl_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DeviceBatch:
+    """Concatenated device arrays of many chains (CSR and CSC, local node ids).
+
+    ``graphs`` is a sequence of objects with ``n``, ``rowptr``, ``col``, ``c``,
+    ``val(dtype)`` and ``csc()`` (as ``workloads.Graph``).
+    """
+
+    def __init__(self, graphs, precision=FP32C_KAHANH, explicit_val=True, device="cuda"):
+        import numpy as np
+        vdt = np.float64 if precision == FP64 else np.float32
+        self.precision = precision
+        self.n_chains = len(graphs)
+        ns = np.array([g.n for g in graphs], dtype=np.int64)
+        ms = np.array([int(g.rowptr[-1]) for g in graphs], dtype=np.int64)
+        self.node_off = np.zeros(self.n_chains + 1, dtype=np.int64)
+        np.cumsum(ns, out=self.node_off[1:])
+        self.edge_off = np.zeros(self.n_chains + 1, dtype=np.int64)
+        np.cumsum(ms, out=self.edge_off[1:])
+        self.damping = np.array([g.c for g in graphs], dtype=np.float64)
+        self.total_n = int(self.node_off[-1])
+        self.total_nnz = int(self.edge_off[-1])
+        rp, cl, cp, rw, vv, cv = [], [], [], [], [], []
+        for g in graphs:
+            colptr, row, perm = g.csc()
+            rp.append(np.asarray(g.rowptr, dtype=np.int32))
+            cl.append(np.asarray(g.col, dtype=np.int32))
+            cp.append(np.asarray(colptr, dtype=np.int32))
+            rw.append(np.asarray(row, dtype=np.int32))
+            if explicit_val:
+                v = g.val(np.float64)
+                vv.append(v.astype(vdt))
+                cv.append(v[perm].astype(vdt))
+        cat = lambda xs, dt: torch.from_numpy(np.ascontiguousarray(np.concatenate(xs), dtype=dt)).to(device)
+        self.rowptr = cat(rp, np.int32)
+        self.col = cat(cl, np.int32)
+        self.colptr = cat(cp, np.int32)
+        self.row = cat(rw, np.int32)
+        self.val = cat(vv, vdt) if explicit_val else None
+        self.cval = cat(cv, vdt) if explicit_val else None
+
+    def struct(self) -> rlgl_batch_graphs:
+        return rlgl_batch_graphs(self.n_chains, self.node_off.ctypes.data, self.edge_off.ctypes.data,
+                                 self.damping.ctypes.data, _ptr(self.rowptr), _ptr(self.col), _ptr(self.val),
+                                 _ptr(self.colptr), _ptr(self.row), _ptr(self.cval))
+
+
+class BatchSolver:
+    """One batched context over a DeviceBatch: workspace, output and results."""
+
+    def __init__(self, db: DeviceBatch, stream=None, **options):
+        options.setdefault("precision", db.precision)
+        self.db = db
+        self.graphs = db.struct()
+        self.opt = rlgl_batch_default_options(**options)
+        self.ws_bytes = rlgl_batch_workspace_bytes(self.graphs, self.opt)
+        if self.ws_bytes == 0:
+            raise RlglError(RLGL_EINVAL, "rlgl_batch_workspace_bytes")
+        dev = db.rowptr.device
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        self.handle = rlgl_batch_create(self.graphs, self.opt, self.workspace, self.ws_bytes, stream)
+        self.pi = torch.empty(db.total_n, dtype=torch.float64, device=dev)
+
+    def solve(self, raise_on_error: bool = True):
+        return rlgl_batch_solve(self.handle, self.pi, self.db.n_chains, raise_on_error)
+
+    def autotune(self) -> dict:
+        best = rlgl_batch_autotune(self.handle, self.pi)
+        return {name: getattr(best, name) for name, _ in best._fields_}
+
+    def chain_pi(self, k: int):
+        return self.pi[int(self.db.node_off[k]):int(self.db.node_off[k + 1])]
+
+    def close(self):
+        if self.handle is not None:
+            rlgl_batch_destroy(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:

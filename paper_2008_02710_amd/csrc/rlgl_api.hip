@@ -20,6 +20,7 @@
 #include "../../include/rlgl.h"
 #include "rlgl_device.h"
 #include "rlgl_kernels.hip"
+#include "rlgl_batch.hip"
 
 using namespace rlgl;
 
@@ -684,6 +685,357 @@ int32_t rlgl_profile_read(rlgl_ctx *c, rlgl_kernel_stat *out, int32_t max_entrie
     ++m;
   }
   return m;
+}
+
+
+// ------------------------------------------------------------ batched solves
+
+}  // extern "C"
+
+namespace {
+
+struct BatchLayout {
+  size_t cash0, cash1, hist, hist_lo, items, chains, order, out, queue, total;
+  size_t max_items;
+};
+
+size_t batch_item_bound(long long n, long long nnz) {
+  // runs (see build_plan) plus one WHOLE item per column longer than CH
+  return 3 * (size_t)(nnz / CH + 2) + (size_t)(n / RUN_MAX_COLS + 2) + (size_t)(nnz / (CH + 1) + 1);
+}
+
+bool batch_layout(const rlgl_batch_graphs *g, const rlgl_batch_options *o, BatchLayout &L, std::string &why) {
+  if (!g || !o || g->n_chains < 1 || !g->node_off || !g->edge_off) { why = "bad batch description"; return false; }
+  if (o->precision < 0 || o->precision > 2) { why = "precision out of range"; return false; }
+  const long long tn = g->node_off[g->n_chains], te = g->edge_off[g->n_chains];
+  size_t items = 0;
+  for (int k = 0; k < g->n_chains; ++k) {
+    const long long n = g->node_off[k + 1] - g->node_off[k], m = g->edge_off[k + 1] - g->edge_off[k];
+    if (n < 1 || n >= (1ll << 31) || m < 0 || m >= (1ll << 31)) { why = "chain sizes out of range"; return false; }
+    items += batch_item_bound(n, m);
+  }
+  (void)te;
+  const size_t cs = (o->precision == RLGL_FP64) ? 8 : 4;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes, 256);
+    return at;
+  };
+  L.cash0 = take(cs * tn);
+  L.cash1 = take(cs * tn);
+  L.hist = take(8 * tn);
+  L.hist_lo = (o->precision == RLGL_FP32C_KAHANH) ? take(4 * tn) : 0;
+  L.max_items = items;
+  L.items = take(sizeof(int4) * items);
+  L.chains = take(sizeof(ChainDesc) * g->n_chains);
+  L.order = take(4 * (size_t)g->n_chains);
+  L.out = take(sizeof(ChainOut) * g->n_chains);
+  L.queue = take(256);
+  L.total = off + 256;
+  return true;
+}
+
+}  // namespace
+
+struct rlgl_batch {
+  BatchDev bd;
+  hipStream_t stream;
+  int prec, hk, nt, per_cu, cus, grid;
+  double clock_khz;
+  int n_chains;
+  long long total_n;
+  ChainOut *host_out;
+  long long *host_t0;
+  long long *dev_t0;
+};
+
+namespace {
+
+template <class T, int HK>
+const void *batch_kernel(int nt) {
+  if (nt == 256) return (const void *)k_batch<T, HK, 256>;
+  if (nt == 512) return (const void *)k_batch<T, HK, 512>;
+  return (const void *)k_batch<T, HK, 1024>;
+}
+
+const void *batch_kernel_for(int prec, int nt) {
+  if (prec == RLGL_FP64) return batch_kernel<double, 0>(nt);
+  if (prec == RLGL_FP32C_KAHANH) return batch_kernel<float, 1>(nt);
+  return batch_kernel<float, 0>(nt);
+}
+
+rlgl_status batch_configure(rlgl_batch *b, int nt, int per_cu) {
+  if (nt != 256 && nt != 512 && nt != 1024) return fail(RLGL_EINVAL, "wg_size must be 256, 512 or 1024");
+  if (per_cu < 1 || per_cu > 8) return fail(RLGL_EINVAL, "wg_per_cu must be in 1..8");
+  int fit = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, batch_kernel_for(b->prec, nt), nt, 0));
+  if (fit < 1) return fail(RLGL_EINVAL, "a %d-thread batch workgroup does not fit on a CU", nt);
+  b->nt = nt;
+  b->per_cu = std::min(per_cu, fit);
+  b->grid = b->cus * b->per_cu;
+  return RLGL_OK;
+}
+
+template <class T, int HK>
+void launch_batch(rlgl_batch *b) {
+  if (b->nt == 256) k_batch<T, HK, 256><<<b->grid, 256, 0, b->stream>>>(b->bd);
+  else if (b->nt == 512) k_batch<T, HK, 512><<<b->grid, 512, 0, b->stream>>>(b->bd);
+  else k_batch<T, HK, 1024><<<b->grid, 1024, 0, b->stream>>>(b->bd);
+}
+
+__global__ void k_batch_start(unsigned int *queue, long long *t0) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *queue = 0u;
+    *t0 = wall_clock64();
+  }
+}
+
+rlgl_status batch_run(rlgl_batch *b, double *dev_pi, float *ms) {
+  b->bd.pi = dev_pi;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(hipEventRecord(e0, b->stream));
+  k_batch_start<<<1, 64, 0, b->stream>>>(b->bd.queue, b->dev_t0);
+  if (b->prec == RLGL_FP64) launch_batch<double, 0>(b);
+  else if (b->hk) launch_batch<float, 1>(b);
+  else launch_batch<float, 0>(b);
+  hipError_t le = hipGetLastError();
+  HIP_TRY(hipEventRecord(e1, b->stream));
+  HIP_TRY(hipEventSynchronize(e1));
+  float t = 0.f;
+  (void)hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (le != hipSuccess) return fail(RLGL_EHIP, "batch launch: %s", hipGetErrorString(le));
+  if (ms) *ms = t;
+  return RLGL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void rlgl_batch_default_options(rlgl_batch_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->sched = RLGL_SCHED_THRESHOLD;
+  o->r = 1.0;
+  o->precision = RLGL_FP32C_KAHANH;
+  o->eps = 1e-7;
+  o->max_steps = 100000;
+  o->refresh = 1;
+  o->wg_size = 512;
+  o->wg_per_cu = 2;
+}
+
+size_t rlgl_batch_workspace_bytes(const rlgl_batch_graphs *g, const rlgl_batch_options *o) {
+  BatchLayout L;
+  std::string why;
+  if (!batch_layout(g, o, L, why)) return 0;
+  return L.total;
+}
+
+rlgl_status rlgl_batch_create(const rlgl_batch_graphs *g, const rlgl_batch_options *o, void *ws, size_t ws_bytes,
+                              void *stream, rlgl_batch **out) {
+  if (!g || !o || !out) return fail(RLGL_EINVAL, "null argument");
+  *out = nullptr;
+  BatchLayout L;
+  std::string why;
+  if (!batch_layout(g, o, L, why)) return fail(RLGL_EINVAL, "%s", why.c_str());
+  if (o->sched != RLGL_SCHED_ALL && o->sched != RLGL_SCHED_THRESHOLD && o->sched != RLGL_SCHED_MAXC)
+    return fail(RLGL_EINVAL, "batched solves support the ALL, THRESHOLD and MAXC schedules");
+  if (!(o->r >= 1.0) || !(o->eps >= 0.0) || o->max_steps < 0) return fail(RLGL_EINVAL, "bad r, eps or max_steps");
+  if (!g->csr_rowptr || !g->csc_colptr || !g->csc_row || !g->damping)
+    return fail(RLGL_EINVAL, "batched solves need the CSR row pointers, the CSC and the damping factors");
+  if ((g->csr_val == nullptr) != (g->csc_val == nullptr)) return fail(RLGL_EINVAL, "csr_val/csc_val mismatch");
+  if (!ws) return fail(RLGL_EINVAL, "workspace is NULL");
+  if (ws_bytes < L.total) return fail(RLGL_ENOMEM, "workspace too small: %zu < %zu", ws_bytes, L.total);
+  const int nc = g->n_chains;
+  for (int k = 0; k < nc; ++k)
+    if (!(g->damping[k] > 0.0 && g->damping[k] <= 1.0)) return fail(RLGL_EINVAL, "damping of chain %d out of (0,1]", k);
+
+  rlgl_batch *b = new (std::nothrow) rlgl_batch();
+  if (!b) return fail(RLGL_ENOMEM, "host allocation failed");
+  b->stream = (hipStream_t)stream;
+  b->prec = o->precision;
+  b->hk = o->precision == RLGL_FP32C_KAHANH;
+  b->n_chains = nc;
+  b->total_n = g->node_off[nc];
+  char *w = (char *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+  BatchDev &d = b->bd;
+  d.n_chains = nc;
+  d.sched = o->sched;
+  d.r = o->r;
+  d.eps = o->eps;
+  d.max_steps = o->max_steps;
+  d.refresh = o->refresh ? 1 : 0;
+  d.rowptr = g->csr_rowptr;
+  d.col = g->csr_col;
+  d.val = g->csr_val;
+  d.colptr = g->csc_colptr;
+  d.crow = g->csc_row;
+  d.cval = g->csc_val;
+  d.cash0 = w + L.cash0;
+  d.cash1 = w + L.cash1;
+  d.hist = w + L.hist;
+  d.hist_lo = b->hk ? (float *)(w + L.hist_lo) : nullptr;
+  d.items = (const int4 *)(w + L.items);
+  d.chains = (const ChainDesc *)(w + L.chains);
+  d.order = (const int *)(w + L.order);
+  d.out = (ChainOut *)(w + L.out);
+  d.queue = (unsigned int *)(w + L.queue);
+  b->dev_t0 = (long long *)(w + L.queue + 64);
+  d.pi = nullptr;
+
+  rlgl_status st = RLGL_OK;
+  auto bail = [&](rlgl_status s) {
+    rlgl_batch_destroy(b);
+    return s;
+  };
+  int dev = 0, cus = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) ||
+      hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev))
+    return bail(fail(RLGL_EHIP, "device attribute query failed"));
+  b->cus = std::max(cus, 1);
+  b->clock_khz = khz > 0 ? khz : 100000.0;
+  if (hipHostMalloc((void **)&b->host_out, sizeof(ChainOut) * nc, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&b->host_t0, sizeof(long long), hipHostMallocDefault) != hipSuccess)
+    return bail(fail(RLGL_EHIP, "pinned host allocation failed"));
+
+  // static plans: runs of at most CH in-links, long columns whole
+  const long long rp_total = b->total_n + nc;
+  std::vector<int> cp((size_t)rp_total);
+  if (hipMemcpyAsync(cp.data(), g->csc_colptr, sizeof(int) * (size_t)rp_total, hipMemcpyDeviceToHost, b->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(b->stream) != hipSuccess)
+    return bail(fail(RLGL_EHIP, "reading the column pointers failed"));
+  std::vector<int4> items;
+  std::vector<ChainDesc> cds((size_t)nc);
+  for (int k = 0; k < nc; ++k) {
+    const long long no = g->node_off[k], rp = no + k;
+    const int n = (int)(g->node_off[k + 1] - no);
+    const int m = (int)(g->edge_off[k + 1] - g->edge_off[k]);
+    const int *c = cp.data() + rp;
+    if (c[0] != 0 || c[n] != m) return bail(fail(RLGL_EINVAL, "chain %d: csc_colptr must run from 0 to its link count", k));
+    ChainDesc &cd = cds[k];
+    cd.node_off = no;
+    cd.rp_off = rp;
+    cd.edge_off = g->edge_off[k];
+    cd.n = n;
+    cd.nnz = m;
+    cd.c = g->damping[k];
+    cd.item_off = (int)items.size();
+    int run0 = -1, run_e = 0;
+    auto flush = [&](int end) {
+      if (run0 >= 0 && end > run0) items.push_back(make_int4(run0, end, c[run0], c[end]));
+      run0 = -1;
+      run_e = 0;
+    };
+    for (int q = 0; q < n; ++q) {
+      const int dg = c[q + 1] - c[q];
+      if (dg < 0) return bail(fail(RLGL_EINVAL, "chain %d: csc_colptr decreases at %d", k, q));
+      if (dg > CH) {
+        flush(q);
+        items.push_back(make_int4(ITEM_WHOLE, q, c[q], c[q + 1]));
+        continue;
+      }
+      if (run0 >= 0 && (run_e + dg > CH || q - run0 >= RUN_MAX_COLS)) flush(q);
+      if (run0 < 0) run0 = q;
+      run_e += dg;
+    }
+    flush(n);
+    cd.n_items = (int)items.size() - cd.item_off;
+  }
+  if (items.size() > L.max_items) return bail(fail(RLGL_EINVAL, "batch plan exceeds its bound (internal)"));
+  std::vector<int> order((size_t)nc);
+  for (int k = 0; k < nc; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c2) {
+    return (long long)cds[a].nnz + cds[a].n > (long long)cds[c2].nnz + cds[c2].n;
+  });
+  if ((!items.empty() &&
+       hipMemcpyAsync(w + L.items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, b->stream)) ||
+      hipMemcpyAsync(w + L.chains, cds.data(), sizeof(ChainDesc) * nc, hipMemcpyHostToDevice, b->stream) ||
+      hipMemcpyAsync(w + L.order, order.data(), sizeof(int) * nc, hipMemcpyHostToDevice, b->stream) ||
+      hipStreamSynchronize(b->stream))
+    return bail(fail(RLGL_EHIP, "uploading the batch plan failed"));
+  st = batch_configure(b, o->wg_size, o->wg_per_cu);
+  if (st != RLGL_OK) return bail(st);
+  *out = b;
+  return RLGL_OK;
+}
+
+rlgl_status rlgl_batch_solve(rlgl_batch *b, double *dev_pi, rlgl_chain_result *res, double *elapsed_ms) {
+  if (!b || !dev_pi) return fail(RLGL_EINVAL, "bad argument");
+  float ms = 0.f;
+  rlgl_status st = batch_run(b, dev_pi, &ms);
+  if (st != RLGL_OK) return st;
+  if (elapsed_ms) *elapsed_ms = ms;
+  HIP_TRY(hipMemcpyAsync(b->host_out, b->bd.out, sizeof(ChainOut) * b->n_chains, hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipMemcpyAsync(b->host_t0, b->dev_t0, sizeof(long long), hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  rlgl_status worst = RLGL_OK;
+  const double us_per_tick = 1000.0 / b->clock_khz;
+  for (int k = 0; k < b->n_chains; ++k) {
+    const ChainOut &o = b->host_out[k];
+    const rlgl_status cs = o.status == ST_CONVERGED ? RLGL_OK : status_of(o.status);
+    if (cs != RLGL_OK && worst == RLGL_OK) worst = cs;
+    if (res) {
+      res[k].t = o.t;
+      res[k].edges_pushed = o.edges;
+      res[k].resid = o.resid;
+      res[k].h_sum = o.hsum;
+      res[k].status = cs;
+      res[k].green_steps = o.green_steps;
+      res[k].start_us = (double)(o.t0 - *b->host_t0) * us_per_tick;
+      res[k].end_us = (double)(o.t1 - *b->host_t0) * us_per_tick;
+    }
+  }
+  if (worst != RLGL_OK) return fail(worst, "at least one chain did not stop on its test");
+  return RLGL_OK;
+}
+
+rlgl_status rlgl_batch_autotune(rlgl_batch *b, double *dev_pi, rlgl_batch_options *best) {
+  if (!b || !dev_pi) return fail(RLGL_EINVAL, "bad argument");
+  const int nts[3] = {256, 512, 1024};
+  const int pcs[4] = {1, 2, 4, 8};
+  double best_ms = 1e300;
+  int best_nt = b->nt, best_pc = b->per_cu;
+  for (int nt : nts)
+    for (int pc : pcs) {
+      if (nt * pc > 2048) continue;  // threads per CU
+      if (batch_configure(b, nt, pc) != RLGL_OK || b->per_cu != pc) continue;
+      float ms = 0.f;
+      rlgl_status st = batch_run(b, dev_pi, &ms);
+      if (st != RLGL_OK) return st;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_nt = nt;
+        best_pc = pc;
+      }
+    }
+  rlgl_status st = batch_configure(b, best_nt, best_pc);
+  if (st != RLGL_OK) return st;
+  if (best) {
+    rlgl_batch_default_options(best);
+    best->sched = b->bd.sched;
+    best->r = b->bd.r;
+    best->precision = b->prec;
+    best->eps = b->bd.eps;
+    best->max_steps = b->bd.max_steps;
+    best->refresh = b->bd.refresh;
+    best->wg_size = b->nt;
+    best->wg_per_cu = b->per_cu;
+  }
+  return RLGL_OK;
+}
+
+void rlgl_batch_destroy(rlgl_batch *b) {
+  if (!b) return;
+  if (b->host_out) (void)hipHostFree(b->host_out);
+  if (b->host_t0) (void)hipHostFree(b->host_t0);
+  delete b;
 }
 
 }  // extern "C"

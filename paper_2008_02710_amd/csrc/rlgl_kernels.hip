@@ -221,9 +221,9 @@ __device__ __forceinline__ bool is_green(T v, int id, int sched, double theta, d
   return a > tau || (a == tau && id <= tie_id);  // top-k: k-th largest |C| and the id bound among its ties
 }
 
-__device__ __forceinline__ double inv_outdeg(const Dev &d, int j) {
-  if ((unsigned)j >= (unsigned)d.n) return 0.0;
-  const int dg = d.rowptr[j + 1] - d.rowptr[j];
+__device__ __forceinline__ double inv_outdeg(const int *rowptr, int n, int j) {
+  if ((unsigned)j >= (unsigned)n) return 0.0;
+  const int dg = rowptr[j + 1] - rowptr[j];
   return dg > 0 ? 1.0 / (double)dg : 0.0;
 }
 
@@ -517,130 +517,166 @@ struct Seg {
 };
 __device__ __forceinline__ Seg seg_op(Seg a, Seg b) { return Seg{b.f ? b.v : a.v + b.v, a.f | b.f}; }
 
+// Item codes of a plan: RUN {k0, k1, p0, p1} with k0 >= 0; PIECE
+// {-1 - slot, k, p0, p1} (one of several workgroups sharing a long column,
+// summed into long_acc[slot]); WHOLE {ITEM_WHOLE, k, p0, p1} (a long column
+// done by a single workgroup).
+constexpr int ITEM_WHOLE = -2147483647 - 1;
+
+// Graph view of one chain for the column pass.
+struct ColView {
+  const int *colptr, *crow, *rowptr;
+  const void *cval;
+  int n;
+};
+
+// LDS of the column pass.
+template <int NT>
+struct ColLds {
+  double con[CH];              // contributions, then inclusive segmented sums
+  unsigned char head[CH];
+  int cp[RUN_MAX_COLS + 1];    // column pointers of the run, relative to p0
+  Seg wave[NT / 64];
+  double red[4 * (NT / 64)];
+};
+
+// One plan item: adds c * sum_j moved(j) P'_jk + kept(k) + off into out[k]
+// for the item's columns and folds the statistics of those values.
 template <class T, int NT, class Moved, class Kept>
-__device__ __forceinline__ void column_pass(const Dev &d, Moved moved, Kept kept, double off, T *__restrict__ out,
-                                            Rec *r) {
-  const double c = d.c;
-  const double rr = d.r;
-  const int *__restrict__ colptr = d.colptr;
-  const int *__restrict__ crow = d.crow;
-  const T *__restrict__ cval = (const T *)d.cval;
-  double l1 = 0.0, cs = 0.0, sr = 0.0, mx = 0.0;
+__device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved moved, Kept kept, double c,
+                                            double off, double rr, T *__restrict__ out, double *long_acc,
+                                            ColLds<NT> &L, double &l1, double &cs, double &sr, double &mx) {
   constexpr int NW = NT / 64;
   constexpr int U = CH / NT;                 // links per thread
   constexpr int KC = RUN_MAX_COLS / NT;      // columns per thread
-  __shared__ double sh_red[4 * NW];
-  __shared__ double s_con[CH];               // contributions, then inclusive segmented sums
-  __shared__ unsigned char s_head[CH];
-  __shared__ int s_cp[RUN_MAX_COLS + 1];     // column pointers of the run, relative to p0
-  __shared__ Seg s_wave[NW];
+  const int *__restrict__ colptr = g.colptr;
+  const int *__restrict__ crow = g.crow;
+  const T *__restrict__ cval = (const T *)g.cval;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-
-  const int nitems = d.n_items;
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const int4 item = d.items[it];
-    if (item.x >= 0) {
-      // RUN {k0, k1, p0, p1}: every load below depends on the item alone
-      const int k0 = item.x, k1 = item.y, p0 = item.z, p1 = item.w;
-      const int ne = p1 - p0, ncol = k1 - k0;
-      if (ne > CH || ne < 0 || ncol > RUN_MAX_COLS || ncol < 0) continue;  // the plan never builds such an item
-      __syncthreads();
+  auto weight = [&](int p, int j) -> double {
+    return cval ? (double)cval[p] : inv_outdeg(g.rowptr, g.n, j);
+  };
+  if (item.x >= 0) {
+    // RUN: every load below depends on the item alone
+    const int k0 = item.x, k1 = item.y, p0 = item.z, p1 = item.w;
+    const int ne = p1 - p0, ncol = k1 - k0;
+    if (ne > CH || ne < 0 || ncol > RUN_MAX_COLS || ncol < 0) return;  // the plan never builds such an item
+    __syncthreads();
+    int jj[U];
+    double ww[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = u * NT + tid;
+      jj[u] = (e < ne) ? crow[p0 + e] : -1;
+      ww[u] = (e < ne && cval) ? (double)cval[p0 + e] : 0.0;
+    }
+    double kv[KC];
+#pragma unroll
+    for (int m = 0; m < KC; ++m) {
+      const int q = m * NT + tid;
+      kv[m] = (q < ncol) ? kept(k0 + q) : 0.0;
+    }
+    for (int q = tid; q <= ncol; q += NT) L.cp[q] = colptr[k0 + q] - p0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = u * NT + tid;
+      if (e < ne) {
+        const double w = cval ? ww[u] : inv_outdeg(g.rowptr, g.n, jj[u]);
+        L.con[e] = moved(jj[u]) * w;
+        L.head[e] = 0;
+      }
+    }
+    __syncthreads();
+    for (int q = tid; q < ncol; q += NT) {
+      const int a = L.cp[q];
+      if (a < L.cp[q + 1]) L.head[a] = 1;
+    }
+    __syncthreads();
+    // segmented inclusive scan: thread t owns elements [t*U, t*U+U)
+    double loc[U];
+    int first_head = U;
+    Seg run{0.0, 0};
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = tid * U + u;
+      const double x = (e < ne) ? L.con[e] : 0.0;
+      const int h = (e < ne) ? L.head[e] : 0;
+      if (h && first_head == U) first_head = u;
+      run = h ? Seg{x, 1} : Seg{run.v + x, run.f};
+      loc[u] = run.v;
+    }
+    Seg inc = run;
+    for (int o = 1; o < 64; o <<= 1) {
+      Seg y;
+      y.v = __shfl_up(inc.v, o, 64);
+      y.f = __shfl_up(inc.f, o, 64);
+      if (lane >= o) inc = seg_op(y, inc);
+    }
+    if (lane == 63) L.wave[wv] = inc;
+    Seg ex;
+    ex.v = __shfl_up(inc.v, 1, 64);
+    ex.f = __shfl_up(inc.f, 1, 64);
+    if (lane == 0) ex = Seg{0.0, 0};
+    __syncthreads();
+    Seg wbase{0.0, 0};
+    for (int q = 0; q < wv; ++q) wbase = seg_op(wbase, L.wave[q]);
+    const Seg carry = seg_op(wbase, ex);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = tid * U + u;
+      if (e < ne) L.con[e] = (u < first_head) ? carry.v + loc[u] : loc[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < KC; ++m) {
+      const int q = m * NT + tid;
+      if (q < ncol) {
+        const int a = L.cp[q], b = L.cp[q + 1];
+        const double acc = (b > a) ? L.con[b - 1] : 0.0;
+        const T x = (T)(kv[m] + c * acc + off);
+        out[k0 + q] = x;
+        fold_stats((double)x, rr, l1, cs, sr, mx);
+      }
+    }
+  } else {
+    // PIECE or WHOLE: a strided walk over [p0, p1) of one column
+    const int k = item.y, pb = item.z, pe = item.w;
+    double acc = 0.0;
+    for (int p0 = pb; p0 < pe; p0 += CH) {
       int jj[U];
       double ww[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int e = u * NT + tid;
-        jj[u] = (e < ne) ? crow[p0 + e] : -1;
-        ww[u] = (e < ne && cval) ? (double)cval[p0 + e] : 0.0;
-      }
-      double kv[KC];
-#pragma unroll
-      for (int m = 0; m < KC; ++m) {
-        const int q = m * NT + tid;
-        kv[m] = (q < ncol) ? kept(k0 + q) : 0.0;
-      }
-      for (int q = tid; q <= ncol; q += NT) s_cp[q] = colptr[k0 + q] - p0;
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int e = u * NT + tid;
-        if (e < ne) {
-          const double w = cval ? ww[u] : inv_outdeg(d, jj[u]);
-          s_con[e] = moved(jj[u]) * w;
-          s_head[e] = 0;
-        }
-      }
-      __syncthreads();
-      for (int q = tid; q < ncol; q += NT) {
-        const int a = s_cp[q];
-        if (a < s_cp[q + 1]) s_head[a] = 1;
-      }
-      __syncthreads();
-      // segmented inclusive scan: thread t owns elements [t*U, t*U+U)
-      double loc[U];
-      int first_head = U;
-      Seg run{0.0, 0};
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int e = tid * U + u;
-        const double x = (e < ne) ? s_con[e] : 0.0;
-        const int h = (e < ne) ? s_head[e] : 0;
-        if (h && first_head == U) first_head = u;
-        run = h ? Seg{x, 1} : Seg{run.v + x, run.f};
-        loc[u] = run.v;
-      }
-      Seg inc = run;
-      for (int o = 1; o < 64; o <<= 1) {
-        Seg y;
-        y.v = __shfl_up(inc.v, o, 64);
-        y.f = __shfl_up(inc.f, o, 64);
-        if (lane >= o) inc = seg_op(y, inc);
-      }
-      if (lane == 63) s_wave[wv] = inc;
-      Seg ex;
-      ex.v = __shfl_up(inc.v, 1, 64);
-      ex.f = __shfl_up(inc.f, 1, 64);
-      if (lane == 0) ex = Seg{0.0, 0};
-      __syncthreads();
-      Seg wbase{0.0, 0};
-      for (int q = 0; q < wv; ++q) wbase = seg_op(wbase, s_wave[q]);
-      const Seg carry = seg_op(wbase, ex);
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int e = tid * U + u;
-        if (e < ne) s_con[e] = (u < first_head) ? carry.v + loc[u] : loc[u];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int m = 0; m < KC; ++m) {
-        const int q = m * NT + tid;
-        if (q < ncol) {
-          const int a = s_cp[q], b = s_cp[q + 1];
-          const double acc = (b > a) ? s_con[b - 1] : 0.0;
-          const T x = (T)(kv[m] + c * acc + off);
-          out[k0 + q] = x;
-          fold_stats((double)x, rr, l1, cs, sr, mx);
-        }
-      }
-    } else {  // PIECE {-1-slot, k, p0, p1}: partial sum of one long column
-      const int slot = -1 - item.x;
-      const int pb = item.z, pe = item.w;
-      double acc = 0.0;
-      int jj[U];
-      double ww[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int p = pb + u * NT + tid;
+        const int p = p0 + u * NT + tid;
         jj[u] = (p < pe) ? crow[p] : -1;
-        ww[u] = (p < pe) ? (cval ? (double)cval[p] : inv_outdeg(d, jj[u])) : 0.0;
+        ww[u] = (p < pe) ? weight(p, jj[u]) : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (jj[u] >= 0) acc += moved(jj[u]) * ww[u];
-      const Red4 t4 = block_sum4<NW>(Red4{acc, 0, 0, 0}, sh_red);
-      if (tid == 0) atomic_add_f64(&d.long_acc[slot], t4.a);
+    }
+    const Red4 t4 = block_sum4<NW>(Red4{acc, 0, 0, 0}, L.red);
+    if (tid == 0) {
+      if (item.x == ITEM_WHOLE) {
+        const T x = (T)(kept(k) + c * t4.a + off);
+        out[k] = x;
+        fold_stats((double)x, rr, l1, cs, sr, mx);
+      } else {
+        atomic_add_f64(&long_acc[-1 - item.x], t4.a);
+      }
     }
   }
-  fold_block_stats<NW>(r, l1, cs, sr, mx, sh_red);
+}
+
+template <class T, int NT, class Moved, class Kept>
+__device__ __forceinline__ void column_pass(const Dev &d, Moved moved, Kept kept, double off, T *__restrict__ out,
+                                            Rec *r) {
+  __shared__ ColLds<NT> L;
+  const ColView g{d.colptr, d.crow, d.rowptr, d.cval, d.n};
+  double l1 = 0.0, cs = 0.0, sr = 0.0, mx = 0.0;
+  for (int it = blockIdx.x; it < d.n_items; it += gridDim.x)
+    column_item<T, NT>(g, d.items[it], moved, kept, d.c, off, d.r, out, d.long_acc, L, l1, cs, sr, mx);
+  fold_block_stats<NT / 64>(r, l1, cs, sr, mx, L.red);
 }
 
 // ----------------------------------------------------------------- complete

@@ -215,17 +215,25 @@ def uniform_values(count: int, lo: float, hi: float, seed: int, stream: int) -> 
 
 
 def batch_chains(count: int = 512, n_lo: float = 1e3, n_hi: float = 2e5, gamma: float = 2.3,
-                 mean_deg: float = 10.0, c_lo: float = 0.8, c_hi: float = 0.95, seed: int = 4):
+                 mean_deg: float = 10.0, c_lo: float = 0.8, c_hi: float = 0.95, seed: int = 4,
+                 with_csc: bool = False):
     """Independent chains: n log-uniform in [n_lo, n_hi], Chung-Lu with
     exponent gamma and the given mean degree (natural dangling nodes), damping
     uniform in [c_lo, c_hi]."""
     sizes = log_uniform_sizes(count, n_lo, n_hi, seed, S_META)
     cs = uniform_values(count, c_lo, c_hi, seed, S_META + 1)
-    out = []
-    for k in range(count):
-        out.append(chung_lu(int(sizes[k]), gamma, mean_deg, 0.0, float(cs[k]), seed=seed * 100003 + 17 * k + 1,
-                            name=f"chain{k}"))
-    return out
+
+    def one(k):
+        g = chung_lu(int(sizes[k]), gamma, mean_deg, 0.0, float(cs[k]), seed=seed * 100003 + 17 * k + 1,
+                     name=f"chain{k}")
+        if with_csc:
+            g.csc()
+        return g
+
+    # the C generators release the GIL: chains are drawn on all host cores
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(one, range(count)))
 
 
 def random_small(n: int, mean_deg: float, c: float, seed: int, dangling_frac: float = 0.0) -> Graph:
