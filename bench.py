@@ -76,8 +76,10 @@ def make_workload(name: str):
 def batched_leg(args, rl, torch, oracle):
     """Independent chains: n log-uniform in [1e3, 2e5], Chung-Lu exponent 2.3,
     mean degree 10, damping uniform in [0.8, 0.95]; FP32 cash with compensated
-    history; one persistent launch.  Reported beside the plain single-chain
-    path solving the same chains one after another."""
+    history; each chain stops at ||C||_1/|H.1| < tol (1 - c_k), tol = 1e-6.
+    Both batch engines are timed; the autotuner picks the launch shape.  The
+    plain single-chain path solving the same chains one after another is
+    reported beside them."""
     import numpy as np
     import workloads
     t0 = time.time()
@@ -87,34 +89,46 @@ def batched_leg(args, rl, torch, oracle):
     print(f"# batched workload: {len(gs)} chains, {tot_n} nodes, {tot_e} links, gen {time.time() - t0:.1f}s",
           file=sys.stderr, flush=True)
     tol = 1e-6
-    eps = (1.0 - max(g.c for g in gs)) * tol
-    db = rl.DeviceBatch(gs, precision=rl.FP32C_KAHANH)
-    bs = rl.BatchSolver(db, eps=eps)
+    db = rl.DeviceBatch(gs, precision=rl.FP32C_KAHANH, tol_l1=tol)
+    bs = rl.BatchSolver(db, max_steps=100000)
     tuned = bs.autotune()
-    bs.solve()  # warm-up with the tuned launch shape
-    runs = []
-    for _ in range(max(1, min(args.steps, 5))):
-        st, res, ms = bs.solve()
-        runs.append((ms, res))
-    ms_best, res = min(runs, key=lambda x: x[0])
-    lat = np.array([r["end_us"] for r in res]) / 1000.0
-    pushes = sum(r["edges_pushed"] for r in res)
-    # accuracy: FP64 residual certificate of every chain (L1 <= resid / (1 - c))
-    worst = 0.0
-    pi = bs.pi.detach().cpu().numpy()
-    for k, g in enumerate(gs):
-        ch = oracle.Chain(g.rowptr, g.col, g.val(), g.c)
-        r = oracle.residual(ch, pi[db.node_off[k]:db.node_off[k + 1]])
-        worst = max(worst, r / (1.0 - g.c))
+    engines = {}
+    for name, eng, shape in (("lockstep", rl.BATCH_LOCKSTEP, None), ("persistent", rl.BATCH_PERSISTENT, None)):
+        if tuned["engine"] == eng:
+            opt = dict(engine=eng, wg_size=tuned["wg_size"], wg_per_cu=tuned["wg_per_cu"])
+        else:
+            opt = dict(engine=eng, wg_size=256 if eng == rl.BATCH_LOCKSTEP else 512, wg_per_cu=1)
+        b2 = rl.BatchSolver(db, max_steps=100000, **opt)
+        b2.solve()  # warm-up
+        runs = []
+        for _ in range(max(1, min(args.steps, 5))):
+            st, res, ms = b2.solve()
+            runs.append((ms, res))
+        ms_best, res = min(runs, key=lambda x: x[0])
+        lat = np.array([r["end_us"] for r in res]) / 1000.0
+        pushes = sum(r["edges_pushed"] for r in res)
+        worst = 0.0
+        pi = b2.pi.detach().cpu().numpy()
+        for k, g in enumerate(gs):
+            ch = oracle.Chain(g.rowptr, g.col, g.val(), g.c)
+            r = oracle.residual(ch, pi[db.node_off[k]:db.node_off[k + 1]])
+            worst = max(worst, r / (1.0 - g.c))
+        b2.close()
+        engines[name] = {"solves_per_s": round(len(gs) / (ms_best / 1000.0), 1), "launch_ms": round(ms_best, 3),
+                         "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                         "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                         "gteps": round(pushes / (ms_best / 1000.0) / 1e9, 2), "worst_certified_l1": worst,
+                         "wg_size": opt["wg_size"], "wg_per_cu": opt["wg_per_cu"],
+                         "mean_steps": round(float(np.mean([r["t"] for r in res])), 1),
+                         "max_steps": int(max(r["t"] for r in res))}
+        print(f"# batched {name}: {json.dumps(engines[name])}", file=sys.stderr, flush=True)
     bs.close()
-    print(f"# batched: {ms_best:.2f} ms for {len(gs)} solves, p50 {np.percentile(lat, 50):.2f} ms, "
-          f"p99 {np.percentile(lat, 99):.2f} ms, tuned {tuned['wg_size']}x{tuned['wg_per_cu']}, "
-          f"worst certified L1 {worst:.2e}", file=sys.stderr, flush=True)
     # the plain single-chain path on the same chains, one after another
     plain = []
     plain_push = 0
     for g in gs:
-        dg = rl.DeviceGraph.from_workload(g, precision=rl.FP32C_KAHANH)
+        eps = tol * (1.0 - g.c)
+        dg = rl.DeviceGraph.from_workload(g, precision=rl.FP32C_KAHANH, explicit_val=False)
         s = rl.Solver(dg, sched=rl.SCHED_THRESHOLD, precision=rl.FP32C_KAHANH)
         s.reset()
         s.solve(eps)
@@ -130,12 +144,13 @@ def batched_leg(args, rl, torch, oracle):
     plain = np.array(plain)
     seq_lat = np.cumsum(plain)
     print(f"# plain path: {plain.sum():.1f} ms for {len(gs)} solves back to back", file=sys.stderr, flush=True)
+    best = engines["lockstep"] if tuned["engine"] == rl.BATCH_LOCKSTEP else engines["persistent"]
     return {"workload": f"chung_lu_batch{len(gs)}", "chains": len(gs), "nodes": tot_n, "links": tot_e,
-            "precision": "fp32c_kahanh", "tol_l1": tol, "eps_resid": eps,
-            "solves_per_s": round(len(gs) / (ms_best / 1000.0), 1), "launch_ms": round(ms_best, 3),
-            "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
-            "gteps": round(pushes / (ms_best / 1000.0) / 1e9, 2), "worst_certified_l1": worst,
-            "tuned": {"wg_size": tuned["wg_size"], "wg_per_cu": tuned["wg_per_cu"]},
+            "precision": "fp32c_kahanh", "tol_l1": tol, "stop": "resid < tol_l1 * (1 - c_k)",
+            "tuned": {"engine": "lockstep" if tuned["engine"] == rl.BATCH_LOCKSTEP else "persistent",
+                      "wg_size": tuned["wg_size"], "wg_per_cu": tuned["wg_per_cu"]},
+            "solves_per_s": best["solves_per_s"], "p50_ms": best["p50_ms"], "p99_ms": best["p99_ms"],
+            "gteps": best["gteps"], "engines": engines,
             "plain_single_chain": {"solves_per_s": round(len(gs) / (plain.sum() / 1000.0), 1),
                                    "solve_ms_p50": round(float(np.percentile(plain, 50)), 3),
                                    "solve_ms_p99": round(float(np.percentile(plain, 99)), 3),

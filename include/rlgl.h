@@ -193,15 +193,25 @@ int32_t rlgl_profile_read(rlgl_ctx *ctx, rlgl_kernel_stat *out, int32_t max_entr
 
 /* ---- batched solves ----------------------------------------------------
  *
- * Many independent chains solved in one persistent launch (the north-star
- * batched workload).  Each chain is the chain of rlgl_graph with its own
- * damping; the method, readings and stop test are those of rlgl_solve
- * (Algorithm 1 from uniform M_0, stop at ||C_t||_1 / |H_t 1| < eps, t >= 2,
- * confirmed on C_t = H_t P - H_t when refresh is set).  The arrays of all
- * chains are concatenated; node ids inside a chain are local (0-based).  The
- * CSC is required (the batched route is the CSC gather).  Same conventions as
- * above: device arrays and workspace belong to the caller and must outlive
- * the batch; the library allocates no device memory. */
+ * Many independent chains of uneven size solved together.  Each chain is the
+ * chain of rlgl_graph with its own damping; the method, readings and stop
+ * test are those of rlgl_solve (Algorithm 1 from uniform M_0, stop at
+ * ||C_t||_1 / |H_t 1| < eps_k, t >= 2, confirmed on C_t = H_t P - H_t when
+ * refresh is set).  The arrays of all chains are concatenated; node ids
+ * inside a chain are local (0-based).  The CSC is required (the batched route
+ * is the CSC gather).  Same conventions as above: device arrays and workspace
+ * belong to the caller and must outlive the batch; the library allocates no
+ * device memory.
+ *
+ * Two engines:
+ *   RLGL_BATCH_PERSISTENT - one launch for the whole batch; each workgroup
+ *     takes the next chain from a device queue (largest first) and runs its
+ *     whole solve with workgroup barriers only;
+ *   RLGL_BATCH_LOCKSTEP - every unfinished chain advances one step per
+ *     iteration of three launches (select, route, control) that span all of
+ *     them, so a large chain is spread over the whole GPU; link weights are
+ *     implicit (1/outdeg in FP64) and csr_val/csc_val are not read. */
+typedef enum { RLGL_BATCH_PERSISTENT = 0, RLGL_BATCH_LOCKSTEP = 1 } rlgl_batch_engine;
 typedef struct rlgl_batch rlgl_batch;
 
 typedef struct {
@@ -216,6 +226,9 @@ typedef struct {
   const int32_t *csc_colptr;  /* device, laid out like csr_rowptr */
   const int32_t *csc_row;     /* device [total links]: local source ids */
   const void *csc_val;        /* device or NULL, as csr_val */
+  const double *tol_l1;       /* host [n_chains] or NULL: chain k stops at ||C_t||_1 / |H_t 1| < tol_l1[k] (1 - c_k),
+                                 which bounds the L1 error of pi_hat by tol_l1[k] (Lemma 1 with
+                                 ||sum_k (P^k - 1 pi)||_1 <= 1 / (1 - c)); NULL: options.eps for every chain */
 } rlgl_batch_graphs;
 
 typedef struct {
@@ -225,8 +238,11 @@ typedef struct {
   double eps;                 /* stop test on ||C_t||_1 / |H_t 1| */
   int64_t max_steps;          /* per chain */
   int32_t refresh;            /* confirm the stop on the cash rebuilt from the history (0/1) */
-  int32_t wg_size;            /* threads per workgroup: 256, 512 or 1024 */
-  int32_t wg_per_cu;          /* resident workgroups per CU: 1..8 */
+  int32_t wg_size;            /* persistent: threads per workgroup, 256, 512 or 1024; lockstep: threads per
+                                 route workgroup, 256 or 512 */
+  int32_t wg_per_cu;          /* persistent: resident workgroups per CU, 1..8 */
+  int32_t engine;             /* rlgl_batch_engine */
+  int32_t check_period;       /* lockstep: iterations between host checks of the finished count (>= 1) */
 } rlgl_batch_options;
 
 /* Outcome of one chain. */
@@ -241,7 +257,8 @@ typedef struct {
 } rlgl_chain_result;
 
 /* Defaults: THRESHOLD, r = 1, FP32C_KAHANH, eps = 1e-7, max_steps = 100000,
- * refresh = 1, wg_size = 512, wg_per_cu = 2. */
+ * refresh = 1, wg_size = 512, wg_per_cu = 2, engine = LOCKSTEP,
+ * check_period = 8. */
 void rlgl_batch_default_options(rlgl_batch_options *opt);
 
 size_t rlgl_batch_workspace_bytes(const rlgl_batch_graphs *g, const rlgl_batch_options *opt);
@@ -251,14 +268,16 @@ size_t rlgl_batch_workspace_bytes(const rlgl_batch_graphs *g, const rlgl_batch_o
 rlgl_status rlgl_batch_create(const rlgl_batch_graphs *g, const rlgl_batch_options *opt, void *dev_workspace,
                               size_t ws_bytes, void *stream, rlgl_batch **out);
 
-/* Solves every chain in one persistent launch.  dev_pi (device, total nodes
- * doubles) receives pi_hat of every chain in the concatenated layout; results
- * (host, n_chains entries, may be NULL) the per-chain outcome; *elapsed_ms
- * (may be NULL) the launch time.  Returns RLGL_OK when every chain stopped on
- * its test, else the first failing chain's status. */
+/* Solves every chain with the configured engine.  dev_pi (device, total
+ * nodes doubles) receives pi_hat of every chain in the concatenated layout;
+ * results (host, n_chains entries, may be NULL) the per-chain outcome;
+ * *elapsed_ms (may be NULL) the time from the first launch to the last
+ * chain's stop.  Returns RLGL_OK when every chain stopped on its test, else
+ * the first failing chain's status. */
 rlgl_status rlgl_batch_solve(rlgl_batch *b, double *dev_pi, rlgl_chain_result *results, double *elapsed_ms);
 
-/* Autotuner: times one batch solve for every (wg_size, wg_per_cu) candidate
+/* Autotuner: times one batch solve for every candidate (persistent: wg_size
+ * in {256, 512} x wg_per_cu in {1, 2}; lockstep: route wg_size in {256, 512})
  * with HIP events and keeps the fastest in the batch; *best (may be NULL)
  * receives the chosen options.  Candidates whose LDS or register needs do not
  * fit are skipped. */

@@ -55,17 +55,21 @@ class rlgl_kernel_stat(ctypes.Structure):
                 ("bytes", ctypes.c_double)]
 
 
+BATCH_PERSISTENT, BATCH_LOCKSTEP = 0, 1
+
+
 class rlgl_batch_graphs(ctypes.Structure):
     _fields_ = [("n_chains", ctypes.c_int32), ("node_off", ctypes.c_void_p), ("edge_off", ctypes.c_void_p),
                 ("damping", ctypes.c_void_p), ("csr_rowptr", ctypes.c_void_p), ("csr_col", ctypes.c_void_p),
                 ("csr_val", ctypes.c_void_p), ("csc_colptr", ctypes.c_void_p), ("csc_row", ctypes.c_void_p),
-                ("csc_val", ctypes.c_void_p)]
+                ("csc_val", ctypes.c_void_p), ("tol_l1", ctypes.c_void_p)]
 
 
 class rlgl_batch_options(ctypes.Structure):
     _fields_ = [("sched", ctypes.c_int32), ("r", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("eps", ctypes.c_double), ("max_steps", ctypes.c_int64), ("refresh", ctypes.c_int32),
-                ("wg_size", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32)]
+                ("wg_size", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32), ("engine", ctypes.c_int32),
+                ("check_period", ctypes.c_int32)]
 
 
 class rlgl_chain_result(ctypes.Structure):
@@ -393,8 +397,10 @@ class DeviceBatch:
     ``val(dtype)`` and ``csc()`` (as ``workloads.Graph``).
     """
 
-    def __init__(self, graphs, precision=FP32C_KAHANH, explicit_val=True, device="cuda"):
+    def __init__(self, graphs, precision=FP32C_KAHANH, explicit_val=False, device="cuda", tol_l1=None):
         import numpy as np
+        self.tol_l1 = None if tol_l1 is None else np.ascontiguousarray(
+            np.broadcast_to(np.asarray(tol_l1, dtype=np.float64), (len(graphs),)))
         vdt = np.float64 if precision == FP64 else np.float32
         self.precision = precision
         self.n_chains = len(graphs)
@@ -429,7 +435,8 @@ class DeviceBatch:
     def struct(self) -> rlgl_batch_graphs:
         return rlgl_batch_graphs(self.n_chains, self.node_off.ctypes.data, self.edge_off.ctypes.data,
                                  self.damping.ctypes.data, _ptr(self.rowptr), _ptr(self.col), _ptr(self.val),
-                                 _ptr(self.colptr), _ptr(self.row), _ptr(self.cval))
+                                 _ptr(self.colptr), _ptr(self.row), _ptr(self.cval),
+                                 None if self.tol_l1 is None else self.tol_l1.ctypes.data)
 
 
 class BatchSolver:

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc", "rlgl_api.hip")
 OUT = os.path.join(HERE, "librlgl.so")
-DEPS = [os.path.join(HERE, "csrc", f) for f in ("rlgl_api.hip", "rlgl_kernels.hip", "rlgl_device.h")] + [
+DEPS = [os.path.join(HERE, "csrc", f) for f in sorted(os.listdir(os.path.join(HERE, "csrc")))] + [
     os.path.join(os.path.dirname(HERE), "include", "rlgl.h")]
 
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared", "-Wall",

@@ -21,6 +21,7 @@
 #include "rlgl_device.h"
 #include "rlgl_kernels.hip"
 #include "rlgl_batch.hip"
+#include "rlgl_lockstep.hip"
 
 using namespace rlgl;
 
@@ -694,27 +695,192 @@ int32_t rlgl_profile_read(rlgl_ctx *c, rlgl_kernel_stat *out, int32_t max_entrie
 
 namespace {
 
-struct BatchLayout {
-  size_t cash0, cash1, hist, hist_lo, items, chains, order, out, queue, total;
-  size_t max_items;
+// ---- the step-synchronous engine (shared by batched solves and the pool)
+
+size_t ls_device_bytes(int cap) {
+  return align_up(sizeof(LsChain) * (size_t)cap, 256) + align_up(sizeof(LsCtl) * (size_t)cap, 256) +
+         align_up(sizeof(LsStripe) * LS_NS * (size_t)cap, 256) + align_up(4 * (4 * (size_t)cap + 3), 256) + 256;
+}
+
+struct LsEngine {
+  hipStream_t stream = nullptr;
+  int prec = 0, hk = 0, nt = 256, cap = 0;
+  LsArgs args{};
+  LsChain *d_chains = nullptr;
+  int *d_lists = nullptr;  // act [cap] | tpre [cap+1] | wpre [cap+1] | rpre [cap+1]
+  int *h_lists = nullptr;  // pinned staging of d_lists
+  LsCtl *h_ctl = nullptr;  // pinned [cap]
+  unsigned int *h_done = nullptr;
+  hipEvent_t staged = nullptr;
+  bool staged_pending = false;
+  int t_total = 0, r_total = 0;
+  std::vector<LsChain> host;  // descriptors as on the device
+  std::vector<int> act;
 };
 
+rlgl_status ls_init(LsEngine &E, char *ws, int cap, int prec, int sched, double r, int refresh, hipStream_t stream) {
+  E.stream = stream;
+  E.prec = prec;
+  E.hk = prec == RLGL_FP32C_KAHANH;
+  E.cap = cap;
+  char *w = (char *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char *p = w + off;
+    off = align_up(off + bytes, 256);
+    return p;
+  };
+  E.d_chains = (LsChain *)take(sizeof(LsChain) * (size_t)cap);
+  LsArgs &a = E.args;
+  a.chains = E.d_chains;
+  a.ctl = (LsCtl *)take(sizeof(LsCtl) * (size_t)cap);
+  a.stats = (LsStripe *)take(sizeof(LsStripe) * LS_NS * (size_t)cap);
+  E.d_lists = (int *)take(4 * (4 * (size_t)cap + 3));
+  a.done = (unsigned int *)take(256);
+  a.act = E.d_lists;
+  a.tpre = E.d_lists + cap;
+  a.wpre = E.d_lists + 2 * cap + 1;
+  a.rpre = E.d_lists + 3 * cap + 2;
+  a.n_act = 0;
+  a.w_total = 0;
+  a.sched = sched;
+  a.refresh = refresh ? 1 : 0;
+  a.r = r;
+  E.host.assign((size_t)cap, LsChain{});
+  HIP_TRY(hipHostMalloc((void **)&E.h_lists, 4 * (4 * (size_t)cap + 3), hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc((void **)&E.h_ctl, sizeof(LsCtl) * (size_t)cap, hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc((void **)&E.h_done, sizeof(unsigned int), hipHostMallocDefault));
+  HIP_TRY(hipEventCreateWithFlags(&E.staged, hipEventDisableTiming));
+  return RLGL_OK;
+}
+
+void ls_free(LsEngine &E) {
+  if (E.staged) {
+    (void)hipEventSynchronize(E.staged);
+    (void)hipEventDestroy(E.staged);
+  }
+  if (E.h_lists) (void)hipHostFree(E.h_lists);
+  if (E.h_ctl) (void)hipHostFree(E.h_ctl);
+  if (E.h_done) (void)hipHostFree(E.h_done);
+  E = LsEngine{};
+}
+
+// Makes `ids` the active slots (launch order: long columns of every chain
+// first, then the runs, chain by chain in the order given).
+rlgl_status ls_set_active(LsEngine &E, const std::vector<int> &ids) {
+  if ((int)ids.size() > E.cap) return fail(RLGL_EINVAL, "active list longer than the engine capacity");
+  if (E.staged_pending) HIP_TRY(hipEventSynchronize(E.staged));
+  const int cap = E.cap, na = (int)ids.size();
+  int *act = E.h_lists, *tp = E.h_lists + cap, *wp = E.h_lists + 2 * cap + 1, *rp = E.h_lists + 3 * cap + 2;
+  long long tt = 0, tw = 0, tr = 0;
+  for (int q = 0; q < na; ++q) {
+    const LsChain &ch = E.host[ids[q]];
+    act[q] = ids[q];
+    tp[q] = (int)tt;
+    wp[q] = (int)tw;
+    rp[q] = (int)tr;
+    tt += (ch.n + LS_TILE - 1) / LS_TILE;
+    tw += ch.n_whole;
+    tr += ch.n_run;
+  }
+  if (tt >= INT32_MAX || tw + tr >= INT32_MAX) return fail(RLGL_EINVAL, "active chains exceed the launch grid");
+  tp[na] = (int)tt;
+  wp[na] = (int)tw;
+  rp[na] = (int)tr;
+  HIP_TRY(hipMemcpyAsync(E.d_lists, E.h_lists, 4 * (4 * (size_t)cap + 3), hipMemcpyHostToDevice, E.stream));
+  HIP_TRY(hipEventRecord(E.staged, E.stream));
+  E.staged_pending = true;
+  E.act = ids;
+  E.args.n_act = na;
+  E.args.w_total = (int)tw;
+  E.t_total = (int)tt;
+  E.r_total = (int)tr;
+  return RLGL_OK;
+}
+
+template <class T, int HK>
+void ls_launch(LsEngine &E) {
+  const LsArgs &a = E.args;
+  k_ls_select<T, HK><<<E.t_total, BLOCK, 0, E.stream>>>(a);
+  const int rg = a.w_total + E.r_total;
+  if (rg > 0) {
+    if (E.nt == 512) k_ls_route<T, HK, 512><<<rg, 512, 0, E.stream>>>(a);
+    else k_ls_route<T, HK, 256><<<rg, 256, 0, E.stream>>>(a);
+  }
+  k_ls_control<<<a.n_act, 64, 0, E.stream>>>(a);
+}
+
+rlgl_status ls_iterate(LsEngine &E, int count) {
+  if (E.args.n_act == 0) return RLGL_OK;
+  for (int i = 0; i < count; ++i) {
+    if (E.prec == RLGL_FP64) ls_launch<double, 0>(E);
+    else if (E.hk) ls_launch<float, 1>(E);
+    else ls_launch<float, 0>(E);
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(RLGL_EHIP, "lockstep launch: %s", hipGetErrorString(e));
+  return RLGL_OK;
+}
+
+// Chain plan: long columns (> CH links) as whole items first, then runs of at
+// most CH links and RUN_MAX_COLS columns.  Returns false on a bad colptr.
+bool chain_plan(const int *c, int n, int m, std::vector<int4> &items, int &n_whole, int &n_run, std::string &why) {
+  if (c[0] != 0 || c[n] != m) {
+    why = "csc_colptr must run from 0 to the link count";
+    return false;
+  }
+  const size_t first = items.size();
+  for (int q = 0; q < n; ++q) {
+    const int dg = c[q + 1] - c[q];
+    if (dg < 0) {
+      why = "csc_colptr decreases";
+      return false;
+    }
+    if (dg > CH) items.push_back(make_int4(ITEM_WHOLE, q, c[q], c[q + 1]));
+  }
+  n_whole = (int)(items.size() - first);
+  int run0 = -1, run_e = 0;
+  auto flush = [&](int end) {
+    if (run0 >= 0 && end > run0) items.push_back(make_int4(run0, end, c[run0], c[end]));
+    run0 = -1;
+    run_e = 0;
+  };
+  for (int q = 0; q < n; ++q) {
+    const int dg = c[q + 1] - c[q];
+    if (dg > CH) {
+      flush(q);
+      continue;
+    }
+    if (run0 >= 0 && (run_e + dg > CH || q - run0 >= RUN_MAX_COLS)) flush(q);
+    if (run0 < 0) run0 = q;
+    run_e += dg;
+  }
+  flush(n);
+  n_run = (int)(items.size() - first) - n_whole;
+  return true;
+}
+
 size_t batch_item_bound(long long n, long long nnz) {
-  // runs (see build_plan) plus one WHOLE item per column longer than CH
+  // runs (see build_plan) plus one whole item per column longer than CH
   return 3 * (size_t)(nnz / CH + 2) + (size_t)(n / RUN_MAX_COLS + 2) + (size_t)(nnz / (CH + 1) + 1);
 }
+
+struct BatchLayout {
+  size_t cash0, cash1, src, hist, hist_lo, items, chains, order, out, queue, engine, total;
+  size_t max_items;
+};
 
 bool batch_layout(const rlgl_batch_graphs *g, const rlgl_batch_options *o, BatchLayout &L, std::string &why) {
   if (!g || !o || g->n_chains < 1 || !g->node_off || !g->edge_off) { why = "bad batch description"; return false; }
   if (o->precision < 0 || o->precision > 2) { why = "precision out of range"; return false; }
-  const long long tn = g->node_off[g->n_chains], te = g->edge_off[g->n_chains];
+  if (g->node_off[0] != 0 || g->edge_off[0] != 0) { why = "node_off[0] and edge_off[0] must be 0"; return false; }
+  const long long tn = g->node_off[g->n_chains];
   size_t items = 0;
   for (int k = 0; k < g->n_chains; ++k) {
     const long long n = g->node_off[k + 1] - g->node_off[k], m = g->edge_off[k + 1] - g->edge_off[k];
     if (n < 1 || n >= (1ll << 31) || m < 0 || m >= (1ll << 31)) { why = "chain sizes out of range"; return false; }
     items += batch_item_bound(n, m);
   }
-  (void)te;
   const size_t cs = (o->precision == RLGL_FP64) ? 8 : 4;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -724,6 +890,7 @@ bool batch_layout(const rlgl_batch_graphs *g, const rlgl_batch_options *o, Batch
   };
   L.cash0 = take(cs * tn);
   L.cash1 = take(cs * tn);
+  L.src = take(cs * tn);
   L.hist = take(8 * tn);
   L.hist_lo = (o->precision == RLGL_FP32C_KAHANH) ? take(4 * tn) : 0;
   L.max_items = items;
@@ -732,6 +899,7 @@ bool batch_layout(const rlgl_batch_graphs *g, const rlgl_batch_options *o, Batch
   L.order = take(4 * (size_t)g->n_chains);
   L.out = take(sizeof(ChainOut) * g->n_chains);
   L.queue = take(256);
+  L.engine = take(ls_device_bytes(g->n_chains));
   L.total = off + 256;
   return true;
 }
@@ -742,12 +910,19 @@ struct rlgl_batch {
   BatchDev bd;
   hipStream_t stream;
   int prec, hk, nt, per_cu, cus, grid;
+  int engine, ls_nt, check_period;
+  double eps;
   double clock_khz;
   int n_chains;
   long long total_n;
   ChainOut *host_out;
   long long *host_t0;
   long long *dev_t0;
+  std::vector<long long> node_off;
+  std::vector<int> order;  // largest chain first
+  int *dev_order;          // the same order on the device
+  LsEngine E;
+  double *ls_pi;           // output vector the lockstep descriptors point into
 };
 
 namespace {
@@ -765,15 +940,29 @@ const void *batch_kernel_for(int prec, int nt) {
   return batch_kernel<float, 0>(nt);
 }
 
-rlgl_status batch_configure(rlgl_batch *b, int nt, int per_cu) {
+rlgl_status batch_configure(rlgl_batch *b, const rlgl_batch_options &o) {
+  if (o.engine != RLGL_BATCH_PERSISTENT && o.engine != RLGL_BATCH_LOCKSTEP)
+    return fail(RLGL_EINVAL, "engine must be RLGL_BATCH_PERSISTENT or RLGL_BATCH_LOCKSTEP");
+  if (o.check_period < 1) return fail(RLGL_EINVAL, "check_period must be >= 1");
+  if (o.engine == RLGL_BATCH_LOCKSTEP) {
+    if (o.wg_size != 256 && o.wg_size != 512) return fail(RLGL_EINVAL, "lockstep wg_size must be 256 or 512");
+    b->engine = RLGL_BATCH_LOCKSTEP;
+    b->ls_nt = o.wg_size;
+    b->E.nt = o.wg_size;
+    b->check_period = o.check_period;
+    return RLGL_OK;
+  }
+  const int nt = o.wg_size, per_cu = o.wg_per_cu;
   if (nt != 256 && nt != 512 && nt != 1024) return fail(RLGL_EINVAL, "wg_size must be 256, 512 or 1024");
   if (per_cu < 1 || per_cu > 8) return fail(RLGL_EINVAL, "wg_per_cu must be in 1..8");
   int fit = 0;
   HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, batch_kernel_for(b->prec, nt), nt, 0));
   if (fit < 1) return fail(RLGL_EINVAL, "a %d-thread batch workgroup does not fit on a CU", nt);
+  b->engine = RLGL_BATCH_PERSISTENT;
   b->nt = nt;
   b->per_cu = std::min(per_cu, fit);
   b->grid = b->cus * b->per_cu;
+  b->check_period = o.check_period;
   return RLGL_OK;
 }
 
@@ -791,25 +980,106 @@ __global__ void k_batch_start(unsigned int *queue, long long *t0) {
   }
 }
 
-rlgl_status batch_run(rlgl_batch *b, double *dev_pi, float *ms) {
+rlgl_status persistent_run(rlgl_batch *b, double *dev_pi) {
   b->bd.pi = dev_pi;
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
-  HIP_TRY(hipEventRecord(e0, b->stream));
   k_batch_start<<<1, 64, 0, b->stream>>>(b->bd.queue, b->dev_t0);
   if (b->prec == RLGL_FP64) launch_batch<double, 0>(b);
   else if (b->hk) launch_batch<float, 1>(b);
   else launch_batch<float, 0>(b);
-  hipError_t le = hipGetLastError();
-  HIP_TRY(hipEventRecord(e1, b->stream));
-  HIP_TRY(hipEventSynchronize(e1));
+  const hipError_t le = hipGetLastError();
+  if (le != hipSuccess) return fail(RLGL_EHIP, "batch launch: %s", hipGetErrorString(le));
+  return RLGL_OK;
+}
+
+rlgl_status lockstep_run(rlgl_batch *b, double *dev_pi) {
+  LsEngine &E = b->E;
+  if (dev_pi != b->ls_pi) {
+    for (int k = 0; k < b->n_chains; ++k) E.host[k].pi = dev_pi + b->node_off[k];
+    HIP_TRY(hipMemcpyAsync(E.d_chains, E.host.data(), sizeof(LsChain) * b->n_chains, hipMemcpyHostToDevice,
+                           b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    b->ls_pi = dev_pi;
+  }
+  rlgl_status st = ls_set_active(E, b->order);
+  if (st != RLGL_OK) return st;
+  k_batch_start<<<1, 64, 0, b->stream>>>(b->bd.queue, b->dev_t0);
+  k_ls_start<<<(b->n_chains + 255) / 256, 256, 0, b->stream>>>(E.args.ctl, E.args.stats, b->dev_order, b->n_chains,
+                                                               E.args.done);
+  long long max_steps = 0;
+  for (int k = 0; k < b->n_chains; ++k) max_steps = std::max(max_steps, E.host[k].max_steps);
+  // every chain stops within max_steps green steps, step 0, one refresh per
+  // step and the normalisation pass
+  const long long limit = 2 * max_steps + 8;
+  long long iters = 0;
+  const int n = b->n_chains;
+  unsigned int done_seen = 0;
+  for (;;) {
+    st = ls_iterate(E, b->check_period);
+    if (st != RLGL_OK) return st;
+    iters += b->check_period;
+    HIP_TRY(hipMemcpyAsync(E.h_done, E.args.done, sizeof(unsigned int), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    if ((int)*E.h_done >= n) break;
+    if (iters > limit) return fail(RLGL_EHIP, "lockstep batch did not finish within its step bound (internal)");
+    // drop finished chains from the launch grids once an eighth of the active
+    // ones have finished since the list was last built
+    if ((size_t)(*E.h_done - done_seen) * 8 >= E.act.size()) {
+      done_seen = *E.h_done;
+      HIP_TRY(hipMemcpyAsync(E.h_ctl, E.args.ctl, sizeof(LsCtl) * n, hipMemcpyDeviceToHost, b->stream));
+      HIP_TRY(hipStreamSynchronize(b->stream));
+      std::vector<int> keep;
+      keep.reserve(E.act.size());
+      for (int k : E.act)
+        if (E.h_ctl[k].mode != LS_DONE) keep.push_back(k);
+      if (keep.size() < E.act.size()) {
+        st = ls_set_active(E, keep);
+        if (st != RLGL_OK) return st;
+      }
+    }
+  }
+  return RLGL_OK;
+}
+
+rlgl_status batch_run(rlgl_batch *b, double *dev_pi, float *ms) {
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  rlgl_status st = RLGL_OK;
+  if (hipEventRecord(e0, b->stream) != hipSuccess) st = fail(RLGL_EHIP, "event record failed");
+  if (st == RLGL_OK) st = (b->engine == RLGL_BATCH_LOCKSTEP) ? lockstep_run(b, dev_pi) : persistent_run(b, dev_pi);
+  if (st == RLGL_OK && (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+    st = fail(RLGL_EHIP, "event wait failed");
   float t = 0.f;
-  (void)hipEventElapsedTime(&t, e0, e1);
+  if (st == RLGL_OK) (void)hipEventElapsedTime(&t, e0, e1);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (le != hipSuccess) return fail(RLGL_EHIP, "batch launch: %s", hipGetErrorString(le));
-  if (ms) *ms = t;
+  if (st == RLGL_OK && ms) *ms = t;
+  return st;
+}
+
+// Per-chain outcomes of the last solve, in the persistent kernel's format.
+rlgl_status batch_outcomes(rlgl_batch *b) {
+  if (b->engine == RLGL_BATCH_PERSISTENT) {
+    HIP_TRY(hipMemcpyAsync(b->host_out, b->bd.out, sizeof(ChainOut) * b->n_chains, hipMemcpyDeviceToHost, b->stream));
+  } else {
+    HIP_TRY(hipMemcpyAsync(b->E.h_ctl, b->E.args.ctl, sizeof(LsCtl) * b->n_chains, hipMemcpyDeviceToHost, b->stream));
+  }
+  HIP_TRY(hipMemcpyAsync(b->host_t0, b->dev_t0, sizeof(long long), hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  if (b->engine == RLGL_BATCH_LOCKSTEP) {
+    for (int k = 0; k < b->n_chains; ++k) {
+      const LsCtl &c = b->E.h_ctl[k];
+      ChainOut &o = b->host_out[k];
+      o.t = c.t;
+      o.edges = c.edges;
+      o.resid = c.resid;
+      o.hsum = c.hsum;
+      o.status = c.status;
+      o.green_steps = c.green_steps;
+      o.t0 = c.t0;
+      o.t1 = c.t1;
+    }
+  }
   return RLGL_OK;
 }
 
@@ -828,6 +1098,8 @@ void rlgl_batch_default_options(rlgl_batch_options *o) {
   o->refresh = 1;
   o->wg_size = 512;
   o->wg_per_cu = 2;
+  o->engine = RLGL_BATCH_LOCKSTEP;
+  o->check_period = 8;
 }
 
 size_t rlgl_batch_workspace_bytes(const rlgl_batch_graphs *g, const rlgl_batch_options *o) {
@@ -846,15 +1118,18 @@ rlgl_status rlgl_batch_create(const rlgl_batch_graphs *g, const rlgl_batch_optio
   if (!batch_layout(g, o, L, why)) return fail(RLGL_EINVAL, "%s", why.c_str());
   if (o->sched != RLGL_SCHED_ALL && o->sched != RLGL_SCHED_THRESHOLD && o->sched != RLGL_SCHED_MAXC)
     return fail(RLGL_EINVAL, "batched solves support the ALL, THRESHOLD and MAXC schedules");
-  if (!(o->r >= 1.0) || !(o->eps >= 0.0) || o->max_steps < 0) return fail(RLGL_EINVAL, "bad r, eps or max_steps");
+  if (!(o->r >= 1.0) || !std::isfinite(o->r) || !(o->eps >= 0.0) || o->max_steps < 0)
+    return fail(RLGL_EINVAL, "bad r, eps or max_steps");
   if (!g->csr_rowptr || !g->csc_colptr || !g->csc_row || !g->damping)
     return fail(RLGL_EINVAL, "batched solves need the CSR row pointers, the CSC and the damping factors");
   if ((g->csr_val == nullptr) != (g->csc_val == nullptr)) return fail(RLGL_EINVAL, "csr_val/csc_val mismatch");
   if (!ws) return fail(RLGL_EINVAL, "workspace is NULL");
   if (ws_bytes < L.total) return fail(RLGL_ENOMEM, "workspace too small: %zu < %zu", ws_bytes, L.total);
   const int nc = g->n_chains;
-  for (int k = 0; k < nc; ++k)
+  for (int k = 0; k < nc; ++k) {
     if (!(g->damping[k] > 0.0 && g->damping[k] <= 1.0)) return fail(RLGL_EINVAL, "damping of chain %d out of (0,1]", k);
+    if (g->tol_l1 && !(g->tol_l1[k] >= 0.0)) return fail(RLGL_EINVAL, "tol_l1 of chain %d is negative", k);
+  }
 
   rlgl_batch *b = new (std::nothrow) rlgl_batch();
   if (!b) return fail(RLGL_ENOMEM, "host allocation failed");
@@ -863,12 +1138,14 @@ rlgl_status rlgl_batch_create(const rlgl_batch_graphs *g, const rlgl_batch_optio
   b->hk = o->precision == RLGL_FP32C_KAHANH;
   b->n_chains = nc;
   b->total_n = g->node_off[nc];
+  b->node_off.assign(g->node_off, g->node_off + nc + 1);
+  b->ls_pi = nullptr;
+  b->eps = o->eps;
   char *w = (char *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
   BatchDev &d = b->bd;
   d.n_chains = nc;
   d.sched = o->sched;
   d.r = o->r;
-  d.eps = o->eps;
   d.max_steps = o->max_steps;
   d.refresh = o->refresh ? 1 : 0;
   d.rowptr = g->csr_rowptr;
@@ -887,9 +1164,9 @@ rlgl_status rlgl_batch_create(const rlgl_batch_graphs *g, const rlgl_batch_optio
   d.out = (ChainOut *)(w + L.out);
   d.queue = (unsigned int *)(w + L.queue);
   b->dev_t0 = (long long *)(w + L.queue + 64);
+  b->dev_order = (int *)(w + L.order);
   d.pi = nullptr;
 
-  rlgl_status st = RLGL_OK;
   auto bail = [&](rlgl_status s) {
     rlgl_batch_destroy(b);
     return s;
@@ -903,8 +1180,10 @@ rlgl_status rlgl_batch_create(const rlgl_batch_graphs *g, const rlgl_batch_optio
   if (hipHostMalloc((void **)&b->host_out, sizeof(ChainOut) * nc, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void **)&b->host_t0, sizeof(long long), hipHostMallocDefault) != hipSuccess)
     return bail(fail(RLGL_EHIP, "pinned host allocation failed"));
+  rlgl_status st = ls_init(b->E, w + L.engine, nc, o->precision, o->sched, o->r, o->refresh, b->stream);
+  if (st != RLGL_OK) return bail(st);
 
-  // static plans: runs of at most CH in-links, long columns whole
+  // static plans: long columns whole, then runs of at most CH in-links
   const long long rp_total = b->total_n + nc;
   std::vector<int> cp((size_t)rp_total);
   if (hipMemcpyAsync(cp.data(), g->csc_colptr, sizeof(int) * (size_t)rp_total, hipMemcpyDeviceToHost, b->stream) !=
@@ -913,12 +1192,11 @@ rlgl_status rlgl_batch_create(const rlgl_batch_graphs *g, const rlgl_batch_optio
     return bail(fail(RLGL_EHIP, "reading the column pointers failed"));
   std::vector<int4> items;
   std::vector<ChainDesc> cds((size_t)nc);
+  const size_t cs = (o->precision == RLGL_FP64) ? 8 : 4;
   for (int k = 0; k < nc; ++k) {
     const long long no = g->node_off[k], rp = no + k;
     const int n = (int)(g->node_off[k + 1] - no);
     const int m = (int)(g->edge_off[k + 1] - g->edge_off[k]);
-    const int *c = cp.data() + rp;
-    if (c[0] != 0 || c[n] != m) return bail(fail(RLGL_EINVAL, "chain %d: csc_colptr must run from 0 to its link count", k));
     ChainDesc &cd = cds[k];
     cd.node_off = no;
     cd.rp_off = rp;
@@ -926,41 +1204,44 @@ rlgl_status rlgl_batch_create(const rlgl_batch_graphs *g, const rlgl_batch_optio
     cd.n = n;
     cd.nnz = m;
     cd.c = g->damping[k];
+    cd.eps = g->tol_l1 ? g->tol_l1[k] * (1.0 - g->damping[k]) : o->eps;
     cd.item_off = (int)items.size();
-    int run0 = -1, run_e = 0;
-    auto flush = [&](int end) {
-      if (run0 >= 0 && end > run0) items.push_back(make_int4(run0, end, c[run0], c[end]));
-      run0 = -1;
-      run_e = 0;
-    };
-    for (int q = 0; q < n; ++q) {
-      const int dg = c[q + 1] - c[q];
-      if (dg < 0) return bail(fail(RLGL_EINVAL, "chain %d: csc_colptr decreases at %d", k, q));
-      if (dg > CH) {
-        flush(q);
-        items.push_back(make_int4(ITEM_WHOLE, q, c[q], c[q + 1]));
-        continue;
-      }
-      if (run0 >= 0 && (run_e + dg > CH || q - run0 >= RUN_MAX_COLS)) flush(q);
-      if (run0 < 0) run0 = q;
-      run_e += dg;
-    }
-    flush(n);
-    cd.n_items = (int)items.size() - cd.item_off;
+    int nw = 0, nr = 0;
+    if (!chain_plan(cp.data() + rp, n, m, items, nw, nr, why))
+      return bail(fail(RLGL_EINVAL, "chain %d: %s", k, why.c_str()));
+    cd.n_items = nw + nr;
+    LsChain &lc = b->E.host[k];
+    lc.rowptr = g->csr_rowptr + rp;
+    lc.colptr = g->csc_colptr + rp;
+    lc.crow = g->csc_row + g->edge_off[k];
+    lc.items = (const int4 *)(w + L.items) + cd.item_off;
+    lc.cash0 = w + L.cash0 + cs * no;
+    lc.cash1 = w + L.cash1 + cs * no;
+    lc.src = w + L.src + cs * no;
+    lc.hist = w + L.hist + (b->hk ? 4 : 8) * no;
+    lc.hist_lo = b->hk ? (float *)(w + L.hist_lo) + no : nullptr;
+    lc.pi = nullptr;
+    lc.nnz = m;
+    lc.max_steps = o->max_steps;
+    lc.c = cd.c;
+    lc.eps = cd.eps;
+    lc.n = n;
+    lc.n_whole = nw;
+    lc.n_run = nr;
   }
   if (items.size() > L.max_items) return bail(fail(RLGL_EINVAL, "batch plan exceeds its bound (internal)"));
-  std::vector<int> order((size_t)nc);
-  for (int k = 0; k < nc; ++k) order[k] = k;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int c2) {
+  b->order.resize((size_t)nc);
+  for (int k = 0; k < nc; ++k) b->order[k] = k;
+  std::stable_sort(b->order.begin(), b->order.end(), [&](int a, int c2) {
     return (long long)cds[a].nnz + cds[a].n > (long long)cds[c2].nnz + cds[c2].n;
   });
   if ((!items.empty() &&
        hipMemcpyAsync(w + L.items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, b->stream)) ||
       hipMemcpyAsync(w + L.chains, cds.data(), sizeof(ChainDesc) * nc, hipMemcpyHostToDevice, b->stream) ||
-      hipMemcpyAsync(w + L.order, order.data(), sizeof(int) * nc, hipMemcpyHostToDevice, b->stream) ||
+      hipMemcpyAsync(w + L.order, b->order.data(), sizeof(int) * nc, hipMemcpyHostToDevice, b->stream) ||
       hipStreamSynchronize(b->stream))
     return bail(fail(RLGL_EHIP, "uploading the batch plan failed"));
-  st = batch_configure(b, o->wg_size, o->wg_per_cu);
+  st = batch_configure(b, *o);
   if (st != RLGL_OK) return bail(st);
   *out = b;
   return RLGL_OK;
@@ -972,9 +1253,8 @@ rlgl_status rlgl_batch_solve(rlgl_batch *b, double *dev_pi, rlgl_chain_result *r
   rlgl_status st = batch_run(b, dev_pi, &ms);
   if (st != RLGL_OK) return st;
   if (elapsed_ms) *elapsed_ms = ms;
-  HIP_TRY(hipMemcpyAsync(b->host_out, b->bd.out, sizeof(ChainOut) * b->n_chains, hipMemcpyDeviceToHost, b->stream));
-  HIP_TRY(hipMemcpyAsync(b->host_t0, b->dev_t0, sizeof(long long), hipMemcpyDeviceToHost, b->stream));
-  HIP_TRY(hipStreamSynchronize(b->stream));
+  st = batch_outcomes(b);
+  if (st != RLGL_OK) return st;
   rlgl_status worst = RLGL_OK;
   const double us_per_tick = 1000.0 / b->clock_khz;
   for (int k = 0; k < b->n_chains; ++k) {
@@ -998,41 +1278,55 @@ rlgl_status rlgl_batch_solve(rlgl_batch *b, double *dev_pi, rlgl_chain_result *r
 
 rlgl_status rlgl_batch_autotune(rlgl_batch *b, double *dev_pi, rlgl_batch_options *best) {
   if (!b || !dev_pi) return fail(RLGL_EINVAL, "bad argument");
-  const int nts[3] = {256, 512, 1024};
-  const int pcs[4] = {1, 2, 4, 8};
-  double best_ms = 1e300;
-  int best_nt = b->nt, best_pc = b->per_cu;
-  for (int nt : nts)
-    for (int pc : pcs) {
-      if (nt * pc > 2048) continue;  // threads per CU
-      if (batch_configure(b, nt, pc) != RLGL_OK || b->per_cu != pc) continue;
-      float ms = 0.f;
-      rlgl_status st = batch_run(b, dev_pi, &ms);
-      if (st != RLGL_OK) return st;
-      if (ms < best_ms) {
-        best_ms = ms;
-        best_nt = nt;
-        best_pc = pc;
-      }
-    }
-  rlgl_status st = batch_configure(b, best_nt, best_pc);
-  if (st != RLGL_OK) return st;
-  if (best) {
-    rlgl_batch_default_options(best);
-    best->sched = b->bd.sched;
-    best->r = b->bd.r;
-    best->precision = b->prec;
-    best->eps = b->bd.eps;
-    best->max_steps = b->bd.max_steps;
-    best->refresh = b->bd.refresh;
-    best->wg_size = b->nt;
-    best->wg_per_cu = b->per_cu;
+  rlgl_batch_options cur;
+  rlgl_batch_default_options(&cur);
+  cur.sched = b->bd.sched;
+  cur.r = b->bd.r;
+  cur.precision = b->prec;
+  cur.eps = b->eps;
+  cur.max_steps = b->bd.max_steps;
+  cur.refresh = b->bd.refresh;
+  cur.check_period = b->check_period;
+  cur.engine = b->engine;
+  cur.wg_size = b->engine == RLGL_BATCH_LOCKSTEP ? b->ls_nt : b->nt;
+  cur.wg_per_cu = b->engine == RLGL_BATCH_LOCKSTEP ? 1 : b->per_cu;
+  std::vector<rlgl_batch_options> cands;
+  for (int nt : {256, 512}) {
+    rlgl_batch_options c = cur;
+    c.engine = RLGL_BATCH_LOCKSTEP;
+    c.wg_size = nt;
+    cands.push_back(c);
   }
+  for (int nt : {256, 512})
+    for (int pc : {1, 2}) {
+      rlgl_batch_options c = cur;
+      c.engine = RLGL_BATCH_PERSISTENT;
+      c.wg_size = nt;
+      c.wg_per_cu = pc;
+      cands.push_back(c);
+    }
+  double best_ms = 1e300;
+  rlgl_batch_options pick = cur;
+  for (const rlgl_batch_options &c : cands) {
+    if (batch_configure(b, c) != RLGL_OK) continue;
+    if (c.engine == RLGL_BATCH_PERSISTENT && b->per_cu != c.wg_per_cu) continue;
+    float ms = 0.f;
+    const rlgl_status st = batch_run(b, dev_pi, &ms);
+    if (st != RLGL_OK) return st;
+    if (ms < best_ms) {
+      best_ms = ms;
+      pick = c;
+    }
+  }
+  const rlgl_status st = batch_configure(b, pick);
+  if (st != RLGL_OK) return st;
+  if (best) *best = pick;
   return RLGL_OK;
 }
 
 void rlgl_batch_destroy(rlgl_batch *b) {
   if (!b) return;
+  ls_free(b->E);
   if (b->host_out) (void)hipHostFree(b->host_out);
   if (b->host_t0) (void)hipHostFree(b->host_t0);
   delete b;

@@ -20,6 +20,7 @@ struct ChainDesc {
   int n, nnz;
   int item_off, n_items;
   double c;
+  double eps;          // stop threshold on ||C_t||_1 / |H_t 1|
 };
 
 struct ChainOut {
@@ -33,7 +34,6 @@ struct BatchDev {
   int n_chains;
   int sched;
   double r;
-  double eps;
   long long max_steps;
   int refresh;
   const ChainDesc *chains;
@@ -64,7 +64,7 @@ __device__ void batch_chain(const BatchDev &b, int k, ColLds<NT> &L) {
   const int tid = threadIdx.x;
   const int *__restrict__ rowptr = b.rowptr + cd.rp_off;
   const ColView g{b.colptr + cd.rp_off, b.crow + cd.edge_off, rowptr,
-                  b.cval ? (const void *)((const T *)b.cval + cd.edge_off) : nullptr, n};
+                  b.cval ? (const void *)((const T *)b.cval + cd.edge_off) : nullptr, n, 0};
   T *Ca = (T *)b.cash0 + cd.node_off;
   T *Cb = (T *)b.cash1 + cd.node_off;
   double *H64 = (double *)b.hist + cd.node_off;
@@ -117,7 +117,7 @@ __device__ void batch_chain(const BatchDev &b, int k, ColLds<NT> &L) {
     // the rounding of FP32 cash leaves C_t 1 != 0; once that drift is half of
     // ||C_t||_1 the cash is rebuilt from the history, as before a stop
     const bool drift = fabs(cs) > 0.5 * l1 && l1 > 0.0;
-    if ((t >= 2 && resid < b.eps) || (drift && b.refresh && refreshed != t)) {
+    if ((t >= 2 && resid < cd.eps) || (drift && b.refresh && refreshed != t)) {
       if (b.refresh && refreshed != t) {
         // confirm the stop on C_t = H_t P - H_t (eq. (7) with C_0 = 0), in FP64
         double pool = 0.0;

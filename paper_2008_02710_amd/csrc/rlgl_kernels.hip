@@ -528,6 +528,7 @@ struct ColView {
   const int *colptr, *crow, *rowptr;
   const void *cval;
   int n;
+  int unit;  // moved(j) already holds M_j P'_jk: every link weight is 1
 };
 
 // LDS of the column pass.
@@ -553,8 +554,9 @@ __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved m
   const int *__restrict__ crow = g.crow;
   const T *__restrict__ cval = (const T *)g.cval;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const bool unit = g.unit != 0;
   auto weight = [&](int p, int j) -> double {
-    return cval ? (double)cval[p] : inv_outdeg(g.rowptr, g.n, j);
+    return unit ? 1.0 : (cval ? (double)cval[p] : inv_outdeg(g.rowptr, g.n, j));
   };
   if (item.x >= 0) {
     // RUN: every load below depends on the item alone
@@ -568,7 +570,7 @@ __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved m
     for (int u = 0; u < U; ++u) {
       const int e = u * NT + tid;
       jj[u] = (e < ne) ? crow[p0 + e] : -1;
-      ww[u] = (e < ne && cval) ? (double)cval[p0 + e] : 0.0;
+      ww[u] = (e < ne && cval && !unit) ? (double)cval[p0 + e] : 0.0;
     }
     double kv[KC];
 #pragma unroll
@@ -581,7 +583,7 @@ __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved m
     for (int u = 0; u < U; ++u) {
       const int e = u * NT + tid;
       if (e < ne) {
-        const double w = cval ? ww[u] : inv_outdeg(g.rowptr, g.n, jj[u]);
+        const double w = unit ? 1.0 : (cval ? ww[u] : inv_outdeg(g.rowptr, g.n, jj[u]));
         L.con[e] = moved(jj[u]) * w;
         L.head[e] = 0;
       }
@@ -672,7 +674,7 @@ template <class T, int NT, class Moved, class Kept>
 __device__ __forceinline__ void column_pass(const Dev &d, Moved moved, Kept kept, double off, T *__restrict__ out,
                                             Rec *r) {
   __shared__ ColLds<NT> L;
-  const ColView g{d.colptr, d.crow, d.rowptr, d.cval, d.n};
+  const ColView g{d.colptr, d.crow, d.rowptr, d.cval, d.n, 0};
   double l1 = 0.0, cs = 0.0, sr = 0.0, mx = 0.0;
   for (int it = blockIdx.x; it < d.n_items; it += gridDim.x)
     column_item<T, NT>(g, d.items[it], moved, kept, d.c, off, d.r, out, d.long_acc, L, l1, cs, sr, mx);

@@ -50,17 +50,21 @@ def reference(g):
     return _cache[key]
 
 
+ENGINES = {"persistent": rl.BATCH_PERSISTENT, "lockstep": rl.BATCH_LOCKSTEP}
+
+
+@pytest.mark.parametrize("engine", list(ENGINES))
 @pytest.mark.parametrize("prec", [rl.FP32C_KAHANH, rl.FP32C_FP64H, rl.FP64], ids=PREC_NAMES.get)
 @pytest.mark.parametrize("sched", ["threshold", "all"])
-def test_batch_matches_oracle(prec, sched):
+def test_batch_matches_oracle(prec, sched, engine):
     gs = chains()
-    say("case batch", PREC_NAMES[prec], sched, len(gs), "chains")
+    say("case batch", PREC_NAMES[prec], sched, engine, len(gs), "chains")
     tol = 1e-10 if prec == rl.FP64 else 1e-6
     worst_c = max(g.c for g in gs)
     eps = (1 - worst_c) * tol * 0.5
     db = rl.DeviceBatch(gs, precision=prec)
     bs = rl.BatchSolver(db, sched={"threshold": rl.SCHED_THRESHOLD, "all": rl.SCHED_ALL}[sched], eps=eps,
-                        wg_size=256, wg_per_cu=2, max_steps=20000)
+                        wg_size=256, wg_per_cu=2, max_steps=20000, engine=ENGINES[engine])
     st, res, ms = bs.solve()
     assert st == rl.RLGL_OK
     for k, g in enumerate(gs):
@@ -76,14 +80,15 @@ def test_batch_matches_oracle(prec, sched):
     bs.close()
 
 
-def test_batch_equals_single_chain_path():
+@pytest.mark.parametrize("engine", list(ENGINES))
+def test_batch_equals_single_chain_path(engine):
     """Each chain's result is the same alone (single-chain solve) and in the
     batch, within the mixed-precision tolerance."""
     gs = chains()
-    say("case batch_vs_single")
+    say("case batch_vs_single", engine)
     eps = 0.05 * 1e-6
     db = rl.DeviceBatch(gs, precision=rl.FP32C_FP64H)
-    bs = rl.BatchSolver(db, eps=eps, max_steps=20000)
+    bs = rl.BatchSolver(db, eps=eps, max_steps=20000, engine=ENGINES[engine])
     st, res, ms = bs.solve()
     assert st == rl.RLGL_OK
     for k, g in enumerate(gs):
@@ -113,11 +118,13 @@ def test_batch_autotune_and_repeat():
     bs.close()
 
 
-def test_batch_maxc_small_chains():
+@pytest.mark.parametrize("engine", list(ENGINES))
+def test_batch_maxc_small_chains(engine):
     gs = [workloads.chung_lu(n, 2.3, 6.0, 0.0, 0.85, seed=n, name=f"s{n}") for n in (40, 120, 333)]
-    say("case batch_maxc")
+    say("case batch_maxc", engine)
     db = rl.DeviceBatch(gs, precision=rl.FP64)
-    bs = rl.BatchSolver(db, sched=rl.SCHED_MAXC, eps=0.15e-10, wg_size=256, wg_per_cu=1, max_steps=200000)
+    bs = rl.BatchSolver(db, sched=rl.SCHED_MAXC, eps=0.15e-10, wg_size=256, wg_per_cu=1, max_steps=200000,
+                        engine=ENGINES[engine])
     st, res, ms = bs.solve()
     assert st == rl.RLGL_OK
     for k, g in enumerate(gs):
@@ -125,12 +132,39 @@ def test_batch_maxc_small_chains():
     bs.close()
 
 
-def test_batch_not_converged_reports_chain_status():
+@pytest.mark.parametrize("engine", list(ENGINES))
+def test_batch_not_converged_reports_chain_status(engine):
     gs = chains()[:4]
-    say("case batch_limit")
+    say("case batch_limit", engine)
     db = rl.DeviceBatch(gs, precision=rl.FP32C_KAHANH)
-    bs = rl.BatchSolver(db, eps=1e-30, max_steps=3)
+    bs = rl.BatchSolver(db, eps=1e-30, max_steps=3, engine=ENGINES[engine])
     st, res, ms = bs.solve(raise_on_error=False)
     assert st == rl.RLGL_ENOT_CONVERGED
     assert all(r["status"] == rl.RLGL_ENOT_CONVERGED and r["t"] == 4 for r in res)
     bs.close()
+
+
+def test_batch_engines_agree_and_tol_l1_certifies():
+    """Per-chain L1 targets: each chain stops at ||C||_1/|H.1| < tol (1 - c_k),
+    and the FP64 residual of its pi_hat certifies L1 <= tol.  Both engines
+    take the same number of steps up to the refresh and rounding order."""
+    gs = chains()
+    say("case batch_tol_l1")
+    tols = [1e-6 if k % 2 else 3e-7 for k in range(len(gs))]
+    db = rl.DeviceBatch(gs, precision=rl.FP32C_KAHANH, tol_l1=tols)
+    out = {}
+    for name, eng in ENGINES.items():
+        bs = rl.BatchSolver(db, engine=eng, max_steps=20000)
+        st, res, ms = bs.solve()
+        assert st == rl.RLGL_OK
+        pis = [to_np(bs.chain_pi(k)).copy() for k in range(len(gs))]
+        out[name] = (res, pis)
+        bs.close()
+    for k, g in enumerate(gs):
+        for name in ENGINES:
+            res, pis = out[name]
+            cert = oracle.residual(oracle_chain(g), pis[k]) / (1 - g.c)
+            assert cert <= tols[k], (name, k, cert)
+            assert l1(pis[k], reference(g)) <= tols[k], (name, k)
+        ta, tb = out["persistent"][0][k]["t"], out["lockstep"][0][k]["t"]
+        assert abs(ta - tb) <= 2, (k, ta, tb)
