@@ -159,6 +159,70 @@ def batched_leg(args, rl, torch, oracle):
                                    "gteps": round(plain_push / (plain.sum() / 1000.0) / 1e9, 2)}}
 
 
+def serving_leg(args, rl, torch, oracle):
+    """Poisson arrivals at 500 requests/s; each request is a chain drawn
+    uniformly from a pool of pre-generated chains (n log-uniform in
+    [1e3, 1e6], Chung-Lu exponent 2.3, mean degree 12, damping 0.85) held in
+    page-locked host memory, tolerance 1e-6 L1.  The upload counts toward the
+    latency.  Run under three arena budgets: one that never binds, 4 GB, and
+    256 MB, where admission waits for memory (a 1e6-node chain takes ~90 MB)."""
+    import numpy as np
+    import workloads
+    from paper_2008_02710_amd.serving import serve
+    t0 = time.time()
+    pool_graphs = workloads.serving_pool(args.serve_pool, seed=5)
+    hcs = [rl.HostChain(g, tol_l1=1e-6) for g in pool_graphs]
+    print(f"# serving pool: {len(hcs)} chains, {sum(g.n for g in pool_graphs)} nodes, "
+          f"{sum(g.nnz for g in pool_graphs)} links, gen {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    total = args.serve_requests + args.serve_warmup
+    draws = workloads.request_draws(total, len(hcs), seed=5)
+    arrivals = workloads.poisson_arrivals(total, args.serve_rate, seed=5)
+    reqs = [hcs[d] for d in draws]
+    sample = set(range(args.serve_warmup, total, max(1, args.serve_requests // 16)))
+    out = {}
+    for label, arena in (("unbounded", 48 << 30), ("4GB", 4 << 30), ("256MB", 256 << 20)):
+        pool = rl.Pool(arena, max_chains=256, precision=rl.FP32C_KAHANH)
+        kept = {}
+
+        def on_result(i, res, pi):
+            if i in sample:
+                kept[i] = pi.detach().cpu().numpy().copy()
+
+        peak = [0]
+        recs = serve(pool, reqs, list(arrivals), iterations=args.serve_iters, on_result=on_result)
+        pool.close()
+        meas = recs[args.serve_warmup:]
+        lat = np.array([r["latency"] for r in meas]) * 1000.0
+        wait = np.array([r["admitted"] - r["arrival"] for r in meas]) * 1000.0
+        span = max(r["finished"] for r in meas) - min(r["arrival"] for r in meas)
+        pushes = sum(r["edges_pushed"] for r in meas)
+        bad = sum(r["status"] != rl.RLGL_OK for r in meas)
+        worst = 0.0
+        for i, pi in kept.items():
+            g = pool_graphs[draws[i]]
+            ch = oracle.Chain(g.rowptr, g.col, g.val(), g.c)
+            worst = max(worst, oracle.residual(ch, pi) / (1.0 - g.c))
+        # requests in flight over time, from the admission and finish times
+        ev = sorted([(r["admitted"], 1) for r in meas] + [(r["finished"], -1) for r in meas])
+        cur = 0
+        for _, d in ev:
+            cur += d
+            peak[0] = max(peak[0], cur)
+        out[label] = {"arena_bytes": arena, "requests": len(meas), "failed": bad,
+                      "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                      "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                      "mean_ms": round(float(lat.mean()), 3),
+                      "admission_wait_p99_ms": round(float(np.percentile(wait, 99)), 3),
+                      "completed_per_s": round(len(meas) / span, 1),
+                      "served_gteps": round(pushes / span / 1e9, 3),
+                      "peak_in_flight": peak[0],
+                      "worst_certified_l1_sampled": worst, "sampled": len(kept)}
+        print(f"# serving {label}: {json.dumps(out[label])}", file=sys.stderr, flush=True)
+    return {"workload": "chung_lu_serving", "rate_per_s": args.serve_rate, "pool_chains": len(hcs),
+            "warmup_requests": args.serve_warmup, "tol_l1": 1e-6, "iterations_per_poll": args.serve_iters,
+            "budgets": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -175,6 +239,12 @@ def main():
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     ap.add_argument("--batch", type=int, default=512,
                     help="chains of the batched workload (0 skips the batched leg)")
+    ap.add_argument("--serve-requests", type=int, default=5000,
+                    help="measured requests of the serving leg (0 skips it)")
+    ap.add_argument("--serve-warmup", type=int, default=1000, help="requests before the measured ones")
+    ap.add_argument("--serve-rate", type=float, default=500.0, help="Poisson arrival rate (requests/s)")
+    ap.add_argument("--serve-pool", type=int, default=64, help="pre-generated chains requests draw from")
+    ap.add_argument("--serve-iters", type=int, default=4, help="lockstep iterations between host polls")
     args = ap.parse_args()
 
     if args.calibrate_copy:
@@ -300,6 +370,7 @@ def main():
         print(f"# cpu oracle: {cpu}", file=sys.stderr, flush=True)
 
     batched = batched_leg(args, rl, torch, oracle) if args.batch > 0 else None
+    serving = serving_leg(args, rl, torch, oracle) if args.serve_requests > 0 else None
 
     out = {
         "metric": METRIC,
@@ -329,6 +400,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched": batched,
+        "serving": serving,
     }
     s.close()
     print(json.dumps(out), flush=True)

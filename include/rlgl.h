@@ -41,7 +41,8 @@ typedef enum {
   RLGL_EHIP = -3,            /* a HIP runtime call failed */
   RLGL_EZERO_HISTORY = -4,   /* |H_t 1| <= 1e-300 or <= 1e-12 ||H_t||_1: the "restart" case of Sec. 2.1 / Example 1 */
   RLGL_ENOT_CONVERGED = -5,  /* max_steps reached before the stop test; pi is still written */
-  RLGL_ENONFINITE = -6       /* ||C_t||_1 or H_t 1 is not finite */
+  RLGL_ENONFINITE = -6,      /* ||C_t||_1 or H_t 1 is not finite */
+  RLGL_EBUSY = -7            /* pool: no free slot or arena block right now, or the chain has not finished */
 } rlgl_status;
 
 /* Green-light rules (Sec. 6, "cash-dependent heuristics"; G_t is chosen from
@@ -284,6 +285,91 @@ rlgl_status rlgl_batch_solve(rlgl_batch *b, double *dev_pi, rlgl_chain_result *r
 rlgl_status rlgl_batch_autotune(rlgl_batch *b, double *dev_pi, rlgl_batch_options *best);
 
 void rlgl_batch_destroy(rlgl_batch *b);
+
+/* ---- serving pool -------------------------------------------------------
+ *
+ * Continuous batching of independent solves.  A pool owns a device arena (a
+ * part of the caller's workspace) in which admitted chains stay resident:
+ * their CSC, row pointers, plan, cash, history and pi_hat.  rlgl_pool_admit
+ * takes a chain held in host memory, reserves its footprint in the arena
+ * (first fit) and enqueues its upload on a copy stream of the pool's own; a
+ * chain joins the step-synchronous iteration of the other resident chains
+ * at the first rlgl_pool_advance after its upload has landed, so requests
+ * that arrive while others run are admitted as slots and memory free up,
+ * and their steps share launches with the others'.  The method, the readings
+ * and the stop test are those of the lockstep batch engine; link weights are
+ * implicit (1/outdeg, FP64).  Calls on one pool must not overlap. */
+typedef struct rlgl_pool rlgl_pool;
+
+typedef struct {
+  int32_t sched;              /* RLGL_SCHED_ALL, _THRESHOLD or _MAXC */
+  double r;                   /* threshold power-mean order, >= 1 */
+  int32_t precision;          /* rlgl_precision */
+  int32_t refresh;            /* confirm the stop on the cash rebuilt from the history (0/1) */
+  int32_t wg_size;            /* threads per route workgroup: 256 or 512 */
+  int32_t max_chains;         /* slots: chains resident at once, >= 1 */
+  int64_t max_steps;          /* per chain */
+} rlgl_pool_options;
+
+/* One request: a chain of the form of rlgl_graph (damping c, uniform restart,
+ * dangling rows uniform, weights 1/outdeg) held in HOST memory.  Page-locked
+ * memory makes the upload asynchronous.  The arrays must stay valid until
+ * the chain's result has been reported by rlgl_pool_poll or the slot has been
+ * released. */
+typedef struct {
+  int32_t n;                  /* >= 1 */
+  int64_t nnz;                /* < 2^31 */
+  const int32_t *csr_rowptr;  /* host [n+1], 0 .. nnz, non-decreasing: the out-degrees */
+  const int32_t *csc_colptr;  /* host [n+1], 0 .. nnz, non-decreasing */
+  const int32_t *csc_row;     /* host [nnz], local source ids (NULL allowed when nnz = 0) */
+  double damping;             /* c in (0, 1] */
+  double tol_l1;              /* stop at ||C_t||_1 / |H_t 1| < tol_l1 (1 - c), which bounds the L1 error of
+                                 pi_hat by tol_l1 (Lemma 1); >= 0 */
+} rlgl_request;
+
+/* Defaults: THRESHOLD, r = 1, FP32C_KAHANH, refresh = 1, wg_size = 256,
+ * max_chains = 256, max_steps = 100000. */
+void rlgl_pool_default_options(rlgl_pool_options *opt);
+
+/* Workspace for a pool whose arena holds arena_bytes (control records of
+ * max_chains slots added); 0 on bad options. */
+size_t rlgl_pool_workspace_bytes(const rlgl_pool_options *opt, size_t arena_bytes);
+
+/* Arena bytes one resident chain of n states and nnz links takes (upper
+ * bound; the plan's exact size is known at admission). */
+size_t rlgl_pool_footprint(const rlgl_pool_options *opt, int32_t n, int64_t nnz);
+
+/* The arena is what is left of the workspace after the control records. */
+rlgl_status rlgl_pool_create(const rlgl_pool_options *opt, void *dev_workspace, size_t ws_bytes, void *stream,
+                             rlgl_pool **out);
+
+/* Checks the request, builds its plan on the host, reserves its footprint and
+ * enqueues its upload.  *slot receives the chain's slot.  RLGL_EBUSY when no
+ * slot or no arena block is free now (nothing was changed). */
+rlgl_status rlgl_pool_admit(rlgl_pool *p, const rlgl_request *req, int32_t *slot);
+
+/* Starts the chains whose upload has landed, runs `iterations` lockstep
+ * iterations (one step of every running chain each, at most) on the pool's
+ * stream, waits for them, and collects the chains that finished.
+ * *running (may be NULL) receives the number of chains still uploading or
+ * running. */
+rlgl_status rlgl_pool_advance(rlgl_pool *p, int32_t iterations, int32_t *running);
+
+/* Writes up to max_slots slots of chains finished since the last call into
+ * slots (host) and returns their number (or a negative rlgl_status). */
+int32_t rlgl_pool_poll(rlgl_pool *p, int32_t *slots, int32_t max_slots);
+
+/* Outcome of a finished chain and its pi_hat (device, n doubles, valid until
+ * the slot is released).  start_us/end_us are device wall-clock times since
+ * the pool was created.  RLGL_EBUSY while the chain runs. */
+rlgl_status rlgl_pool_result(rlgl_pool *p, int32_t slot, rlgl_chain_result *result, const double **dev_pi);
+
+/* Frees a finished chain's slot and arena block.  RLGL_EBUSY while the chain
+ * is uploading or running. */
+rlgl_status rlgl_pool_release(rlgl_pool *p, int32_t slot);
+
+/* Waits for the pool's work and frees its host resources. */
+void rlgl_pool_destroy(rlgl_pool *p);
 
 #ifdef __cplusplus
 }

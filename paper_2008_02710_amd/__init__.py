@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librlgl.so")
 
 RLGL_OK, RLGL_EINVAL, RLGL_ENOMEM, RLGL_EHIP = 0, -1, -2, -3
-RLGL_EZERO_HISTORY, RLGL_ENOT_CONVERGED, RLGL_ENONFINITE = -4, -5, -6
+RLGL_EZERO_HISTORY, RLGL_ENOT_CONVERGED, RLGL_ENONFINITE, RLGL_EBUSY = -4, -5, -6, -7
 SCHED_ALL, SCHED_THRESHOLD, SCHED_TOPK, SCHED_MAXC = 0, 1, 2, 3
 FP64, FP32C_FP64H, FP32C_KAHANH = 0, 1, 2
 ROUTE_PUSH, ROUTE_PULL, ROUTE_AUTO = 0, 1, 2
@@ -81,11 +81,26 @@ class rlgl_chain_result(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class rlgl_pool_options(ctypes.Structure):
+    _fields_ = [("sched", ctypes.c_int32), ("r", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("refresh", ctypes.c_int32), ("wg_size", ctypes.c_int32), ("max_chains", ctypes.c_int32),
+                ("max_steps", ctypes.c_int64)]
+
+
+class rlgl_request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("csr_rowptr", ctypes.c_void_p),
+                ("csc_colptr", ctypes.c_void_p), ("csc_row", ctypes.c_void_p), ("damping", ctypes.c_double),
+                ("tol_l1", ctypes.c_double)]
+
+
 EXPORTED = ["rlgl_default_options", "rlgl_workspace_bytes", "rlgl_create", "rlgl_step", "rlgl_solve",
             "rlgl_destroy", "rlgl_last_error", "rlgl_reset", "rlgl_get_state", "rlgl_set_state",
             "rlgl_get_green", "rlgl_refresh", "rlgl_profile_enable", "rlgl_profile_read",
             "rlgl_batch_default_options", "rlgl_batch_workspace_bytes", "rlgl_batch_create", "rlgl_batch_solve",
-            "rlgl_batch_autotune", "rlgl_batch_destroy"]
+            "rlgl_batch_autotune", "rlgl_batch_destroy",
+            "rlgl_pool_default_options", "rlgl_pool_workspace_bytes", "rlgl_pool_footprint", "rlgl_pool_create",
+            "rlgl_pool_admit", "rlgl_pool_advance", "rlgl_pool_poll", "rlgl_pool_result", "rlgl_pool_release",
+            "rlgl_pool_destroy"]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -135,6 +150,27 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rlgl_batch_autotune.restype = i32
     lib.rlgl_batch_destroy.argtypes = [vp]
     lib.rlgl_batch_destroy.restype = None
+    PO, RQ = ctypes.POINTER(rlgl_pool_options), ctypes.POINTER(rlgl_request)
+    lib.rlgl_pool_default_options.argtypes = [PO]
+    lib.rlgl_pool_default_options.restype = None
+    lib.rlgl_pool_workspace_bytes.argtypes = [PO, ctypes.c_size_t]
+    lib.rlgl_pool_workspace_bytes.restype = ctypes.c_size_t
+    lib.rlgl_pool_footprint.argtypes = [PO, i32, i64]
+    lib.rlgl_pool_footprint.restype = ctypes.c_size_t
+    lib.rlgl_pool_create.argtypes = [PO, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    lib.rlgl_pool_create.restype = i32
+    lib.rlgl_pool_admit.argtypes = [vp, RQ, ctypes.POINTER(i32)]
+    lib.rlgl_pool_admit.restype = i32
+    lib.rlgl_pool_advance.argtypes = [vp, i32, ctypes.POINTER(i32)]
+    lib.rlgl_pool_advance.restype = i32
+    lib.rlgl_pool_poll.argtypes = [vp, ctypes.POINTER(i32), i32]
+    lib.rlgl_pool_poll.restype = i32
+    lib.rlgl_pool_result.argtypes = [vp, i32, ctypes.POINTER(rlgl_chain_result), ctypes.POINTER(vp)]
+    lib.rlgl_pool_result.restype = i32
+    lib.rlgl_pool_release.argtypes = [vp, i32]
+    lib.rlgl_pool_release.restype = i32
+    lib.rlgl_pool_destroy.argtypes = [vp]
+    lib.rlgl_pool_destroy.restype = None
     return lib
 
 
@@ -278,6 +314,68 @@ def rlgl_batch_autotune(handle, pi_out) -> rlgl_batch_options:
 
 def rlgl_batch_destroy(handle) -> None:
     _lib.rlgl_batch_destroy(handle)
+
+
+def rlgl_pool_default_options(**overrides) -> rlgl_pool_options:
+    o = rlgl_pool_options()
+    _lib.rlgl_pool_default_options(ctypes.byref(o))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def rlgl_pool_workspace_bytes(opt: rlgl_pool_options, arena_bytes: int) -> int:
+    return int(_lib.rlgl_pool_workspace_bytes(ctypes.byref(opt), int(arena_bytes)))
+
+
+def rlgl_pool_footprint(opt: rlgl_pool_options, n: int, nnz: int) -> int:
+    return int(_lib.rlgl_pool_footprint(ctypes.byref(opt), int(n), int(nnz)))
+
+
+def rlgl_pool_create(opt: rlgl_pool_options, workspace, ws_bytes: int, stream=None):
+    h = ctypes.c_void_p()
+    _check(_lib.rlgl_pool_create(ctypes.byref(opt), _ptr(workspace), int(ws_bytes), _stream_handle(stream),
+                                 ctypes.byref(h)), "rlgl_pool_create")
+    return h
+
+
+def rlgl_pool_admit(handle, req: rlgl_request):
+    """Slot of the admitted chain, or None when the pool is full right now."""
+    slot = ctypes.c_int32(-1)
+    st = _lib.rlgl_pool_admit(handle, ctypes.byref(req), ctypes.byref(slot))
+    if st == RLGL_EBUSY:
+        return None
+    _check(st, "rlgl_pool_admit")
+    return slot.value
+
+
+def rlgl_pool_advance(handle, iterations: int) -> int:
+    running = ctypes.c_int32(0)
+    _check(_lib.rlgl_pool_advance(handle, int(iterations), ctypes.byref(running)), "rlgl_pool_advance")
+    return running.value
+
+
+def rlgl_pool_poll(handle, max_slots: int = 1024):
+    buf = (ctypes.c_int32 * max_slots)()
+    m = _lib.rlgl_pool_poll(handle, buf, max_slots)
+    if m < 0:
+        raise RlglError(m, "rlgl_pool_poll")
+    return [buf[i] for i in range(m)]
+
+
+def rlgl_pool_result(handle, slot: int):
+    r = rlgl_chain_result()
+    ptr = ctypes.c_void_p()
+    _check(_lib.rlgl_pool_result(handle, int(slot), ctypes.byref(r), ctypes.byref(ptr)), "rlgl_pool_result")
+    return r.as_dict(), ptr.value
+
+
+def rlgl_pool_release(handle, slot: int) -> None:
+    _check(_lib.rlgl_pool_release(handle, int(slot)), "rlgl_pool_release")
+
+
+def rlgl_pool_destroy(handle) -> None:
+    _lib.rlgl_pool_destroy(handle)
 
 
 def _stream_handle(stream):
@@ -468,6 +566,82 @@ class BatchSolver:
     def close(self):
         if self.handle is not None:
             rlgl_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class HostChain:
+    """A request held in page-locked host memory: CSR row pointers (the
+    out-degrees), the CSC and the damping, as ``rlgl_request`` wants them."""
+
+    def __init__(self, g, tol_l1: float = 1e-6):
+        import numpy as np
+        colptr, row, _ = g.csc()
+        self.n, self.nnz, self.c, self.tol_l1, self.name = g.n, g.nnz, float(g.c), float(tol_l1), g.name
+
+        def pinned(a):
+            t = torch.empty(len(a), dtype=torch.int32, pin_memory=True)
+            t.numpy()[:] = np.asarray(a, dtype=np.int32)
+            return t
+
+        self.rowptr = pinned(g.rowptr)
+        self.colptr = pinned(colptr)
+        self.row = pinned(row) if self.nnz > 0 else None
+
+    def request(self) -> rlgl_request:
+        return rlgl_request(self.n, self.nnz, self.rowptr.data_ptr(), self.colptr.data_ptr(),
+                            None if self.row is None else self.row.data_ptr(), self.c, self.tol_l1)
+
+
+class Pool:
+    """A serving pool: workspace tensor (control records + arena) and handle."""
+
+    def __init__(self, arena_bytes: int, stream=None, device="cuda", **options):
+        self.opt = rlgl_pool_default_options(**options)
+        self.ws_bytes = rlgl_pool_workspace_bytes(self.opt, arena_bytes)
+        if self.ws_bytes == 0:
+            raise RlglError(RLGL_EINVAL, "rlgl_pool_workspace_bytes")
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.handle = rlgl_pool_create(self.opt, self.workspace, self.ws_bytes, stream)
+        self.requests = {}
+
+    def footprint(self, n: int, nnz: int) -> int:
+        return rlgl_pool_footprint(self.opt, n, nnz)
+
+    def admit(self, hc: HostChain):
+        """Slot of the admitted chain, or None when no slot or memory is free."""
+        req = hc.request()
+        slot = rlgl_pool_admit(self.handle, req)
+        if slot is not None:
+            self.requests[slot] = hc  # keeps the host arrays alive until release
+        return slot
+
+    def advance(self, iterations: int = 4) -> int:
+        return rlgl_pool_advance(self.handle, iterations)
+
+    def poll(self):
+        return rlgl_pool_poll(self.handle)
+
+    def result(self, slot: int):
+        """(outcome dict, pi_hat as a float64 view into the workspace)."""
+        res, ptr = rlgl_pool_result(self.handle, slot)
+        n = self.requests[slot].n
+        off = ptr - self.workspace.data_ptr()
+        pi = self.workspace[off:off + 8 * n].view(torch.float64)
+        return res, pi
+
+    def release(self, slot: int) -> None:
+        rlgl_pool_release(self.handle, slot)
+        self.requests.pop(slot, None)
+
+    def close(self):
+        if self.handle is not None:
+            rlgl_pool_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

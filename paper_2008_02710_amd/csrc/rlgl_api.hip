@@ -1333,3 +1333,374 @@ void rlgl_batch_destroy(rlgl_batch *b) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------- serving pool
+
+namespace {
+
+enum { SLOT_FREE = 0, SLOT_UPLOADING = 1, SLOT_RUNNING = 2, SLOT_FINISHED = 3 };
+
+struct PoolSlot {
+  int state = SLOT_FREE;
+  size_t off = 0, bytes = 0;  // arena block
+  hipEvent_t ready = nullptr;
+  int4 *stage = nullptr;      // page-locked copy of the plan for the upload
+  size_t stage_cap = 0;
+  LsChain desc{};
+};
+
+// Arena bytes of a chain: row and column pointers, CSC sources, plan, two
+// cash buffers, the scaled source buffer, the history and pi_hat.
+size_t pool_chain_bytes(int prec, long long n, long long nnz, size_t n_items) {
+  const size_t cs = (prec == RLGL_FP64) ? 8 : 4;
+  size_t b = 0;
+  b += align_up(4 * (size_t)(n + 1), 256) * 2;
+  b += align_up(4 * (size_t)nnz, 256);
+  b += align_up(sizeof(int4) * n_items, 256);
+  b += align_up(cs * (size_t)n, 256) * 3;
+  b += align_up(8 * (size_t)n, 256);  // double, or the float hi part
+  if (prec == RLGL_FP32C_KAHANH) b += align_up(4 * (size_t)n, 256);
+  b += align_up(8 * (size_t)n, 256);
+  return b;
+}
+
+bool valid_pool_options(const rlgl_pool_options *o, std::string &why) {
+  if (!o) { why = "null options"; return false; }
+  if (o->sched != RLGL_SCHED_ALL && o->sched != RLGL_SCHED_THRESHOLD && o->sched != RLGL_SCHED_MAXC) {
+    why = "the pool supports the ALL, THRESHOLD and MAXC schedules";
+    return false;
+  }
+  if (!(o->r >= 1.0) || !std::isfinite(o->r)) { why = "r must be >= 1"; return false; }
+  if (o->precision < 0 || o->precision > 2) { why = "precision out of range"; return false; }
+  if (o->wg_size != 256 && o->wg_size != 512) { why = "wg_size must be 256 or 512"; return false; }
+  if (o->max_chains < 1 || o->max_chains > (1 << 20)) { why = "max_chains out of range"; return false; }
+  if (o->max_steps < 0) { why = "max_steps must be >= 0"; return false; }
+  return true;
+}
+
+}  // namespace
+
+struct rlgl_pool {
+  rlgl_pool_options opt;
+  hipStream_t stream = nullptr, copy = nullptr;
+  LsEngine E;
+  char *arena = nullptr;
+  size_t arena_bytes = 0;
+  std::vector<std::pair<size_t, size_t>> free_list;  // (offset, bytes), sorted, coalesced
+  std::vector<PoolSlot> slots;
+  std::vector<int> running;   // slots in the active list, admission order
+  std::vector<int> finished;  // finished since the last poll
+  bool dirty = false;
+  long long t_origin = 0;
+  double clock_khz = 100000.0;
+};
+
+namespace {
+
+bool arena_take(rlgl_pool *p, size_t bytes, size_t &off) {
+  for (size_t q = 0; q < p->free_list.size(); ++q) {
+    auto &f = p->free_list[q];
+    if (f.second >= bytes) {
+      off = f.first;
+      f.first += bytes;
+      f.second -= bytes;
+      if (f.second == 0) p->free_list.erase(p->free_list.begin() + (long)q);
+      return true;
+    }
+  }
+  return false;
+}
+
+void arena_give(rlgl_pool *p, size_t off, size_t bytes) {
+  auto &fl = p->free_list;
+  auto it = std::lower_bound(fl.begin(), fl.end(), std::make_pair(off, (size_t)0));
+  it = fl.insert(it, {off, bytes});
+  // coalesce with the next and the previous block
+  if (it + 1 != fl.end() && it->first + it->second == (it + 1)->first) {
+    it->second += (it + 1)->second;
+    fl.erase(it + 1);
+  }
+  if (it != fl.begin() && (it - 1)->first + (it - 1)->second == it->first) {
+    (it - 1)->second += it->second;
+    fl.erase(it);
+  }
+}
+
+__global__ void k_wall_clock(long long *out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *out = wall_clock64();
+}
+
+}  // namespace
+
+extern "C" {
+
+void rlgl_pool_default_options(rlgl_pool_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->sched = RLGL_SCHED_THRESHOLD;
+  o->r = 1.0;
+  o->precision = RLGL_FP32C_KAHANH;
+  o->refresh = 1;
+  o->wg_size = 256;
+  o->max_chains = 256;
+  o->max_steps = 100000;
+}
+
+size_t rlgl_pool_workspace_bytes(const rlgl_pool_options *o, size_t arena_bytes) {
+  std::string why;
+  if (!valid_pool_options(o, why)) return 0;
+  return ls_device_bytes(o->max_chains) + align_up(arena_bytes, 256) + 512;
+}
+
+size_t rlgl_pool_footprint(const rlgl_pool_options *o, int32_t n, int64_t nnz) {
+  std::string why;
+  if (!valid_pool_options(o, why) || n < 1 || nnz < 0) return 0;
+  return pool_chain_bytes(o->precision, n, nnz, batch_item_bound(n, nnz));
+}
+
+rlgl_status rlgl_pool_create(const rlgl_pool_options *o, void *ws, size_t ws_bytes, void *stream, rlgl_pool **out) {
+  if (!out) return fail(RLGL_EINVAL, "null argument");
+  *out = nullptr;
+  std::string why;
+  if (!valid_pool_options(o, why)) return fail(RLGL_EINVAL, "%s", why.c_str());
+  if (!ws) return fail(RLGL_EINVAL, "workspace is NULL");
+  const size_t ctl = ls_device_bytes(o->max_chains);
+  if (ws_bytes < ctl + 512 + 256) return fail(RLGL_ENOMEM, "workspace too small for the pool's control records");
+  rlgl_pool *p = new (std::nothrow) rlgl_pool();
+  if (!p) return fail(RLGL_ENOMEM, "host allocation failed");
+  auto bail = [&](rlgl_status s) {
+    rlgl_pool_destroy(p);
+    return s;
+  };
+  p->opt = *o;
+  p->stream = (hipStream_t)stream;
+  char *w = (char *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+  const size_t lead = (size_t)(w - (char *)ws);
+  rlgl_status st = ls_init(p->E, w, o->max_chains, o->precision, o->sched, o->r, o->refresh, p->stream);
+  if (st != RLGL_OK) return bail(st);
+  p->E.nt = o->wg_size;
+  p->arena = w + ctl;
+  p->arena_bytes = (ws_bytes - lead - ctl) / 256 * 256;
+  p->free_list.push_back({0, p->arena_bytes});
+  p->slots.resize((size_t)o->max_chains);
+  if (hipStreamCreateWithFlags(&p->copy, hipStreamNonBlocking) != hipSuccess)
+    return bail(fail(RLGL_EHIP, "creating the upload stream failed"));
+  for (PoolSlot &s : p->slots)
+    if (hipEventCreateWithFlags(&s.ready, hipEventDisableTiming) != hipSuccess)
+      return bail(fail(RLGL_EHIP, "event creation failed"));
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev))
+    return bail(fail(RLGL_EHIP, "device attribute query failed"));
+  p->clock_khz = khz > 0 ? khz : 100000.0;
+  // device wall clock at creation: the origin of start_us / end_us
+  long long *origin = (long long *)(p->E.args.done) + 8;
+  k_wall_clock<<<1, 64, 0, p->stream>>>(origin);
+  if (hipMemcpyAsync(&p->t_origin, origin, sizeof(long long), hipMemcpyDeviceToHost, p->stream) != hipSuccess ||
+      hipStreamSynchronize(p->stream) != hipSuccess)
+    return bail(fail(RLGL_EHIP, "reading the device clock failed"));
+  *out = p;
+  return RLGL_OK;
+}
+
+rlgl_status rlgl_pool_admit(rlgl_pool *p, const rlgl_request *q, int32_t *slot) {
+  if (!p || !q || !slot) return fail(RLGL_EINVAL, "null argument");
+  const long long n = q->n, m = q->nnz;
+  if (n < 1 || m < 0 || m >= (1ll << 31)) return fail(RLGL_EINVAL, "request sizes out of range");
+  if (!q->csr_rowptr || !q->csc_colptr || (m > 0 && !q->csc_row)) return fail(RLGL_EINVAL, "request arrays are NULL");
+  if (!(q->damping > 0.0 && q->damping <= 1.0)) return fail(RLGL_EINVAL, "damping out of (0,1]");
+  if (!(q->tol_l1 >= 0.0)) return fail(RLGL_EINVAL, "tol_l1 must be >= 0");
+  const int32_t *rp = q->csr_rowptr;
+  if (rp[0] != 0 || rp[n] != m) return fail(RLGL_EINVAL, "csr_rowptr must run from 0 to nnz");
+  for (long long i = 0; i < n; ++i)
+    if (rp[i + 1] < rp[i]) return fail(RLGL_EINVAL, "csr_rowptr decreases at %lld", i);
+  int k = -1;
+  for (int s = 0; s < (int)p->slots.size(); ++s)
+    if (p->slots[s].state == SLOT_FREE) {
+      k = s;
+      break;
+    }
+  if (k < 0) return fail(RLGL_EBUSY, "no free slot");
+  PoolSlot &S = p->slots[k];
+  // the plan is built into the slot's page-locked staging buffer
+  std::vector<int4> items;
+  items.reserve(batch_item_bound(n, m));
+  int nw = 0, nr = 0;
+  std::string why;
+  if (!chain_plan(q->csc_colptr, (int)n, (int)m, items, nw, nr, why)) return fail(RLGL_EINVAL, "%s", why.c_str());
+  const int prec = p->opt.precision;
+  const size_t bytes = pool_chain_bytes(prec, n, m, items.size());
+  size_t off = 0;
+  if (!arena_take(p, bytes, off)) return fail(RLGL_EBUSY, "no arena block of %zu bytes free", bytes);
+  if (S.stage_cap < items.size()) {
+    if (S.stage) (void)hipHostFree(S.stage);
+    S.stage = nullptr;
+    S.stage_cap = 0;
+    const size_t cap = std::max(items.size(), (size_t)1024);
+    if (hipHostMalloc((void **)&S.stage, sizeof(int4) * cap, hipHostMallocDefault) != hipSuccess) {
+      arena_give(p, off, bytes);
+      return fail(RLGL_ENOMEM, "page-locked staging allocation failed");
+    }
+    S.stage_cap = cap;
+  }
+  std::copy(items.begin(), items.end(), S.stage);
+  char *base = p->arena + off;
+  size_t at = 0;
+  auto take = [&](size_t b) {
+    char *r = base + at;
+    at += align_up(b, 256);
+    return r;
+  };
+  const size_t cs = (prec == RLGL_FP64) ? 8 : 4;
+  const bool hk = prec == RLGL_FP32C_KAHANH;
+  LsChain &d = S.desc;
+  d = LsChain{};
+  int *d_rowptr = (int *)take(4 * (size_t)(n + 1));
+  int *d_colptr = (int *)take(4 * (size_t)(n + 1));
+  int *d_crow = (int *)take(4 * (size_t)m);
+  int4 *d_items = (int4 *)take(sizeof(int4) * items.size());
+  d.rowptr = d_rowptr;
+  d.colptr = d_colptr;
+  d.crow = d_crow;
+  d.items = d_items;
+  d.cash0 = take(cs * (size_t)n);
+  d.cash1 = take(cs * (size_t)n);
+  d.src = take(cs * (size_t)n);
+  d.hist = take(8 * (size_t)n);
+  d.hist_lo = hk ? (float *)take(4 * (size_t)n) : nullptr;
+  d.pi = (double *)take(8 * (size_t)n);
+  d.nnz = m;
+  d.max_steps = p->opt.max_steps;
+  d.c = q->damping;
+  d.eps = q->tol_l1 * (1.0 - q->damping);
+  d.n = (int)n;
+  d.n_whole = nw;
+  d.n_run = nr;
+  hipError_t e = hipMemcpyAsync(d_rowptr, q->csr_rowptr, 4 * (size_t)(n + 1), hipMemcpyHostToDevice, p->copy);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_colptr, q->csc_colptr, 4 * (size_t)(n + 1), hipMemcpyHostToDevice, p->copy);
+  if (e == hipSuccess && m > 0) e = hipMemcpyAsync(d_crow, q->csc_row, 4 * (size_t)m, hipMemcpyHostToDevice, p->copy);
+  if (e == hipSuccess && !items.empty())
+    e = hipMemcpyAsync(d_items, S.stage, sizeof(int4) * items.size(), hipMemcpyHostToDevice, p->copy);
+  if (e == hipSuccess) e = hipEventRecord(S.ready, p->copy);
+  if (e != hipSuccess) {
+    // let whatever was enqueued finish before the block can be reused
+    (void)hipStreamSynchronize(p->copy);
+    arena_give(p, off, bytes);
+    return fail(RLGL_EHIP, "request upload: %s", hipGetErrorString(e));
+  }
+  S.off = off;
+  S.bytes = bytes;
+  S.state = SLOT_UPLOADING;
+  *slot = k;
+  return RLGL_OK;
+}
+
+rlgl_status rlgl_pool_advance(rlgl_pool *p, int32_t iterations, int32_t *running) {
+  if (!p || iterations < 0) return fail(RLGL_EINVAL, "bad argument");
+  // start the chains whose upload has landed
+  for (int k = 0; k < (int)p->slots.size(); ++k) {
+    PoolSlot &S = p->slots[k];
+    if (S.state != SLOT_UPLOADING) continue;
+    const hipError_t q = hipEventQuery(S.ready);
+    if (q == hipErrorNotReady) continue;
+    if (q != hipSuccess) return fail(RLGL_EHIP, "upload of slot %d: %s", k, hipGetErrorString(q));
+    p->E.host[k] = S.desc;
+    k_ls_admit<<<1, 64, 0, p->stream>>>(p->E.d_chains, p->E.args.ctl, p->E.args.stats, k, S.desc);
+    S.state = SLOT_RUNNING;
+    p->running.push_back(k);
+    p->dirty = true;
+  }
+  HIP_TRY(hipGetLastError());
+  if (p->dirty) {
+    rlgl_status st = ls_set_active(p->E, p->running);
+    if (st != RLGL_OK) return st;
+    p->dirty = false;
+  }
+  if (!p->running.empty() && iterations > 0) {
+    rlgl_status st = ls_iterate(p->E, iterations);
+    if (st != RLGL_OK) return st;
+    HIP_TRY(hipMemcpyAsync(p->E.h_ctl, p->E.args.ctl, sizeof(LsCtl) * p->slots.size(), hipMemcpyDeviceToHost,
+                           p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    std::vector<int> keep;
+    keep.reserve(p->running.size());
+    for (int k : p->running) {
+      if (p->E.h_ctl[k].mode == LS_DONE) {
+        p->slots[k].state = SLOT_FINISHED;
+        p->finished.push_back(k);
+      } else {
+        keep.push_back(k);
+      }
+    }
+    if (keep.size() != p->running.size()) {
+      p->running.swap(keep);
+      p->dirty = true;
+    }
+  }
+  if (running) {
+    int c = 0;
+    for (const PoolSlot &S : p->slots) c += (S.state == SLOT_UPLOADING || S.state == SLOT_RUNNING);
+    *running = c;
+  }
+  return RLGL_OK;
+}
+
+int32_t rlgl_pool_poll(rlgl_pool *p, int32_t *slots, int32_t max_slots) {
+  if (!p || (max_slots > 0 && !slots) || max_slots < 0) return fail(RLGL_EINVAL, "bad argument");
+  const int m = std::min((int)p->finished.size(), (int)max_slots);
+  for (int i = 0; i < m; ++i) slots[i] = p->finished[i];
+  p->finished.erase(p->finished.begin(), p->finished.begin() + m);
+  return m;
+}
+
+rlgl_status rlgl_pool_result(rlgl_pool *p, int32_t slot, rlgl_chain_result *r, const double **dev_pi) {
+  if (!p || slot < 0 || slot >= (int)p->slots.size()) return fail(RLGL_EINVAL, "bad slot");
+  const PoolSlot &S = p->slots[slot];
+  if (S.state == SLOT_FREE) return fail(RLGL_EINVAL, "slot %d holds no chain", slot);
+  if (S.state != SLOT_FINISHED) return fail(RLGL_EBUSY, "slot %d has not finished", slot);
+  const LsCtl &c = p->E.h_ctl[slot];
+  if (r) {
+    const double us = 1000.0 / p->clock_khz;
+    r->t = c.t;
+    r->edges_pushed = c.edges;
+    r->resid = c.resid;
+    r->h_sum = c.hsum;
+    r->status = c.status == ST_CONVERGED ? RLGL_OK : status_of(c.status);
+    r->green_steps = c.green_steps;
+    r->start_us = (double)(c.t0 - p->t_origin) * us;
+    r->end_us = (double)(c.t1 - p->t_origin) * us;
+  }
+  if (dev_pi) *dev_pi = S.desc.pi;
+  return RLGL_OK;
+}
+
+rlgl_status rlgl_pool_release(rlgl_pool *p, int32_t slot) {
+  if (!p || slot < 0 || slot >= (int)p->slots.size()) return fail(RLGL_EINVAL, "bad slot");
+  PoolSlot &S = p->slots[slot];
+  if (S.state == SLOT_FREE) return fail(RLGL_EINVAL, "slot %d holds no chain", slot);
+  if (S.state != SLOT_FINISHED) return fail(RLGL_EBUSY, "slot %d is still uploading or running", slot);
+  p->finished.erase(std::remove(p->finished.begin(), p->finished.end(), slot), p->finished.end());
+  // the chain's kernels have all completed (it finished before the last
+  // synchronisation of the pool's stream), so the block can be reused
+  arena_give(p, S.off, S.bytes);
+  S.state = SLOT_FREE;
+  S.off = S.bytes = 0;
+  return RLGL_OK;
+}
+
+void rlgl_pool_destroy(rlgl_pool *p) {
+  if (!p) return;
+  if (p->copy) {
+    (void)hipStreamSynchronize(p->copy);
+  }
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  for (PoolSlot &S : p->slots) {
+    if (S.ready) (void)hipEventDestroy(S.ready);
+    if (S.stage) (void)hipHostFree(S.stage);
+  }
+  if (p->copy) (void)hipStreamDestroy(p->copy);
+  ls_free(p->E);
+  delete p;
+}
+
+}  // extern "C"

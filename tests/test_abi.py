@@ -46,9 +46,12 @@ def test_struct_sizes_match_header():
     exe = os.path.join(ROOT, "_sizes_probe")
     open(src, "w").write(
         '#include <stdio.h>\n#include <stddef.h>\n#include "rlgl.h"\n'
-        'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(rlgl_graph), sizeof(rlgl_options),'
-        ' sizeof(rlgl_step_info), sizeof(rlgl_kernel_stat), offsetof(rlgl_options, record_green),'
-        ' offsetof(rlgl_step_info, last_route));return 0;}\n')
+        'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(rlgl_graph),'
+        ' sizeof(rlgl_options), sizeof(rlgl_step_info), sizeof(rlgl_kernel_stat),'
+        ' offsetof(rlgl_options, record_green), offsetof(rlgl_step_info, last_route),'
+        ' sizeof(rlgl_batch_graphs), sizeof(rlgl_batch_options), offsetof(rlgl_batch_options, check_period),'
+        ' sizeof(rlgl_chain_result), sizeof(rlgl_pool_options), sizeof(rlgl_request),'
+        ' offsetof(rlgl_request, tol_l1));return 0;}\n')
     try:
         import subprocess
         subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", exe, src])
@@ -59,7 +62,10 @@ def test_struct_sizes_match_header():
                 os.remove(p)
     got = [ctypes.sizeof(rl.rlgl_graph), ctypes.sizeof(rl.rlgl_options), ctypes.sizeof(rl.rlgl_step_info),
            ctypes.sizeof(rl.rlgl_kernel_stat), rl.rlgl_options.record_green.offset,
-           rl.rlgl_step_info.last_route.offset]
+           rl.rlgl_step_info.last_route.offset, ctypes.sizeof(rl.rlgl_batch_graphs),
+           ctypes.sizeof(rl.rlgl_batch_options), rl.rlgl_batch_options.check_period.offset,
+           ctypes.sizeof(rl.rlgl_chain_result), ctypes.sizeof(rl.rlgl_pool_options), ctypes.sizeof(rl.rlgl_request),
+           rl.rlgl_request.tol_l1.offset]
     assert [int(x) for x in out] == got
 
 
@@ -89,3 +95,31 @@ def test_host_side_argument_checks():
     o = rl.rlgl_default_options(route=rl.ROUTE_PULL)
     assert lib.rlgl_create(ctypes.byref(g), ctypes.byref(o), 4096, 1 << 30, None, ctypes.byref(ctx)) == rl.RLGL_EINVAL
     assert ctx.value is None
+
+
+def test_pool_host_side_checks():
+    import paper_2008_02710_amd as rl
+    lib = rl._lib
+    o = rl.rlgl_pool_default_options()
+    assert o.sched == rl.SCHED_THRESHOLD and o.precision == rl.FP32C_KAHANH and o.max_chains == 256
+    ws = rl.rlgl_pool_workspace_bytes(o, 1 << 30)
+    assert ws >= 1 << 30
+    # footprints grow with the chain and bound its arrays
+    f1, f2 = rl.rlgl_pool_footprint(o, 1000, 10000), rl.rlgl_pool_footprint(o, 100000, 1000000)
+    assert 0 < f1 < f2 and f2 >= 4 * 1000000 + 32 * 100000
+    assert rl.rlgl_pool_footprint(o, 0, 0) == 0
+    for field, value in (("sched", rl.SCHED_TOPK), ("r", 0.5), ("precision", 5), ("wg_size", 128),
+                         ("max_chains", 0), ("max_steps", -1)):
+        bad = rl.rlgl_pool_default_options(**{field: value})
+        assert rl.rlgl_pool_workspace_bytes(bad, 1 << 20) == 0, field
+        h = ctypes.c_void_p()
+        assert lib.rlgl_pool_create(ctypes.byref(bad), 4096, 1 << 30, None, ctypes.byref(h)) == rl.RLGL_EINVAL
+    h = ctypes.c_void_p()
+    assert lib.rlgl_pool_create(ctypes.byref(o), None, 1 << 30, None, ctypes.byref(h)) == rl.RLGL_EINVAL
+    assert lib.rlgl_pool_create(ctypes.byref(o), 4096, 1024, None, ctypes.byref(h)) == rl.RLGL_ENOMEM
+    assert h.value is None
+    slot = ctypes.c_int32(-1)
+    req = rl.rlgl_request(10, 0, None, None, None, 0.85, 1e-6)
+    assert lib.rlgl_pool_admit(None, ctypes.byref(req), ctypes.byref(slot)) == rl.RLGL_EINVAL
+    assert lib.rlgl_pool_poll(None, None, 0) == rl.RLGL_EINVAL
+    assert lib.rlgl_pool_release(None, 0) == rl.RLGL_EINVAL

@@ -236,6 +236,38 @@ def batch_chains(count: int = 512, n_lo: float = 1e3, n_hi: float = 2e5, gamma: 
         return list(ex.map(one, range(count)))
 
 
+def poisson_arrivals(count: int, rate: float, seed: int, stream: int = S_META + 2) -> np.ndarray:
+    """Arrival times (s) of a Poisson process of the given rate: cumulative
+    exponential gaps -log(1 - u) / rate."""
+    u = np.empty(count, dtype=np.float64)
+    _load().wl_uniform01(count, seed, stream, _p(u))
+    return np.cumsum(-np.log1p(-u) / rate)
+
+
+def serving_pool(count: int = 128, n_lo: float = 1e3, n_hi: float = 1e6, gamma: float = 2.3, mean_deg: float = 12.0,
+                 c: float = 0.85, seed: int = 5):
+    """Chains the serving requests draw from: n log-uniform in [n_lo, n_hi],
+    Chung-Lu with exponent gamma and the given mean degree (natural dangling
+    nodes), damping c, CSC built."""
+    sizes = log_uniform_sizes(count, n_lo, n_hi, seed, S_META)
+
+    def one(k):
+        g = chung_lu(int(sizes[k]), gamma, mean_deg, 0.0, c, seed=seed * 100003 + 17 * k + 1, name=f"req{k}")
+        g.csc()
+        return g
+
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(one, range(count)))
+
+
+def request_draws(count: int, pool_size: int, seed: int, stream: int = S_META + 3) -> np.ndarray:
+    """Which pool chain each request asks for (uniform, with replacement)."""
+    out = np.empty(count, dtype=np.int32)
+    _load().wl_uniform_int(count, pool_size, seed, stream, _p(out))
+    return out.astype(np.int64)
+
+
 def random_small(n: int, mean_deg: float, c: float, seed: int, dangling_frac: float = 0.0) -> Graph:
     """Small Chung-Lu test graph (gamma 2.5) used for parity cases."""
     return chung_lu(n, 2.5, mean_deg, dangling_frac, c, seed, name=f"small{n}")
