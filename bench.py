@@ -97,7 +97,8 @@ def batched_leg(args, rl, torch, oracle):
         if tuned["engine"] == eng:
             opt = dict(engine=eng, wg_size=tuned["wg_size"], wg_per_cu=tuned["wg_per_cu"])
         else:
-            opt = dict(engine=eng, wg_size=256 if eng == rl.BATCH_LOCKSTEP else 512, wg_per_cu=1)
+            opt = dict(engine=eng, wg_size=256 if eng == rl.BATCH_LOCKSTEP else 512,
+                       wg_per_cu=8 if eng == rl.BATCH_LOCKSTEP else 1)
         b2 = rl.BatchSolver(db, max_steps=100000, **opt)
         b2.solve()  # warm-up
         runs = []

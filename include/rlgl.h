@@ -241,7 +241,8 @@ typedef struct {
   int32_t refresh;            /* confirm the stop on the cash rebuilt from the history (0/1) */
   int32_t wg_size;            /* persistent: threads per workgroup, 256, 512 or 1024; lockstep: threads per
                                  route workgroup, 256 or 512 */
-  int32_t wg_per_cu;          /* persistent: resident workgroups per CU, 1..8 */
+  int32_t wg_per_cu;          /* persistent: resident workgroups per CU, 1..8; lockstep: route workgroups per CU
+                                 (the plan items are strided over them), 1..16 */
   int32_t engine;             /* rlgl_batch_engine */
   int32_t check_period;       /* lockstep: iterations between host checks of the finished count (>= 1) */
 } rlgl_batch_options;
@@ -258,7 +259,7 @@ typedef struct {
 } rlgl_chain_result;
 
 /* Defaults: THRESHOLD, r = 1, FP32C_KAHANH, eps = 1e-7, max_steps = 100000,
- * refresh = 1, wg_size = 512, wg_per_cu = 2, engine = LOCKSTEP,
+ * refresh = 1, wg_size = 256, wg_per_cu = 8, engine = LOCKSTEP,
  * check_period = 8. */
 void rlgl_batch_default_options(rlgl_batch_options *opt);
 
@@ -278,7 +279,8 @@ rlgl_status rlgl_batch_create(const rlgl_batch_graphs *g, const rlgl_batch_optio
 rlgl_status rlgl_batch_solve(rlgl_batch *b, double *dev_pi, rlgl_chain_result *results, double *elapsed_ms);
 
 /* Autotuner: times one batch solve for every candidate (persistent: wg_size
- * in {256, 512} x wg_per_cu in {1, 2}; lockstep: route wg_size in {256, 512})
+ * in {256, 512} x wg_per_cu in {1, 2}; lockstep: route wg_size in {256, 512}
+ * x wg_per_cu in {4, 8, 16})
  * with HIP events and keeps the fastest in the batch; *best (may be NULL)
  * receives the chosen options.  Candidates whose LDS or register needs do not
  * fit are skipped. */

@@ -707,13 +707,14 @@ struct LsEngine {
   int prec = 0, hk = 0, nt = 256, cap = 0;
   LsArgs args{};
   LsChain *d_chains = nullptr;
-  int *d_lists = nullptr;  // act [cap] | tpre [cap+1] | wpre [cap+1] | rpre [cap+1]
+  int *d_lists = nullptr;  // act [cap] | tpre [cap+1] | wpre [cap+1] (pieces) | rpre [cap+1] (runs)
   int *h_lists = nullptr;  // pinned staging of d_lists
   LsCtl *h_ctl = nullptr;  // pinned [cap]
   unsigned int *h_done = nullptr;
   hipEvent_t staged = nullptr;
   bool staged_pending = false;
-  int t_total = 0, r_total = 0;
+  int t_total = 0;
+  int route_grid = 2048;      // workgroups of the route launch (items are strided over them)
   std::vector<LsChain> host;  // descriptors as on the device
   std::vector<int> act;
 };
@@ -743,6 +744,7 @@ rlgl_status ls_init(LsEngine &E, char *ws, int cap, int prec, int sched, double 
   a.rpre = E.d_lists + 3 * cap + 2;
   a.n_act = 0;
   a.w_total = 0;
+  a.r_total = 0;
   a.sched = sched;
   a.refresh = refresh ? 1 : 0;
   a.r = r;
@@ -780,7 +782,7 @@ rlgl_status ls_set_active(LsEngine &E, const std::vector<int> &ids) {
     wp[q] = (int)tw;
     rp[q] = (int)tr;
     tt += (ch.n + LS_TILE - 1) / LS_TILE;
-    tw += ch.n_whole;
+    tw += ch.n_piece;
     tr += ch.n_run;
   }
   if (tt >= INT32_MAX || tw + tr >= INT32_MAX) return fail(RLGL_EINVAL, "active chains exceed the launch grid");
@@ -793,8 +795,8 @@ rlgl_status ls_set_active(LsEngine &E, const std::vector<int> &ids) {
   E.act = ids;
   E.args.n_act = na;
   E.args.w_total = (int)tw;
+  E.args.r_total = (int)tr;
   E.t_total = (int)tt;
-  E.r_total = (int)tr;
   return RLGL_OK;
 }
 
@@ -802,12 +804,12 @@ template <class T, int HK>
 void ls_launch(LsEngine &E) {
   const LsArgs &a = E.args;
   k_ls_select<T, HK><<<E.t_total, BLOCK, 0, E.stream>>>(a);
-  const int rg = a.w_total + E.r_total;
+  const int rg = std::min(a.w_total + a.r_total, E.route_grid);
   if (rg > 0) {
     if (E.nt == 512) k_ls_route<T, HK, 512><<<rg, 512, 0, E.stream>>>(a);
     else k_ls_route<T, HK, 256><<<rg, 256, 0, E.stream>>>(a);
   }
-  k_ls_control<<<a.n_act, 64, 0, E.stream>>>(a);
+  k_ls_control<T, HK><<<a.n_act, 64, 0, E.stream>>>(a);
 }
 
 rlgl_status ls_iterate(LsEngine &E, int count) {
@@ -822,23 +824,36 @@ rlgl_status ls_iterate(LsEngine &E, int count) {
   return RLGL_OK;
 }
 
-// Chain plan: long columns (> CH links) as whole items first, then runs of at
-// most CH links and RUN_MAX_COLS columns.  Returns false on a bad colptr.
-bool chain_plan(const int *c, int n, int m, std::vector<int4> &items, int &n_whole, int &n_run, std::string &why) {
+// Chain plan: the long columns (> CH links) first - as one whole item each
+// (persistent engine) or as pieces of at most LS_PIECE links that add into
+// long_acc[q] of the column's position q in long_cols (lockstep engine) -
+// then runs of at most CH links and RUN_MAX_COLS columns.  Returns false on
+// a bad colptr.
+bool chain_plan(const int *c, int n, int m, bool pieces, std::vector<int4> &items, std::vector<int> &long_cols,
+                int &n_first, int &n_run, std::string &why) {
   if (c[0] != 0 || c[n] != m) {
     why = "csc_colptr must run from 0 to the link count";
     return false;
   }
   const size_t first = items.size();
+  const size_t lfirst = long_cols.size();
   for (int q = 0; q < n; ++q) {
     const int dg = c[q + 1] - c[q];
     if (dg < 0) {
       why = "csc_colptr decreases";
       return false;
     }
-    if (dg > CH) items.push_back(make_int4(ITEM_WHOLE, q, c[q], c[q + 1]));
+    if (dg <= CH) continue;
+    if (!pieces) {
+      items.push_back(make_int4(ITEM_WHOLE, q, c[q], c[q + 1]));
+      continue;
+    }
+    const int slot = (int)(long_cols.size() - lfirst);
+    long_cols.push_back(q);
+    for (int p = c[q]; p < c[q + 1]; p += LS_PIECE)
+      items.push_back(make_int4(-1 - slot, q, p, std::min(p + LS_PIECE, c[q + 1])));
   }
-  n_whole = (int)(items.size() - first);
+  n_first = (int)(items.size() - first);
   int run0 = -1, run_e = 0;
   auto flush = [&](int end) {
     if (run0 >= 0 && end > run0) items.push_back(make_int4(run0, end, c[run0], c[end]));
@@ -856,18 +871,23 @@ bool chain_plan(const int *c, int n, int m, std::vector<int4> &items, int &n_who
     run_e += dg;
   }
   flush(n);
-  n_run = (int)(items.size() - first) - n_whole;
+  n_run = (int)(items.size() - first) - n_first;
   return true;
 }
 
+size_t long_col_bound(long long nnz) { return (size_t)(nnz / (CH + 1) + 1); }
+
 size_t batch_item_bound(long long n, long long nnz) {
-  // runs (see build_plan) plus one whole item per column longer than CH
-  return 3 * (size_t)(nnz / CH + 2) + (size_t)(n / RUN_MAX_COLS + 2) + (size_t)(nnz / (CH + 1) + 1);
+  // runs (see build_plan) plus, per column longer than CH, one whole item or
+  // its pieces
+  return 3 * (size_t)(nnz / CH + 2) + (size_t)(n / RUN_MAX_COLS + 2) + (size_t)(nnz / LS_PIECE + 1) +
+         2 * long_col_bound(nnz);
 }
 
 struct BatchLayout {
-  size_t cash0, cash1, src, hist, hist_lo, items, chains, order, out, queue, engine, total;
-  size_t max_items;
+  size_t cash0, cash1, src, hist, hist_lo, items, ls_items, long_cols, long_acc, chains, order, out, queue, engine,
+      total;
+  size_t max_items, max_long;
 };
 
 bool batch_layout(const rlgl_batch_graphs *g, const rlgl_batch_options *o, BatchLayout &L, std::string &why) {
@@ -875,11 +895,12 @@ bool batch_layout(const rlgl_batch_graphs *g, const rlgl_batch_options *o, Batch
   if (o->precision < 0 || o->precision > 2) { why = "precision out of range"; return false; }
   if (g->node_off[0] != 0 || g->edge_off[0] != 0) { why = "node_off[0] and edge_off[0] must be 0"; return false; }
   const long long tn = g->node_off[g->n_chains];
-  size_t items = 0;
+  size_t items = 0, longs = 0;
   for (int k = 0; k < g->n_chains; ++k) {
     const long long n = g->node_off[k + 1] - g->node_off[k], m = g->edge_off[k + 1] - g->edge_off[k];
     if (n < 1 || n >= (1ll << 31) || m < 0 || m >= (1ll << 31)) { why = "chain sizes out of range"; return false; }
     items += batch_item_bound(n, m);
+    longs += long_col_bound(m);
   }
   const size_t cs = (o->precision == RLGL_FP64) ? 8 : 4;
   size_t off = 0;
@@ -894,7 +915,11 @@ bool batch_layout(const rlgl_batch_graphs *g, const rlgl_batch_options *o, Batch
   L.hist = take(8 * tn);
   L.hist_lo = (o->precision == RLGL_FP32C_KAHANH) ? take(4 * tn) : 0;
   L.max_items = items;
+  L.max_long = longs;
   L.items = take(sizeof(int4) * items);
+  L.ls_items = take(sizeof(int4) * items);
+  L.long_cols = take(4 * longs);
+  L.long_acc = take(8 * longs);
   L.chains = take(sizeof(ChainDesc) * g->n_chains);
   L.order = take(4 * (size_t)g->n_chains);
   L.out = take(sizeof(ChainOut) * g->n_chains);
@@ -910,7 +935,7 @@ struct rlgl_batch {
   BatchDev bd;
   hipStream_t stream;
   int prec, hk, nt, per_cu, cus, grid;
-  int engine, ls_nt, check_period;
+  int engine, ls_nt, ls_per_cu, check_period;
   double eps;
   double clock_khz;
   int n_chains;
@@ -946,9 +971,12 @@ rlgl_status batch_configure(rlgl_batch *b, const rlgl_batch_options &o) {
   if (o.check_period < 1) return fail(RLGL_EINVAL, "check_period must be >= 1");
   if (o.engine == RLGL_BATCH_LOCKSTEP) {
     if (o.wg_size != 256 && o.wg_size != 512) return fail(RLGL_EINVAL, "lockstep wg_size must be 256 or 512");
+    if (o.wg_per_cu < 1 || o.wg_per_cu > 16) return fail(RLGL_EINVAL, "lockstep wg_per_cu must be in 1..16");
     b->engine = RLGL_BATCH_LOCKSTEP;
     b->ls_nt = o.wg_size;
+    b->ls_per_cu = o.wg_per_cu;
     b->E.nt = o.wg_size;
+    b->E.route_grid = b->cus * o.wg_per_cu;
     b->check_period = o.check_period;
     return RLGL_OK;
   }
@@ -1003,8 +1031,8 @@ rlgl_status lockstep_run(rlgl_batch *b, double *dev_pi) {
   rlgl_status st = ls_set_active(E, b->order);
   if (st != RLGL_OK) return st;
   k_batch_start<<<1, 64, 0, b->stream>>>(b->bd.queue, b->dev_t0);
-  k_ls_start<<<(b->n_chains + 255) / 256, 256, 0, b->stream>>>(E.args.ctl, E.args.stats, b->dev_order, b->n_chains,
-                                                               E.args.done);
+  k_ls_start<<<(b->n_chains + 255) / 256, 256, 0, b->stream>>>(E.d_chains, E.args.ctl, E.args.stats, b->dev_order,
+                                                               b->n_chains, E.args.done);
   long long max_steps = 0;
   for (int k = 0; k < b->n_chains; ++k) max_steps = std::max(max_steps, E.host[k].max_steps);
   // every chain stops within max_steps green steps, step 0, one refresh per
@@ -1096,8 +1124,8 @@ void rlgl_batch_default_options(rlgl_batch_options *o) {
   o->eps = 1e-7;
   o->max_steps = 100000;
   o->refresh = 1;
-  o->wg_size = 512;
-  o->wg_per_cu = 2;
+  o->wg_size = 256;
+  o->wg_per_cu = 8;
   o->engine = RLGL_BATCH_LOCKSTEP;
   o->check_period = 8;
 }
@@ -1190,7 +1218,8 @@ rlgl_status rlgl_batch_create(const rlgl_batch_graphs *g, const rlgl_batch_optio
           hipSuccess ||
       hipStreamSynchronize(b->stream) != hipSuccess)
     return bail(fail(RLGL_EHIP, "reading the column pointers failed"));
-  std::vector<int4> items;
+  std::vector<int4> items, ls_items;
+  std::vector<int> long_cols, no_longs;
   std::vector<ChainDesc> cds((size_t)nc);
   const size_t cs = (o->precision == RLGL_FP64) ? 8 : 4;
   for (int k = 0; k < nc; ++k) {
@@ -1206,15 +1235,21 @@ rlgl_status rlgl_batch_create(const rlgl_batch_graphs *g, const rlgl_batch_optio
     cd.c = g->damping[k];
     cd.eps = g->tol_l1 ? g->tol_l1[k] * (1.0 - g->damping[k]) : o->eps;
     cd.item_off = (int)items.size();
-    int nw = 0, nr = 0;
-    if (!chain_plan(cp.data() + rp, n, m, items, nw, nr, why))
+    int nw = 0, nr = 0, np = 0, nr2 = 0;
+    if (!chain_plan(cp.data() + rp, n, m, false, items, no_longs, nw, nr, why))
       return bail(fail(RLGL_EINVAL, "chain %d: %s", k, why.c_str()));
     cd.n_items = nw + nr;
+    const size_t li = ls_items.size(), lo = long_cols.size();
+    if (!chain_plan(cp.data() + rp, n, m, true, ls_items, long_cols, np, nr2, why))
+      return bail(fail(RLGL_EINVAL, "chain %d: %s", k, why.c_str()));
     LsChain &lc = b->E.host[k];
     lc.rowptr = g->csr_rowptr + rp;
     lc.colptr = g->csc_colptr + rp;
     lc.crow = g->csc_row + g->edge_off[k];
-    lc.items = (const int4 *)(w + L.items) + cd.item_off;
+    lc.items = (const int4 *)(w + L.ls_items) + li;
+    lc.long_cols = (const int *)(w + L.long_cols) + lo;
+    lc.long_acc = (double *)(w + L.long_acc) + lo;
+    lc.n_long = (int)(long_cols.size() - lo);
     lc.cash0 = w + L.cash0 + cs * no;
     lc.cash1 = w + L.cash1 + cs * no;
     lc.src = w + L.src + cs * no;
@@ -1226,10 +1261,11 @@ rlgl_status rlgl_batch_create(const rlgl_batch_graphs *g, const rlgl_batch_optio
     lc.c = cd.c;
     lc.eps = cd.eps;
     lc.n = n;
-    lc.n_whole = nw;
-    lc.n_run = nr;
+    lc.n_piece = np;
+    lc.n_run = nr2;
   }
-  if (items.size() > L.max_items) return bail(fail(RLGL_EINVAL, "batch plan exceeds its bound (internal)"));
+  if (items.size() > L.max_items || ls_items.size() > L.max_items || long_cols.size() > L.max_long)
+    return bail(fail(RLGL_EINVAL, "batch plan exceeds its bound (internal)"));
   b->order.resize((size_t)nc);
   for (int k = 0; k < nc; ++k) b->order[k] = k;
   std::stable_sort(b->order.begin(), b->order.end(), [&](int a, int c2) {
@@ -1237,6 +1273,10 @@ rlgl_status rlgl_batch_create(const rlgl_batch_graphs *g, const rlgl_batch_optio
   });
   if ((!items.empty() &&
        hipMemcpyAsync(w + L.items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, b->stream)) ||
+      (!ls_items.empty() && hipMemcpyAsync(w + L.ls_items, ls_items.data(), sizeof(int4) * ls_items.size(),
+                                           hipMemcpyHostToDevice, b->stream)) ||
+      (!long_cols.empty() && hipMemcpyAsync(w + L.long_cols, long_cols.data(), 4 * long_cols.size(),
+                                            hipMemcpyHostToDevice, b->stream)) ||
       hipMemcpyAsync(w + L.chains, cds.data(), sizeof(ChainDesc) * nc, hipMemcpyHostToDevice, b->stream) ||
       hipMemcpyAsync(w + L.order, b->order.data(), sizeof(int) * nc, hipMemcpyHostToDevice, b->stream) ||
       hipStreamSynchronize(b->stream))
@@ -1289,14 +1329,16 @@ rlgl_status rlgl_batch_autotune(rlgl_batch *b, double *dev_pi, rlgl_batch_option
   cur.check_period = b->check_period;
   cur.engine = b->engine;
   cur.wg_size = b->engine == RLGL_BATCH_LOCKSTEP ? b->ls_nt : b->nt;
-  cur.wg_per_cu = b->engine == RLGL_BATCH_LOCKSTEP ? 1 : b->per_cu;
+  cur.wg_per_cu = b->engine == RLGL_BATCH_LOCKSTEP ? b->ls_per_cu : b->per_cu;
   std::vector<rlgl_batch_options> cands;
-  for (int nt : {256, 512}) {
-    rlgl_batch_options c = cur;
-    c.engine = RLGL_BATCH_LOCKSTEP;
-    c.wg_size = nt;
-    cands.push_back(c);
-  }
+  for (int nt : {256, 512})
+    for (int pc : {4, 8, 16}) {
+      rlgl_batch_options c = cur;
+      c.engine = RLGL_BATCH_LOCKSTEP;
+      c.wg_size = nt;
+      c.wg_per_cu = pc;
+      cands.push_back(c);
+    }
   for (int nt : {256, 512})
     for (int pc : {1, 2}) {
       rlgl_batch_options c = cur;
@@ -1344,19 +1386,20 @@ struct PoolSlot {
   int state = SLOT_FREE;
   size_t off = 0, bytes = 0;  // arena block
   hipEvent_t ready = nullptr;
-  int4 *stage = nullptr;      // page-locked copy of the plan for the upload
+  char *stage = nullptr;      // page-locked copy of the plan and the long columns for the upload
   size_t stage_cap = 0;
   LsChain desc{};
 };
 
 // Arena bytes of a chain: row and column pointers, CSC sources, plan, two
 // cash buffers, the scaled source buffer, the history and pi_hat.
-size_t pool_chain_bytes(int prec, long long n, long long nnz, size_t n_items) {
+size_t pool_chain_bytes(int prec, long long n, long long nnz, size_t n_items, size_t n_long) {
   const size_t cs = (prec == RLGL_FP64) ? 8 : 4;
   size_t b = 0;
   b += align_up(4 * (size_t)(n + 1), 256) * 2;
   b += align_up(4 * (size_t)nnz, 256);
-  b += align_up(sizeof(int4) * n_items, 256);
+  b += align_up(sizeof(int4) * n_items + 4 * n_long, 256);
+  b += align_up(8 * n_long, 256);
   b += align_up(cs * (size_t)n, 256) * 3;
   b += align_up(8 * (size_t)n, 256);  // double, or the float hi part
   if (prec == RLGL_FP32C_KAHANH) b += align_up(4 * (size_t)n, 256);
@@ -1455,7 +1498,7 @@ size_t rlgl_pool_workspace_bytes(const rlgl_pool_options *o, size_t arena_bytes)
 size_t rlgl_pool_footprint(const rlgl_pool_options *o, int32_t n, int64_t nnz) {
   std::string why;
   if (!valid_pool_options(o, why) || n < 1 || nnz < 0) return 0;
-  return pool_chain_bytes(o->precision, n, nnz, batch_item_bound(n, nnz));
+  return pool_chain_bytes(o->precision, n, nnz, batch_item_bound(n, nnz), long_col_bound(nnz));
 }
 
 rlgl_status rlgl_pool_create(const rlgl_pool_options *o, void *ws, size_t ws_bytes, void *stream, rlgl_pool **out) {
@@ -1479,6 +1522,12 @@ rlgl_status rlgl_pool_create(const rlgl_pool_options *o, void *ws, size_t ws_byt
   rlgl_status st = ls_init(p->E, w, o->max_chains, o->precision, o->sched, o->r, o->refresh, p->stream);
   if (st != RLGL_OK) return bail(st);
   p->E.nt = o->wg_size;
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev))
+      return bail(fail(RLGL_EHIP, "device attribute query failed"));
+    p->E.route_grid = std::max(cus, 1) * 8;
+  }
   p->arena = w + ctl;
   p->arena_bytes = (ws_bytes - lead - ctl) / 256 * 256;
   p->free_list.push_back({0, p->arena_bytes});
@@ -1523,26 +1572,29 @@ rlgl_status rlgl_pool_admit(rlgl_pool *p, const rlgl_request *q, int32_t *slot) 
   PoolSlot &S = p->slots[k];
   // the plan is built into the slot's page-locked staging buffer
   std::vector<int4> items;
-  items.reserve(batch_item_bound(n, m));
-  int nw = 0, nr = 0;
+  std::vector<int> longs;
+  int np = 0, nr = 0;
   std::string why;
-  if (!chain_plan(q->csc_colptr, (int)n, (int)m, items, nw, nr, why)) return fail(RLGL_EINVAL, "%s", why.c_str());
+  if (!chain_plan(q->csc_colptr, (int)n, (int)m, true, items, longs, np, nr, why))
+    return fail(RLGL_EINVAL, "%s", why.c_str());
   const int prec = p->opt.precision;
-  const size_t bytes = pool_chain_bytes(prec, n, m, items.size());
+  const size_t bytes = pool_chain_bytes(prec, n, m, items.size(), longs.size());
   size_t off = 0;
   if (!arena_take(p, bytes, off)) return fail(RLGL_EBUSY, "no arena block of %zu bytes free", bytes);
-  if (S.stage_cap < items.size()) {
+  const size_t plan_bytes = sizeof(int4) * items.size() + 4 * longs.size();
+  if (S.stage_cap < plan_bytes) {
     if (S.stage) (void)hipHostFree(S.stage);
     S.stage = nullptr;
     S.stage_cap = 0;
-    const size_t cap = std::max(items.size(), (size_t)1024);
-    if (hipHostMalloc((void **)&S.stage, sizeof(int4) * cap, hipHostMallocDefault) != hipSuccess) {
+    const size_t cap = std::max(plan_bytes, (size_t)16384);
+    if (hipHostMalloc((void **)&S.stage, cap, hipHostMallocDefault) != hipSuccess) {
       arena_give(p, off, bytes);
       return fail(RLGL_ENOMEM, "page-locked staging allocation failed");
     }
     S.stage_cap = cap;
   }
-  std::copy(items.begin(), items.end(), S.stage);
+  std::memcpy(S.stage, items.data(), sizeof(int4) * items.size());
+  std::memcpy(S.stage + sizeof(int4) * items.size(), longs.data(), 4 * longs.size());
   char *base = p->arena + off;
   size_t at = 0;
   auto take = [&](size_t b) {
@@ -1557,11 +1609,14 @@ rlgl_status rlgl_pool_admit(rlgl_pool *p, const rlgl_request *q, int32_t *slot) 
   int *d_rowptr = (int *)take(4 * (size_t)(n + 1));
   int *d_colptr = (int *)take(4 * (size_t)(n + 1));
   int *d_crow = (int *)take(4 * (size_t)m);
-  int4 *d_items = (int4 *)take(sizeof(int4) * items.size());
+  int4 *d_items = (int4 *)take(plan_bytes);  // the plan, then the long columns
   d.rowptr = d_rowptr;
   d.colptr = d_colptr;
   d.crow = d_crow;
   d.items = d_items;
+  d.long_cols = (const int *)(d_items + items.size());
+  d.long_acc = (double *)take(8 * longs.size());
+  d.n_long = (int)longs.size();
   d.cash0 = take(cs * (size_t)n);
   d.cash1 = take(cs * (size_t)n);
   d.src = take(cs * (size_t)n);
@@ -1573,14 +1628,14 @@ rlgl_status rlgl_pool_admit(rlgl_pool *p, const rlgl_request *q, int32_t *slot) 
   d.c = q->damping;
   d.eps = q->tol_l1 * (1.0 - q->damping);
   d.n = (int)n;
-  d.n_whole = nw;
+  d.n_piece = np;
   d.n_run = nr;
   hipError_t e = hipMemcpyAsync(d_rowptr, q->csr_rowptr, 4 * (size_t)(n + 1), hipMemcpyHostToDevice, p->copy);
   if (e == hipSuccess)
     e = hipMemcpyAsync(d_colptr, q->csc_colptr, 4 * (size_t)(n + 1), hipMemcpyHostToDevice, p->copy);
   if (e == hipSuccess && m > 0) e = hipMemcpyAsync(d_crow, q->csc_row, 4 * (size_t)m, hipMemcpyHostToDevice, p->copy);
-  if (e == hipSuccess && !items.empty())
-    e = hipMemcpyAsync(d_items, S.stage, sizeof(int4) * items.size(), hipMemcpyHostToDevice, p->copy);
+  if (e == hipSuccess && plan_bytes > 0)
+    e = hipMemcpyAsync(d_items, S.stage, plan_bytes, hipMemcpyHostToDevice, p->copy);
   if (e == hipSuccess) e = hipEventRecord(S.ready, p->copy);
   if (e != hipSuccess) {
     // let whatever was enqueued finish before the block can be reused

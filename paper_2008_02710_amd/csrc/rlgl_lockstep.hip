@@ -7,11 +7,14 @@
 //                  H += M (eq. (5)), the restart pool T and sum M, and the
 //                  scaled green mass M_j / outdeg(j) of every node into the
 //                  chain's source buffer;
-//   k_ls_route   - one workgroup per plan item (the long columns of every
-//                  chain first, then runs of at most CH links): the CSC
-//                  gather of eq. (6), C_{t+1}[k] = kept(k) + c sum_j src[j]
-//                  + T/N, and the statistics of C_{t+1};
-//   k_ls_control - one wave per active chain: adds up the chain's statistics,
+//   k_ls_route   - plan items (the pieces of the long columns of every
+//                  chain first, then runs of at most CH links), strided over
+//                  a machine-sized grid: the CSC gather of eq. (6), C_{t+1}[k] = kept(k) +
+//                  c sum_j src[j] + T/N, and the statistics of C_{t+1}; a
+//                  piece of a column with more than CH in-links adds its
+//                  partial sum into the chain's FP64 long-column accumulator;
+//   k_ls_control - one wave per active chain: finishes the long columns,
+//                  adds up the chain's statistics,
 //                  applies the stop test of Algorithm 1 step (7), the drift
 //                  and stop-confirming FP64 refresh (eq. (7)), the step
 //                  limit, and sets the threshold and the mode of the next
@@ -27,8 +30,9 @@
 
 namespace rlgl {
 
-constexpr int LS_NS = 16;      // stat stripes per chain
-constexpr int LS_TILE = 1024;  // nodes per select workgroup (BLOCK threads x VPT)
+constexpr int LS_NS = 16;       // stat stripes per chain
+constexpr int LS_TILE = 1024;   // nodes per select workgroup (BLOCK threads x VPT)
+constexpr int LS_PIECE = 4096;  // links per piece of a long column
 static_assert(LS_TILE == BLOCK * VPT, "select tile");
 
 enum : int { LS_IDLE = 0, LS_INIT = 1, LS_STEP = 2, LS_REFRESH = 3, LS_FINISH = 4, LS_DONE = 5 };
@@ -38,14 +42,16 @@ struct LsChain {
   const int *rowptr;  // [n+1] CSR row pointers (out-degrees)
   const int *colptr;  // [n+1] CSC column pointers, 0-based
   const int *crow;    // [nnz] CSC sources
-  const int4 *items;  // plan: the n_whole long columns, then n_run runs
+  const int4 *items;      // plan: n_piece pieces of long columns, then n_run runs
+  const int *long_cols;   // [n_long] the columns with more than CH links
+  double *long_acc;       // [n_long] their partial sums, zero between passes
   void *cash0, *cash1, *src;
   void *hist;
   float *hist_lo;
   double *pi;
   long long nnz, max_steps;
   double c, eps;
-  int n, n_whole, n_run, pad;
+  int n, n_piece, n_run, n_long;
 };
 
 // Per-chain control record, written by k_ls_control (and k_ls_select at step 0).
@@ -67,10 +73,10 @@ struct LsArgs {
   LsStripe *stats;
   const int *act;   // [n_act] active chain slots
   const int *tpre;  // [n_act+1] exclusive prefix of select tiles
-  const int *wpre;  // [n_act+1] exclusive prefix of long-column items
+  const int *wpre;  // [n_act+1] exclusive prefix of long-column pieces
   const int *rpre;  // [n_act+1] exclusive prefix of run items
   unsigned int *done;
-  int n_act, w_total;
+  int n_act, w_total, r_total;
   int sched, refresh;
   double r;
 };
@@ -179,66 +185,85 @@ __global__ __launch_bounds__(NT) void k_ls_route(LsArgs a) {
   constexpr int NW = NT / 64;
   __shared__ ColLds<NT> L;
   __shared__ double sh_T;
-  const bool whole = (int)blockIdx.x < a.w_total;
-  const int b = whole ? (int)blockIdx.x : (int)blockIdx.x - a.w_total;
-  const int ai = ls_find(whole ? a.wpre : a.rpre, a.n_act, b);
-  const int k = a.act[ai];
-  const LsCtl *ctl = &a.ctl[k];
-  const int mode = ctl->mode;
-  if (mode != LS_INIT && mode != LS_STEP && mode != LS_REFRESH) return;
-  const LsChain ch = a.chains[k];
-  const int local = whole ? b - a.wpre[ai] : ch.n_whole + (b - a.rpre[ai]);
-  const int n = ch.n;
-  // the pool of this pass, from the select statistics
-  if (threadIdx.x < 64) {
-    double v = threadIdx.x < LS_NS ? a.stats[(size_t)k * LS_NS + threadIdx.x].T : 0.0;
-    v = wave_sum(v);
-    if (threadIdx.x == 0) sh_T = v;
-  }
-  __syncthreads();
-  const double off = sh_T / (double)n;
-  const ColView g{ch.colptr, ch.crow, ch.rowptr, nullptr, n, 1};
-  const T *__restrict__ cur = (const T *)(ctl->buf ? ch.cash1 : ch.cash0);
-  T *__restrict__ out = (T *)(ctl->buf ? ch.cash0 : ch.cash1);
-  const T *__restrict__ src = (const T *)ch.src;
-  const int4 item = ch.items[local];
-  const double c = ch.c, rr = a.r;
+  const int total = a.w_total + a.r_total;
+  const int stripe = blockIdx.x % LS_NS;
+  int kc = -1, mode = LS_IDLE;  // chain of the previous item, its mode
+  double off = 0.0;
   double l1 = 0.0, cs = 0.0, sr = 0.0, mx = 0.0;
-  auto gathered = [&](int j) -> double { return ((unsigned)j < (unsigned)n) ? (double)src[j] : 0.0; };
-  if (mode == LS_REFRESH) {
-    // C_t = H_t P - H_t (eq. (7) with C_0 = 0), FP64 weights 1/outdeg
-    const int *__restrict__ rowptr = ch.rowptr;
-    column_item<T, NT>(
-        g, item, [&](int j) -> double { return ls_hist<HK>(ch, j) * inv_outdeg(rowptr, n, j); },
-        [&](int kk) -> double { return -ls_hist<HK>(ch, kk); }, c, off, rr, out, nullptr, L, l1, cs, sr, mx);
-  } else if (mode == LS_INIT) {
-    // step 0: C_1 = 0 - M_0 + M_0 P
-    const double m0 = (double)(T)(1.0 / (double)n);
-    column_item<T, NT>(g, item, gathered, [&](int) -> double { return -m0; }, c, off, rr, out, nullptr, L, l1, cs,
-                       sr, mx);
-  } else {
-    const double theta = ctl->theta, maxabs = ctl->maxabs;
-    const int sched = a.sched;
-    column_item<T, NT>(
-        g, item, gathered,
-        [&](int kk) -> double {
-          const T v = cur[kk];
-          return is_green(v, kk, sched, theta, maxabs, 0.0, -1) ? 0.0 : (double)v;
-        },
-        c, off, rr, out, nullptr, L, l1, cs, sr, mx);
+  // statistics of the values this workgroup wrote for chain kc
+  auto flush = [&]() {
+    const Red4 t4 = block_sum4<NW>(Red4{l1, cs, sr, 0.0}, L.red);
+    const double bm = block_max<NW>(mx, L.red);
+    if (threadIdx.x == 0) {
+      LsStripe *st = &a.stats[(size_t)kc * LS_NS + stripe];
+      if (t4.a != 0.0) atomic_add_f64(&st->l1, t4.a);
+      if (t4.b != 0.0) atomic_add_f64(&st->cs, t4.b);
+      if (t4.c != 0.0) atomic_add_f64(&st->sr, t4.c);
+      if (bm > 0.0) atomic_max_nonneg(&st->mx, bm);
+    }
+    l1 = cs = sr = mx = 0.0;
+  };
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const bool piece = it < a.w_total;
+    const int b = piece ? it : it - a.w_total;
+    const int ai = ls_find(piece ? a.wpre : a.rpre, a.n_act, b);
+    const int k = a.act[ai];
+    if (k != kc) {
+      if (kc >= 0) flush();
+      kc = k;
+      mode = a.ctl[k].mode;
+      if (mode == LS_INIT || mode == LS_STEP || mode == LS_REFRESH) {
+        // the pool of this pass, from the select statistics
+        if (threadIdx.x < 64) {
+          double v = threadIdx.x < LS_NS ? a.stats[(size_t)k * LS_NS + threadIdx.x].T : 0.0;
+          v = wave_sum(v);
+          if (threadIdx.x == 0) sh_T = v;
+        }
+        __syncthreads();
+        off = sh_T / (double)a.chains[k].n;
+      }
+    }
+    if (mode != LS_INIT && mode != LS_STEP && mode != LS_REFRESH) continue;
+    const LsChain ch = a.chains[k];
+    const LsCtl *ctl = &a.ctl[k];
+    const int local = piece ? b - a.wpre[ai] : ch.n_piece + (b - a.rpre[ai]);
+    const int n = ch.n;
+    const ColView g{ch.colptr, ch.crow, ch.rowptr, nullptr, n, 1};
+    const int buf = ctl->buf;
+    const T *__restrict__ cur = (const T *)(buf ? ch.cash1 : ch.cash0);
+    T *__restrict__ out = (T *)(buf ? ch.cash0 : ch.cash1);
+    const T *__restrict__ src = (const T *)ch.src;
+    const int4 item = ch.items[local];
+    const double c = ch.c, rr = a.r;
+    auto gathered = [&](int j) -> double { return ((unsigned)j < (unsigned)n) ? (double)src[j] : 0.0; };
+    if (mode == LS_REFRESH) {
+      // C_t = H_t P - H_t (eq. (7) with C_0 = 0), FP64 weights 1/outdeg
+      const int *__restrict__ rowptr = ch.rowptr;
+      column_item<T, NT>(
+          g, item, [&](int j) -> double { return ls_hist<HK>(ch, j) * inv_outdeg(rowptr, n, j); },
+          [&](int kk) -> double { return -ls_hist<HK>(ch, kk); }, c, off, rr, out, ch.long_acc, L, l1, cs, sr, mx);
+    } else if (mode == LS_INIT) {
+      // step 0: C_1 = 0 - M_0 + M_0 P
+      const double m0 = (double)(T)(1.0 / (double)n);
+      column_item<T, NT>(g, item, gathered, [&](int) -> double { return -m0; }, c, off, rr, out, ch.long_acc, L, l1,
+                         cs, sr, mx);
+    } else {
+      const double theta = ctl->theta, maxabs = ctl->maxabs;
+      const int sched = a.sched;
+      column_item<T, NT>(
+          g, item, gathered,
+          [&](int kk) -> double {
+            const T v = cur[kk];
+            return is_green(v, kk, sched, theta, maxabs, 0.0, -1) ? 0.0 : (double)v;
+          },
+          c, off, rr, out, ch.long_acc, L, l1, cs, sr, mx);
+    }
   }
-  const Red4 t4 = block_sum4<NW>(Red4{l1, cs, sr, 0.0}, L.red);
-  const double bm = block_max<NW>(mx, L.red);
-  if (threadIdx.x == 0) {
-    LsStripe *st = &a.stats[(size_t)k * LS_NS + local % LS_NS];
-    if (t4.a != 0.0) atomic_add_f64(&st->l1, t4.a);
-    if (t4.b != 0.0) atomic_add_f64(&st->cs, t4.b);
-    if (t4.c != 0.0) atomic_add_f64(&st->sr, t4.c);
-    if (bm > 0.0) atomic_max_nonneg(&st->mx, bm);
-  }
+  if (kc >= 0) flush();
 }
 
 // One wave per active chain.
+template <class Tc, int HK>
 __global__ __launch_bounds__(64) void k_ls_control(LsArgs a) {
   const int ai = blockIdx.x;
   if (ai >= a.n_act) return;
@@ -260,6 +285,34 @@ __global__ __launch_bounds__(64) void k_ls_control(LsArgs a) {
     dh = s.dh;
     ge = s.ge;
   }
+  T = wave_sum(T);
+  const LsChain &ch = a.chains[k];
+  if ((mode == LS_INIT || mode == LS_STEP || mode == LS_REFRESH) && ch.n_long > 0) {
+    // the columns with more than CH links: x_k = kept(k) + c acc_k + T/N
+    const int n = ch.n;
+    const double off = T / (double)n, c = ch.c;
+    const Tc *cur = (const Tc *)(ctl->buf ? ch.cash1 : ch.cash0);
+    Tc *out = (Tc *)(ctl->buf ? ch.cash0 : ch.cash1);
+    const double theta = ctl->theta, maxabs = ctl->maxabs;
+    const double m0 = (double)(Tc)(1.0 / (double)n);
+    for (int q = lane; q < ch.n_long; q += 64) {
+      const int kk = ch.long_cols[q];
+      const double acc = ch.long_acc[q];
+      ch.long_acc[q] = 0.0;
+      double kept;
+      if (mode == LS_INIT) {
+        kept = -m0;
+      } else if (mode == LS_REFRESH) {
+        kept = -ls_hist<HK>(ch, kk);
+      } else {
+        const Tc v = cur[kk];
+        kept = is_green(v, kk, a.sched, theta, maxabs, 0.0, -1) ? 0.0 : (double)v;
+      }
+      const Tc x = (Tc)(kept + c * acc + off);
+      out[kk] = x;
+      fold_stats((double)x, a.r, l1, cs, sr, mx);
+    }
+  }
   l1 = wave_sum(l1);
   cs = wave_sum(cs);
   sr = wave_sum(sr);
@@ -267,7 +320,6 @@ __global__ __launch_bounds__(64) void k_ls_control(LsArgs a) {
   ms = wave_sum(ms);
   dh = wave_sum(dh);
   ge = wave_sum(ge);
-  (void)T;
   if (lane < LS_NS) {
     LsStripe &s = st[lane];
     s.l1 = 0.0;
@@ -280,7 +332,6 @@ __global__ __launch_bounds__(64) void k_ls_control(LsArgs a) {
     s.ge = 0.0;
   }
   if (lane != 0) return;
-  const LsChain &ch = a.chains[k];
   if (mode == LS_FINISH) {
     ctl->mode = LS_DONE;
     ctl->t1 = wall_clock64();
@@ -342,12 +393,15 @@ __global__ __launch_bounds__(64) void k_ls_control(LsArgs a) {
 }
 
 // Puts chains [0, count) of the slots in `ids` at the start of a solve: mode
-// LS_INIT, counters cleared, stripes zeroed.
-__global__ void k_ls_start(LsCtl *ctl, LsStripe *stats, const int *ids, int count, unsigned int *done) {
+// LS_INIT, counters cleared, stripes and long-column sums zeroed.
+__global__ void k_ls_start(const LsChain *chains, LsCtl *ctl, LsStripe *stats, const int *ids, int count,
+                           unsigned int *done) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q == 0) *done = 0u;
   if (q >= count) return;
   const int k = ids[q];
+  const LsChain &ch = chains[k];
+  for (int i = 0; i < ch.n_long; ++i) ch.long_acc[i] = 0.0;
   LsCtl z;
   z.t = 0;
   z.refreshed = -1;
@@ -379,6 +433,7 @@ __global__ void k_ls_start(LsCtl *ctl, LsStripe *stats, const int *ids, int coun
 
 // Writes one chain's descriptor and starts it (pool admission).
 __global__ void k_ls_admit(LsChain *chains, LsCtl *ctl, LsStripe *stats, int slot, LsChain ch) {
+  for (int i = threadIdx.x; i < ch.n_long; i += blockDim.x) ch.long_acc[i] = 0.0;
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   chains[slot] = ch;
   LsCtl z;
@@ -419,5 +474,8 @@ template __global__ void k_ls_route<double, 0, 256>(LsArgs);
 template __global__ void k_ls_route<float, 0, 512>(LsArgs);
 template __global__ void k_ls_route<float, 1, 512>(LsArgs);
 template __global__ void k_ls_route<double, 0, 512>(LsArgs);
+template __global__ void k_ls_control<float, 0>(LsArgs);
+template __global__ void k_ls_control<float, 1>(LsArgs);
+template __global__ void k_ls_control<double, 0>(LsArgs);
 
 }  // namespace rlgl
