@@ -1,0 +1,97 @@
+"""Parity at the full benchmark sizes, in the launch configuration the
+benchmark times (threshold r = 1, FP32 cash with FP64 history, FP32 link
+values, AUTO route):
+
+  * Chung-Lu power law, N = 2^20, 16.8M links, exponent 2.1, 5% dangling;
+  * R-MAT scale 24 (16.8M nodes, 268M links, a/b/c = 0.57/0.19/0.19).
+
+Per graph: one green-light step from a device state against the oracle's
+step on the very same state (green set bit for bit, C and H elementwise),
+for a pull and a push step; and a full solve whose pi_hat the oracle's FP64
+residual certifies to L1 <= 1e-6 (the bound ||pi_hat - pi*||_1 <=
+||pi_hat - pi_hat P||_1 / (1 - c), for pi_hat summing to one).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import l1, say, to_np
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2008_02710_amd as rl  # noqa: E402
+
+_cache = {}
+
+
+def graph(name):
+    if name not in _cache:
+        say("generating", name)
+        if name == "chung_lu_2p20":
+            g = workloads.chung_lu(1 << 20, 2.1, 16.0, 0.05, 0.85, seed=0, name=name)
+        else:
+            g = workloads.rmat(24, 16, 0.57, 0.19, 0.19, 0.85, seed=0)
+            g.name = name
+        g.csc()
+        say("generated", name, g.n, g.nnz, "dangling", g.n_dangling)
+        dg = rl.DeviceGraph.from_workload(g, precision=rl.FP32C_FP64H, with_csc=True, explicit_val=True)
+        say("uploaded", name)
+        _cache[name] = (g, dg, oracle.Chain(g.rowptr, g.col, g.val(), g.c))
+    return _cache[name]
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name", ["chung_lu_2p20", "rmat_s24"])
+def test_full_size_solve_certified(name):
+    g, dg, ch = graph(name)
+    say("case full_solve", name)
+    eps = (1 - g.c) * 1e-6
+    s = rl.Solver(dg, sched=rl.SCHED_THRESHOLD, route=rl.ROUTE_AUTO, precision=rl.FP32C_FP64H)
+    st, info = s.solve(eps, max_steps=100000)
+    assert st == rl.RLGL_OK and info["resid"] < eps
+    pi = to_np(s.pi)
+    s.close()
+    say("solved", name, info["t"], "steps")
+    assert np.all(pi >= 0.0) and abs(pi.sum() - 1.0) < 1e-9
+    cert = oracle.residual(ch, pi) / (1 - g.c)
+    say("certified L1 bound", cert)
+    assert cert <= 1e-6
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("route", ["pull", "push"])
+@pytest.mark.parametrize("name", ["chung_lu_2p20", "rmat_s24"])
+def test_full_size_one_step_parity(name, route):
+    g, dg, ch = graph(name)
+    say("case full_step", name, route)
+    s = rl.Solver(dg, sched=rl.SCHED_THRESHOLD, route=rl.ROUTE_AUTO, precision=rl.FP32C_FP64H, record_green=1)
+    s.step(3)
+    C, H, info0 = s.state()
+    C, H = to_np(C).astype(np.float64), to_np(H)
+    s.close()
+    # the same state, one step with the route forced
+    s = rl.Solver(dg, sched=rl.SCHED_THRESHOLD, precision=rl.FP32C_FP64H, record_green=1,
+                  route=rl.ROUTE_PULL if route == "pull" else rl.ROUTE_PUSH)
+    s.set_state(torch.from_numpy(C).cuda(), torch.from_numpy(H).cuda(), info0["h_sum"],
+                t=info0["t"])
+    info1 = s.step(1)
+    mask = to_np(s.green()).astype(bool)
+    theta = info1["theta"]
+    assert theta == pytest.approx(oracle.theta(C), rel=1e-12)
+    want = oracle.select(C, oracle.THRESHOLD, theta, 0)
+    assert np.array_equal(mask, want), (int(mask.sum()), int(want.sum()))
+    ost = oracle.State.from_arrays(ch, C, H, info0["h_sum"], t=info0["t"])
+    moved = float(np.abs(C[want]).sum())
+    ost.step_mask(want)
+    C1, H1, info2 = s.state()
+    s.close()
+    # one float rounding per stored value and per add: 2e-6 of the moved mass
+    assert l1(to_np(C1), ost.C) <= 2e-6 * moved
+    assert l1(to_np(H1), ost.H) <= 1e-15 * moved + 1e-300
+    assert abs(info2["h_sum"] - ost.hsum) <= 1e-14
+    say("step parity", name, route, "green", int(want.sum()), "moved", moved)
