@@ -98,7 +98,7 @@ def batched_leg(args, rl, torch, oracle):
             opt = dict(engine=eng, wg_size=tuned["wg_size"], wg_per_cu=tuned["wg_per_cu"])
         else:
             opt = dict(engine=eng, wg_size=256 if eng == rl.BATCH_LOCKSTEP else 512,
-                       wg_per_cu=8 if eng == rl.BATCH_LOCKSTEP else 1)
+                       wg_per_cu=0 if eng == rl.BATCH_LOCKSTEP else 1)
         b2 = rl.BatchSolver(db, max_steps=100000, **opt)
         b2.solve()  # warm-up
         runs = []
@@ -361,6 +361,7 @@ def main():
         osched = {rl.SCHED_THRESHOLD: oracle.THRESHOLD, rl.SCHED_ALL: oracle.ALL}[sched]
         solves, steps, opushes, tcpu = 0, 0, 0, 0.0
         a = time.perf_counter()
+        t_print = a
         st = oracle.State(ch)
         while True:
             if st.t >= 2 and st.resid < eps:
@@ -374,8 +375,9 @@ def main():
                 break
             st.step(osched, r=wl["r"])
             steps += 1
-            if steps % 10 == 0:
-                print(f"# cpu oracle: {steps} steps, {time.perf_counter() - a:.1f}s", file=sys.stderr, flush=True)
+            if time.perf_counter() - t_print >= 3.0:
+                t_print = time.perf_counter()
+                print(f"# cpu oracle: {steps} steps, {t_print - a:.1f}s", file=sys.stderr, flush=True)
         if st is not None:
             opushes += st.edges
         tcpu = time.perf_counter() - a

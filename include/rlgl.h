@@ -96,7 +96,7 @@ typedef struct {
   int32_t theta_period;       /* recompute theta every theta_period steps (>= 1, default 1) */
   int32_t precision;          /* rlgl_precision */
   int32_t route;              /* rlgl_route */
-  double pull_alpha;          /* AUTO switch point as a fraction of nnz (default 0.05) */
+  double pull_alpha;          /* AUTO switch point as a fraction of nnz (default 0.15) */
   int32_t check_period;       /* rlgl_solve: steps enqueued between host reads of the stop flag; 0 = adaptive */
   int32_t record_green;       /* non-zero: keep the green mask of the last step for rlgl_get_green */
   int32_t refresh;            /* rebuild C_t = H_t P - H_t in FP64 (needs the CSC; see rlgl_refresh):
@@ -120,7 +120,7 @@ typedef struct {
 } rlgl_step_info;
 
 /* Fills *opt with the defaults: THRESHOLD, r = 1, k = 1, theta_period = 1,
- * FP32C_FP64H, AUTO, pull_alpha = 0.05, check_period = 0, record_green = 0,
+ * FP32C_FP64H, AUTO, pull_alpha = 0.15, check_period = 0, record_green = 0,
  * refresh = 1. */
 void rlgl_default_options(rlgl_options *opt);
 
@@ -241,8 +241,9 @@ typedef struct {
   int32_t refresh;            /* confirm the stop on the cash rebuilt from the history (0/1) */
   int32_t wg_size;            /* persistent: threads per workgroup, 256, 512 or 1024; lockstep: threads per
                                  route workgroup, 256 or 512 */
-  int32_t wg_per_cu;          /* persistent: resident workgroups per CU, 1..8; lockstep: route workgroups per CU
-                                 (the plan items are strided over them), 1..16 */
+  int32_t wg_per_cu;          /* persistent: resident workgroups per CU, 1..8 (0 means 1); lockstep: route
+                                 workgroups per CU the plan items are strided over, 1..16, or 0 for one
+                                 workgroup per item */
   int32_t engine;             /* rlgl_batch_engine */
   int32_t check_period;       /* lockstep: iterations between host checks of the finished count (>= 1) */
 } rlgl_batch_options;
@@ -259,7 +260,7 @@ typedef struct {
 } rlgl_chain_result;
 
 /* Defaults: THRESHOLD, r = 1, FP32C_KAHANH, eps = 1e-7, max_steps = 100000,
- * refresh = 1, wg_size = 256, wg_per_cu = 8, engine = LOCKSTEP,
+ * refresh = 1, wg_size = 256, wg_per_cu = 0, engine = LOCKSTEP,
  * check_period = 8. */
 void rlgl_batch_default_options(rlgl_batch_options *opt);
 
@@ -280,7 +281,7 @@ rlgl_status rlgl_batch_solve(rlgl_batch *b, double *dev_pi, rlgl_chain_result *r
 
 /* Autotuner: times one batch solve for every candidate (persistent: wg_size
  * in {256, 512} x wg_per_cu in {1, 2}; lockstep: route wg_size in {256, 512}
- * x wg_per_cu in {4, 8, 16})
+ * x wg_per_cu in {0, 4, 8})
  * with HIP events and keeps the fastest in the batch; *best (may be NULL)
  * receives the chosen options.  Candidates whose LDS or register needs do not
  * fit are skipped. */
@@ -311,6 +312,7 @@ typedef struct {
   int32_t wg_size;            /* threads per route workgroup: 256 or 512 */
   int32_t max_chains;         /* slots: chains resident at once, >= 1 */
   int64_t max_steps;          /* per chain */
+  int32_t route_per_cu;       /* route workgroups per CU the plan items are strided over, 1..16; 0: one per item */
 } rlgl_pool_options;
 
 /* One request: a chain of the form of rlgl_graph (damping c, uniform restart,
@@ -330,7 +332,7 @@ typedef struct {
 } rlgl_request;
 
 /* Defaults: THRESHOLD, r = 1, FP32C_KAHANH, refresh = 1, wg_size = 256,
- * max_chains = 256, max_steps = 100000. */
+ * max_chains = 256, max_steps = 100000, route_per_cu = 8. */
 void rlgl_pool_default_options(rlgl_pool_options *opt);
 
 /* Workspace for a pool whose arena holds arena_bytes (control records of

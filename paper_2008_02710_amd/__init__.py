@@ -84,7 +84,7 @@ class rlgl_chain_result(ctypes.Structure):
 class rlgl_pool_options(ctypes.Structure):
     _fields_ = [("sched", ctypes.c_int32), ("r", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("refresh", ctypes.c_int32), ("wg_size", ctypes.c_int32), ("max_chains", ctypes.c_int32),
-                ("max_steps", ctypes.c_int64)]
+                ("max_steps", ctypes.c_int64), ("route_per_cu", ctypes.c_int32)]
 
 
 class rlgl_request(ctypes.Structure):

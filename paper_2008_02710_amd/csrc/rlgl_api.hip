@@ -81,11 +81,11 @@ Layout make_layout(long long n, long long nnz, int prec, bool has_csc) {
   L.log = take(sizeof(StepLog) * LOG_STEPS);
   if (has_csc) {
     // upper bounds of the plan built in rlgl_create: a run ends because it is
-    // full (CH links or RUN_MAX_COLS columns) or because a long column follows
-    L.max_long = (size_t)(nnz / (CH + 1) + 1);
-    // runs: two consecutive runs hold more than CH links unless a column-count
-    // or long-column break separates them; pieces: nnz / CH + one per long column
-    L.max_items = 3 * (size_t)(nnz / CH + 2) + (size_t)(n / RUN_MAX_COLS + 2) + 2 * L.max_long + 2;
+    // full (PCH links or PCOLS columns) or because a long column follows
+    L.max_long = (size_t)(nnz / (PCH + 1) + 1);
+    // runs: two consecutive runs hold more than PCH links unless a column-count
+    // or long-column break separates them; pieces: nnz / PCH + one per long column
+    L.max_items = 3 * (size_t)(nnz / PCH + 2) + (size_t)(n / PCOLS + 2) + 2 * L.max_long + 2;
     L.items = take(sizeof(int4) * L.max_items);
     L.long_cols = take(4 * L.max_long);
     L.long_acc = take(8 * L.max_long);
@@ -291,16 +291,16 @@ rlgl_status build_plan(rlgl_ctx *c, const rlgl_graph *g, const Layout &L, char *
   for (int k = 0; k < n; ++k) {
     const int dg = cp[k + 1] - cp[k];
     if (dg < 0) return fail(RLGL_EINVAL, "csc_colptr is not non-decreasing at %d", k);
-    if (dg > CH) {
-      // a long column: pieces of CH links, completed by the last workgroup
+    if (dg > PCH) {
+      // a long column: pieces of PCH links, completed by the last workgroup
       flush(k);
       const int slot = (int)lng.size();
       lng.push_back(k);
-      for (int p = cp[k]; p < cp[k + 1]; p += CH)
-        items.push_back(make_int4(-1 - slot, k, p, std::min(p + CH, cp[k + 1])));
+      for (int p = cp[k]; p < cp[k + 1]; p += PCH)
+        items.push_back(make_int4(-1 - slot, k, p, std::min(p + PCH, cp[k + 1])));
       continue;
     }
-    if (run0 >= 0 && (run_e + dg > CH || k - run0 >= RUN_MAX_COLS)) flush(k);
+    if (run0 >= 0 && (run_e + dg > PCH || k - run0 >= PCOLS)) flush(k);
     if (run0 < 0) run0 = k;
     run_e += dg;
   }
@@ -378,7 +378,7 @@ void rlgl_default_options(rlgl_options *o) {
   o->theta_period = 1;
   o->precision = RLGL_FP32C_FP64H;
   o->route = RLGL_ROUTE_AUTO;
-  o->pull_alpha = 0.05;
+  o->pull_alpha = 0.15;
   o->check_period = 0;
   o->record_green = 0;
   o->refresh = 1;
@@ -714,7 +714,7 @@ struct LsEngine {
   hipEvent_t staged = nullptr;
   bool staged_pending = false;
   int t_total = 0;
-  int route_grid = 2048;      // workgroups of the route launch (items are strided over them)
+  int route_grid = 0;         // route workgroups the plan items are strided over; 0: one per item
   std::vector<LsChain> host;  // descriptors as on the device
   std::vector<int> act;
 };
@@ -804,10 +804,15 @@ template <class T, int HK>
 void ls_launch(LsEngine &E) {
   const LsArgs &a = E.args;
   k_ls_select<T, HK><<<E.t_total, BLOCK, 0, E.stream>>>(a);
-  const int rg = std::min(a.w_total + a.r_total, E.route_grid);
-  if (rg > 0) {
-    if (E.nt == 512) k_ls_route<T, HK, 512><<<rg, 512, 0, E.stream>>>(a);
-    else k_ls_route<T, HK, 256><<<rg, 256, 0, E.stream>>>(a);
+  const int items = a.w_total + a.r_total;
+  if (items > 0 && E.route_grid <= 0) {
+    // one workgroup per plan item
+    if (E.nt == 512) k_ls_route<T, HK, 512><<<items, 512, 0, E.stream>>>(a);
+    else k_ls_route<T, HK, 256><<<items, 256, 0, E.stream>>>(a);
+  } else if (items > 0) {
+    const int rg = std::min(items, E.route_grid);
+    if (E.nt == 512) k_ls_route_strided<T, HK, 512><<<rg, 512, 0, E.stream>>>(a);
+    else k_ls_route_strided<T, HK, 256><<<rg, 256, 0, E.stream>>>(a);
   }
   k_ls_control<T, HK><<<a.n_act, 64, 0, E.stream>>>(a);
 }
@@ -971,7 +976,7 @@ rlgl_status batch_configure(rlgl_batch *b, const rlgl_batch_options &o) {
   if (o.check_period < 1) return fail(RLGL_EINVAL, "check_period must be >= 1");
   if (o.engine == RLGL_BATCH_LOCKSTEP) {
     if (o.wg_size != 256 && o.wg_size != 512) return fail(RLGL_EINVAL, "lockstep wg_size must be 256 or 512");
-    if (o.wg_per_cu < 1 || o.wg_per_cu > 16) return fail(RLGL_EINVAL, "lockstep wg_per_cu must be in 1..16");
+    if (o.wg_per_cu < 0 || o.wg_per_cu > 16) return fail(RLGL_EINVAL, "lockstep wg_per_cu must be in 0..16");
     b->engine = RLGL_BATCH_LOCKSTEP;
     b->ls_nt = o.wg_size;
     b->ls_per_cu = o.wg_per_cu;
@@ -980,7 +985,7 @@ rlgl_status batch_configure(rlgl_batch *b, const rlgl_batch_options &o) {
     b->check_period = o.check_period;
     return RLGL_OK;
   }
-  const int nt = o.wg_size, per_cu = o.wg_per_cu;
+  const int nt = o.wg_size, per_cu = o.wg_per_cu == 0 ? 1 : o.wg_per_cu;
   if (nt != 256 && nt != 512 && nt != 1024) return fail(RLGL_EINVAL, "wg_size must be 256, 512 or 1024");
   if (per_cu < 1 || per_cu > 8) return fail(RLGL_EINVAL, "wg_per_cu must be in 1..8");
   int fit = 0;
@@ -1125,7 +1130,7 @@ void rlgl_batch_default_options(rlgl_batch_options *o) {
   o->max_steps = 100000;
   o->refresh = 1;
   o->wg_size = 256;
-  o->wg_per_cu = 8;
+  o->wg_per_cu = 0;
   o->engine = RLGL_BATCH_LOCKSTEP;
   o->check_period = 8;
 }
@@ -1332,7 +1337,7 @@ rlgl_status rlgl_batch_autotune(rlgl_batch *b, double *dev_pi, rlgl_batch_option
   cur.wg_per_cu = b->engine == RLGL_BATCH_LOCKSTEP ? b->ls_per_cu : b->per_cu;
   std::vector<rlgl_batch_options> cands;
   for (int nt : {256, 512})
-    for (int pc : {4, 8, 16}) {
+    for (int pc : {0, 4, 8}) {
       rlgl_batch_options c = cur;
       c.engine = RLGL_BATCH_LOCKSTEP;
       c.wg_size = nt;
@@ -1418,6 +1423,7 @@ bool valid_pool_options(const rlgl_pool_options *o, std::string &why) {
   if (o->wg_size != 256 && o->wg_size != 512) { why = "wg_size must be 256 or 512"; return false; }
   if (o->max_chains < 1 || o->max_chains > (1 << 20)) { why = "max_chains out of range"; return false; }
   if (o->max_steps < 0) { why = "max_steps must be >= 0"; return false; }
+  if (o->route_per_cu < 0 || o->route_per_cu > 16) { why = "route_per_cu must be in 0..16"; return false; }
   return true;
 }
 
@@ -1487,6 +1493,7 @@ void rlgl_pool_default_options(rlgl_pool_options *o) {
   o->wg_size = 256;
   o->max_chains = 256;
   o->max_steps = 100000;
+  o->route_per_cu = 8;
 }
 
 size_t rlgl_pool_workspace_bytes(const rlgl_pool_options *o, size_t arena_bytes) {
@@ -1526,7 +1533,7 @@ rlgl_status rlgl_pool_create(const rlgl_pool_options *o, void *ws, size_t ws_byt
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev))
       return bail(fail(RLGL_EHIP, "device attribute query failed"));
-    p->E.route_grid = std::max(cus, 1) * 8;
+    p->E.route_grid = std::max(cus, 1) * o->route_per_cu;
   }
   p->arena = w + ctl;
   p->arena_bytes = (ws_bytes - lead - ctl) / 256 * 256;

@@ -9,8 +9,10 @@ constexpr int BLOCK = 256;          // threads per workgroup (4 waves of 64)
 constexpr int NWAVE = BLOCK / 64;
 constexpr int VPT = 4;              // nodes per thread in node-parallel passes
 constexpr int TILE = BLOCK * VPT;   // nodes per tile
-constexpr int CH = 2048;            // links per push/pull chunk
-constexpr int RUN_MAX_COLS = 1024; // pull: columns per run item (4 per thread)
+constexpr int CH = 2048;            // links per push chunk and per batched pull item
+constexpr int RUN_MAX_COLS = 1024; // batched pull: columns per run item (4 per thread)
+constexpr int PCH = 1024;          // single-chain pull: links per run item and per long-column piece
+constexpr int PCOLS = 512;         // single-chain pull: columns per run item (2 per thread)
 constexpr int LOG_STEPS = 4096;     // ring of per-step records kept for profiling
 constexpr int MAX_GRID = 2048;      // edge-parallel launches
 constexpr int NODE_GRID = 512;      // node-parallel launches (2 workgroups per CU)

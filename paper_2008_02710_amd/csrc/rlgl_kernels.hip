@@ -531,25 +531,27 @@ struct ColView {
   int unit;  // moved(j) already holds M_j P'_jk: every link weight is 1
 };
 
-// LDS of the column pass.
-template <int NT>
+// LDS of the column pass over items of at most IC links and IK columns.
+template <int NT, int IC = CH, int IK = RUN_MAX_COLS>
 struct ColLds {
-  double con[CH];              // contributions, then inclusive segmented sums
-  unsigned char head[CH];
-  int cp[RUN_MAX_COLS + 1];    // column pointers of the run, relative to p0
+  double con[IC];              // contributions, then inclusive segmented sums
+  unsigned char head[IC];
+  int cp[IK + 1];              // column pointers of the run, relative to p0
   Seg wave[NT / 64];
   double red[4 * (NT / 64)];
 };
 
 // One plan item: adds c * sum_j moved(j) P'_jk + kept(k) + off into out[k]
 // for the item's columns and folds the statistics of those values.
-template <class T, int NT, class Moved, class Kept>
+template <class T, int NT, int IC = CH, int IK = RUN_MAX_COLS, class Moved, class Kept>
 __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved moved, Kept kept, double c,
                                             double off, double rr, T *__restrict__ out, double *long_acc,
-                                            ColLds<NT> &L, double &l1, double &cs, double &sr, double &mx) {
+                                            ColLds<NT, IC, IK> &L, double &l1, double &cs, double &sr,
+                                            double &mx) {
   constexpr int NW = NT / 64;
-  constexpr int U = CH / NT;                 // links per thread
-  constexpr int KC = RUN_MAX_COLS / NT;      // columns per thread
+  constexpr int U = IC / NT;                 // links per thread
+  constexpr int KC = IK / NT;                // columns per thread
+  static_assert(U >= 1 && KC >= 1 && U * NT == IC && KC * NT == IK, "item shape");
   const int *__restrict__ colptr = g.colptr;
   const int *__restrict__ crow = g.crow;
   const T *__restrict__ cval = (const T *)g.cval;
@@ -562,7 +564,7 @@ __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved m
     // RUN: every load below depends on the item alone
     const int k0 = item.x, k1 = item.y, p0 = item.z, p1 = item.w;
     const int ne = p1 - p0, ncol = k1 - k0;
-    if (ne > CH || ne < 0 || ncol > RUN_MAX_COLS || ncol < 0) return;  // the plan never builds such an item
+    if (ne > IC || ne < 0 || ncol > IK || ncol < 0) return;  // the plan never builds such an item
     __syncthreads();
     int jj[U];
     double ww[U];
@@ -644,7 +646,7 @@ __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved m
     // PIECE or WHOLE: a strided walk over [p0, p1) of one column
     const int k = item.y, pb = item.z, pe = item.w;
     double acc = 0.0;
-    for (int p0 = pb; p0 < pe; p0 += CH) {
+    for (int p0 = pb; p0 < pe; p0 += IC) {
       int jj[U];
       double ww[U];
 #pragma unroll
@@ -673,11 +675,11 @@ __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved m
 template <class T, int NT, class Moved, class Kept>
 __device__ __forceinline__ void column_pass(const Dev &d, Moved moved, Kept kept, double off, T *__restrict__ out,
                                             Rec *r) {
-  __shared__ ColLds<NT> L;
+  __shared__ ColLds<NT, PCH, PCOLS> L;
   const ColView g{d.colptr, d.crow, d.rowptr, d.cval, d.n, 0};
   double l1 = 0.0, cs = 0.0, sr = 0.0, mx = 0.0;
   for (int it = blockIdx.x; it < d.n_items; it += gridDim.x)
-    column_item<T, NT>(g, d.items[it], moved, kept, d.c, off, d.r, out, d.long_acc, L, l1, cs, sr, mx);
+    column_item<T, NT, PCH, PCOLS>(g, d.items[it], moved, kept, d.c, off, d.r, out, d.long_acc, L, l1, cs, sr, mx);
   fold_block_stats<NT / 64>(r, l1, cs, sr, mx, L.red);
 }
 

@@ -8,8 +8,8 @@
 //                  scaled green mass M_j / outdeg(j) of every node into the
 //                  chain's source buffer;
 //   k_ls_route   - plan items (the pieces of the long columns of every
-//                  chain first, then runs of at most CH links), strided over
-//                  a machine-sized grid: the CSC gather of eq. (6), C_{t+1}[k] = kept(k) +
+//                  chain first, then runs of at most CH links), one per
+//                  workgroup or strided over a machine-sized grid: the CSC gather of eq. (6), C_{t+1}[k] = kept(k) +
 //                  c sum_j src[j] + T/N, and the statistics of C_{t+1}; a
 //                  piece of a column with more than CH in-links adds its
 //                  partial sum into the chain's FP64 long-column accumulator;
@@ -25,7 +25,8 @@
 // add into the stripes, the control kernel folds and clears them.  Chains
 // that have stopped cost one record load per workgroup until the host drops
 // them from the active list.  The link weights are implicit, 1/outdeg(j) in
-// FP64, so the refresh that confirms a stop is exact to FP64 rounding.
+// FP64, so the refresh that confirms a stop is exact to FP64 rounding (its
+// scaled history H_j / outdeg(j) is gathered in FP64).
 #include "rlgl_device.h"
 
 namespace rlgl {
@@ -128,7 +129,11 @@ __global__ __launch_bounds__(BLOCK) void k_ls_select(LsArgs a) {
     if (mode == LS_FINISH) {
       ch.pi[i] = ls_hist<HK>(ch, i) / hsum;  // eq. (2)
     } else if (mode == LS_REFRESH) {
-      aT += ls_hist<HK>(ch, i) * (dg > 0 ? 1.0 - c : 1.0);
+      // the FP64 scaled history H_j / outdeg(j) for the route, parked in the
+      // output vector, which is not written before the final pass
+      const double h = ls_hist<HK>(ch, i);
+      aT += h * (dg > 0 ? 1.0 - c : 1.0);
+      ch.pi[i] = dg > 0 ? h / (double)dg : 0.0;
     } else if (mode == LS_INIT) {
       // eq. (3): H_1 = M_0 = (1/N) 1, every node green
       if (HK == 0) {
@@ -180,9 +185,94 @@ __global__ __launch_bounds__(BLOCK) void k_ls_select(LsArgs a) {
   }
 }
 
+// One plan item of chain k (its index `local` in the chain's plan): step 0
+// (C_1 = 0 - M_0 + M_0 P), a green-light step, or the refresh C_t = H_t P -
+// H_t (eq. (7) with C_0 = 0) from the FP64 scaled history.  Adds the
+// statistics of the written values to l1..mx.
+template <class T, int HK, int NT>
+__device__ __forceinline__ void ls_item(const LsArgs &a, int k, int mode, int local, double off, ColLds<NT> &L,
+                                        double &l1, double &cs, double &sr, double &mx) {
+  const LsChain ch = a.chains[k];
+  const LsCtl *ctl = &a.ctl[k];
+  const int n = ch.n;
+  const ColView g{ch.colptr, ch.crow, ch.rowptr, nullptr, n, 1};
+  const int buf = ctl->buf;
+  const T *__restrict__ cur = (const T *)(buf ? ch.cash1 : ch.cash0);
+  T *__restrict__ out = (T *)(buf ? ch.cash0 : ch.cash1);
+  const T *__restrict__ src = (const T *)ch.src;
+  const int4 item = ch.items[local];
+  const bool refresh = mode == LS_REFRESH, init = mode == LS_INIT;
+  const double *__restrict__ hs = ch.pi;
+  const double m0 = (double)(T)(1.0 / (double)n);
+  const double theta = ctl->theta, maxabs = ctl->maxabs;
+  const int sched = a.sched;
+  column_item<T, NT>(
+      g, item,
+      [&](int j) -> double {
+        if ((unsigned)j >= (unsigned)n) return 0.0;
+        return refresh ? hs[j] : (double)src[j];
+      },
+      [&](int kk) -> double {
+        if (init) return -m0;
+        if (refresh) return -ls_hist<HK>(ch, kk);
+        const T v = cur[kk];
+        return is_green(v, kk, sched, theta, maxabs, 0.0, -1) ? 0.0 : (double)v;
+      },
+      ch.c, off, a.r, out, ch.long_acc, L, l1, cs, sr, mx);
+}
+
+// The pool T of chain k's pass from its select statistics (one wave adds the
+// stripes), divided by N.
+template <int NT>
+__device__ __forceinline__ double ls_offset(const LsArgs &a, int k, double *sh) {
+  if (threadIdx.x < 64) {
+    double v = threadIdx.x < LS_NS ? a.stats[(size_t)k * LS_NS + threadIdx.x].T : 0.0;
+    v = wave_sum(v);
+    if (threadIdx.x == 0) *sh = v;
+  }
+  __syncthreads();
+  return *sh / (double)a.chains[k].n;
+}
+
+template <int NT>
+__device__ __forceinline__ void ls_fold(const LsArgs &a, int k, int stripe, double l1, double cs, double sr,
+                                        double mx, ColLds<NT> &L) {
+  constexpr int NW = NT / 64;
+  const Red4 t4 = block_sum4<NW>(Red4{l1, cs, sr, 0.0}, L.red);
+  const double bm = block_max<NW>(mx, L.red);
+  if (threadIdx.x == 0) {
+    LsStripe *st = &a.stats[(size_t)k * LS_NS + stripe];
+    if (t4.a != 0.0) atomic_add_f64(&st->l1, t4.a);
+    if (t4.b != 0.0) atomic_add_f64(&st->cs, t4.b);
+    if (t4.c != 0.0) atomic_add_f64(&st->sr, t4.c);
+    if (bm > 0.0) atomic_max_nonneg(&st->mx, bm);
+  }
+}
+
+__device__ __forceinline__ bool ls_routes(int mode) { return mode == LS_INIT || mode == LS_STEP || mode == LS_REFRESH; }
+
+// One workgroup per plan item.
 template <class T, int HK, int NT>
 __global__ __launch_bounds__(NT) void k_ls_route(LsArgs a) {
-  constexpr int NW = NT / 64;
+  __shared__ ColLds<NT> L;
+  __shared__ double sh_T;
+  const bool piece = (int)blockIdx.x < a.w_total;
+  const int b = piece ? (int)blockIdx.x : (int)blockIdx.x - a.w_total;
+  const int ai = ls_find(piece ? a.wpre : a.rpre, a.n_act, b);
+  const int k = a.act[ai];
+  const int mode = a.ctl[k].mode;
+  if (!ls_routes(mode)) return;
+  const int local = piece ? b - a.wpre[ai] : a.chains[k].n_piece + (b - a.rpre[ai]);
+  const double off = ls_offset<NT>(a, k, &sh_T);
+  double l1 = 0.0, cs = 0.0, sr = 0.0, mx = 0.0;
+  ls_item<T, HK, NT>(a, k, mode, local, off, L, l1, cs, sr, mx);
+  ls_fold<NT>(a, k, local % LS_NS, l1, cs, sr, mx, L);
+}
+
+// Plan items strided over a machine-sized grid; the pool and the statistics
+// are kept across consecutive items of one chain.
+template <class T, int HK, int NT>
+__global__ __launch_bounds__(NT) void k_ls_route_strided(LsArgs a) {
   __shared__ ColLds<NT> L;
   __shared__ double sh_T;
   const int total = a.w_total + a.r_total;
@@ -190,76 +280,25 @@ __global__ __launch_bounds__(NT) void k_ls_route(LsArgs a) {
   int kc = -1, mode = LS_IDLE;  // chain of the previous item, its mode
   double off = 0.0;
   double l1 = 0.0, cs = 0.0, sr = 0.0, mx = 0.0;
-  // statistics of the values this workgroup wrote for chain kc
-  auto flush = [&]() {
-    const Red4 t4 = block_sum4<NW>(Red4{l1, cs, sr, 0.0}, L.red);
-    const double bm = block_max<NW>(mx, L.red);
-    if (threadIdx.x == 0) {
-      LsStripe *st = &a.stats[(size_t)kc * LS_NS + stripe];
-      if (t4.a != 0.0) atomic_add_f64(&st->l1, t4.a);
-      if (t4.b != 0.0) atomic_add_f64(&st->cs, t4.b);
-      if (t4.c != 0.0) atomic_add_f64(&st->sr, t4.c);
-      if (bm > 0.0) atomic_max_nonneg(&st->mx, bm);
-    }
-    l1 = cs = sr = mx = 0.0;
-  };
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     const bool piece = it < a.w_total;
     const int b = piece ? it : it - a.w_total;
     const int ai = ls_find(piece ? a.wpre : a.rpre, a.n_act, b);
     const int k = a.act[ai];
     if (k != kc) {
-      if (kc >= 0) flush();
+      if (kc >= 0) {
+        ls_fold<NT>(a, kc, stripe, l1, cs, sr, mx, L);
+        l1 = cs = sr = mx = 0.0;
+      }
       kc = k;
       mode = a.ctl[k].mode;
-      if (mode == LS_INIT || mode == LS_STEP || mode == LS_REFRESH) {
-        // the pool of this pass, from the select statistics
-        if (threadIdx.x < 64) {
-          double v = threadIdx.x < LS_NS ? a.stats[(size_t)k * LS_NS + threadIdx.x].T : 0.0;
-          v = wave_sum(v);
-          if (threadIdx.x == 0) sh_T = v;
-        }
-        __syncthreads();
-        off = sh_T / (double)a.chains[k].n;
-      }
+      if (ls_routes(mode)) off = ls_offset<NT>(a, k, &sh_T);
     }
-    if (mode != LS_INIT && mode != LS_STEP && mode != LS_REFRESH) continue;
-    const LsChain ch = a.chains[k];
-    const LsCtl *ctl = &a.ctl[k];
-    const int local = piece ? b - a.wpre[ai] : ch.n_piece + (b - a.rpre[ai]);
-    const int n = ch.n;
-    const ColView g{ch.colptr, ch.crow, ch.rowptr, nullptr, n, 1};
-    const int buf = ctl->buf;
-    const T *__restrict__ cur = (const T *)(buf ? ch.cash1 : ch.cash0);
-    T *__restrict__ out = (T *)(buf ? ch.cash0 : ch.cash1);
-    const T *__restrict__ src = (const T *)ch.src;
-    const int4 item = ch.items[local];
-    const double c = ch.c, rr = a.r;
-    auto gathered = [&](int j) -> double { return ((unsigned)j < (unsigned)n) ? (double)src[j] : 0.0; };
-    if (mode == LS_REFRESH) {
-      // C_t = H_t P - H_t (eq. (7) with C_0 = 0), FP64 weights 1/outdeg
-      const int *__restrict__ rowptr = ch.rowptr;
-      column_item<T, NT>(
-          g, item, [&](int j) -> double { return ls_hist<HK>(ch, j) * inv_outdeg(rowptr, n, j); },
-          [&](int kk) -> double { return -ls_hist<HK>(ch, kk); }, c, off, rr, out, ch.long_acc, L, l1, cs, sr, mx);
-    } else if (mode == LS_INIT) {
-      // step 0: C_1 = 0 - M_0 + M_0 P
-      const double m0 = (double)(T)(1.0 / (double)n);
-      column_item<T, NT>(g, item, gathered, [&](int) -> double { return -m0; }, c, off, rr, out, ch.long_acc, L, l1,
-                         cs, sr, mx);
-    } else {
-      const double theta = ctl->theta, maxabs = ctl->maxabs;
-      const int sched = a.sched;
-      column_item<T, NT>(
-          g, item, gathered,
-          [&](int kk) -> double {
-            const T v = cur[kk];
-            return is_green(v, kk, sched, theta, maxabs, 0.0, -1) ? 0.0 : (double)v;
-          },
-          c, off, rr, out, ch.long_acc, L, l1, cs, sr, mx);
-    }
+    if (!ls_routes(mode)) continue;
+    const int local = piece ? b - a.wpre[ai] : a.chains[k].n_piece + (b - a.rpre[ai]);
+    ls_item<T, HK, NT>(a, k, mode, local, off, L, l1, cs, sr, mx);
   }
-  if (kc >= 0) flush();
+  if (kc >= 0) ls_fold<NT>(a, kc, stripe, l1, cs, sr, mx, L);
 }
 
 // One wave per active chain.
@@ -474,6 +513,12 @@ template __global__ void k_ls_route<double, 0, 256>(LsArgs);
 template __global__ void k_ls_route<float, 0, 512>(LsArgs);
 template __global__ void k_ls_route<float, 1, 512>(LsArgs);
 template __global__ void k_ls_route<double, 0, 512>(LsArgs);
+template __global__ void k_ls_route_strided<float, 0, 256>(LsArgs);
+template __global__ void k_ls_route_strided<float, 1, 256>(LsArgs);
+template __global__ void k_ls_route_strided<double, 0, 256>(LsArgs);
+template __global__ void k_ls_route_strided<float, 0, 512>(LsArgs);
+template __global__ void k_ls_route_strided<float, 1, 512>(LsArgs);
+template __global__ void k_ls_route_strided<double, 0, 512>(LsArgs);
 template __global__ void k_ls_control<float, 0>(LsArgs);
 template __global__ void k_ls_control<float, 1>(LsArgs);
 template __global__ void k_ls_control<double, 0>(LsArgs);

@@ -108,7 +108,7 @@ def test_batch_autotune_and_repeat():
     db = rl.DeviceBatch(gs, precision=rl.FP32C_KAHANH)
     bs = rl.BatchSolver(db, eps=1e-7, max_steps=20000)
     best = bs.autotune()
-    assert best["wg_size"] in (256, 512, 1024) and 1 <= best["wg_per_cu"] <= 16
+    assert best["wg_size"] in (256, 512, 1024) and 0 <= best["wg_per_cu"] <= 16
     st, res, ms = bs.solve()
     assert st == rl.RLGL_OK
     pa = to_np(bs.pi).copy()
