@@ -233,6 +233,8 @@ def main():
     ap.add_argument("--route", default="auto", choices=["auto", "push", "pull"])
     ap.add_argument("--precision", default="fp32c_fp64h", choices=["fp64", "fp32c_fp64h", "fp32c_kahanh"])
     ap.add_argument("--tol", type=float, default=1e-6, help="certified L1 target")
+    ap.add_argument("--relabel", type=int, default=1, choices=[0, 1],
+                    help="renumber the states by decreasing out-degree inside the library (layout step)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-ref", action="store_true", help="skip the FP64 power-iteration reference")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -280,7 +282,7 @@ def main():
     dev = torch.device("cuda:0")
     dg = rl.DeviceGraph.from_workload(g, precision=prec, with_csc=True, explicit_val=True, device=dev)
     stream = torch.cuda.current_stream(dev)
-    s = rl.Solver(dg, stream=stream, sched=sched, r=wl["r"], route=route, precision=prec)
+    s = rl.Solver(dg, stream=stream, sched=sched, r=wl["r"], route=route, precision=prec, relabel=args.relabel)
     eps = (1.0 - g.c) * args.tol
     max_steps = 100000
 
@@ -382,7 +384,7 @@ def main():
             opushes += st.edges
         tcpu = time.perf_counter() - a
         sample = (f"{solves} full serial FP64 oracle solves of the same graph to the same eps ({steps} steps)"
-                  if st is None else
+                  if st is None or st.t <= 1 else
                   f"{solves} full solves and the first {st.t - 1} steps of another: serial FP64 oracle steps of "
                   f"the same graph and schedule, {steps} steps in all")
         cpu = {"value": round(opushes / tcpu / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
@@ -408,6 +410,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": g.name, "n": g.n, "nnz": g.nnz, "dangling": g.n_dangling, "damping": g.c,
                    "schedule": wl["sched"], "r": wl["r"], "precision": args.precision, "route": args.route,
+                   "relabel": args.relabel,
                    "eps_resid": eps, "tol_l1": args.tol, "generator": g.params.get("generator"),
                    "seed": g.params.get("seed")},
         "steps_per_solve": last["t"] - 1,

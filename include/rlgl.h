@@ -102,6 +102,11 @@ typedef struct {
   int32_t refresh;            /* rebuild C_t = H_t P - H_t in FP64 (needs the CSC; see rlgl_refresh):
                                  0 never; 1 in rlgl_solve before a stop is accepted and whenever |C_t 1| exceeds
                                  ||C_t||_1 / 2 (rounding drift); k > 1 also every k steps of rlgl_solve */
+  int32_t relabel;            /* non-zero: rlgl_create renumbers the states internally by decreasing out-degree
+                                 (ties by id) and keeps relabelled copies of the CSR/CSC in the workspace, so
+                                 the cash of the states gathered most often shares cache lines; every value
+                                 that crosses this interface (C, H, the green mask, pi_hat) stays in the
+                                 caller's numbering.  Not with RLGL_SCHED_TOPK (its ties go by id) */
 } rlgl_options;
 
 /* Snapshot of the solver after the last enqueued step. */
@@ -121,11 +126,12 @@ typedef struct {
 
 /* Fills *opt with the defaults: THRESHOLD, r = 1, k = 1, theta_period = 1,
  * FP32C_FP64H, AUTO, pull_alpha = 0.15, check_period = 0, record_green = 0,
- * refresh = 1. */
+ * refresh = 1, relabel = 0. */
 void rlgl_default_options(rlgl_options *opt);
 
 /* Device workspace the context needs, in bytes (0 on a bad argument).  Depends
- * on n, nnz, the precision and whether the CSC is given. */
+ * on n, nnz, the precision, whether the CSC and the link values are given and
+ * on relabel. */
 size_t rlgl_workspace_bytes(const rlgl_graph *g, const rlgl_options *opt);
 
 /* Checks the arguments, lays out the workspace, builds the static pull plan

@@ -37,7 +37,7 @@ class rlgl_options(ctypes.Structure):
     _fields_ = [("sched", ctypes.c_int32), ("r", ctypes.c_double), ("k", ctypes.c_int64),
                 ("theta_period", ctypes.c_int32), ("precision", ctypes.c_int32), ("route", ctypes.c_int32),
                 ("pull_alpha", ctypes.c_double), ("check_period", ctypes.c_int32),
-                ("record_green", ctypes.c_int32), ("refresh", ctypes.c_int32)]
+                ("record_green", ctypes.c_int32), ("refresh", ctypes.c_int32), ("relabel", ctypes.c_int32)]
 
 
 class rlgl_step_info(ctypes.Structure):

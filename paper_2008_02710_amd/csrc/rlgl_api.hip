@@ -52,9 +52,11 @@ struct Layout {
       hot_nodes, rec, glob,
       log, items, long_cols, long_acc, total;
   size_t max_items, max_long;
+  // relabelled layout
+  size_t perm, old2new, nrowptr, ncol, nval, ncolptr, nrow, ncval;
 };
 
-Layout make_layout(long long n, long long nnz, int prec, bool has_csc) {
+Layout make_layout(long long n, long long nnz, int prec, bool has_csc, bool relabel = false, bool has_val = false) {
   Layout L{};
   const size_t cs = (prec == RLGL_FP64) ? 8 : 4;
   size_t off = 0;
@@ -90,6 +92,19 @@ Layout make_layout(long long n, long long nnz, int prec, bool has_csc) {
     L.long_cols = take(4 * L.max_long);
     L.long_acc = take(8 * L.max_long);
   }
+  if (relabel) {
+    const size_t vs = (prec == RLGL_FP64) ? 8 : 4;
+    L.perm = take(4 * n);
+    L.old2new = take(4 * n);
+    L.nrowptr = take(4 * (n + 1));
+    L.ncol = take(4 * (size_t)nnz);
+    L.nval = has_val ? take(vs * (size_t)nnz) : 0;
+    if (has_csc) {
+      L.ncolptr = take(4 * (n + 1));
+      L.nrow = take(4 * (size_t)nnz);
+      L.ncval = has_val ? take(vs * (size_t)nnz) : 0;
+    }
+  }
   L.total = off + 256;
   return L;
 }
@@ -104,6 +119,7 @@ bool valid_options(const rlgl_options *o, std::string &why) {
   if (!(o->pull_alpha >= 0.0)) { why = "pull_alpha must be >= 0"; return false; }
   if (o->check_period < 0) { why = "check_period must be >= 0"; return false; }
   if (o->refresh < 0) { why = "refresh must be >= 0"; return false; }
+  if (o->relabel && o->sched == RLGL_SCHED_TOPK) { why = "relabel does not combine with TOPK"; return false; }
   return true;
 }
 
@@ -272,6 +288,103 @@ rlgl_status status_of(int dev_status) {
   }
 }
 
+// Relabelled layout (a1): states renumbered by decreasing out-degree, ties by
+// id (a stable counting sort on the host, from the row pointers), and the CSR
+// and CSC rewritten in the new numbering into the workspace by k_relabel_side.
+// gi receives the relabelled graph; the context keeps the new -> old map.
+rlgl_status relabel_graph(rlgl_ctx *c, const rlgl_graph *g, const Layout &L, char *w, rlgl_graph &gi) {
+  const int n = g->n;
+  Dev &d = c->d;
+  std::vector<int> rp((size_t)n + 1), cp(g->csc_colptr ? (size_t)n + 1 : 0);
+  HIP_TRY(hipMemcpyAsync(rp.data(), g->csr_rowptr, sizeof(int) * ((size_t)n + 1), hipMemcpyDeviceToHost, c->stream));
+  if (g->csc_colptr)
+    HIP_TRY(hipMemcpyAsync(cp.data(), g->csc_colptr, sizeof(int) * ((size_t)n + 1), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (rp[0] != 0) return fail(RLGL_EINVAL, "csr_rowptr[0] must be 0");
+  int maxdeg = 0;
+  for (int i = 0; i < n; ++i) {
+    const int dg = rp[i + 1] - rp[i];
+    if (dg < 0) return fail(RLGL_EINVAL, "csr_rowptr decreases at %d", i);
+    maxdeg = std::max(maxdeg, dg);
+  }
+  if (g->csc_colptr) {
+    if (cp[0] != 0 || (long long)cp[n] != g->nnz) return fail(RLGL_EINVAL, "csc_colptr must run from 0 to nnz");
+    for (int i = 0; i < n; ++i)
+      if (cp[i + 1] < cp[i]) return fail(RLGL_EINVAL, "csc_colptr decreases at %d", i);
+  }
+  std::vector<int> new2old((size_t)n), old2new((size_t)n);
+  if ((long long)maxdeg <= 4ll * n + 1024) {
+    // counting sort by degree, largest first, stable in the id
+    std::vector<long long> start((size_t)maxdeg + 2, 0);
+    for (int i = 0; i < n; ++i) ++start[(size_t)(maxdeg - (rp[i + 1] - rp[i]))];
+    long long acc = 0;
+    for (auto &x : start) {
+      const long long cnt = x;
+      x = acc;
+      acc += cnt;
+    }
+    for (int i = 0; i < n; ++i) new2old[(size_t)start[(size_t)(maxdeg - (rp[i + 1] - rp[i]))]++] = i;
+  } else {
+    for (int i = 0; i < n; ++i) new2old[i] = i;
+    std::stable_sort(new2old.begin(), new2old.end(),
+                     [&](int a, int b) { return rp[a + 1] - rp[a] > rp[b + 1] - rp[b]; });
+  }
+  for (int i = 0; i < n; ++i) old2new[new2old[i]] = i;
+  std::vector<int> nrp((size_t)n + 1), ncp(g->csc_colptr ? (size_t)n + 1 : 0);
+  nrp[0] = 0;
+  for (int i = 0; i < n; ++i) nrp[i + 1] = nrp[i] + (rp[new2old[i] + 1] - rp[new2old[i]]);
+  if (g->csc_colptr) {
+    ncp[0] = 0;
+    for (int i = 0; i < n; ++i) ncp[i + 1] = ncp[i] + (cp[new2old[i] + 1] - cp[new2old[i]]);
+  }
+  int *d_perm = (int *)(w + L.perm), *d_o2n = (int *)(w + L.old2new), *d_nrp = (int *)(w + L.nrowptr);
+  HIP_TRY(hipMemcpyAsync(d_perm, new2old.data(), sizeof(int) * (size_t)n, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(d_o2n, old2new.data(), sizeof(int) * (size_t)n, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(d_nrp, nrp.data(), sizeof(int) * ((size_t)n + 1), hipMemcpyHostToDevice, c->stream));
+  int *d_ncp = nullptr;
+  if (g->csc_colptr) {
+    d_ncp = (int *)(w + L.ncolptr);
+    HIP_TRY(hipMemcpyAsync(d_ncp, ncp.data(), sizeof(int) * ((size_t)n + 1), hipMemcpyHostToDevice, c->stream));
+  }
+  const int grid = std::max(1, std::min((n + (BLOCK / 64) - 1) / (BLOCK / 64), 8192));
+  int *ncol = (int *)(w + L.ncol);
+  void *nval = g->csr_val ? (void *)(w + L.nval) : nullptr;
+  if (c->prec == RLGL_FP64)
+    k_relabel_side<double><<<grid, BLOCK, 0, c->stream>>>(n, g->csr_rowptr, g->csr_col, (const double *)g->csr_val,
+                                                          d_perm, d_o2n, d_nrp, ncol, (double *)nval);
+  else
+    k_relabel_side<float><<<grid, BLOCK, 0, c->stream>>>(n, g->csr_rowptr, g->csr_col, (const float *)g->csr_val,
+                                                         d_perm, d_o2n, d_nrp, ncol, (float *)nval);
+  gi.csr_rowptr = d_nrp;
+  gi.csr_col = ncol;
+  gi.csr_val = nval;
+  if (g->csc_colptr) {
+    int *nrow = (int *)(w + L.nrow);
+    void *ncval = g->csc_val ? (void *)(w + L.ncval) : nullptr;
+    if (c->prec == RLGL_FP64)
+      k_relabel_side<double><<<grid, BLOCK, 0, c->stream>>>(n, g->csc_colptr, g->csc_row,
+                                                            (const double *)g->csc_val, d_perm, d_o2n, d_ncp, nrow,
+                                                            (double *)ncval);
+    else
+      k_relabel_side<float><<<grid, BLOCK, 0, c->stream>>>(n, g->csc_colptr, g->csc_row, (const float *)g->csc_val,
+                                                           d_perm, d_o2n, d_ncp, nrow, (float *)ncval);
+    gi.csc_colptr = d_ncp;
+    gi.csc_row = nrow;
+    gi.csc_val = ncval;
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  d.rowptr = gi.csr_rowptr;
+  d.col = gi.csr_col;
+  d.val = gi.csr_val;
+  d.colptr = gi.csc_colptr;
+  d.crow = gi.csc_row;
+  d.cval = gi.csc_val;
+  d.perm = d_perm;
+  return RLGL_OK;
+}
+
 // Host-side construction of the static pull plan from the CSC column pointers.
 rlgl_status build_plan(rlgl_ctx *c, const rlgl_graph *g, const Layout &L, char *ws) {
   const int n = g->n;
@@ -388,7 +501,8 @@ const char *rlgl_last_error(void) { return g_err.c_str(); }
 
 size_t rlgl_workspace_bytes(const rlgl_graph *g, const rlgl_options *o) {
   if (!g || !o || g->n < 1 || g->nnz < 0 || o->precision < 0 || o->precision > 2) return 0;
-  return make_layout(g->n, g->nnz, o->precision, g->csc_colptr != nullptr).total;
+  return make_layout(g->n, g->nnz, o->precision, g->csc_colptr != nullptr, o->relabel != 0, g->csr_val != nullptr)
+      .total;
 }
 
 rlgl_status rlgl_create(const rlgl_graph *g, const rlgl_options *o, void *ws, size_t ws_bytes, void *stream,
@@ -406,7 +520,8 @@ rlgl_status rlgl_create(const rlgl_graph *g, const rlgl_options *o, void *ws, si
   if ((g->csr_val == nullptr) != (g->csc_colptr ? g->csc_val == nullptr : g->csr_val == nullptr))
     return fail(RLGL_EINVAL, "csr_val and csc_val must both be given or both be NULL");
   if (!ws) return fail(RLGL_EINVAL, "workspace is NULL");
-  const Layout L = make_layout(g->n, g->nnz, o->precision, g->csc_colptr != nullptr);
+  const Layout L =
+      make_layout(g->n, g->nnz, o->precision, g->csc_colptr != nullptr, o->relabel != 0, g->csr_val != nullptr);
   if (ws_bytes < L.total) return fail(RLGL_ENOMEM, "workspace too small: %zu < %zu", ws_bytes, L.total);
 
   rlgl_ctx *c = new (std::nothrow) rlgl_ctx();
@@ -457,6 +572,7 @@ rlgl_status rlgl_create(const rlgl_graph *g, const rlgl_options *o, void *ws, si
   d.long_cols = nullptr;
   d.long_acc = nullptr;
   d.n_long = 0;
+  d.perm = nullptr;
 
   const int tiles = (g->n + TILE - 1) / TILE;
   c->grid_sel = std::max(1, std::min(tiles, NODE_GRID));
@@ -476,8 +592,10 @@ rlgl_status rlgl_create(const rlgl_graph *g, const rlgl_options *o, void *ws, si
     else if ((long long)last != g->nnz)
       st = fail(RLGL_EINVAL, "csr_rowptr[n] = %d differs from nnz = %lld", last, (long long)g->nnz);
   }
-  if (st == RLGL_OK && g->csc_colptr) st = build_plan(c, g, L, w);
-  if (st == RLGL_OK) st = build_hot(c, g, L, w);
+  rlgl_graph gi = *g;  // the graph the kernels see: the caller's, or its relabelled copy
+  if (st == RLGL_OK && o->relabel) st = relabel_graph(c, g, L, w, gi);
+  if (st == RLGL_OK && gi.csc_colptr) st = build_plan(c, &gi, L, w);
+  if (st == RLGL_OK) st = build_hot(c, &gi, L, w);
   if (st == RLGL_OK) {
     c->grid_cmp = std::max({1, std::min(tiles, NODE_GRID), std::min(d.n_items, MAX_GRID)});
     st = reset_device(c);
@@ -622,7 +740,12 @@ rlgl_status rlgl_set_state(rlgl_ctx *c, const double *dC, const double *dH, doub
 rlgl_status rlgl_get_green(rlgl_ctx *c, uint8_t *dmask) {
   if (!c || !dmask) return fail(RLGL_EINVAL, "bad argument");
   if (!c->has_mask) return fail(RLGL_EINVAL, "the context was created without record_green");
-  HIP_TRY(hipMemcpyAsync(dmask, c->d.green_mask, (size_t)c->d.n, hipMemcpyDeviceToDevice, c->stream));
+  if (c->d.perm) {
+    k_export_mask<<<c->grid_misc, BLOCK, 0, c->stream>>>(c->d, dmask);
+    HIP_TRY(hipGetLastError());
+  } else {
+    HIP_TRY(hipMemcpyAsync(dmask, c->d.green_mask, (size_t)c->d.n, hipMemcpyDeviceToDevice, c->stream));
+  }
   HIP_TRY(hipStreamSynchronize(c->stream));
   return RLGL_OK;
 }

@@ -121,6 +121,8 @@ struct Dev {
   const int *long_cols;
   double *long_acc;
   int n_long;
+  // relabelled layout: internal index -> caller's id (NULL: the caller's numbering)
+  const int *perm;
 };
 
 // Host-side sum of the stripes (same order as the device).

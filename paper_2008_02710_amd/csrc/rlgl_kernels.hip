@@ -969,7 +969,7 @@ __global__ __launch_bounds__(BLOCK) void k_normalize(Dev d, double *pi) {
   const double hs = d.rec[t % 3].hsum;
   const int n = d.n;
   for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
-    pi[i] = hist_at<HK>(d, i) / hs;  // pi_hat_t = H_t / (H_t 1), eq. (2)
+    pi[d.perm ? d.perm[i] : i] = hist_at<HK>(d, i) / hs;  // pi_hat_t = H_t / (H_t 1), eq. (2)
   }
 }
 
@@ -979,8 +979,35 @@ __global__ __launch_bounds__(BLOCK) void k_export(Dev d, double *Cout, double *H
   const T *C = (const T *)d.cash[d.rec[t % 3].buf];
   const int n = d.n;
   for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
-    if (Cout) Cout[i] = (double)C[i];
-    if (Hout) Hout[i] = hist_at<HK>(d, i);
+    const int o = d.perm ? d.perm[i] : i;
+    if (Cout) Cout[o] = (double)C[i];
+    if (Hout) Hout[o] = hist_at<HK>(d, i);
+  }
+}
+
+// Green mask of the last step in the caller's numbering.
+__global__ __launch_bounds__(BLOCK) void k_export_mask(Dev d, unsigned char *out) {
+  for (int i = blockIdx.x * BLOCK + threadIdx.x; i < d.n; i += gridDim.x * BLOCK)
+    out[d.perm ? d.perm[i] : i] = d.green_mask[i];
+}
+
+// Relabelled copy of one side of the graph (CSR or CSC): new row i is old row
+// new2old[i], its ids mapped through old2new (ids outside [0, n) are kept, so
+// the kernels still ignore them).  One wave per row.
+template <class V>
+__global__ __launch_bounds__(BLOCK) void k_relabel_side(int n, const int *ptr, const int *idx, const V *val,
+                                                        const int *new2old, const int *old2new, const int *nptr,
+                                                        int *nidx, V *nval) {
+  const int lane = threadIdx.x & 63;
+  const int waves = gridDim.x * (BLOCK / 64);
+  for (int i = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6); i < n; i += waves) {
+    const int o = new2old[i];
+    const int b = ptr[o], deg = ptr[o + 1] - b, dst = nptr[i];
+    for (int e = lane; e < deg; e += 64) {
+      const int j = idx[b + e];
+      nidx[dst + e] = ((unsigned)j < (unsigned)n) ? old2new[j] : j;
+      if (val) nval[dst + e] = val[b + e];
+    }
   }
 }
 
@@ -996,10 +1023,11 @@ __global__ __launch_bounds__(BLOCK) void k_import(Dev d, const double *Cin, cons
   __shared__ double sh_red[4 * NWAVE];
   for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
     if (d.delta) d.delta[i] = 0.0;
-    const T x = (T)Cin[i];
+    const int o = d.perm ? d.perm[i] : i;
+    const T x = (T)Cin[o];
     C[i] = x;
     fold_stats((double)x, r, l1, cs, sr, mx);
-    const double h = Hin[i];
+    const double h = Hin[o];
     if (HK == 0) {
       ((double *)d.hist)[i] = h;
       hs += h;
@@ -1088,5 +1116,9 @@ template __global__ void k_export<double, 0>(Dev, double *, double *);
 template __global__ void k_import<float, 0>(Dev, const double *, const double *, long long, int);
 template __global__ void k_import<float, 1>(Dev, const double *, const double *, long long, int);
 template __global__ void k_import<double, 0>(Dev, const double *, const double *, long long, int);
+template __global__ void k_relabel_side<float>(int, const int *, const int *, const float *, const int *,
+                                               const int *, const int *, int *, float *);
+template __global__ void k_relabel_side<double>(int, const int *, const int *, const double *, const int *,
+                                                const int *, const int *, int *, double *);
 
 }  // namespace rlgl

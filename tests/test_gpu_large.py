@@ -46,12 +46,13 @@ def graph(name):
 
 
 @pytest.mark.timeout(900)
+@pytest.mark.parametrize("relabel", [0, 1])
 @pytest.mark.parametrize("name", ["chung_lu_2p20", "rmat_s24"])
-def test_full_size_solve_certified(name):
+def test_full_size_solve_certified(name, relabel):
     g, dg, ch = graph(name)
-    say("case full_solve", name)
+    say("case full_solve", name, "relabel" if relabel else "")
     eps = (1 - g.c) * 1e-6
-    s = rl.Solver(dg, sched=rl.SCHED_THRESHOLD, route=rl.ROUTE_AUTO, precision=rl.FP32C_FP64H)
+    s = rl.Solver(dg, sched=rl.SCHED_THRESHOLD, route=rl.ROUTE_AUTO, precision=rl.FP32C_FP64H, relabel=relabel)
     st, info = s.solve(eps, max_steps=100000)
     assert st == rl.RLGL_OK and info["resid"] < eps
     pi = to_np(s.pi)
@@ -64,18 +65,18 @@ def test_full_size_solve_certified(name):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("route", ["pull", "push"])
+@pytest.mark.parametrize("route,relabel", [("pull", 0), ("push", 0), ("pull", 1)])
 @pytest.mark.parametrize("name", ["chung_lu_2p20", "rmat_s24"])
-def test_full_size_one_step_parity(name, route):
+def test_full_size_one_step_parity(name, route, relabel):
     g, dg, ch = graph(name)
-    say("case full_step", name, route)
+    say("case full_step", name, route, "relabel" if relabel else "")
     s = rl.Solver(dg, sched=rl.SCHED_THRESHOLD, route=rl.ROUTE_AUTO, precision=rl.FP32C_FP64H, record_green=1)
     s.step(3)
     C, H, info0 = s.state()
     C, H = to_np(C).astype(np.float64), to_np(H)
     s.close()
     # the same state, one step with the route forced
-    s = rl.Solver(dg, sched=rl.SCHED_THRESHOLD, precision=rl.FP32C_FP64H, record_green=1,
+    s = rl.Solver(dg, sched=rl.SCHED_THRESHOLD, precision=rl.FP32C_FP64H, record_green=1, relabel=relabel,
                   route=rl.ROUTE_PULL if route == "pull" else rl.ROUTE_PUSH)
     s.set_state(torch.from_numpy(C).cuda(), torch.from_numpy(H).cuda(), info0["h_sum"],
                 t=info0["t"])

@@ -104,10 +104,24 @@ def _nontrivial_state(g, prec, steps=3):
 @pytest.mark.parametrize("sched", ["all", "threshold", "topk", "maxc"])
 @pytest.mark.parametrize("which", ["small", "hub"])
 def test_single_step_parity(prec, route, sched, which):
+    _step_parity(prec, route, sched, which, relabel=0)
+
+
+@pytest.mark.parametrize("prec", [rl.FP64, rl.FP32C_KAHANH], ids=PREC_NAMES.get)
+@pytest.mark.parametrize("route", ["push", "pull"])
+@pytest.mark.parametrize("sched", ["all", "threshold", "maxc"])
+@pytest.mark.parametrize("which", ["small", "hub"])
+def test_relabel_single_step_parity(prec, route, sched, which):
+    """The relabelled layout: state in and out, the green mask and the step
+    itself, all in the caller's numbering, against the oracle."""
+    _step_parity(prec, route, sched, which, relabel=1)
+
+
+def _step_parity(prec, route, sched, which, relabel):
     g = small_graph() if which == "small" else hub_graph()
-    say("case single_step", which, PREC_NAMES[prec], route, sched)
+    say("case single_step", which, PREC_NAMES[prec], route, sched, "relabel" if relabel else "")
     k = 97
-    s = solver(g, prec, route=ROUTES[route], sched=SCHEDS[sched], k=k, record_green=1)
+    s = solver(g, prec, route=ROUTES[route], sched=SCHEDS[sched], k=k, record_green=1, relabel=relabel)
     C0, H0, hs0 = _nontrivial_state(g, prec)
     s.set_state(torch.from_numpy(C0).cuda(), torch.from_numpy(H0).cuda(), hs0, t=4)
     Cg, Hg, info0 = s.state()
@@ -295,3 +309,27 @@ def test_two_wheels_closed_form():
         assert st == rl.RLGL_OK
         assert l1(to_np(s.pi), ref) <= 1e-11
         s.close()
+
+
+@pytest.mark.parametrize("prec", [rl.FP64, rl.FP32C_FP64H], ids=PREC_NAMES.get)
+@pytest.mark.parametrize("which", ["small", "hub"])
+def test_relabel_solve_matches_plain(prec, which):
+    """Relabelled and plain layouts: the same chain, the same stop, pi_hat
+    in the caller's numbering within the precision's tolerance of each other
+    and of the FP64 reference."""
+    g = small_graph() if which == "small" else hub_graph()
+    say("case relabel_solve", which, PREC_NAMES[prec])
+    tol = tol_solve(prec)
+    eps = (1 - g.c) * tol * 0.5
+    out = []
+    for relabel in (0, 1):
+        s = solver(g, prec, sched=rl.SCHED_THRESHOLD, relabel=relabel)
+        st, info = s.solve(eps)
+        assert st == rl.RLGL_OK
+        out.append((info, to_np(s.pi).copy()))
+        s.close()
+    (ia, pa), (ib, pb) = out
+    assert abs(ia["t"] - ib["t"]) <= 1
+    assert l1(pa, pb) <= 2 * tol
+    assert l1(pb, reference(g)) <= tol
+    assert abs(ia["edges_pushed"] - ib["edges_pushed"]) <= 0.01 * ia["edges_pushed"]
