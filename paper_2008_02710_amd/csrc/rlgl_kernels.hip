@@ -541,13 +541,56 @@ struct ColLds {
   double red[4 * (NT / 64)];
 };
 
+// LDS staging of a run item's CSC sources (and FP32 link values), filled by
+// direct global-to-LDS loads while the previous item is being summed.
+template <class T, int IC, int IK>
+struct ColStage {
+  int row[IC];
+  T val[sizeof(T) == 4 ? IC : 1];
+  int cp[IK + 64];  // the run's column pointers (absolute), IK + 1 used
+};
+
+// Issues the direct-to-LDS loads of a run item's sources (and values) into S:
+// lane l of the wave with base thread b writes the entry u*NT + b + l.
+template <class T, int NT, int IC, int IK>
+__device__ __forceinline__ void stage_item(const ColView &g, int4 item, ColStage<T, IC, IK> &S) {
+  if (item.x < 0) return;
+  const int k0 = item.x, ncol = item.y - item.x;
+  const int p0 = item.z, ne = item.w - item.z;
+  if (ne < 0 || ne > IC || ncol < 0 || ncol > IK) return;
+  const int wb = threadIdx.x & ~63;
+  for (int q0 = 0; q0 <= ncol; q0 += NT) {
+    const int q = q0 + (int)threadIdx.x;
+    if (q <= ncol)
+      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(g.colptr + k0 + q),
+                                       (void __attribute__((address_space(3))) *)(&S.cp[q0 + wb]), 4, 0, 0);
+  }
+  const bool vals = sizeof(T) == 4 && g.cval != nullptr && !g.unit;
+#pragma unroll
+  for (int u = 0; u < IC / NT; ++u) {
+    const int e = u * NT + (int)threadIdx.x;
+    if (e < ne) {
+      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(g.crow + p0 + e),
+                                       (void __attribute__((address_space(3))) *)(&S.row[u * NT + wb]), 4, 0, 0);
+      if (vals)
+        __builtin_amdgcn_global_load_lds(
+            (const void __attribute__((address_space(1))) *)((const T *)g.cval + p0 + e),
+            (void __attribute__((address_space(3))) *)(&S.val[u * NT + wb]), 4, 0, 0);
+    }
+  }
+}
+
 // One plan item: adds c * sum_j moved(j) P'_jk + kept(k) + off into out[k]
-// for the item's columns and folds the statistics of those values.
-template <class T, int NT, int IC = CH, int IK = RUN_MAX_COLS, class Moved, class Kept>
+// for the item's columns and folds the statistics of those values.  With
+// STAGED, a run item's sources (and FP32 values) come from the stage S, filled
+// by stage_item for this item beforehand, and the loads of `next` are issued
+// into S as soon as this item has read it.
+template <class T, int NT, int IC = CH, int IK = RUN_MAX_COLS, bool STAGED = false, class Moved, class Kept>
 __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved moved, Kept kept, double c,
                                             double off, double rr, T *__restrict__ out, double *long_acc,
                                             ColLds<NT, IC, IK> &L, double &l1, double &cs, double &sr,
-                                            double &mx) {
+                                            double &mx, ColStage<T, IC, IK> *S = nullptr,
+                                            int4 next = make_int4(-1, 0, 0, 0)) {
   constexpr int NW = NT / 64;
   constexpr int U = IC / NT;                 // links per thread
   constexpr int KC = IK / NT;                // columns per thread
@@ -565,14 +608,25 @@ __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved m
     const int k0 = item.x, k1 = item.y, p0 = item.z, p1 = item.w;
     const int ne = p1 - p0, ncol = k1 - k0;
     if (ne > IC || ne < 0 || ncol > IK || ncol < 0) return;  // the plan never builds such an item
+    if (STAGED) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's loads into the stage
     __syncthreads();
     int jj[U];
     double ww[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = u * NT + tid;
-      jj[u] = (e < ne) ? crow[p0 + e] : -1;
-      ww[u] = (e < ne && cval && !unit) ? (double)cval[p0 + e] : 0.0;
+      if (STAGED) {
+        jj[u] = (e < ne) ? S->row[e] : -1;
+        ww[u] = (e < ne && cval && !unit) ? (sizeof(T) == 4 ? (double)S->val[e] : (double)cval[p0 + e]) : 0.0;
+      } else {
+        jj[u] = (e < ne) ? crow[p0 + e] : -1;
+        ww[u] = (e < ne && cval && !unit) ? (double)cval[p0 + e] : 0.0;
+      }
+    }
+    if (STAGED) {
+      for (int q = tid; q <= ncol; q += NT) L.cp[q] = S->cp[q] - p0;
+      __syncthreads();  // every wave has read the stage
+      stage_item<T, NT, IC, IK>(g, next, *S);
     }
     double kv[KC];
 #pragma unroll
@@ -580,7 +634,8 @@ __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved m
       const int q = m * NT + tid;
       kv[m] = (q < ncol) ? kept(k0 + q) : 0.0;
     }
-    for (int q = tid; q <= ncol; q += NT) L.cp[q] = colptr[k0 + q] - p0;
+    if (!STAGED)
+      for (int q = tid; q <= ncol; q += NT) L.cp[q] = colptr[k0 + q] - p0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = u * NT + tid;
@@ -644,6 +699,11 @@ __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved m
     }
   } else {
     // PIECE or WHOLE: a strided walk over [p0, p1) of one column
+    if (STAGED) {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+      stage_item<T, NT, IC, IK>(g, next, *S);
+    }
     const int k = item.y, pb = item.z, pe = item.w;
     double acc = 0.0;
     for (int p0 = pb; p0 < pe; p0 += IC) {
@@ -676,17 +736,25 @@ template <class T, int NT, class Moved, class Kept>
 __device__ __forceinline__ void column_pass(const Dev &d, Moved moved, Kept kept, double off, T *__restrict__ out,
                                             Rec *r) {
   __shared__ ColLds<NT, PCH, PCOLS> L;
+  __shared__ ColStage<T, PCH, PCOLS> S;
   const ColView g{d.colptr, d.crow, d.rowptr, d.cval, d.n, 0};
   double l1 = 0.0, cs = 0.0, sr = 0.0, mx = 0.0;
-  for (int it = blockIdx.x; it < d.n_items; it += gridDim.x)
-    column_item<T, NT, PCH, PCOLS>(g, d.items[it], moved, kept, d.c, off, d.r, out, d.long_acc, L, l1, cs, sr, mx);
+  // software pipeline: the sources of item it + gridDim.x load into the stage
+  // while item it is gathered and summed
+  if ((int)blockIdx.x < d.n_items) stage_item<T, NT, PCH, PCOLS>(g, d.items[blockIdx.x], S);
+  for (int it = blockIdx.x; it < d.n_items; it += gridDim.x) {
+    const int nx = it + (int)gridDim.x;
+    const int4 next = nx < d.n_items ? d.items[nx] : make_int4(-1, 0, 0, 0);
+    column_item<T, NT, PCH, PCOLS, true>(g, d.items[it], moved, kept, d.c, off, d.r, out, d.long_acc, L, l1, cs, sr,
+                                         mx, &S, next);
+  }
   fold_block_stats<NT / 64>(r, l1, cs, sr, mx, L.red);
 }
 
 // ----------------------------------------------------------------- complete
 
 template <class T>
-__global__ __launch_bounds__(BLOCK) void k_complete(Dev d, long long s, int init) {
+__global__ __launch_bounds__(BLOCK, 4) void k_complete(Dev d, long long s, int init) {
   Glob *g = d.glob;
   if (g->status != 0) return;
   Rec *cur = &d.rec[s % 3];
