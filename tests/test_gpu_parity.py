@@ -333,3 +333,39 @@ def test_relabel_solve_matches_plain(prec, which):
     assert l1(pa, pb) <= 2 * tol
     assert l1(pb, reference(g)) <= tol
     assert abs(ia["edges_pushed"] - ib["edges_pushed"]) <= 0.01 * ia["edges_pushed"]
+
+
+def scc_graph():
+    # the largest strongly connected component of a power-law graph, c = 1
+    if "scc" not in _cache:
+        base = workloads.chung_lu(20000, 2.3, 8.0, 0.0, 1.0, seed=7, name="cl20k")
+        _cache["scc"] = workloads.largest_scc(base, c=1.0)
+    return _cache["scc"]
+
+
+@pytest.mark.parametrize("prec", [rl.FP64, rl.FP32C_FP64H, rl.FP32C_KAHANH], ids=PREC_NAMES.get)
+@pytest.mark.parametrize("relabel", [0, 1])
+def test_undamped_largest_scc(prec, relabel):
+    """c = 1 on the largest strongly connected component (18,012 states): no
+    restart, so the residual no longer bounds the error by 1/(1-c); pi_hat is
+    compared with FP64 power iteration run to ||x_{k+1} - x_k||_1 <= 1e-15,
+    and the FP64 step count with the oracle's RLGL solve."""
+    g = scc_graph()
+    say("case undamped_scc", PREC_NAMES[prec], "relabel" if relabel else "", g.n, g.nnz)
+    ch = oracle_chain(g)
+    key = ("scc_ref",)
+    if key not in _cache:
+        st, x, it = oracle.power_iteration(ch, 1e-15, 100000)
+        assert st == oracle.OK
+        _cache[key] = x
+    ref = _cache[key]
+    eps, tol = (1e-11, 1e-10) if prec == rl.FP64 else (1e-7, 1e-6)
+    s = solver(g, prec, sched=rl.SCHED_THRESHOLD, relabel=relabel)
+    st, info = s.solve(eps)
+    assert st == rl.RLGL_OK and info["resid"] < eps
+    pi = to_np(s.pi)
+    s.close()
+    assert l1(pi, ref) <= tol
+    if prec == rl.FP64:
+        ost, _, oinfo = oracle.solve(ch, oracle.THRESHOLD, eps=eps)
+        assert abs(info["t"] - oinfo["t"]) <= 2, (info["t"], oinfo["t"])

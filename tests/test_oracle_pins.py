@@ -315,3 +315,19 @@ def test_zero_cash_green_nodes_push_nothing():
     assert s.edges == 0 and np.array_equal(s.C, [0.0, 0.5, -0.5, 0.0])
     s.step_mask([0, 1, 0, 0])
     assert s.edges == 1
+
+
+def test_largest_scc_input():
+    """The undamped workload's input: the largest strongly connected component
+    of a graph built by hand, renumbered in order, its internal links kept."""
+    import workloads
+    # a 3-cycle 0->1->2->0, a 4-cycle 3->4->5->6->3 with a self-loop on 4,
+    # a one-way bridge 2->3 and a tail 6->7
+    src = np.array([0, 1, 2, 3, 4, 5, 6, 4, 2, 6], dtype=np.int32)
+    dst = np.array([1, 2, 0, 4, 5, 6, 3, 4, 3, 7], dtype=np.int32)
+    g = workloads.from_edges(8, src, dst, 0.85, name="toy")
+    h = workloads.largest_scc(g, c=1.0)
+    assert h.n == 4 and h.c == 1.0 and h.nnz == 5
+    edges = sorted(zip(np.repeat(np.arange(h.n), h.outdeg).tolist(), h.col.tolist()))
+    assert edges == [(0, 1), (1, 1), (1, 2), (2, 3), (3, 0)]
+    assert np.all(h.outdeg > 0)

@@ -236,6 +236,27 @@ def batch_chains(count: int = 512, n_lo: float = 1e3, n_hi: float = 2e5, gamma: 
         return list(ex.map(one, range(count)))
 
 
+def largest_scc(g: Graph, c: float = 1.0, name: str = "") -> Graph:
+    """The chain restricted to the largest strongly connected component of
+    g's link graph: its states renumbered 0..m-1 in their original order and
+    the links among them (multiplicity kept), with damping c (c = 1: the
+    undamped stationary distribution).  Every state of a component with more
+    than one state keeps at least one out-link, so there is no dangling state."""
+    import scipy.sparse as sp
+    import scipy.sparse.csgraph as cg
+    A = sp.csr_matrix((np.ones(g.nnz, dtype=np.int8), g.col, g.rowptr), shape=(g.n, g.n))
+    _, lab = cg.connected_components(A, directed=True, connection="strong")
+    keep = lab == np.bincount(lab).argmax()
+    new = np.full(g.n, -1, dtype=np.int64)
+    m = int(keep.sum())
+    new[keep] = np.arange(m)
+    src = np.repeat(np.arange(g.n, dtype=np.int64), g.outdeg)
+    inside = keep[src] & keep[g.col]
+    params = dict(g.params, scc_of=g.name, c=c)
+    return from_edges(m, new[src[inside]].astype(np.int32), new[g.col[inside]].astype(np.int32), c,
+                      name or f"{g.name}_scc", params)
+
+
 def poisson_arrivals(count: int, rate: float, seed: int, stream: int = S_META + 2) -> np.ndarray:
     """Arrival times (s) of a Poisson process of the given rate: cumulative
     exponential gaps -log(1 - u) / rate."""
