@@ -28,7 +28,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rlgl_oracle.c")
 _LIB = os.path.join(_HERE, "librlgl_oracle.so")
 
-ALL, THRESHOLD, TOPK, MAXC = 0, 1, 2, 3
+ALL, THRESHOLD, TOPK, MAXC, PC = 0, 1, 2, 3, 4
 OK, EINVAL, ENOMEM, EZERO_HISTORY, ENOT_CONVERGED, ENONFINITE = 0, -1, -2, -4, -5, -6
 
 
@@ -79,7 +79,12 @@ def _load():
         lib.orc_init.restype = None
         lib.orc_step.argtypes = [pc, vp, vp, vp, ctypes.POINTER(f64), ctypes.POINTER(i64), vp]
         lib.orc_step.restype = None
-        lib.orc_solve.argtypes = [pc, vp, i32, f64, i64, i32, f64, i64, vp, vp, vp, ctypes.POINTER(Info)]
+        lib.orc_select_pc.argtypes = [i32, vp, ctypes.c_uint64, i64, vp]
+        lib.orc_select_pc.restype = i64
+        lib.orc_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        lib.orc_splitmix64.restype = ctypes.c_uint64
+        lib.orc_solve.argtypes = [pc, vp, i32, f64, i64, i32, f64, i64, ctypes.c_uint64, vp, vp, vp,
+                                  ctypes.POINTER(Info)]
         lib.orc_solve.restype = i32
         lib.orc_power_iteration.argtypes = [pc, f64, i64, vp, ctypes.POINTER(i64)]
         lib.orc_power_iteration.restype = i32
@@ -132,10 +137,19 @@ def theta(C, r: float = 1.0) -> float:
     return float(_load().orc_theta(C.shape[0], _ptr(C), float(r)))
 
 
-def select(C, sched: int, theta_value: float = 0.0, k: int = 1) -> np.ndarray:
-    """Green mask (bool array) chosen from the cash snapshot C."""
+def splitmix64(seed: int, index: int) -> int:
+    """Output number `index` of splitmix64 started at `seed`."""
+    return int(_load().orc_splitmix64(seed & (2 ** 64 - 1), index & (2 ** 64 - 1)))
+
+
+def select(C, sched: int, theta_value: float = 0.0, k: int = 1, seed: int = 0, t: int = 0) -> np.ndarray:
+    """Green mask (bool array) chosen from the cash snapshot C (of step t for
+    PC, whose draws also use the seed)."""
     C = np.ascontiguousarray(C, dtype=np.float64)
     mask = np.zeros(C.shape[0], dtype=np.uint8)
+    if sched == PC:
+        g = _load().orc_select_pc(C.shape[0], _ptr(C), seed & (2 ** 64 - 1), int(t), _ptr(mask))
+        return mask.astype(bool)
     g = _load().orc_select(C.shape[0], _ptr(C), int(sched), float(theta_value), int(k), _ptr(mask))
     if g < 0:
         raise ValueError("bad selection arguments")
@@ -180,9 +194,9 @@ class State:
         self.edges = ed.value
         self.t += 1
 
-    def step(self, sched: int, r: float = 1.0, k: int = 1, theta_value=None):
+    def step(self, sched: int, r: float = 1.0, k: int = 1, theta_value=None, seed: int = 0):
         th = theta(self.C, r) if (sched == THRESHOLD and theta_value is None) else (theta_value or 0.0)
-        mask = select(self.C, sched, th, k)
+        mask = select(self.C, sched, th, k, seed=seed, t=self.t)
         self.step_mask(mask)
         return mask, th
 
@@ -200,7 +214,7 @@ class State:
 
 
 def solve(ch: Chain, sched: int = ALL, eps: float = 1e-10, max_steps: int = 10 ** 7, r: float = 1.0, k: int = 1,
-          theta_period: int = 1, M0=None, want_state: bool = False):
+          theta_period: int = 1, M0=None, want_state: bool = False, seed: int = 0):
     """Algorithm 1 to its stop test.  Returns (status, pi_hat, info dict[, C, H])."""
     pi = np.zeros(ch.n, dtype=np.float64)
     C = np.zeros(ch.n, dtype=np.float64) if want_state else None
@@ -208,7 +222,7 @@ def solve(ch: Chain, sched: int = ALL, eps: float = 1e-10, max_steps: int = 10 *
     info = Info()
     m0 = None if M0 is None else np.ascontiguousarray(M0, dtype=np.float64)
     st = _load().orc_solve(ch.ref(), _ptr(m0), int(sched), float(r), int(k), int(theta_period), float(eps),
-                           int(max_steps), _ptr(pi), _ptr(C), _ptr(H), ctypes.byref(info))
+                           int(max_steps), seed & (2 ** 64 - 1), _ptr(pi), _ptr(C), _ptr(H), ctypes.byref(info))
     if want_state:
         return st, pi, info.as_dict(), C, H
     return st, pi, info.as_dict()

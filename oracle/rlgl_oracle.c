@@ -31,6 +31,10 @@
  *     once: G_t = { i : |C_t,i| >= theta_t }, theta_t = (sum_j |C_t,j|^r / N)^(1/r)
  *     recomputed every theta_period steps.
  *   - top-k (not in the paper) orders by |C| descending, then node id ascending.
+ *   - RLGL_PC (Sec. 6) is drawn for all nodes at once: node i is green with
+ *     probability |C_t,i| / max_j |C_t,j|, its uniform draw taken from
+ *     splitmix64 at counter t 2^32 + i (the synchronous form of the Poisson
+ *     clock the paper mentions, normalised by the largest cash).
  *   - H_t 1 counts as zero when |H_t 1| <= 1e-300 or |H_t 1| <= 1e-12 ||H_t||_1
  *     (the restart case of Sec. 2.1 and Example 1).
  */
@@ -39,7 +43,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { ORC_ALL = 0, ORC_THRESHOLD = 1, ORC_TOPK = 2, ORC_MAXC = 3 };
+enum { ORC_ALL = 0, ORC_THRESHOLD = 1, ORC_TOPK = 2, ORC_MAXC = 3, ORC_PC = 4 };
 enum {
   ORC_OK = 0,
   ORC_EINVAL = -1,
@@ -116,6 +120,38 @@ static int topk_cmp(const void *a, const void *b) {
   if (ai > aj) return -1;
   if (ai < aj) return 1;
   return (i < j) ? -1 : (i > j);
+}
+
+/* splitmix64 (Steele, Lea and Flood, OOPSLA 2014): output number `index`
+ * (0-based) of the generator whose state starts at `seed` and advances by the
+ * golden gamma 0x9E3779B97F4A7C15 before each output. */
+uint64_t orc_splitmix64(uint64_t seed, uint64_t index) {
+  uint64_t z = seed + (index + 1u) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+/* RLGL_PC (Sec. 6) with every node drawn at once: node i is green at step t
+ * with probability |C_t,i| / max_j |C_t,j|.  Its uniform draw is
+ * u = (splitmix64 output number t 2^32 + i, shifted right by 11) 2^-53, and it
+ * is green iff u < |C_t,i| / max_j |C_t,j| (both in FP64).  A node of maximal
+ * |C| is always green; zero cash never is. */
+int64_t orc_select_pc(int32_t n, const double *C, uint64_t seed, int64_t t, uint8_t *mask) {
+  double mx = 0.0;
+  int64_t cnt = 0;
+  for (int32_t i = 0; i < n; ++i)
+    if (fabs(C[i]) > mx) mx = fabs(C[i]);
+  for (int32_t i = 0; i < n; ++i) {
+    mask[i] = 0;
+    if (mx > 0.0) {
+      const uint64_t z = orc_splitmix64(seed, ((uint64_t)t << 32) + (uint64_t)i);
+      const double u = (double)(z >> 11) * 0x1.0p-53;
+      mask[i] = u < fabs(C[i]) / mx;
+    }
+    cnt += mask[i];
+  }
+  return cnt;
 }
 
 /* Green-light set G_t chosen from the cash snapshot C_t.  Writes mask[i] in
@@ -212,7 +248,8 @@ static double l1norm(int32_t n, const double *x) {
  * receives pi_hat_t = H_t / (H_t 1) whenever H_t 1 is usable.  C_out and H_out
  * (n doubles each, may be NULL) receive the final C_t and H_t. */
 int32_t orc_solve(const orc_chain *ch, const double *M0, int32_t sched, double r, int64_t k, int32_t theta_period,
-                  double eps, int64_t max_steps, double *pi_out, double *C_out, double *H_out, orc_info *info) {
+                  double eps, int64_t max_steps, uint64_t seed, double *pi_out, double *C_out, double *H_out,
+                  orc_info *info) {
   const int32_t n = ch->n;
   if (n <= 0 || !(ch->c > 0.0 && ch->c <= 1.0) || theta_period < 1 || !(r >= 1.0)) return ORC_EINVAL;
   double *C = (double *)malloc(sizeof(double) * (size_t)n);
@@ -236,7 +273,7 @@ int32_t orc_solve(const orc_chain *ch, const double *M0, int32_t sched, double r
     if (t >= 2 && resid < eps) { status = ORC_OK; break; }
     if (t - 1 >= max_steps) { status = ORC_ENOT_CONVERGED; break; }
     if (sched == ORC_THRESHOLD && (t - 1) % theta_period == 0) theta = orc_theta(n, C, r);
-    const int64_t g = orc_select(n, C, sched, theta, k, mask);
+    const int64_t g = (sched == ORC_PC) ? orc_select_pc(n, C, seed, t, mask) : orc_select(n, C, sched, theta, k, mask);
     if (g < 0) { status = ORC_EINVAL; break; }
     green_total += g;
     orc_step(ch, mask, C, H, &hsum, &edges, M);

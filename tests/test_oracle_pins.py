@@ -331,3 +331,40 @@ def test_largest_scc_input():
     edges = sorted(zip(np.repeat(np.arange(h.n), h.outdeg).tolist(), h.col.tolist()))
     assert edges == [(0, 1), (1, 1), (1, 2), (2, 3), (3, 0)]
     assert np.all(h.outdeg > 0)
+
+
+def test_pc_generator_and_selection():
+    """RLGL_PC drawn for all nodes at once.  The generator is splitmix64 (the
+    three first outputs from state 0 are the published reference values);
+    node i is green with frequency |C_i| / max |C|; the (seed, step) pair
+    fixes the draw."""
+    assert [oracle.splitmix64(0, i) for i in range(3)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4,
+                                                           0x06C45D188009454F]
+    C = np.array([0.0, -1.0, 0.5, 0.25, -0.125, 1.0, 0.75])
+    steps = 4000
+    counts = sum(oracle.select(C, oracle.PC, seed=11, t=t).astype(int) for t in range(1, steps + 1))
+    p = np.abs(C) / np.abs(C).max()
+    assert counts[0] == 0 and counts[1] == steps and counts[5] == steps
+    sd = np.sqrt(steps * p * (1 - p))
+    assert np.all(np.abs(counts - steps * p) <= 5 * sd + 1e-9)
+    x = np.linspace(0.1, 1.0, 64)
+    a = oracle.select(x, oracle.PC, seed=3, t=5)
+    assert np.array_equal(a, oracle.select(x, oracle.PC, seed=3, t=5))
+    assert not np.array_equal(a, oracle.select(x, oracle.PC, seed=4, t=5))
+    assert not np.array_equal(a, oracle.select(x, oracle.PC, seed=3, t=6))
+    # the draw of node i at step t is splitmix64 output t 2^32 + i, top 53 bits
+    u = np.array([(oracle.splitmix64(3, (5 << 32) + i) >> 11) * 2.0 ** -53 for i in range(64)])
+    assert np.array_equal(a, u < x / x.max())
+
+
+def test_pc_solve_reaches_stationary_distribution():
+    ch, _ = random_chain(60, 5, c=0.85, dangling=0.1)
+    x = oracle.stationary_gth(oracle.dense_P(ch))
+    st, pi, info = oracle.solve(ch, oracle.PC, eps=1e-13 * 0.15, seed=9)
+    assert st == oracle.OK
+    assert np.abs(pi - x).sum() <= 1e-12
+    # invariants hold along a PC trajectory
+    s = oracle.State(ch)
+    for _ in range(50):
+        s.step(oracle.PC, seed=9)
+        assert abs(s.C.sum()) <= 1e-13
