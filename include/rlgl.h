@@ -51,7 +51,10 @@ typedef enum {
   RLGL_SCHED_ALL = 0,        /* G_t = [N]: power iteration (Sec. 2.3.1) */
   RLGL_SCHED_THRESHOLD = 1,  /* |C_t,i| >= theta_t, theta_t = (sum_j |C_t,j|^r / N)^(1/r) (RLGL_Theta, all nodes at once) */
   RLGL_SCHED_TOPK = 2,       /* the k largest |C_t,i|, ties broken by smaller node id (Gauss-Southwell style) */
-  RLGL_SCHED_MAXC = 3        /* every node with |C_t,i| = max_j |C_t,j| (RLGL_MaxC) */
+  RLGL_SCHED_MAXC = 3,       /* every node with |C_t,i| = max_j |C_t,j| (RLGL_MaxC) */
+  RLGL_SCHED_PC = 4          /* RLGL_PC drawn for every node at once: node i is green with probability
+                                |C_t,i| / max_j |C_t,j|, green iff u < |C_t,i| / max_j |C_t,j| with
+                                u = (splitmix64(seed) output number t 2^32 + i) >> 11, times 2^-53 */
 } rlgl_sched;
 
 /* Arithmetic.  Cash routing runs in the cash type; H_t 1, ||C_t||_1, theta
@@ -106,7 +109,8 @@ typedef struct {
                                  (ties by id) and keeps relabelled copies of the CSR/CSC in the workspace, so
                                  the cash of the states gathered most often shares cache lines; every value
                                  that crosses this interface (C, H, the green mask, pi_hat) stays in the
-                                 caller's numbering.  Not with RLGL_SCHED_TOPK (its ties go by id) */
+                                 caller's numbering.  Not with RLGL_SCHED_TOPK or _PC (they use the ids) */
+  uint64_t seed;              /* RLGL_SCHED_PC: the splitmix64 seed of the draws */
 } rlgl_options;
 
 /* Snapshot of the solver after the last enqueued step. */
@@ -126,7 +130,7 @@ typedef struct {
 
 /* Fills *opt with the defaults: THRESHOLD, r = 1, k = 1, theta_period = 1,
  * FP32C_FP64H, AUTO, pull_alpha = 0.15, check_period = 0, record_green = 0,
- * refresh = 1, relabel = 0. */
+ * refresh = 1, relabel = 0, seed = 0. */
 void rlgl_default_options(rlgl_options *opt);
 
 /* Device workspace the context needs, in bytes (0 on a bad argument).  Depends

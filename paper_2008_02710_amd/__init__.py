@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "librlgl.so")
 
 RLGL_OK, RLGL_EINVAL, RLGL_ENOMEM, RLGL_EHIP = 0, -1, -2, -3
 RLGL_EZERO_HISTORY, RLGL_ENOT_CONVERGED, RLGL_ENONFINITE, RLGL_EBUSY = -4, -5, -6, -7
-SCHED_ALL, SCHED_THRESHOLD, SCHED_TOPK, SCHED_MAXC = 0, 1, 2, 3
+SCHED_ALL, SCHED_THRESHOLD, SCHED_TOPK, SCHED_MAXC, SCHED_PC = 0, 1, 2, 3, 4
 FP64, FP32C_FP64H, FP32C_KAHANH = 0, 1, 2
 ROUTE_PUSH, ROUTE_PULL, ROUTE_AUTO = 0, 1, 2
 
@@ -37,7 +37,8 @@ class rlgl_options(ctypes.Structure):
     _fields_ = [("sched", ctypes.c_int32), ("r", ctypes.c_double), ("k", ctypes.c_int64),
                 ("theta_period", ctypes.c_int32), ("precision", ctypes.c_int32), ("route", ctypes.c_int32),
                 ("pull_alpha", ctypes.c_double), ("check_period", ctypes.c_int32),
-                ("record_green", ctypes.c_int32), ("refresh", ctypes.c_int32), ("relabel", ctypes.c_int32)]
+                ("record_green", ctypes.c_int32), ("refresh", ctypes.c_int32), ("relabel", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
 
 
 class rlgl_step_info(ctypes.Structure):

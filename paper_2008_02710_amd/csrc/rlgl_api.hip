@@ -110,7 +110,7 @@ Layout make_layout(long long n, long long nnz, int prec, bool has_csc, bool rela
 }
 
 bool valid_options(const rlgl_options *o, std::string &why) {
-  if (o->sched < 0 || o->sched > 3) { why = "sched out of range"; return false; }
+  if (o->sched < 0 || o->sched > 4) { why = "sched out of range"; return false; }
   if (!(o->r >= 1.0) || !std::isfinite(o->r)) { why = "r must be >= 1"; return false; }
   if (o->sched == RLGL_SCHED_TOPK && o->k < 1) { why = "k must be >= 1"; return false; }
   if (o->theta_period < 1) { why = "theta_period must be >= 1"; return false; }
@@ -119,7 +119,10 @@ bool valid_options(const rlgl_options *o, std::string &why) {
   if (!(o->pull_alpha >= 0.0)) { why = "pull_alpha must be >= 0"; return false; }
   if (o->check_period < 0) { why = "check_period must be >= 0"; return false; }
   if (o->refresh < 0) { why = "refresh must be >= 0"; return false; }
-  if (o->relabel && o->sched == RLGL_SCHED_TOPK) { why = "relabel does not combine with TOPK"; return false; }
+  if (o->relabel && (o->sched == RLGL_SCHED_TOPK || o->sched == RLGL_SCHED_PC)) {
+    why = "relabel does not combine with TOPK or PC";
+    return false;
+  }
   return true;
 }
 
@@ -547,6 +550,7 @@ rlgl_status rlgl_create(const rlgl_graph *g, const rlgl_options *o, void *ws, si
   d.theta_period = o->theta_period;
   d.route = g->csc_colptr ? o->route : RLGL_ROUTE_PUSH;
   d.pull_alpha = o->pull_alpha;
+  d.seed = o->seed;
   d.cash[0] = w + L.cash0;
   d.cash[1] = w + L.cash1;
   d.hist = w + L.hist;

@@ -24,7 +24,7 @@ constexpr int PUSH_GRID = 512;      // push launches (hot partials flushed once 
 // (block b -> stripe b mod NSTRIPE); readers add the stripes up.
 constexpr int NSTRIPE = 32;
 
-enum { SCHED_ALL = 0, SCHED_THRESHOLD = 1, SCHED_TOPK = 2, SCHED_MAXC = 3 };
+enum { SCHED_ALL = 0, SCHED_THRESHOLD = 1, SCHED_TOPK = 2, SCHED_MAXC = 3, SCHED_PC = 4 };
 enum { ROUTE_PUSH = 0, ROUTE_PULL = 1, ROUTE_AUTO = 2 };
 enum { ST_RUNNING = 0, ST_CONVERGED = 1, ST_LIMIT = 2, ST_ZERO_HISTORY = -4, ST_NONFINITE = -6 };
 
@@ -98,6 +98,7 @@ struct Dev {
   int theta_period;
   int route;
   double pull_alpha;
+  unsigned long long seed;  // SCHED_PC draws
   // workspace
   void *cash[2];
   void *hist;        // double[n], or float[n] (hi part) for the compensated history

@@ -212,12 +212,31 @@ __device__ __forceinline__ void fold_stats(double x, double r, double &l1, doubl
 }
 
 // Green test of a node with cash v on the snapshot of step t.
+// splitmix64 (Steele, Lea and Flood, 2014): output number `index` of the
+// generator whose state starts at `seed` and advances by the golden gamma.
+__device__ __forceinline__ unsigned long long splitmix64_at(unsigned long long seed, unsigned long long index) {
+  unsigned long long z = seed + (index + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Green test of the node `id` with cash v on the snapshot C_t.  PC (RLGL_PC of
+// Sec. 6, every node drawn at once): green with probability |v| / max |C_t|,
+// the uniform draw being splitmix64 output t 2^32 + id, top 53 bits.
 template <class T>
-__device__ __forceinline__ bool is_green(T v, int id, int sched, double theta, double maxabs, double tau, int tie_id) {
+__device__ __forceinline__ bool is_green(T v, int id, int sched, double theta, double maxabs, double tau, int tie_id,
+                                         unsigned long long seed = 0ull, long long t = 0) {
   const double a = fabs((double)v);
   if (sched == SCHED_ALL) return true;
   if (sched == SCHED_THRESHOLD) return a >= theta;
   if (sched == SCHED_MAXC) return a == maxabs;
+  if (sched == SCHED_PC) {
+    if (!(maxabs > 0.0)) return false;
+    const unsigned long long z = splitmix64_at(seed, ((unsigned long long)t << 32) + (unsigned int)id);
+    const double u = (double)(z >> 11) * 0x1.0p-53;
+    return u < a / maxabs;
+  }
   return a > tau || (a == tau && id <= tie_id);  // top-k: k-th largest |C| and the id bound among its ties
 }
 
@@ -317,7 +336,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(Dev d, long long s, double eps
       rs[q] = 0;
       v[q] = T(0);
       const T x = (i < n) ? C[i] : T(0);
-      const bool gr = (i < n) && is_green(x, i, sched, theta, maxabs, tau, tie_id);
+      const bool gr = (i < n) && is_green(x, i, sched, theta, maxabs, tau, tie_id, d.seed, s);
       if (i < n) {
         if (d.green_mask) d.green_mask[i] = gr ? 1 : 0;
         if (gr) {
@@ -800,12 +819,12 @@ __global__ __launch_bounds__(BLOCK, 4) void k_complete(Dev d, long long s, int i
     auto moved = [&](int j) -> double {
       if ((unsigned)j >= (unsigned)n) return 0.0;  // links outside [0, N) are ignored
       const T v = Cc[j];
-      return is_green(v, j, sched, theta, maxabs, tau, tie_id) ? (double)v : 0.0;
+      return is_green(v, j, sched, theta, maxabs, tau, tie_id, d.seed, s) ? (double)v : 0.0;
     };
     auto kept = [&](int k) -> double {
       const T v = Cc[k];
       if (init) return -(double)v;  // step 0: C_0 - M_0 with C_0 = 0
-      return is_green(v, k, sched, theta, maxabs, tau, tie_id) ? 0.0 : (double)v;
+      return is_green(v, k, sched, theta, maxabs, tau, tie_id, d.seed, s) ? 0.0 : (double)v;
     };
     column_pass<T, BLOCK>(d, moved, kept, off, Cn, nxt);
   }
@@ -859,7 +878,7 @@ __global__ __launch_bounds__(BLOCK) void k_complete_long(Dev d, long long s, int
   auto kept = [&](int k) -> double {
     const T v = Cc[k];
     if (init) return -(double)v;
-    return is_green(v, k, sched, theta, maxabs, tau, tie_id) ? 0.0 : (double)v;
+    return is_green(v, k, sched, theta, maxabs, tau, tie_id, d.seed, s) ? 0.0 : (double)v;
   };
   long_finish<T>(d, kept, tot.T / (double)d.n, (T *)d.cash[cur->buf ^ 1], nxt);
 }

@@ -46,12 +46,13 @@ def test_struct_sizes_match_header():
     exe = os.path.join(ROOT, "_sizes_probe")
     open(src, "w").write(
         '#include <stdio.h>\n#include <stddef.h>\n#include "rlgl.h"\n'
-        'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(rlgl_graph),'
+        'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(rlgl_graph),'
         ' sizeof(rlgl_options), sizeof(rlgl_step_info), sizeof(rlgl_kernel_stat),'
         ' offsetof(rlgl_options, record_green), offsetof(rlgl_step_info, last_route),'
         ' sizeof(rlgl_batch_graphs), sizeof(rlgl_batch_options), offsetof(rlgl_batch_options, check_period),'
         ' sizeof(rlgl_chain_result), sizeof(rlgl_pool_options), sizeof(rlgl_request),'
-        ' offsetof(rlgl_request, tol_l1), offsetof(rlgl_options, relabel));return 0;}\n')
+        ' offsetof(rlgl_request, tol_l1), offsetof(rlgl_options, relabel), offsetof(rlgl_options, seed));'
+        'return 0;}\n')
     try:
         import subprocess
         subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", exe, src])
@@ -65,7 +66,7 @@ def test_struct_sizes_match_header():
            rl.rlgl_step_info.last_route.offset, ctypes.sizeof(rl.rlgl_batch_graphs),
            ctypes.sizeof(rl.rlgl_batch_options), rl.rlgl_batch_options.check_period.offset,
            ctypes.sizeof(rl.rlgl_chain_result), ctypes.sizeof(rl.rlgl_pool_options), ctypes.sizeof(rl.rlgl_request),
-           rl.rlgl_request.tol_l1.offset, rl.rlgl_options.relabel.offset]
+           rl.rlgl_request.tol_l1.offset, rl.rlgl_options.relabel.offset, rl.rlgl_options.seed.offset]
     assert [int(x) for x in out] == got
 
 
@@ -89,9 +90,11 @@ def test_host_side_argument_checks():
     for field, value in (("sched", 9), ("r", 0.5), ("theta_period", 0), ("precision", 7), ("route", 5)):
         o = rl.rlgl_default_options(**{field: value})
         assert lib.rlgl_create(ctypes.byref(g), ctypes.byref(o), 4096, 1 << 30, None, ctypes.byref(ctx)) == rl.RLGL_EINVAL
-    o = rl.rlgl_default_options(sched=rl.SCHED_TOPK, k=5, relabel=1)
-    assert lib.rlgl_create(ctypes.byref(g), ctypes.byref(o), 4096, 1 << 30, None, ctypes.byref(ctx)) == rl.RLGL_EINVAL
-    assert "relabel" in rl.rlgl_last_error()
+    for sched in (rl.SCHED_TOPK, rl.SCHED_PC):
+        o = rl.rlgl_default_options(sched=sched, k=5, relabel=1)
+        assert lib.rlgl_create(ctypes.byref(g), ctypes.byref(o), 4096, 1 << 30, None,
+                               ctypes.byref(ctx)) == rl.RLGL_EINVAL
+        assert "relabel" in rl.rlgl_last_error()
     # the relabelled layout needs room for a second copy of the graph
     o = rl.rlgl_default_options(relabel=1)
     g2 = rl.rlgl_graph(1000, 5000, 1, 1, None, 1, 1, None, 0.85)

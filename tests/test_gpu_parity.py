@@ -28,9 +28,11 @@ import paper_2008_02710_amd as rl  # noqa: E402
 
 PRECS = [rl.FP64, rl.FP32C_FP64H, rl.FP32C_KAHANH]
 PREC_NAMES = {rl.FP64: "fp64", rl.FP32C_FP64H: "fp32c_fp64h", rl.FP32C_KAHANH: "fp32c_kahanh"}
-SCHEDS = {"all": rl.SCHED_ALL, "threshold": rl.SCHED_THRESHOLD, "topk": rl.SCHED_TOPK, "maxc": rl.SCHED_MAXC}
+SCHEDS = {"all": rl.SCHED_ALL, "threshold": rl.SCHED_THRESHOLD, "topk": rl.SCHED_TOPK, "maxc": rl.SCHED_MAXC,
+          "pc": rl.SCHED_PC}
 ORC_SCHED = {rl.SCHED_ALL: oracle.ALL, rl.SCHED_THRESHOLD: oracle.THRESHOLD, rl.SCHED_TOPK: oracle.TOPK,
-             rl.SCHED_MAXC: oracle.MAXC}
+             rl.SCHED_MAXC: oracle.MAXC, rl.SCHED_PC: oracle.PC}
+PC_SEED = 0x5EED5EED1234
 ROUTES = {"push": rl.ROUTE_PUSH, "pull": rl.ROUTE_PULL, "auto": rl.ROUTE_AUTO}
 
 
@@ -101,7 +103,7 @@ def _nontrivial_state(g, prec, steps=3):
 
 @pytest.mark.parametrize("prec", PRECS, ids=PREC_NAMES.get)
 @pytest.mark.parametrize("route", ["push", "pull", "auto"])
-@pytest.mark.parametrize("sched", ["all", "threshold", "topk", "maxc"])
+@pytest.mark.parametrize("sched", ["all", "threshold", "topk", "maxc", "pc"])
 @pytest.mark.parametrize("which", ["small", "hub"])
 def test_single_step_parity(prec, route, sched, which):
     _step_parity(prec, route, sched, which, relabel=0)
@@ -121,7 +123,8 @@ def _step_parity(prec, route, sched, which, relabel):
     g = small_graph() if which == "small" else hub_graph()
     say("case single_step", which, PREC_NAMES[prec], route, sched, "relabel" if relabel else "")
     k = 97
-    s = solver(g, prec, route=ROUTES[route], sched=SCHEDS[sched], k=k, record_green=1, relabel=relabel)
+    s = solver(g, prec, route=ROUTES[route], sched=SCHEDS[sched], k=k, record_green=1, relabel=relabel,
+               seed=PC_SEED)
     C0, H0, hs0 = _nontrivial_state(g, prec)
     s.set_state(torch.from_numpy(C0).cuda(), torch.from_numpy(H0).cuda(), hs0, t=4)
     Cg, Hg, info0 = s.state()
@@ -135,7 +138,7 @@ def _step_parity(prec, route, sched, which, relabel):
     osch = ORC_SCHED[SCHEDS[sched]]
     if osch == oracle.THRESHOLD:
         assert theta == pytest.approx(oracle.theta(Cg), rel=1e-12)
-    want = oracle.select(Cg, osch, theta, k)
+    want = oracle.select(Cg, osch, theta, k, seed=PC_SEED, t=4)
     assert np.array_equal(mask, want), (int(mask.sum()), int(want.sum()))
     assert info1["green"] == int(want.sum())
     ost = oracle.State.from_arrays(oracle_chain(g), Cg, Hg, info0["h_sum"], t=4)
@@ -153,22 +156,22 @@ def _step_parity(prec, route, sched, which, relabel):
 # --------------------------------------------------------------- solves
 
 @pytest.mark.parametrize("prec", PRECS, ids=PREC_NAMES.get)
-@pytest.mark.parametrize("sched", ["all", "threshold", "topk", "maxc"])
+@pytest.mark.parametrize("sched", ["all", "threshold", "topk", "maxc", "pc"])
 def test_solve_small(prec, sched):
     g = small_graph()
     say("case solve_small", PREC_NAMES[prec], sched)
     tol = tol_solve(prec)
     eps = (1 - g.c) * tol * 0.5
-    s = solver(g, prec, sched=SCHEDS[sched], k=50)
+    s = solver(g, prec, sched=SCHEDS[sched], k=50, seed=PC_SEED)
     st, info = s.solve(eps)
     assert st == rl.RLGL_OK and info["resid"] < eps and info["t"] >= 2
     pi = to_np(s.pi)
     x = reference(g)
     assert l1(pi, x) <= tol, info
     assert abs(pi.sum() - 1.0) <= 1e-12
-    ost, opi, oinfo = oracle.solve(oracle_chain(g), ORC_SCHED[SCHEDS[sched]], eps=eps, k=50)
+    ost, opi, oinfo = oracle.solve(oracle_chain(g), ORC_SCHED[SCHEDS[sched]], eps=eps, k=50, seed=PC_SEED)
     assert ost == oracle.OK
-    if prec == rl.FP64 and sched == "all":
+    if prec == rl.FP64 and sched in ("all", "pc"):
         assert abs(info["t"] - oinfo["t"]) <= 1
     else:
         assert info["t"] <= 2 * oinfo["t"] + 5
@@ -369,3 +372,21 @@ def test_undamped_largest_scc(prec, relabel):
     if prec == rl.FP64:
         ost, _, oinfo = oracle.solve(ch, oracle.THRESHOLD, eps=eps)
         assert abs(info["t"] - oinfo["t"]) <= 2, (info["t"], oinfo["t"])
+
+
+@pytest.mark.parametrize("route", ["push", "pull"])
+def test_pc_trajectory_matches_oracle(route):
+    """RLGL_PC in FP64: the device and the oracle draw the same green sets
+    from the same seed, so their trajectories agree step by step."""
+    g = small_graph()
+    say("case pc_trajectory", route)
+    s = solver(g, rl.FP64, sched=rl.SCHED_PC, route=ROUTES[route], seed=PC_SEED, record_green=1)
+    st = oracle.State(oracle_chain(g))
+    for t in range(1, 16):
+        info = s.step(1)
+        want, _ = st.step(oracle.PC, seed=PC_SEED)
+        assert np.array_equal(to_np(s.green()).astype(bool), want), t
+        C, H, _ = s.state()
+        assert l1(to_np(C), st.C) <= 1e-13 * max(1.0, float(np.abs(st.C).sum())), t
+        assert l1(to_np(H), st.H) <= 1e-13, t
+    s.close()
