@@ -238,8 +238,11 @@ def main():
     ap.add_argument("--route", default="auto", choices=["auto", "push", "pull"])
     ap.add_argument("--precision", default="fp32c_fp64h", choices=["fp64", "fp32c_fp64h", "fp32c_kahanh"])
     ap.add_argument("--tol", type=float, default=1e-6, help="certified L1 target")
-    ap.add_argument("--sched", default=None, choices=["all", "threshold", "maxc"],
+    ap.add_argument("--sched", default=None, choices=["all", "threshold", "maxc", "pc"],
                     help="green-light schedule (default: the workload's)")
+    ap.add_argument("--r", type=float, default=None, help="threshold power-mean order (default: the workload's)")
+    ap.add_argument("--theta-period", type=int, default=1, help="steps between threshold refreshes")
+    ap.add_argument("--seed", type=int, default=1, help="seed of the PC draws")
     ap.add_argument("--relabel", type=int, default=1, choices=[0, 1],
                     help="renumber the states by decreasing out-degree inside the library (layout step)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
@@ -284,14 +287,20 @@ def main():
     g, wl = make_workload(args.workload)
     if args.sched:
         wl["sched"] = args.sched
-    sched = {"threshold": rl.SCHED_THRESHOLD, "all": rl.SCHED_ALL, "maxc": rl.SCHED_MAXC}[wl["sched"]]
+    if args.r is not None:
+        wl["r"] = args.r
+    sched = {"threshold": rl.SCHED_THRESHOLD, "all": rl.SCHED_ALL, "maxc": rl.SCHED_MAXC,
+             "pc": rl.SCHED_PC}[wl["sched"]]
+    if sched == rl.SCHED_PC and args.relabel:
+        args.relabel = 0  # the PC draws are keyed by the caller's node ids
     print(f"# workload {g.name}: n={g.n} nnz={g.nnz} dangling={g.n_dangling} gen={time.time() - t0:.1f}s",
           file=sys.stderr, flush=True)
 
     dev = torch.device("cuda:0")
     dg = rl.DeviceGraph.from_workload(g, precision=prec, with_csc=True, explicit_val=True, device=dev)
     stream = torch.cuda.current_stream(dev)
-    s = rl.Solver(dg, stream=stream, sched=sched, r=wl["r"], route=route, precision=prec, relabel=args.relabel)
+    s = rl.Solver(dg, stream=stream, sched=sched, r=wl["r"], route=route, precision=prec, relabel=args.relabel,
+                  theta_period=args.theta_period, seed=args.seed)
     # c < 1: the residual certifies the L1 error through 1/(1-c); c = 1 has no
     # such bound, so the stop is a tenth of the target and the error is
     # measured against FP64 power iteration
@@ -377,7 +386,8 @@ def main():
     # graphs, the first steps of one solve on large ones)
     cpu = None
     if not args.no_cpu:
-        osched = {rl.SCHED_THRESHOLD: oracle.THRESHOLD, rl.SCHED_ALL: oracle.ALL, rl.SCHED_MAXC: oracle.MAXC}[sched]
+        osched = {rl.SCHED_THRESHOLD: oracle.THRESHOLD, rl.SCHED_ALL: oracle.ALL, rl.SCHED_MAXC: oracle.MAXC,
+                  rl.SCHED_PC: oracle.PC}[sched]
         solves, steps, opushes, tcpu = 0, 0, 0, 0.0
         a = time.perf_counter()
         t_print = a
@@ -392,7 +402,7 @@ def main():
                 st = oracle.State(ch)
             if time.perf_counter() - a >= args.cpu_seconds:
                 break
-            st.step(osched, r=wl["r"])
+            st.step(osched, r=wl["r"], seed=args.seed)
             steps += 1
             if time.perf_counter() - t_print >= 3.0:
                 t_print = time.perf_counter()
@@ -427,7 +437,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": g.name, "n": g.n, "nnz": g.nnz, "dangling": g.n_dangling, "damping": g.c,
                    "schedule": wl["sched"], "r": wl["r"], "precision": args.precision, "route": args.route,
-                   "relabel": args.relabel,
+                   "relabel": args.relabel, "theta_period": args.theta_period,
                    "eps_resid": eps, "tol_l1": args.tol, "generator": g.params.get("generator"),
                    "seed": g.params.get("seed")},
         "steps_per_solve": last["t"] - 1,

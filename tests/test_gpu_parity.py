@@ -390,3 +390,47 @@ def test_pc_trajectory_matches_oracle(route):
         assert l1(to_np(C), st.C) <= 1e-13 * max(1.0, float(np.abs(st.C).sum())), t
         assert l1(to_np(H), st.H) <= 1e-13, t
     s.close()
+
+
+@pytest.mark.parametrize("route", ["push", "pull"])
+@pytest.mark.parametrize("r,period", [(2.0, 1), (1.0, 3), (2.0, 4)])
+def test_threshold_order_and_stale_theta(route, r, period):
+    """RLGL_Theta with r = 2 and with theta refreshed every `period` steps
+    (Sec. 6 allows a threshold updated less often): each step's threshold is
+    the oracle's power mean of the device's own cash when it is refreshed and
+    the previous one otherwise, the green set matches bit for bit, and the FP64
+    trajectory follows the oracle's."""
+    g = small_graph()
+    say("case threshold_variants", route, r, period)
+    s = solver(g, rl.FP64, sched=rl.SCHED_THRESHOLD, r=r, theta_period=period, route=ROUTES[route], record_green=1)
+    st = oracle.State(oracle_chain(g))
+    th = None
+    for t in range(1, 25):
+        C, H, info0 = s.state()
+        assert info0["t"] == t
+        Cd = to_np(C).astype(np.float64)
+        info = s.step(1)
+        if (t - 1) % period == 0:
+            assert info["theta"] == pytest.approx(oracle.theta(Cd, r), rel=1e-12), t
+        else:
+            assert info["theta"] == th, t
+        th = info["theta"]
+        want = oracle.select(Cd, oracle.THRESHOLD, th)
+        assert np.array_equal(to_np(s.green()).astype(bool), want), t
+        st.step_mask(want)
+        C1, H1, _ = s.state()
+        assert l1(to_np(C1), st.C) <= 1e-12, t
+        assert l1(to_np(H1), st.H) <= 1e-12, t
+    s.close()
+
+
+@pytest.mark.parametrize("prec", [rl.FP32C_FP64H, rl.FP32C_KAHANH], ids=PREC_NAMES.get)
+def test_threshold_order_two_solve(prec):
+    g = hub_graph()
+    say("case threshold_r2_solve", PREC_NAMES[prec])
+    eps = (1 - g.c) * 0.5e-6
+    s = solver(g, prec, sched=rl.SCHED_THRESHOLD, r=2.0, theta_period=2)
+    st, info = s.solve(eps)
+    assert st == rl.RLGL_OK
+    assert l1(to_np(s.pi), reference(g)) <= 1e-6
+    s.close()
