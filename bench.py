@@ -340,6 +340,20 @@ def main():
           f"steps={last['t'] - 1} pushes/solve={last['edges_pushed']} GTEPS={gteps:.1f}",
           file=sys.stderr, flush=True)
 
+    # ---- a plain device copy on the same GPU (STREAM-copy style): 2 x 1 GiB moved
+    cbuf = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    cdst = torch.empty_like(cbuf)
+    cdst.copy_(cbuf)
+    ce0 = torch.cuda.Event(enable_timing=True)
+    ce1 = torch.cuda.Event(enable_timing=True)
+    ce0.record()
+    for _ in range(5):
+        cdst.copy_(cbuf)
+    ce1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 5 * 2 * cbuf.numel() * 4 / (ce0.elapsed_time(ce1) * 1e-3) / 1e9
+    del cbuf, cdst
+
     # ---- roofline of the dominant kernel: same solve, events around each launch
     rl.rlgl_profile_enable(s.ctx, True)
     one_solve()
@@ -356,6 +370,7 @@ def main():
                 "traffic": traffic, "algorithmic_bytes_per_launch": round(per_launch_bytes),
                 "avg_launch_us": round(1000.0 * dom_stat["ms"] / max(dom_stat["launches"], 1), 2),
                 "launches_per_solve": dom_stat["launches"],
+                "stream_copy_GBps": round(copy_gbps, 1), "frac_of_copy": round(achieved / copy_gbps, 4),
                 "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 4),
                                 "GBps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)} for k, v in prof.items()}}
     print(f"# profile: {json.dumps(roofline['kernels'])}", file=sys.stderr, flush=True)
@@ -416,8 +431,20 @@ def main():
                   f"the same graph and schedule, {steps} steps in all")
         cpu = {"value": round(opushes / tcpu / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
                "sample": f"{sample} ({tcpu:.1f} s, step 0 included)",
-               "host": platform.processor() or platform.machine()}
+               "host": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
         print(f"# cpu oracle: {cpu}", file=sys.stderr, flush=True)
+        # all host cores: FP64 power iteration (pull by columns, OpenMP) to the same L1 target
+        if g.c < 1.0:
+            a = time.perf_counter()
+            pst, _, pit, threads = oracle.power_iteration_omp(ch, (1.0 - g.c) * args.tol, 100000)
+            tpi = time.perf_counter() - a
+            links = int(g.nnz)
+            cpu["power_iteration_all_cores"] = {
+                "value": round(pit * links / tpi / 1e9, 5), "unit": "GTEPS", "cores": threads,
+                "kind": "OpenMP FP64 power iteration", "iterations": pit, "seconds": round(tpi, 3),
+                "sample": "one full solve to the same L1 target, transpose built inside the timed region"}
+            print(f"# cpu power iteration, all cores: {cpu['power_iteration_all_cores']}", file=sys.stderr,
+                  flush=True)
 
     batched = batched_leg(args, rl, torch, oracle) if args.batch > 0 else None
     serving = serving_leg(args, rl, torch, oracle) if args.serve_requests > 0 else None

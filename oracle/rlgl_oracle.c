@@ -39,6 +39,7 @@
  *     (the restart case of Sec. 2.1 and Example 1).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -326,6 +327,71 @@ int32_t orc_power_iteration(const orc_chain *ch, double tol, int64_t max_iter, d
   memcpy(x_out, x, sizeof(double) * (size_t)n);
   if (iters) *iters = it;
   free(x); free(y);
+  return status;
+}
+
+/* The same power iteration with its product x P taken column by column on
+ * every host core (OpenMP): a CPU baseline, not a reference.  It builds the
+ * transpose of W once; each y_k = c sum_j x_j W_jk + pool / N, the pool as in
+ * orc_route.  *threads_used receives the thread count. */
+int32_t orc_power_iteration_omp(const orc_chain *ch, double tol, int64_t max_iter, double *x_out, int64_t *iters,
+                                int32_t *threads_used) {
+  const int32_t n = ch->n;
+  if (n <= 0) return ORC_EINVAL;
+  const int64_t m = ch->rowptr[n];
+  int64_t *cp = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+  int32_t *rw = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+  double *wv = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+  double *x = (double *)malloc(sizeof(double) * (size_t)n);
+  double *y = (double *)malloc(sizeof(double) * (size_t)n);
+  int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+  if (!cp || !rw || !wv || !x || !y || !fill) {
+    free(cp); free(rw); free(wv); free(x); free(y); free(fill);
+    return ORC_ENOMEM;
+  }
+  for (int64_t e = 0; e < m; ++e) cp[ch->col[e] + 1] += 1;
+  for (int32_t k = 0; k < n; ++k) cp[k + 1] += cp[k];
+  for (int32_t k = 0; k < n; ++k) fill[k] = cp[k];
+  for (int32_t i = 0; i < n; ++i) {
+    const int64_t d = outdeg(ch, i);
+    for (int64_t e = ch->rowptr[i]; e < ch->rowptr[i + 1]; ++e) {
+      const int64_t q = fill[ch->col[e]]++;
+      rw[q] = i;
+      wv[q] = ch->val ? ch->val[e] : 1.0 / (double)d;
+    }
+  }
+  for (int32_t i = 0; i < n; ++i) x[i] = 1.0 / (double)n;
+  int32_t status = ORC_ENOT_CONVERGED;
+  int64_t it = 0;
+  int32_t used = 1;
+  const double c = ch->c;
+  while (it < max_iter) {
+    double pool = 0.0;
+#pragma omp parallel for reduction(+ : pool) schedule(static)
+    for (int32_t i = 0; i < n; ++i) pool += (outdeg(ch, i) > 0 ? 1.0 - c : 1.0) * x[i];
+    const double share = pool / (double)n;
+    double d = 0.0;
+#pragma omp parallel for reduction(+ : d) schedule(dynamic, 4096)
+    for (int32_t k = 0; k < n; ++k) {
+      double acc = 0.0;
+      for (int64_t q = cp[k]; q < cp[k + 1]; ++q) acc += x[rw[q]] * wv[q];
+      y[k] = c * acc + share;
+      d += fabs(y[k] - x[k]);
+    }
+#pragma omp parallel
+    {
+#pragma omp single
+      used = omp_get_num_threads();
+    }
+    ++it;
+    double *tmp = x; x = y; y = tmp;
+    if (!isfinite(d)) { status = ORC_ENONFINITE; break; }
+    if (d <= tol) { status = ORC_OK; break; }
+  }
+  memcpy(x_out, x, sizeof(double) * (size_t)n);
+  if (iters) *iters = it;
+  if (threads_used) *threads_used = used;
+  free(cp); free(rw); free(wv); free(x); free(y); free(fill);
   return status;
 }
 

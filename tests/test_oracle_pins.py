@@ -368,3 +368,13 @@ def test_pc_solve_reaches_stationary_distribution():
     for _ in range(50):
         s.step(oracle.PC, seed=9)
         assert abs(s.C.sum()) <= 1e-13
+
+
+def test_parallel_power_iteration_baseline_agrees():
+    """The all-core power iteration (a CPU baseline) takes the same iterates
+    as the serial one."""
+    ch, _ = random_chain(3000, 2, c=0.85, dangling=0.1, deg=6.0)
+    st, x, it = oracle.power_iteration(ch, 1e-13)
+    st2, y, it2, threads = oracle.power_iteration_omp(ch, 1e-13)
+    assert st == st2 == oracle.OK and it == it2 and threads >= 1
+    assert np.abs(x - y).sum() <= 1e-13
