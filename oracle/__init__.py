@@ -90,6 +90,8 @@ def _load():
         lib.orc_power_iteration.restype = i32
         lib.orc_power_iteration_omp.argtypes = [pc, f64, i64, vp, ctypes.POINTER(i64), ctypes.POINTER(i32)]
         lib.orc_power_iteration_omp.restype = i32
+        lib.orc_gso_pr.argtypes = [pc, vp, f64, i64, vp, vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        lib.orc_gso_pr.restype = i32
         lib.orc_residual.argtypes = [pc, vp]
         lib.orc_residual.restype = f64
         _lib = lib
@@ -247,6 +249,18 @@ def power_iteration_omp(ch: Chain, tol: float, max_iter: int = 100000):
     st = _load().orc_power_iteration_omp(ch.ref(), float(tol), int(max_iter), _ptr(x), ctypes.byref(it),
                                          ctypes.byref(th))
     return st, x, it.value, th.value
+
+
+def gso_pr(ch: Chain, eps: float, max_steps: int = 10 ** 8, s=None):
+    """Algorithm 2 (GSo-PR): (status, H, C, steps, edges); pi_hat = H."""
+    H = np.zeros(ch.n, dtype=np.float64)
+    C = np.zeros(ch.n, dtype=np.float64)
+    sv = None if s is None else np.ascontiguousarray(s, dtype=np.float64)
+    steps = ctypes.c_int64(0)
+    edges = ctypes.c_int64(0)
+    st = _load().orc_gso_pr(ch.ref(), _ptr(sv), float(eps), int(max_steps), _ptr(H), _ptr(C), ctypes.byref(steps),
+                            ctypes.byref(edges))
+    return st, H, C, steps.value, edges.value
 
 
 def reference_pagerank(ch: Chain, l1_target: float = 1e-13, max_iter: int = 100000):

@@ -330,6 +330,51 @@ int32_t orc_power_iteration(const orc_chain *ch, double tol, int64_t max_iter, d
   return status;
 }
 
+/* Algorithm 2 (Gauss-Southwell for PageRank, GSo-PR, Sec. 2.4), the
+ * positive-cash special case of RLGL: C_1 = (1-c) s, H_1 = 0; step t moves the
+ * largest cash C_t,k (ties: the smallest k) along c P,
+ *   H_{t+1} = H_t + C_t,k e_k,  C_{t+1} = C_t - C_t,k e_k (I - c P),
+ * until ||C_t||_1 < eps (t >= 2).  P is the chain's link matrix W (a row with
+ * no stored link is uniform); the restart is carried by s (uniform when NULL).
+ * pi_hat_t = H_t.  Writes H_t and C_t, *steps gets the moves made and *edges the
+ * links they used. */
+int32_t orc_gso_pr(const orc_chain *ch, const double *s, double eps, int64_t max_steps, double *H, double *C,
+                   int64_t *steps, int64_t *edges) {
+  const int32_t n = ch->n;
+  if (n <= 0 || !(ch->c > 0.0 && ch->c < 1.0)) return ORC_EINVAL;
+  const double c = ch->c;
+  for (int32_t i = 0; i < n; ++i) {
+    C[i] = (1.0 - c) * (s ? s[i] : 1.0 / (double)n);
+    H[i] = 0.0;
+  }
+  int64_t t = 1, e = 0;
+  int32_t status = ORC_ENOT_CONVERGED;
+  for (;;) {
+    const double l1 = l1norm(n, C);
+    if (!isfinite(l1)) { status = ORC_ENONFINITE; break; }
+    if (t >= 2 && l1 < eps) { status = ORC_OK; break; }
+    if (t - 1 >= max_steps) break;
+    int32_t k = 0;
+    for (int32_t i = 1; i < n; ++i)
+      if (C[i] > C[k]) k = i;
+    const double m = C[k];
+    H[k] += m;
+    C[k] -= m;
+    const int64_t d = outdeg(ch, k);
+    if (d == 0) {
+      for (int32_t j = 0; j < n; ++j) C[j] += c * m / (double)n;
+    } else {
+      for (int64_t q = ch->rowptr[k]; q < ch->rowptr[k + 1]; ++q)
+        C[ch->col[q]] += c * m * (ch->val ? ch->val[q] : 1.0 / (double)d);
+      e += d;
+    }
+    ++t;
+  }
+  if (steps) *steps = t - 1;
+  if (edges) *edges = e;
+  return status;
+}
+
 /* The same power iteration with its product x P taken column by column on
  * every host core (OpenMP): a CPU baseline, not a reference.  It builds the
  * transpose of W once; each y_k = c sum_j x_j W_jk + pool / N, the pool as in

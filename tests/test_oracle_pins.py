@@ -378,3 +378,47 @@ def test_parallel_power_iteration_baseline_agrees():
     st2, y, it2, threads = oracle.power_iteration_omp(ch, 1e-13)
     assert st == st2 == oracle.OK and it == it2 and threads >= 1
     assert np.abs(x - y).sum() <= 1e-13
+
+
+def test_gso_pr_error_identity():
+    """Algorithm 2 keeps C_t >= 0 and H_t (I - cP) + C_t = (1-c) s, so
+    pi* - H_t = C_t (I - cP)^-1 >= 0 and ||pi* - H_t||_1 = ||C_t||_1 / (1-c)
+    exactly (the row sums of (I - cP)^-1 are 1/(1-c))."""
+    ch, g = random_chain(80, 4, c=0.85, dangling=0.0)
+    P = oracle.dense_P(ch)
+    W = oracle.dense_P(oracle.Chain(g.rowptr, g.col, None, 1.0))
+    pi = oracle.stationary_gth(P)
+    for eps in (1e-2, 1e-5, 1e-9):
+        st, H, C, steps, edges = oracle.gso_pr(ch, eps)
+        assert st == oracle.OK and np.all(C >= 0.0) and C.sum() < eps
+        assert np.abs(H @ (np.eye(ch.n) - 0.85 * W) + C - 0.15 / ch.n).max() < 1e-15
+        assert np.all(pi - H >= -1e-16)
+        assert abs(np.abs(pi - H).sum() - C.sum() / 0.15) < 1e-14
+
+
+def test_gso_pr_is_rlgl_on_the_auxiliary_chain():
+    """Sec. 2.4: RLGL on P^(0) from M_0 = e_0, with the green set {k} that
+    Algorithm 2 picks, reproduces Algorithm 2's H_t and C_t on states 1..N;
+    the first step of RLGL gives C_1 = (-(1-c), (1-c) s) and H_1 = e_0."""
+    import workloads
+    c = 0.85
+    g = workloads.poisson_uniform(60, 3.0, c, seed=2)
+    ch = oracle.Chain(g.rowptr, g.col, None, c)
+    aux = workloads.auxiliary_node_chain(g, c)
+    cha = oracle.Chain(aux.rowptr, aux.col, aux.val(), 1.0)
+    e0 = np.zeros(aux.n)
+    e0[0] = 1.0
+    st0 = oracle.State(cha, M0=e0)
+    assert np.allclose(st0.C, np.concatenate([[-(1 - c)], np.full(g.n, (1 - c) / g.n)]), atol=1e-16, rtol=0)
+    assert np.array_equal(st0.H, e0) and st0.hsum == 1.0
+    # Algorithm 2 step by step, mirrored on the auxiliary chain
+    C = np.full(g.n, (1 - c) / g.n)
+    for t in range(200):
+        k = int(np.argmax(C))
+        mask = np.zeros(aux.n, dtype=bool)
+        mask[k + 1] = True
+        st0.step_mask(mask)
+        _, H, C, steps, _ = oracle.gso_pr(ch, 0.0, max_steps=t + 1)
+        assert steps == t + 1
+        assert np.abs(st0.H[1:] - H).max() < 1e-15
+        assert np.abs(st0.C[1:] - C).max() < 1e-15

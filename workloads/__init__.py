@@ -83,6 +83,7 @@ class Graph:
     name: str = ""
     params: dict = field(default_factory=dict)
     _csc: tuple | None = None
+    weights: np.ndarray | None = None  # explicit W_ij per stored link (float64); None: 1/outdeg(i)
 
     @property
     def nnz(self) -> int:
@@ -97,7 +98,10 @@ class Graph:
         return int((self.outdeg == 0).sum())
 
     def val(self, dtype=np.float64) -> np.ndarray:
-        """1/outdeg(i) for every stored link, computed in float64 then cast."""
+        """W_ij of every stored link: the explicit weights, or 1/outdeg(i),
+        computed in float64 then cast."""
+        if self.weights is not None:
+            return self.weights.astype(dtype)
         deg = self.outdeg
         inv = np.zeros(self.n, dtype=np.float64)
         nz = deg > 0
@@ -255,6 +259,39 @@ def largest_scc(g: Graph, c: float = 1.0, name: str = "") -> Graph:
     params = dict(g.params, scc_of=g.name, c=c)
     return from_edges(m, new[src[inside]].astype(np.int32), new[g.col[inside]].astype(np.int32), c,
                       name or f"{g.name}_scc", params)
+
+
+def auxiliary_node_chain(g: Graph, c: float, name: str = "") -> Graph:
+    """The (N+1)-state chain P^(0) of Sec. 2.4 on which RLGL is GSo-PR: state 0
+    is the auxiliary node (self-loop c, then (1-c)/N to every state), state
+    i+1 is g's state i (1-c back to 0, then c/outdeg(i) along each of its
+    links).  Needs a graph without dangling states.  Explicit weights; used
+    with damping 1 (the chain already carries the restart)."""
+    n = g.n
+    deg = g.outdeg
+    if np.any(deg == 0):
+        raise ValueError("the auxiliary-node chain needs a graph without dangling states")
+    rowlen = np.concatenate([[n + 1], 1 + deg]).astype(np.int64)
+    rowptr = np.zeros(n + 2, dtype=np.int64)
+    np.cumsum(rowlen, out=rowptr[1:])
+    total = int(rowptr[-1])
+    col = np.empty(total, dtype=np.int32)
+    w = np.empty(total, dtype=np.float64)
+    col[:n + 1] = np.arange(n + 1, dtype=np.int32)
+    w[0] = c
+    w[1:n + 1] = (1.0 - c) / n
+    first = np.zeros(total, dtype=bool)
+    first[rowptr[1:n + 1]] = True
+    first[:n + 1] = False
+    rest = np.zeros(total, dtype=bool)
+    rest[n + 1:] = True
+    links = rest & ~first
+    col[first] = 0
+    w[first] = 1.0 - c
+    col[links] = g.col + 1
+    w[links] = c / np.repeat(deg, deg)
+    return Graph(n + 1, rowptr, col, 1.0, name or f"{g.name}_aux", dict(g.params, aux_of=g.name, c_inner=c),
+                 weights=w)
 
 
 def poisson_arrivals(count: int, rate: float, seed: int, stream: int = S_META + 2) -> np.ndarray:
