@@ -434,3 +434,29 @@ def test_threshold_order_two_solve(prec):
     assert st == rl.RLGL_OK
     assert l1(to_np(s.pi), reference(g)) <= 1e-6
     s.close()
+
+
+@pytest.mark.parametrize("prec", [rl.FP64, rl.FP32C_FP64H], ids=PREC_NAMES.get)
+@pytest.mark.parametrize("route", ["push", "pull", "auto"])
+def test_auxiliary_node_chain_gives_pagerank(prec, route):
+    """RLGL on the auxiliary-node chain P^(0) of Sec. 2.4 (damping 1, explicit
+    weights; state 0 has N+1 out-links and N in-links, the hub paths of both
+    routes) started from M_0 = e_0: pi^(0) = (1/2, pi*/2), with pi* the
+    PageRank of the original chain."""
+    c = 0.85
+    base = workloads.poisson_uniform(6000, 8.0, c, seed=11)
+    aux = workloads.auxiliary_node_chain(base, c)
+    say("case aux_chain", PREC_NAMES[prec], route, aux.n, aux.nnz)
+    ref = oracle.reference_pagerank(oracle_chain(base), 1e-13)[0]
+    s = solver(aux, prec, sched=rl.SCHED_THRESHOLD, route=ROUTES[route])
+    C1 = np.concatenate([[-(1 - c)], np.full(base.n, (1 - c) / base.n)])
+    H1 = np.zeros(aux.n)
+    H1[0] = 1.0
+    s.set_state(torch.from_numpy(C1).cuda(), torch.from_numpy(H1).cuda(), 1.0, t=1)
+    tol = 1e-10 if prec == rl.FP64 else 1e-6
+    st, info = s.solve(tol * 0.05)
+    assert st == rl.RLGL_OK
+    pi = to_np(s.pi)
+    s.close()
+    assert abs(pi[0] - 0.5) <= tol
+    assert l1(2.0 * pi[1:], ref) <= 2 * tol
