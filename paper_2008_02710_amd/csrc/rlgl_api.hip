@@ -350,7 +350,7 @@ rlgl_status relabel_graph(rlgl_ctx *c, const rlgl_graph *g, const Layout &L, cha
     d_ncp = (int *)(w + L.ncolptr);
     HIP_TRY(hipMemcpyAsync(d_ncp, ncp.data(), sizeof(int) * ((size_t)n + 1), hipMemcpyHostToDevice, c->stream));
   }
-  const int grid = std::max(1, std::min((n + (BLOCK / 64) - 1) / (BLOCK / 64), 8192));
+  const int grid = (int)std::max<long long>(1, std::min<long long>((g->nnz + BLOCK - 1) / BLOCK, 16384));
   int *ncol = (int *)(w + L.ncol);
   void *nval = g->csr_val ? (void *)(w + L.nval) : nullptr;
   if (c->prec == RLGL_FP64)

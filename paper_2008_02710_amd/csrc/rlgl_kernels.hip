@@ -1080,21 +1080,25 @@ __global__ __launch_bounds__(BLOCK) void k_export_mask(Dev d, unsigned char *out
 
 // Relabelled copy of one side of the graph (CSR or CSC): new row i is old row
 // new2old[i], its ids mapped through old2new (ids outside [0, n) are kept, so
-// the kernels still ignore them).  One wave per row.
+// the kernels still ignore them).  One thread per link of the new layout; the
+// new row of link p is found by a binary search of the new row pointers, so a
+// hub row is spread over many threads.
 template <class V>
 __global__ __launch_bounds__(BLOCK) void k_relabel_side(int n, const int *ptr, const int *idx, const V *val,
                                                         const int *new2old, const int *old2new, const int *nptr,
                                                         int *nidx, V *nval) {
-  const int lane = threadIdx.x & 63;
-  const int waves = gridDim.x * (BLOCK / 64);
-  for (int i = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6); i < n; i += waves) {
-    const int o = new2old[i];
-    const int b = ptr[o], deg = ptr[o + 1] - b, dst = nptr[i];
-    for (int e = lane; e < deg; e += 64) {
-      const int j = idx[b + e];
-      nidx[dst + e] = ((unsigned)j < (unsigned)n) ? old2new[j] : j;
-      if (val) nval[dst + e] = val[b + e];
+  const int m = nptr[n];
+  for (int p = blockIdx.x * BLOCK + threadIdx.x; p < m; p += gridDim.x * BLOCK) {
+    int lo = 0, hi = n;  // nptr[lo] <= p < nptr[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (nptr[mid] <= p) lo = mid;
+      else hi = mid;
     }
+    const int src = ptr[new2old[lo]] + (p - nptr[lo]);
+    const int j = idx[src];
+    nidx[p] = ((unsigned)j < (unsigned)n) ? old2new[j] : j;
+    if (val) nval[p] = val[src];
   }
 }
 
