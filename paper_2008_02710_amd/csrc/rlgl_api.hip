@@ -190,8 +190,18 @@ hipError_t enqueue_step(rlgl_ctx *c, long long s, double eps, long long s_limit,
   hipError_t e = hipSuccess;
   if (!force_all && d.sched == SCHED_TOPK) {
     e = timed(c, KS_TOPK, s, [&] {
-      if (c->prec == RLGL_FP64) k_topk<double><<<1, 1024, 0, c->stream>>>(d, s);
-      else k_topk<float><<<1, 1024, 0, c->stream>>>(d, s);
+      // radix select of the k-th largest |C| and of the id bound among its ties
+      const int key_bits = (c->prec == RLGL_FP64) ? 64 : 32;
+      const int hg = std::max(1, std::min((d.n + BLOCK - 1) / BLOCK, 1024));
+      k_topk_init<<<1, 256, 0, c->stream>>>(d);
+      for (int ids = 0; ids < 2; ++ids) {
+        const int bits = ids ? 32 : key_bits;
+        for (int shift = bits - 8; shift >= 0; shift -= 8) {
+          if (c->prec == RLGL_FP64) k_topk_hist<double><<<hg, BLOCK, 0, c->stream>>>(d, s, shift, ids);
+          else k_topk_hist<float><<<hg, BLOCK, 0, c->stream>>>(d, s, shift, ids);
+          k_topk_pick<<<1, 64, 0, c->stream>>>(d, s, shift, ids, shift == 0, key_bits);
+        }
+      }
     });
     if (e != hipSuccess) return e;
   }

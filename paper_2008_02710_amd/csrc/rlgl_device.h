@@ -73,6 +73,10 @@ struct Glob {
   unsigned int ticket;        // last-block detection in k_refresh
   long long t;                // index of the current state
   double rpool;               // refresh: sum_j H_j (1 - c [outdeg_j > 0])
+  // top-k radix select: bits fixed so far, entries still to take, the k-th key
+  unsigned long long tk_prefix, tk_key;
+  long long tk_rem;
+  unsigned int tk_hist[256];
 };
 
 struct StepLog {

@@ -891,57 +891,97 @@ __global__ __launch_bounds__(BLOCK) void k_refresh_long(Dev d, long long t, int 
 
 // -------------------------------------------------- top-k threshold search
 //
-// k_topk finds, for the snapshot C_t, the k-th largest |C| (tau) and the
-// largest node id that still fits among the nodes with |C| = tau, so that
-// green = |C| > tau or (|C| = tau and id <= tie_id) selects exactly k nodes
-// ordered by |C| descending, then id ascending.  One block, bitwise radix
-// search on the 63-bit pattern of |C| as a double, then a search on ids.
+// The k-th largest |C| of the snapshot C_t (tau) and the largest node id that
+// still fits among the nodes with |C| = tau, so that green = |C| > tau or
+// (|C| = tau and id <= tie_id) selects exactly k nodes ordered by |C|
+// descending, then id ascending.  A radix select over the bit pattern of |C|
+// (non-negative floats order as their bits): each 8-bit digit, from the top,
+// is one k_topk_hist launch (per-workgroup LDS histograms of the digit among
+// the keys that match the prefix fixed so far, added into one global
+// histogram) and one single-workgroup k_topk_pick that fixes the digit.  Then
+// the same over the 32-bit ids of the nodes whose key equals tau, ascending.
+
 template <class T>
-__global__ __launch_bounds__(1024) void k_topk(Dev d, long long s) {
-  if (d.glob->status != 0) return;
-  Rec *cur = &d.rec[s % 3];
-  const T *C = (const T *)d.cash[cur->buf];
-  const int n = d.n;
-  const long long k = d.k < (long long)n ? d.k : (long long)n;
-  __shared__ unsigned long long sh_cnt[1024 / 64];
-  __shared__ unsigned long long sh_prefix;
-  auto block_count = [&](auto pred) -> unsigned long long {
-    unsigned long long c = 0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) c += pred(i) ? 1ull : 0ull;
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-    if ((threadIdx.x & 63) == 0) sh_cnt[threadIdx.x >> 6] = c;
-    __syncthreads();
-    unsigned long long t = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh_cnt[w];
-    __syncthreads();
-    return t;
-  };
-  auto keyof = [&](int i) -> unsigned long long {
-    return (unsigned long long)__double_as_longlong(fabs((double)C[i]));
-  };
-  // largest pattern P such that #(key >= P) >= k: bitwise from the top
-  if (threadIdx.x == 0) sh_prefix = 0ull;
-  __syncthreads();
-  for (int bit = 62; bit >= 0; --bit) {
-    const unsigned long long cand = sh_prefix | (1ull << bit);
-    const unsigned long long c = block_count([&](int i) { return keyof(i) >= cand; });
-    if (threadIdx.x == 0 && c >= (unsigned long long)k) sh_prefix = cand;
-    __syncthreads();
-  }
-  const unsigned long long tau_bits = sh_prefix;
-  const unsigned long long above = block_count([&](int i) { return keyof(i) > tau_bits; });
-  const long long need = k - (long long)above;  // >= 1 ties to take
-  // smallest id bound I such that #(key == tau, id <= I) >= need
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = lo + (hi - lo) / 2;
-    const unsigned long long c = block_count([&](int i) { return i <= mid && keyof(i) == tau_bits; });
-    if (c >= (unsigned long long)need) hi = mid;
-    else lo = mid + 1;
-  }
+__device__ __forceinline__ unsigned long long topk_key(T v) {
+  if (sizeof(T) == 4) return (unsigned long long)__float_as_uint(fabsf((float)v));
+  return (unsigned long long)__double_as_longlong(fabs((double)v));
+}
+
+__global__ void k_topk_init(Dev d) {
+  Glob *g = d.glob;
+  if (g->status != 0) return;
+  for (int q = threadIdx.x; q < 256; q += blockDim.x) g->tk_hist[q] = 0u;
   if (threadIdx.x == 0) {
-    cur->topk_tau = __longlong_as_double((long long)tau_bits);
-    cur->topk_tie_id = lo;
+    g->tk_prefix = 0ull;
+    g->tk_key = 0ull;
+    g->tk_rem = d.k < (long long)d.n ? d.k : (long long)d.n;
+  }
+}
+
+// ids = 0: digit `shift` of the keys whose bits above it equal the prefix;
+// ids = 1: digit `shift` of the ids of the nodes whose key is tk_key and
+// whose id bits above it equal the prefix.
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_topk_hist(Dev d, long long s, int shift, int ids) {
+  Glob *g = d.glob;
+  if (g->status != 0) return;
+  const T *C = (const T *)d.cash[d.rec[s % 3].buf];
+  __shared__ unsigned int h[256];
+  for (int q = threadIdx.x; q < 256; q += BLOCK) h[q] = 0u;
+  __syncthreads();
+  const unsigned long long prefix = g->tk_prefix, tkey = g->tk_key;
+  const int hi = shift + 8;
+  const int n = d.n;
+  for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
+    const unsigned long long key = topk_key(C[i]);
+    unsigned long long x;
+    if (ids) {
+      if (key != tkey) continue;
+      x = (unsigned long long)(unsigned int)i;
+    } else {
+      x = key;
+    }
+    if (hi < 64 && (x >> hi) != (prefix >> hi)) continue;
+    atomicAdd(&h[(x >> shift) & 255ull], 1u);
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < 256; q += BLOCK)
+    if (h[q]) atomicAdd(&g->tk_hist[q], h[q]);
+}
+
+// Fixes the digit at `shift`: keys take the largest digits first, ids the
+// smallest.  `last` ends a phase: after the keys, tau is written and the id
+// phase starts from an empty prefix; after the ids, tie_id is written.
+__global__ void k_topk_pick(Dev d, long long s, int shift, int ids, int last, int key_bits) {
+  Glob *g = d.glob;
+  if (g->status != 0 || threadIdx.x != 0 || blockIdx.x != 0) return;
+  long long rem = g->tk_rem;
+  int dig = ids ? 255 : 0;
+  long long before = 0;  // entries in digits taken ahead of dig
+  for (int q = 0; q < 256; ++q) {
+    const int b = ids ? q : 255 - q;
+    const long long cnt = (long long)g->tk_hist[b];
+    if (before + cnt >= rem) {
+      dig = b;
+      break;
+    }
+    before += cnt;
+  }
+  for (int q = 0; q < 256; ++q) g->tk_hist[q] = 0u;
+  const unsigned long long prefix = g->tk_prefix | ((unsigned long long)dig << shift);
+  rem -= before;
+  Rec *cur = &d.rec[s % 3];
+  if (!last) {
+    g->tk_prefix = prefix;
+    g->tk_rem = rem;
+  } else if (!ids) {
+    g->tk_key = prefix;
+    cur->topk_tau = key_bits == 32 ? (double)__uint_as_float((unsigned int)prefix)
+                                   : __longlong_as_double((long long)prefix);
+    g->tk_prefix = 0ull;
+    g->tk_rem = rem;  // ties of tau still to take, >= 1
+  } else {
+    cur->topk_tie_id = (int)prefix;
   }
 }
 
@@ -1189,8 +1229,8 @@ template __global__ void k_complete_long<double>(Dev, long long, int);
 template __global__ void k_refresh_long<float, 0>(Dev, long long, int);
 template __global__ void k_refresh_long<float, 1>(Dev, long long, int);
 template __global__ void k_refresh_long<double, 0>(Dev, long long, int);
-template __global__ void k_topk<float>(Dev, long long);
-template __global__ void k_topk<double>(Dev, long long);
+template __global__ void k_topk_hist<float>(Dev, long long, int, int);
+template __global__ void k_topk_hist<double>(Dev, long long, int, int);
 template __global__ void k_refresh_pool<0>(Dev);
 template __global__ void k_refresh_pool<1>(Dev);
 template __global__ void k_refresh<float, 0>(Dev, long long, int);

@@ -460,3 +460,25 @@ def test_auxiliary_node_chain_gives_pagerank(prec, route):
     s.close()
     assert abs(pi[0] - 0.5) <= tol
     assert l1(2.0 * pi[1:], ref) <= 2 * tol
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=PREC_NAMES.get)
+@pytest.mark.parametrize("k", [1, 37, 600, 1249, 2500])
+def test_topk_with_heavy_ties(prec, k):
+    """Top-k on a cash vector of a few distinct magnitudes (zero included), k
+    cutting through a tie group: the device's green set is the oracle's (|C|
+    descending, then smaller id) bit for bit, for every precision."""
+    g = small_graph()
+    say("case topk_ties", PREC_NAMES[prec], k)
+    rng = np.random.default_rng(k)
+    levels = np.array([0.0, 0.00048828125, 0.0009765625, 0.001953125])  # exact in FP32
+    C0 = levels[rng.integers(0, 4, g.n)] * rng.choice([-1.0, 1.0], g.n)
+    H0 = np.full(g.n, 1.0 / g.n)
+    s = solver(g, prec, sched=rl.SCHED_TOPK, k=k, record_green=1, route=rl.ROUTE_PULL)
+    s.set_state(torch.from_numpy(C0).cuda(), torch.from_numpy(H0).cuda(), float(H0.sum()), t=4)
+    s.step(1)
+    mask = to_np(s.green()).astype(bool)
+    want = oracle.select(C0, oracle.TOPK, 0.0, k)
+    assert int(mask.sum()) == min(k, g.n)
+    assert np.array_equal(mask, want)
+    s.close()
