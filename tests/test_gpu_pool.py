@@ -156,3 +156,21 @@ def test_pool_rejects_bad_requests():
     drain(pool, [s])
     pool.release(s)
     pool.close()
+
+
+def test_pool_reports_step_limit_per_request():
+    """A pool whose step limit is too small for the tolerance reports
+    RLGL_ENOT_CONVERGED for that request (pi_hat still written) and keeps
+    serving the next one."""
+    gs = requests()[:2]
+    say("case pool_limit")
+    pool = rl.Pool(64 << 20, max_chains=2, max_steps=3)
+    hcs = [rl.HostChain(g, tol_l1=1e-12) for g in gs]
+    slots = [pool.admit(h) for h in hcs]
+    got = drain(pool, slots)
+    for s in slots:
+        res, pi = got[s]
+        assert res["status"] == rl.RLGL_ENOT_CONVERGED and res["t"] == 4
+        assert abs(pi.sum() - 1.0) < 1e-6
+        pool.release(s)
+    pool.close()
