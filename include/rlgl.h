@@ -366,8 +366,17 @@ rlgl_status rlgl_pool_admit(rlgl_pool *p, const rlgl_request *req, int32_t *slot
  * iterations (one step of every running chain each, at most) on the pool's
  * stream, waits for them, and collects the chains that finished.
  * *running (may be NULL) receives the number of chains still uploading or
- * running. */
+ * running.  Equal to rlgl_pool_launch followed by rlgl_pool_wait. */
 rlgl_status rlgl_pool_advance(rlgl_pool *p, int32_t iterations, int32_t *running);
+
+/* The two halves of rlgl_pool_advance, so that the host can admit requests
+ * while the iterations run: rlgl_pool_launch enqueues them and returns at
+ * once (RLGL_EINVAL if a launch is still in flight); rlgl_pool_wait waits for
+ * them and collects the chains that finished (it returns at once when nothing
+ * is in flight).  Between the two, rlgl_pool_admit, _poll, _result and
+ * _release may be called; a chain admitted then joins at the next launch. */
+rlgl_status rlgl_pool_launch(rlgl_pool *p, int32_t iterations);
+rlgl_status rlgl_pool_wait(rlgl_pool *p, int32_t *running);
 
 /* Writes up to max_slots slots of chains finished since the last call into
  * slots (host) and returns their number (or a negative rlgl_status). */

@@ -100,8 +100,8 @@ EXPORTED = ["rlgl_default_options", "rlgl_workspace_bytes", "rlgl_create", "rlgl
             "rlgl_batch_default_options", "rlgl_batch_workspace_bytes", "rlgl_batch_create", "rlgl_batch_solve",
             "rlgl_batch_autotune", "rlgl_batch_destroy",
             "rlgl_pool_default_options", "rlgl_pool_workspace_bytes", "rlgl_pool_footprint", "rlgl_pool_create",
-            "rlgl_pool_admit", "rlgl_pool_advance", "rlgl_pool_poll", "rlgl_pool_result", "rlgl_pool_release",
-            "rlgl_pool_destroy"]
+            "rlgl_pool_admit", "rlgl_pool_advance", "rlgl_pool_launch", "rlgl_pool_wait", "rlgl_pool_poll",
+            "rlgl_pool_result", "rlgl_pool_release", "rlgl_pool_destroy"]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -164,6 +164,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rlgl_pool_admit.restype = i32
     lib.rlgl_pool_advance.argtypes = [vp, i32, ctypes.POINTER(i32)]
     lib.rlgl_pool_advance.restype = i32
+    lib.rlgl_pool_launch.argtypes = [vp, i32]
+    lib.rlgl_pool_launch.restype = i32
+    lib.rlgl_pool_wait.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.rlgl_pool_wait.restype = i32
     lib.rlgl_pool_poll.argtypes = [vp, ctypes.POINTER(i32), i32]
     lib.rlgl_pool_poll.restype = i32
     lib.rlgl_pool_result.argtypes = [vp, i32, ctypes.POINTER(rlgl_chain_result), ctypes.POINTER(vp)]
@@ -353,6 +357,16 @@ def rlgl_pool_admit(handle, req: rlgl_request):
 def rlgl_pool_advance(handle, iterations: int) -> int:
     running = ctypes.c_int32(0)
     _check(_lib.rlgl_pool_advance(handle, int(iterations), ctypes.byref(running)), "rlgl_pool_advance")
+    return running.value
+
+
+def rlgl_pool_launch(handle, iterations: int) -> None:
+    _check(_lib.rlgl_pool_launch(handle, int(iterations)), "rlgl_pool_launch")
+
+
+def rlgl_pool_wait(handle) -> int:
+    running = ctypes.c_int32(0)
+    _check(_lib.rlgl_pool_wait(handle, ctypes.byref(running)), "rlgl_pool_wait")
     return running.value
 
 
@@ -624,6 +638,12 @@ class Pool:
 
     def advance(self, iterations: int = 4) -> int:
         return rlgl_pool_advance(self.handle, iterations)
+
+    def launch(self, iterations: int = 4) -> None:
+        rlgl_pool_launch(self.handle, iterations)
+
+    def wait(self) -> int:
+        return rlgl_pool_wait(self.handle)
 
     def poll(self):
         return rlgl_pool_poll(self.handle)

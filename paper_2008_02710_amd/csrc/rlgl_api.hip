@@ -1531,6 +1531,7 @@ struct PoolSlot {
   char *stage = nullptr;      // page-locked copy of the plan and the long columns for the upload
   size_t stage_cap = 0;
   LsChain desc{};
+  LsCtl final{};              // the chain's control record when it was collected
 };
 
 // Arena bytes of a chain: row and column pointers, CSC sources, plan, two
@@ -1577,6 +1578,8 @@ struct rlgl_pool {
   std::vector<int> running;   // slots in the active list, admission order
   std::vector<int> finished;  // finished since the last poll
   bool dirty = false;
+  bool in_flight = false;     // iterations enqueued by rlgl_pool_launch, not yet waited for
+  hipEvent_t launched = nullptr;
   long long t_origin = 0;
   double clock_khz = 100000.0;
 };
@@ -1678,6 +1681,8 @@ rlgl_status rlgl_pool_create(const rlgl_pool_options *o, void *ws, size_t ws_byt
   p->slots.resize((size_t)o->max_chains);
   if (hipStreamCreateWithFlags(&p->copy, hipStreamNonBlocking) != hipSuccess)
     return bail(fail(RLGL_EHIP, "creating the upload stream failed"));
+  if (hipEventCreateWithFlags(&p->launched, hipEventDisableTiming) != hipSuccess)
+    return bail(fail(RLGL_EHIP, "event creation failed"));
   for (PoolSlot &s : p->slots)
     if (hipEventCreateWithFlags(&s.ready, hipEventDisableTiming) != hipSuccess)
       return bail(fail(RLGL_EHIP, "event creation failed"));
@@ -1717,6 +1722,8 @@ rlgl_status rlgl_pool_admit(rlgl_pool *p, const rlgl_request *q, int32_t *slot) 
   // the plan is built into the slot's page-locked staging buffer
   std::vector<int4> items;
   std::vector<int> longs;
+  items.reserve(batch_item_bound(n, m));
+  longs.reserve(long_col_bound(m));
   int np = 0, nr = 0;
   std::string why;
   if (!chain_plan(q->csc_colptr, (int)n, (int)m, true, items, longs, np, nr, why))
@@ -1794,8 +1801,9 @@ rlgl_status rlgl_pool_admit(rlgl_pool *p, const rlgl_request *q, int32_t *slot) 
   return RLGL_OK;
 }
 
-rlgl_status rlgl_pool_advance(rlgl_pool *p, int32_t iterations, int32_t *running) {
+rlgl_status rlgl_pool_launch(rlgl_pool *p, int32_t iterations) {
   if (!p || iterations < 0) return fail(RLGL_EINVAL, "bad argument");
+  if (p->in_flight) return fail(RLGL_EINVAL, "iterations are already in flight (call rlgl_pool_wait)");
   // start the chains whose upload has landed
   for (int k = 0; k < (int)p->slots.size(); ++k) {
     PoolSlot &S = p->slots[k];
@@ -1820,11 +1828,22 @@ rlgl_status rlgl_pool_advance(rlgl_pool *p, int32_t iterations, int32_t *running
     if (st != RLGL_OK) return st;
     HIP_TRY(hipMemcpyAsync(p->E.h_ctl, p->E.args.ctl, sizeof(LsCtl) * p->slots.size(), hipMemcpyDeviceToHost,
                            p->stream));
-    HIP_TRY(hipStreamSynchronize(p->stream));
+    HIP_TRY(hipEventRecord(p->launched, p->stream));
+    p->in_flight = true;
+  }
+  return RLGL_OK;
+}
+
+rlgl_status rlgl_pool_wait(rlgl_pool *p, int32_t *running) {
+  if (!p) return fail(RLGL_EINVAL, "null pool");
+  if (p->in_flight) {
+    HIP_TRY(hipEventSynchronize(p->launched));
+    p->in_flight = false;
     std::vector<int> keep;
     keep.reserve(p->running.size());
     for (int k : p->running) {
       if (p->E.h_ctl[k].mode == LS_DONE) {
+        p->slots[k].final = p->E.h_ctl[k];
         p->slots[k].state = SLOT_FINISHED;
         p->finished.push_back(k);
       } else {
@@ -1844,6 +1863,12 @@ rlgl_status rlgl_pool_advance(rlgl_pool *p, int32_t iterations, int32_t *running
   return RLGL_OK;
 }
 
+rlgl_status rlgl_pool_advance(rlgl_pool *p, int32_t iterations, int32_t *running) {
+  const rlgl_status st = rlgl_pool_launch(p, iterations);
+  if (st != RLGL_OK) return st;
+  return rlgl_pool_wait(p, running);
+}
+
 int32_t rlgl_pool_poll(rlgl_pool *p, int32_t *slots, int32_t max_slots) {
   if (!p || (max_slots > 0 && !slots) || max_slots < 0) return fail(RLGL_EINVAL, "bad argument");
   const int m = std::min((int)p->finished.size(), (int)max_slots);
@@ -1857,7 +1882,7 @@ rlgl_status rlgl_pool_result(rlgl_pool *p, int32_t slot, rlgl_chain_result *r, c
   const PoolSlot &S = p->slots[slot];
   if (S.state == SLOT_FREE) return fail(RLGL_EINVAL, "slot %d holds no chain", slot);
   if (S.state != SLOT_FINISHED) return fail(RLGL_EBUSY, "slot %d has not finished", slot);
-  const LsCtl &c = p->E.h_ctl[slot];
+  const LsCtl &c = S.final;
   if (r) {
     const double us = 1000.0 / p->clock_khz;
     r->t = c.t;
@@ -1898,6 +1923,7 @@ void rlgl_pool_destroy(rlgl_pool *p) {
     if (S.stage) (void)hipHostFree(S.stage);
   }
   if (p->copy) (void)hipStreamDestroy(p->copy);
+  if (p->launched) (void)hipEventDestroy(p->launched);
   ls_free(p->E);
   delete p;
 }

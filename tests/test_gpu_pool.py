@@ -174,3 +174,40 @@ def test_pool_reports_step_limit_per_request():
         assert abs(pi.sum() - 1.0) < 1e-6
         pool.release(s)
     pool.close()
+
+
+def test_pool_launch_wait_with_admissions_in_flight():
+    """The split advance: requests admitted and results collected while
+    iterations are in flight give the same answers; a second launch before
+    the wait is refused."""
+    gs = requests()[:8]
+    say("case pool_launch_wait")
+    pool = rl.Pool(128 << 20, max_chains=8)
+    hcs = [rl.HostChain(g, tol_l1=1e-6) for g in gs]
+    slots = {pool.admit(hcs[0]): 0, pool.admit(hcs[1]): 1}
+    pool.launch(4)
+    with pytest.raises(rl.RlglError) as e:
+        pool.launch(4)
+    assert e.value.status == rl.RLGL_EINVAL
+    nxt = 2
+    got = {}
+    for _ in range(100000):
+        if nxt < len(hcs):
+            s = pool.admit(hcs[nxt])  # while the launch runs
+            assert s is not None
+            slots[s] = nxt
+            nxt += 1
+        pool.wait()
+        for s in pool.poll():
+            res, pi = pool.result(s)
+            got[slots[s]] = (res, to_np(pi).copy())
+            pool.release(s)
+        if len(got) == len(hcs):
+            break
+        pool.launch(4)
+    assert len(got) == len(hcs)
+    for k, g in enumerate(gs):
+        res, pi = got[k]
+        assert res["status"] == rl.RLGL_OK, (k, res)
+        assert l1(pi, reference(g)) <= 1e-6, k
+    pool.close()
