@@ -243,6 +243,8 @@ def main():
     ap.add_argument("--r", type=float, default=None, help="threshold power-mean order (default: the workload's)")
     ap.add_argument("--theta-period", type=int, default=1, help="steps between threshold refreshes")
     ap.add_argument("--seed", type=int, default=1, help="seed of the PC draws")
+    ap.add_argument("--link-values", default="implicit", choices=["implicit", "stored"],
+                    help="link weights 1/outdeg implied by the CSR row pointers, or stored per link")
     ap.add_argument("--relabel", type=int, default=1, choices=[0, 1],
                     help="renumber the states by decreasing out-degree inside the library (layout step)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
@@ -297,7 +299,8 @@ def main():
           file=sys.stderr, flush=True)
 
     dev = torch.device("cuda:0")
-    dg = rl.DeviceGraph.from_workload(g, precision=prec, with_csc=True, explicit_val=True, device=dev)
+    dg = rl.DeviceGraph.from_workload(g, precision=prec, with_csc=True, explicit_val=args.link_values == "stored",
+                                      device=dev)
     stream = torch.cuda.current_stream(dev)
     s = rl.Solver(dg, stream=stream, sched=sched, r=wl["r"], route=route, precision=prec, relabel=args.relabel,
                   theta_period=args.theta_period, seed=args.seed)
@@ -464,7 +467,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": g.name, "n": g.n, "nnz": g.nnz, "dangling": g.n_dangling, "damping": g.c,
                    "schedule": wl["sched"], "r": wl["r"], "precision": args.precision, "route": args.route,
-                   "relabel": args.relabel, "theta_period": args.theta_period,
+                   "relabel": args.relabel, "link_values": args.link_values, "theta_period": args.theta_period,
                    "eps_resid": eps, "tol_l1": args.tol, "generator": g.params.get("generator"),
                    "seed": g.params.get("seed")},
         "steps_per_solve": last["t"] - 1,

@@ -83,11 +83,11 @@ Layout make_layout(long long n, long long nnz, int prec, bool has_csc, bool rela
   L.log = take(sizeof(StepLog) * LOG_STEPS);
   if (has_csc) {
     // upper bounds of the plan built in rlgl_create: a run ends because it is
-    // full (PCH links or PCOLS columns) or because a long column follows
-    L.max_long = (size_t)(nnz / (PCH + 1) + 1);
-    // runs: two consecutive runs hold more than PCH links unless a column-count
-    // or long-column break separates them; pieces: nnz / PCH + one per long column
-    L.max_items = 3 * (size_t)(nnz / PCH + 2) + (size_t)(n / PCOLS + 2) + 2 * L.max_long + 2;
+    // full (WL links or WCOLS columns) or because a long column follows
+    L.max_long = (size_t)(nnz / (WL + 1) + 1);
+    // runs: two consecutive runs hold more than WL links unless a column-count
+    // or long-column break separates them; pieces: nnz / WL + one per long column
+    L.max_items = 3 * (size_t)(nnz / WL + 2) + (size_t)(n / WCOLS + 2) + 2 * L.max_long + 2;
     L.items = take(sizeof(int4) * L.max_items);
     L.long_cols = take(4 * L.max_long);
     L.long_acc = take(8 * L.max_long);
@@ -184,6 +184,42 @@ hipError_t timed(rlgl_ctx *c, int kind, long long s, F launch) {
   return e;
 }
 
+// k_complete and k_refresh come in variants by stored or implied link values
+// and by whether the threshold's power mean needs sum |C|^r (r != 1).
+template <class T>
+void launch_complete(rlgl_ctx *c, long long s, int force_all) {
+  const Dev &d = c->d;
+  const bool v = d.cval != nullptr, rp = d.r != 1.0;
+  if (v && rp) k_complete<T, true, true><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, s, force_all);
+  else if (v) k_complete<T, true, false><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, s, force_all);
+  else if (rp) k_complete<T, false, true><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, s, force_all);
+  else k_complete<T, false, false><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, s, force_all);
+}
+
+// Workgroups of the k_complete variant launch_complete picks that fit one CU together.
+hipError_t complete_occupancy(const rlgl_ctx *c, int *per_cu) {
+  const Dev &d = c->d;
+  const bool v = d.cval != nullptr, rp = d.r != 1.0;
+  const void *f;
+  if (c->prec == RLGL_FP64)
+    f = v ? (rp ? (const void *)k_complete<double, true, true> : (const void *)k_complete<double, true, false>)
+          : (rp ? (const void *)k_complete<double, false, true> : (const void *)k_complete<double, false, false>);
+  else
+    f = v ? (rp ? (const void *)k_complete<float, true, true> : (const void *)k_complete<float, true, false>)
+          : (rp ? (const void *)k_complete<float, false, true> : (const void *)k_complete<float, false, false>);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, f, BLOCK, 0);
+}
+
+template <class T, int HK>
+void launch_refresh(rlgl_ctx *c, long long t, int out) {
+  const Dev &d = c->d;
+  const bool v = d.cval != nullptr, rp = d.r != 1.0;
+  if (v && rp) k_refresh<T, HK, true, true><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, t, out);
+  else if (v) k_refresh<T, HK, true, false><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, t, out);
+  else if (rp) k_refresh<T, HK, false, true><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, t, out);
+  else k_refresh<T, HK, false, false><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, t, out);
+}
+
 hipError_t enqueue_step(rlgl_ctx *c, long long s, double eps, long long s_limit, int force_all) {
   const dim3 blk(BLOCK);
   const Dev &d = c->d;
@@ -219,8 +255,8 @@ hipError_t enqueue_step(rlgl_ctx *c, long long s, double eps, long long s_limit,
     if (e != hipSuccess) return e;
   }
   e = timed(c, KS_COMPLETE, s, [&] {
-    if (c->prec == RLGL_FP64) k_complete<double><<<c->grid_cmp, blk, 0, c->stream>>>(d, s, force_all);
-    else k_complete<float><<<c->grid_cmp, blk, 0, c->stream>>>(d, s, force_all);
+    if (c->prec == RLGL_FP64) launch_complete<double>(c, s, force_all);
+    else launch_complete<float>(c, s, force_all);
   });
   if (e != hipSuccess || d.n_long == 0) return e;
   const int gl = std::max(1, std::min((d.n_long + BLOCK - 1) / BLOCK, NODE_GRID));
@@ -277,15 +313,17 @@ rlgl_status do_refresh(rlgl_ctx *c) {
   k_refresh_prep<<<1, 64, 0, c->stream>>>(d, t);
   if (c->hk) k_refresh_pool<1><<<c->grid_misc, BLOCK, 0, c->stream>>>(d);
   else k_refresh_pool<0><<<c->grid_misc, BLOCK, 0, c->stream>>>(d);
-  if (c->prec == RLGL_FP64) k_refresh<double, 0><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, t, out);
-  else if (c->hk) k_refresh<float, 1><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, t, out);
-  else k_refresh<float, 0><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, t, out);
+  if (c->prec == RLGL_FP64) launch_refresh<double, 0>(c, t, out);
+  else if (c->hk) launch_refresh<float, 1>(c, t, out);
+  else launch_refresh<float, 0>(c, t, out);
   if (d.n_long > 0) {
     const int gl = std::max(1, std::min((d.n_long + BLOCK - 1) / BLOCK, NODE_GRID));
     if (c->prec == RLGL_FP64) k_refresh_long<double, 0><<<gl, BLOCK, 0, c->stream>>>(d, t, out);
     else if (c->hk) k_refresh_long<float, 1><<<gl, BLOCK, 0, c->stream>>>(d, t, out);
     else k_refresh_long<float, 0><<<gl, BLOCK, 0, c->stream>>>(d, t, out);
   }
+  // with FP32 cash the refresh sources lived in the push accumulators
+  if (d.rsrc == d.delta) k_zero_f64<<<c->grid_misc, BLOCK, 0, c->stream>>>(d.delta, d.n);
   k_refresh_done<<<1, 64, 0, c->stream>>>(d, t, out);
   HIP_TRY(hipGetLastError());
   ++c->refreshes;
@@ -417,16 +455,16 @@ rlgl_status build_plan(rlgl_ctx *c, const rlgl_graph *g, const Layout &L, char *
   for (int k = 0; k < n; ++k) {
     const int dg = cp[k + 1] - cp[k];
     if (dg < 0) return fail(RLGL_EINVAL, "csc_colptr is not non-decreasing at %d", k);
-    if (dg > PCH) {
-      // a long column: pieces of PCH links, completed by the last workgroup
+    if (dg > WL) {
+      // a long column: pieces of WL links, completed by k_complete_long
       flush(k);
       const int slot = (int)lng.size();
       lng.push_back(k);
-      for (int p = cp[k]; p < cp[k + 1]; p += PCH)
-        items.push_back(make_int4(-1 - slot, k, p, std::min(p + PCH, cp[k + 1])));
+      for (int p = cp[k]; p < cp[k + 1]; p += WL)
+        items.push_back(make_int4(-1 - slot, k, p, std::min(p + WL, cp[k + 1])));
       continue;
     }
-    if (run0 >= 0 && (run_e + dg > PCH || k - run0 >= PCOLS)) flush(k);
+    if (run0 >= 0 && (run_e + dg > WL || k - run0 >= WCOLS)) flush(k);
     if (run0 < 0) run0 = k;
     run_e += dg;
   }
@@ -572,6 +610,11 @@ rlgl_status rlgl_create(const rlgl_graph *g, const rlgl_options *o, void *ws, si
   d.chunk_first = (int *)(w + L.chunk_first);
   d.green_mask = o->record_green ? (unsigned char *)(w + L.green_mask) : nullptr;
   d.delta = (o->precision == RLGL_FP64) ? nullptr : (double *)(w + L.delta);
+  // the pull's per-node send values take the push frontier's scale array (a
+  // step pulls or pushes, never both); the refresh's FP64 ones take the FP64
+  // push accumulators, or that same array when the cash is FP64
+  d.src = d.fr_scale;
+  d.rsrc = (o->precision == RLGL_FP64) ? (double *)d.fr_scale : d.delta;
   d.colt = nullptr;
   d.hot_nodes = (const int *)(w + L.hot_nodes);
   d.n_hot = 0;
@@ -611,9 +654,17 @@ rlgl_status rlgl_create(const rlgl_graph *g, const rlgl_options *o, void *ws, si
   if (st == RLGL_OK && gi.csc_colptr) st = build_plan(c, &gi, L, w);
   if (st == RLGL_OK) st = build_hot(c, &gi, L, w);
   if (st == RLGL_OK) {
-    c->grid_cmp = std::max({1, std::min(tiles, NODE_GRID), std::min(d.n_items, MAX_GRID)});
-    st = reset_device(c);
+    // the pull's waves take items until the plan is done: one round of
+    // workgroups, as many as stay resident together, keeps every wave's
+    // one-item-ahead loads flowing from start to end
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) ||
+        complete_occupancy(c, &per_cu) != hipSuccess || cus < 1 || per_cu < 1)
+      st = fail(RLGL_EHIP, "occupancy query failed");
+    else
+      c->grid_cmp = std::max({1, std::min(tiles, NODE_GRID), std::min(d.n_items, cus * per_cu)});
   }
+  if (st == RLGL_OK) st = reset_device(c);
   if (st != RLGL_OK) {
     rlgl_destroy(c);
     return st;
@@ -790,6 +841,7 @@ int32_t rlgl_profile_read(rlgl_ctx *c, rlgl_kernel_stat *out, int32_t max_entrie
     if (L.kind == KS_SELECT) {
       b = cs * n + (double)lg.green * (8.0 + hb);
       if (push) b += (double)lg.nfront * (4 + 4 + 4 + cs) + (double)lg.green * cs;
+      else b += cs * n;  // what each node sends along its links in the pull
     } else if (L.kind == KS_PUSH) {
       if (!push) continue;
       b = (double)lg.gedges * (4.0 + vs + 2.0 * cs) + (double)lg.nfront * (8.0 + cs);

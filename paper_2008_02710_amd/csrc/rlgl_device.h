@@ -11,8 +11,9 @@ constexpr int VPT = 4;              // nodes per thread in node-parallel passes
 constexpr int TILE = BLOCK * VPT;   // nodes per tile
 constexpr int CH = 2048;            // links per push chunk and per batched pull item
 constexpr int RUN_MAX_COLS = 1024; // batched pull: columns per run item (4 per thread)
-constexpr int PCH = 1024;          // single-chain pull: links per run item and per long-column piece
-constexpr int PCOLS = 512;         // single-chain pull: columns per run item (2 per thread)
+constexpr int WU = 8;               // single-chain pull: links per lane of a wave item
+constexpr int WL = 64 * WU;         // single-chain pull: links per run item and per long-column piece
+constexpr int WCOLS = 64;           // single-chain pull: columns per run item
 constexpr int LOG_STEPS = 4096;     // ring of per-step records kept for profiling
 constexpr int MAX_GRID = 2048;      // edge-parallel launches
 constexpr int NODE_GRID = 512;      // node-parallel launches (2 workgroups per CU)
@@ -114,6 +115,8 @@ struct Dev {
   int *chunk_first;
   unsigned char *green_mask;
   double *delta;         // push with FP32 cash: FP64 sums of the routed cash, folded into C by complete
+  void *src;             // pull: what each node sends along one of its links this step (cash type, n)
+  double *rsrc;          // refresh: what each node's history sends along one link (FP64, n)
   const int *colt;       // push: CSR columns with hot destinations tagged as -1 - slot
   const int *hot_nodes;  // push: node of each hot slot
   int n_hot;

@@ -203,11 +203,14 @@ __device__ __forceinline__ void fold_block_stats(Rec *r, double l1, double cs, d
   }
 }
 
+// RP = false: the caller knows r = 1 (no power sum, which keeps pow out of
+// the register budget of the hot passes).
+template <bool RP = true>
 __device__ __forceinline__ void fold_stats(double x, double r, double &l1, double &cs, double &sr, double &mx) {
   const double a = fabs(x);
   l1 += a;
   cs += x;
-  if (r != 1.0) sr += pow(a, r);
+  if (RP && r != 1.0) sr += pow(a, r);
   mx = fmax(mx, a);
 }
 
@@ -339,11 +342,14 @@ __global__ __launch_bounds__(BLOCK) void k_select(Dev d, long long s, double eps
       const bool gr = (i < n) && is_green(x, i, sched, theta, maxabs, tau, tie_id, d.seed, s);
       if (i < n) {
         if (d.green_mask) d.green_mask[i] = gr ? 1 : 0;
+        T sent = T(0);  // pull: M_i P'_ij for each link i -> j (M_i itself with stored link values)
         if (gr) {
           ++accG;
           if (x != T(0)) {
             const int r0 = d.rowptr[i];
             const int dg = d.rowptr[i + 1] - r0;
+            if (d.cval) sent = x;
+            else if (dg > 0) sent = (T)((double)x / (double)dg);
             // history: H_{t+1} = H_t + M_t (eq. (5))
             if (HK == 0) {
               double *H = (double *)d.hist;
@@ -380,6 +386,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(Dev d, long long s, double eps
             }
           }
         }
+        if (mode == 1) ((T *)d.src)[i] = sent;
       }
     }
     if (mode == 0) {
@@ -751,28 +758,206 @@ __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved m
   }
 }
 
-template <class T, int NT, class Moved, class Kept>
-__device__ __forceinline__ void column_pass(const Dev &d, Moved moved, Kept kept, double off, T *__restrict__ out,
-                                            Rec *r) {
-  __shared__ ColLds<NT, PCH, PCOLS> L;
-  __shared__ ColStage<T, PCH, PCOLS> S;
-  const ColView g{d.colptr, d.crow, d.rowptr, d.cval, d.n, 0};
+// Wave-level column pass of one chain.  Every wave takes plan items on its
+// own (no workgroup barrier inside the item loop): a RUN {k0, k1, p0, p1} of
+// whole columns holding at most WL links and WCOLS columns, or a PIECE
+// {-1 - slot, k, p0, p1} of at most WL links of a longer column, whose sum
+// goes to long_acc[slot] (k_complete_long finishes those columns).
+//
+// The loads of an item (its CSC sources, column pointers and, with STAGEK,
+// the raw cash values its kept part needs) are issued coalesced into
+// registers one item ahead, so they travel while the wave gathers and sums
+// the item before; at the top of the next round they are parked in the
+// wave's LDS.
+//
+// In a RUN, lane l owns the WU consecutive links [l*WU, l*WU + WU) of the
+// item and gathers what their sources send.  A lane finds the column of its
+// first link by a binary search of the staged column pointers, then walks its
+// links: a column that both starts and ends among them stores its sum at
+// once; the sum of the leading part of its first column (which may have
+// started in an earlier lane) waits for the carry, the sum of the trailing
+// part goes into a segmented scan across the lanes, whose exclusive value is
+// that carry.  Then the lanes write the item's columns, consecutive lanes to
+// consecutive columns: x_k = kept(k) + c * sum_k + off (columns without
+// in-links have sum 0).
+__device__ __forceinline__ void wave_lds_fence() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <class T, class S, bool VAL, bool STAGEK, bool RP, class Keep>
+__device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ src, const T *__restrict__ kraw,
+                                          Keep keep, double off, T *__restrict__ out, Rec *r) {
+  constexpr int KW = STAGEK ? (int)(sizeof(T) / 4) : 0;      // dwords per staged raw value
+  constexpr int NCP = (WCOLS + 1 + 63) / 64;                 // column pointers per lane
+  constexpr int NK = STAGEK ? (WCOLS * KW + 63) / 64 : 1;    // staged raw dwords per lane
+  __shared__ int s_row[NWAVE][WL];
+  __shared__ int s_cp[NWAVE][NCP * 64];
+  __shared__ unsigned int s_kr[NWAVE][NK * 64];
+  __shared__ double s_sum[NWAVE][WCOLS];
+  __shared__ double sh_red[4 * NWAVE];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  int *row = s_row[wv];
+  int *cp = s_cp[wv];
+  unsigned int *kr = s_kr[wv];
+  double *sum = s_sum[wv];
+  const int n = d.n, n_items = d.n_items;
+  const double c = d.c, rr = d.r;
+  const int *__restrict__ colptr = d.colptr;
+  const int *__restrict__ crow = d.crow;
+  const T *__restrict__ cval = (const T *)d.cval;
+  const unsigned int *__restrict__ kw = (const unsigned int *)kraw;
   double l1 = 0.0, cs = 0.0, sr = 0.0, mx = 0.0;
-  // software pipeline: the sources of item it + gridDim.x load into the stage
-  // while item it is gathered and summed
-  if ((int)blockIdx.x < d.n_items) stage_item<T, NT, PCH, PCOLS>(g, d.items[blockIdx.x], S);
-  for (int it = blockIdx.x; it < d.n_items; it += gridDim.x) {
-    const int nx = it + (int)gridDim.x;
-    const int4 next = nx < d.n_items ? d.items[nx] : make_int4(-1, 0, 0, 0);
-    column_item<T, NT, PCH, PCOLS, true>(g, d.items[it], moved, kept, d.c, off, d.r, out, d.long_acc, L, l1, cs, sr,
-                                         mx, &S, next);
+  const int e0 = lane * WU;
+  const int stride = (int)gridDim.x * NWAVE;
+  const int4 none = make_int4(-1, 0, 0, 0);
+
+  // registers of the item fetched ahead
+  int pr[WU], pc[NCP];
+  unsigned int pk[NK];
+  auto fetch = [&](int4 item) {
+    // item-relative bases (uniform) keep the per-lane offsets 32-bit
+    const int p0 = item.z, ne = item.w - item.z;
+    const int *__restrict__ rows = crow + p0;
+#pragma unroll
+    for (int u = 0; u < WU; ++u) {
+      const unsigned int e = (unsigned int)(u * 64 + lane);
+      pr[u] = ((int)e < ne) ? rows[e] : -1;
+    }
+    const int k0 = item.x, ncol = item.y - item.x;
+    const bool run = item.x >= 0;
+    const int *__restrict__ cps = colptr + (run ? k0 : 0);
+#pragma unroll
+    for (int q = 0; q < NCP; ++q) {
+      const unsigned int j = (unsigned int)(q * 64 + lane);
+      pc[q] = (run && (int)j <= ncol) ? cps[j] - p0 : 0;
+    }
+    if (STAGEK) {
+      const unsigned int *__restrict__ kws = kw + (run ? (size_t)k0 * KW : 0);
+#pragma unroll
+      for (int q = 0; q < NK; ++q) {
+        const unsigned int j = (unsigned int)(q * 64 + lane);
+        pk[q] = (run && (int)j < ncol * KW) ? kws[j] : 0u;
+      }
+    }
+  };
+
+  int it = (int)blockIdx.x * NWAVE + wv;
+  int4 cur = (it < n_items) ? d.items[it] : none;
+  int4 nxt = (it + stride < n_items) ? d.items[it + stride] : none;
+  // an item the plan cannot have built is skipped whole
+  auto valid = [&](int4 item) {
+    const int ne = item.w - item.z;
+    if (ne < 0 || ne > WL) return false;
+    return item.x < 0 || (item.y - item.x >= 1 && item.y - item.x <= WCOLS);
+  };
+  if (it < n_items) fetch(valid(cur) ? cur : none);
+  for (; it < n_items; it += stride) {
+    // park the fetched item in LDS, then send the next one's loads
+#pragma unroll
+    for (int u = 0; u < WU; ++u) row[u * 64 + lane] = pr[u];
+#pragma unroll
+    for (int q = 0; q < NCP; ++q) cp[q * 64 + lane] = pc[q];
+    if (STAGEK) {
+#pragma unroll
+      for (int q = 0; q < NK; ++q) kr[q * 64 + lane] = pk[q];
+    }
+    const int4 item = valid(cur) ? cur : none;
+    if (it + stride < n_items) fetch(valid(nxt) ? nxt : none);
+    const int4 nx2 = (it + 2 * stride < n_items) ? d.items[it + 2 * stride] : none;
+    wave_lds_fence();
+    const int ne = item.w - item.z;
+    int jj[WU];
+    {
+      const int4 a = *(const int4 *)&row[e0];
+      const int4 b = *(const int4 *)&row[e0 + 4];
+      jj[0] = a.x; jj[1] = a.y; jj[2] = a.z; jj[3] = a.w;
+      jj[4] = b.x; jj[5] = b.y; jj[6] = b.z; jj[7] = b.w;
+    }
+    static_assert(WU == 8, "lane loads below assume 8 links per lane");
+    S x[WU];
+#pragma unroll
+    for (int u = 0; u < WU; ++u) {
+      const bool ok = e0 + u < ne && (unsigned)jj[u] < (unsigned)n;
+      x[u] = ok ? src[(unsigned)jj[u]] : S(0);
+    }
+    double w[WU];
+    const T *__restrict__ vals = cval + (VAL ? item.z : 0);
+#pragma unroll
+    for (int u = 0; u < WU; ++u) w[u] = (VAL && e0 + u < ne) ? (double)vals[(unsigned)(e0 + u)] : 1.0;
+    if (item.x >= 0) {
+      const int k0 = item.x, ncol = item.y - item.x;
+      for (int q = lane; q < ncol; q += 64) sum[q] = 0.0;
+      double acc = 0.0, head = 0.0;
+      int ended = 0, f = 0;
+      if (e0 < ne) {
+        // the last column starting at or before this lane's first link
+        int lo = 0, hi = ncol;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (cp[mid] <= e0) lo = mid;
+          else hi = mid - 1;
+        }
+        f = lo;
+        int q = f, nb = cp[f + 1];
+#pragma unroll
+        for (int u = 0; u < WU; ++u) {
+          if (e0 + u < ne) {
+            acc += (double)x[u] * w[u];
+            if (e0 + u + 1 == nb) {
+              if (ended) sum[q] = acc;
+              else head = acc;
+              ended = 1;
+              acc = 0.0;
+              ++q;
+              while (q < ncol && cp[q + 1] == cp[q]) ++q;  // columns without in-links
+              nb = (q < ncol) ? cp[q + 1] : 0x7fffffff;
+            }
+          }
+        }
+      }
+      // inclusive segmented scan of the trailing sums (a lane with a column
+      // end starts a segment); its exclusive value is the carry
+      double iv = acc;
+      int fl = ended;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const double yv = __shfl_up(iv, o, 64);
+        const int yf = __shfl_up(fl, o, 64);
+        if (lane >= o) {
+          if (!fl) iv += yv;
+          fl |= yf;
+        }
+      }
+      const double carry = __shfl_up(iv, 1, 64);
+      if (ended) sum[f] = (lane > 0 ? carry : 0.0) + head;
+      wave_lds_fence();
+      T *__restrict__ outs = out + k0;
+      for (int q = lane; q < ncol; q += 64) {
+        const double kv = STAGEK ? keep(((const T *)kr)[q], k0 + q) : keep(T(0), k0 + q);
+        const T y = (T)(kv + c * sum[q] + off);
+        outs[(unsigned)q] = y;
+        fold_stats<RP>((double)y, rr, l1, cs, sr, mx);
+      }
+    } else if (ne > 0) {
+      double acc = 0.0;
+#pragma unroll
+      for (int u = 0; u < WU; ++u) acc += (double)x[u] * w[u];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+      if (lane == 0) atomic_add_f64(&d.long_acc[-1 - item.x], acc);
+    }
+    wave_lds_fence();  // this item's LDS reads are done before the next park
+    cur = nxt;
+    nxt = nx2;
   }
-  fold_block_stats<NT / 64>(r, l1, cs, sr, mx, L.red);
+  fold_block_stats(r, l1, cs, sr, mx, sh_red);
 }
 
 // ----------------------------------------------------------------- complete
 
-template <class T>
+template <class T, bool VAL, bool RP>
 __global__ __launch_bounds__(BLOCK, 4) void k_complete(Dev d, long long s, int init) {
   Glob *g = d.glob;
   if (g->status != 0) return;
@@ -803,7 +988,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_complete(Dev d, long long s, int i
           }
           const T y = (T)x;
           C[i] = y;
-          fold_stats((double)y, r, l1, cs, sr, mx);
+          fold_stats<RP>((double)y, r, l1, cs, sr, mx);
         }
       }
     }
@@ -816,17 +1001,14 @@ __global__ __launch_bounds__(BLOCK, 4) void k_complete(Dev d, long long s, int i
     const int tie_id = cur->topk_tie_id;
     const T *__restrict__ Cc = (const T *)d.cash[cur->buf];
     T *__restrict__ Cn = (T *)d.cash[cur->buf ^ 1];
-    auto moved = [&](int j) -> double {
-      if ((unsigned)j >= (unsigned)n) return 0.0;  // links outside [0, N) are ignored
-      const T v = Cc[j];
-      return is_green(v, j, sched, theta, maxabs, tau, tie_id, d.seed, s) ? (double)v : 0.0;
-    };
-    auto kept = [&](int k) -> double {
-      const T v = Cc[k];
+    // the kept part C_t - M_t of node k from its cash v
+    auto keep = [&](T v, int k) -> double {
       if (init) return -(double)v;  // step 0: C_0 - M_0 with C_0 = 0
       return is_green(v, k, sched, theta, maxabs, tau, tie_id, d.seed, s) ? 0.0 : (double)v;
     };
-    column_pass<T, BLOCK>(d, moved, kept, off, Cn, nxt);
+    // what the sources send was written by select (zero off the green set;
+    // links outside [0, N) are ignored)
+    wave_pull<T, T, VAL, true, RP>(d, (const T *)d.src, Cc, keep, off, Cn, nxt);
   }
 
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1016,21 +1198,28 @@ __global__ __launch_bounds__(BLOCK) void k_refresh_pool(Dev d) {
   double acc = 0.0;
   __shared__ double sh_red[4 * NWAVE];
   for (int j = blockIdx.x * BLOCK + threadIdx.x; j < n; j += gridDim.x * BLOCK) {
-    const bool dangling = d.rowptr[j + 1] == d.rowptr[j];
-    acc += hist_at<HK>(d, j) * (dangling ? 1.0 : 1.0 - c);
+    const int dg = d.rowptr[j + 1] - d.rowptr[j];
+    const double h = hist_at<HK>(d, j);
+    acc += h * (dg == 0 ? 1.0 : 1.0 - c);
+    // H_j P'_jk per link j -> k (H_j itself with stored link values)
+    d.rsrc[j] = d.cval ? h : (dg > 0 ? h / (double)dg : 0.0);
   }
   const Red4 r = block_sum4(Red4{acc, 0, 0, 0}, sh_red);
   if (threadIdx.x == 0 && r.a != 0.0) atomic_add_f64(&d.glob->rpool, r.a);
 }
 
-template <class T, int HK>
-__global__ __launch_bounds__(BLOCK) void k_refresh(Dev d, long long t, int out_buf) {
+template <class T, int HK, bool VAL, bool RP>
+__global__ __launch_bounds__(BLOCK, 4) void k_refresh(Dev d, long long t, int out_buf) {
   Rec *cur = &d.rec[t % 3];
   const int n = d.n;
   const double off = d.glob->rpool / (double)n;
-  auto moved = [&](int j) -> double { return ((unsigned)j < (unsigned)n) ? hist_at<HK>(d, j) : 0.0; };
-  auto kept = [&](int k) -> double { return -hist_at<HK>(d, k); };
-  column_pass<T, BLOCK>(d, moved, kept, off, (T *)d.cash[out_buf], cur);
+  auto keep = [&](T, int k) -> double { return -hist_at<HK>(d, k); };
+  wave_pull<T, double, VAL, false, RP>(d, d.rsrc, (const T *)nullptr, keep, off, (T *)d.cash[out_buf], cur);
+}
+
+// Clears an FP64 array (the push accumulators after the refresh used them).
+__global__ __launch_bounds__(BLOCK) void k_zero_f64(double *p, int n) {
+  for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) p[i] = 0.0;
 }
 
 __global__ void k_refresh_done(Dev d, long long t, int out_buf) {
@@ -1222,8 +1411,14 @@ template __global__ void k_select<float, 1>(Dev, long long, double, long long, i
 template __global__ void k_select<double, 0>(Dev, long long, double, long long, int);
 template __global__ void k_push<float>(Dev, long long);
 template __global__ void k_push<double>(Dev, long long);
-template __global__ void k_complete<float>(Dev, long long, int);
-template __global__ void k_complete<double>(Dev, long long, int);
+template __global__ void k_complete<float, false, false>(Dev, long long, int);
+template __global__ void k_complete<float, false, true>(Dev, long long, int);
+template __global__ void k_complete<float, true, false>(Dev, long long, int);
+template __global__ void k_complete<float, true, true>(Dev, long long, int);
+template __global__ void k_complete<double, false, false>(Dev, long long, int);
+template __global__ void k_complete<double, false, true>(Dev, long long, int);
+template __global__ void k_complete<double, true, false>(Dev, long long, int);
+template __global__ void k_complete<double, true, true>(Dev, long long, int);
 template __global__ void k_complete_long<float>(Dev, long long, int);
 template __global__ void k_complete_long<double>(Dev, long long, int);
 template __global__ void k_refresh_long<float, 0>(Dev, long long, int);
@@ -1233,9 +1428,18 @@ template __global__ void k_topk_hist<float>(Dev, long long, int, int);
 template __global__ void k_topk_hist<double>(Dev, long long, int, int);
 template __global__ void k_refresh_pool<0>(Dev);
 template __global__ void k_refresh_pool<1>(Dev);
-template __global__ void k_refresh<float, 0>(Dev, long long, int);
-template __global__ void k_refresh<float, 1>(Dev, long long, int);
-template __global__ void k_refresh<double, 0>(Dev, long long, int);
+template __global__ void k_refresh<float, 0, false, false>(Dev, long long, int);
+template __global__ void k_refresh<float, 0, false, true>(Dev, long long, int);
+template __global__ void k_refresh<float, 0, true, false>(Dev, long long, int);
+template __global__ void k_refresh<float, 0, true, true>(Dev, long long, int);
+template __global__ void k_refresh<float, 1, false, false>(Dev, long long, int);
+template __global__ void k_refresh<float, 1, false, true>(Dev, long long, int);
+template __global__ void k_refresh<float, 1, true, false>(Dev, long long, int);
+template __global__ void k_refresh<float, 1, true, true>(Dev, long long, int);
+template __global__ void k_refresh<double, 0, false, false>(Dev, long long, int);
+template __global__ void k_refresh<double, 0, false, true>(Dev, long long, int);
+template __global__ void k_refresh<double, 0, true, false>(Dev, long long, int);
+template __global__ void k_refresh<double, 0, true, true>(Dev, long long, int);
 template __global__ void k_reset<float, 0>(Dev);
 template __global__ void k_reset<float, 1>(Dev);
 template __global__ void k_reset<double, 0>(Dev);

@@ -1,6 +1,7 @@
 """Parity at the full benchmark sizes, in the launch configuration the
-benchmark times (threshold r = 1, FP32 cash with FP64 history, FP32 link
-values, AUTO route):
+benchmark times (threshold r = 1, FP32 cash with FP64 history, link weights
+1/outdeg implied by the row pointers, AUTO route, relabelled layout), and
+with FP32 link values stored per link:
 
   * Chung-Lu power law, N = 2^20, 16.8M links, exponent 2.1, 5% dangling;
   * R-MAT scale 24 (16.8M nodes, 268M links, a/b/c = 0.57/0.19/0.19).
@@ -29,28 +30,32 @@ import paper_2008_02710_amd as rl  # noqa: E402
 _cache = {}
 
 
-def graph(name):
-    if name not in _cache:
-        say("generating", name)
-        if name == "chung_lu_2p20":
-            g = workloads.chung_lu(1 << 20, 2.1, 16.0, 0.05, 0.85, seed=0, name=name)
-        else:
-            g = workloads.rmat(24, 16, 0.57, 0.19, 0.19, 0.85, seed=0)
-            g.name = name
-        g.csc()
-        say("generated", name, g.n, g.nnz, "dangling", g.n_dangling)
-        dg = rl.DeviceGraph.from_workload(g, precision=rl.FP32C_FP64H, with_csc=True, explicit_val=True)
-        say("uploaded", name)
-        _cache[name] = (g, dg, oracle.Chain(g.rowptr, g.col, g.val(), g.c))
-    return _cache[name]
+def graph(name, stored=False):
+    key = (name, stored)
+    if key not in _cache:
+        if name not in _cache:
+            say("generating", name)
+            if name == "chung_lu_2p20":
+                g = workloads.chung_lu(1 << 20, 2.1, 16.0, 0.05, 0.85, seed=0, name=name)
+            else:
+                g = workloads.rmat(24, 16, 0.57, 0.19, 0.19, 0.85, seed=0)
+                g.name = name
+            g.csc()
+            say("generated", name, g.n, g.nnz, "dangling", g.n_dangling)
+            _cache[name] = (g, oracle.Chain(g.rowptr, g.col, g.val(), g.c))
+        g, ch = _cache[name]
+        dg = rl.DeviceGraph.from_workload(g, precision=rl.FP32C_FP64H, with_csc=True, explicit_val=stored)
+        say("uploaded", name, "stored values" if stored else "implied values")
+        _cache[key] = (g, dg, ch)
+    return _cache[key]
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("relabel", [0, 1])
+@pytest.mark.parametrize("relabel,stored", [(0, False), (1, False), (1, True)])
 @pytest.mark.parametrize("name", ["chung_lu_2p20", "rmat_s24"])
-def test_full_size_solve_certified(name, relabel):
-    g, dg, ch = graph(name)
-    say("case full_solve", name, "relabel" if relabel else "")
+def test_full_size_solve_certified(name, relabel, stored):
+    g, dg, ch = graph(name, stored)
+    say("case full_solve", name, "relabel" if relabel else "", "stored" if stored else "")
     eps = (1 - g.c) * 1e-6
     s = rl.Solver(dg, sched=rl.SCHED_THRESHOLD, route=rl.ROUTE_AUTO, precision=rl.FP32C_FP64H, relabel=relabel)
     st, info = s.solve(eps, max_steps=100000)
@@ -65,11 +70,12 @@ def test_full_size_solve_certified(name, relabel):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("route,relabel", [("pull", 0), ("push", 0), ("pull", 1)])
+@pytest.mark.parametrize("route,relabel,stored", [("pull", 0, False), ("push", 0, False), ("pull", 1, False),
+                                                  ("pull", 1, True)])
 @pytest.mark.parametrize("name", ["chung_lu_2p20", "rmat_s24"])
-def test_full_size_one_step_parity(name, route, relabel):
-    g, dg, ch = graph(name)
-    say("case full_step", name, route, "relabel" if relabel else "")
+def test_full_size_one_step_parity(name, route, relabel, stored):
+    g, dg, ch = graph(name, stored)
+    say("case full_step", name, route, "relabel" if relabel else "", "stored" if stored else "")
     s = rl.Solver(dg, sched=rl.SCHED_THRESHOLD, route=rl.ROUTE_AUTO, precision=rl.FP32C_FP64H, record_green=1)
     s.step(3)
     C, H, info0 = s.state()
