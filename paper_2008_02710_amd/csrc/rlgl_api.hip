@@ -632,7 +632,7 @@ rlgl_status rlgl_create(const rlgl_graph *g, const rlgl_options *o, void *ws, si
   d.perm = nullptr;
 
   const int tiles = (g->n + TILE - 1) / TILE;
-  c->grid_sel = std::max(1, std::min(tiles, NODE_GRID));
+  c->grid_sel = std::max(1, std::min(tiles, SEL_GRID));
   c->grid_push = (int)std::max<long long>(1, std::min<long long>((g->nnz + CH - 1) / CH, PUSH_GRID));
   c->grid_misc = std::max(1, std::min((g->n + BLOCK - 1) / BLOCK, NODE_GRID));
 

@@ -17,6 +17,7 @@ constexpr int WCOLS = 64;           // single-chain pull: columns per run item
 constexpr int LOG_STEPS = 4096;     // ring of per-step records kept for profiling
 constexpr int MAX_GRID = 2048;      // edge-parallel launches
 constexpr int NODE_GRID = 512;      // node-parallel launches (2 workgroups per CU)
+constexpr int SEL_GRID = 1024;      // select launches (4 workgroups per CU, one tile each at N = 2^20)
 constexpr int HOT_MAX = 2048;       // push: destinations privatised in LDS (FP64) per workgroup
 constexpr int HOT_MIN_INDEG = 256;  // push: in-degree from which a destination is privatised
 constexpr int PUSH_GRID = 512;      // push launches (hot partials flushed once per workgroup)

@@ -260,7 +260,6 @@ __device__ __forceinline__ double hist_at(const Dev &d, int j) {
 template <class T, int HK>
 __global__ __launch_bounds__(BLOCK) void k_select(Dev d, long long s, double eps, long long s_limit, int init) {
   Glob *g = d.glob;
-  if (g->status != 0) return;
   Rec *cur = &d.rec[s % 3];
   Rec *prv = &d.rec[(s + 2) % 3];
   Rec *nxt = &d.rec[(s + 1) % 3];
@@ -270,6 +269,35 @@ __global__ __launch_bounds__(BLOCK) void k_select(Dev d, long long s, double eps
   __shared__ double sh_red[4 * NWAVE];
   __shared__ long long sh_ll[NWAVE];
   __shared__ unsigned long long sh_base;
+
+  // The node loads of this block's first tile depend on nothing the step's
+  // scalars decide, so they are sent before the records are read.
+  T *C = (T *)d.cash[cur->buf];
+  const int n = d.n;
+  const int ntiles = (n + TILE - 1) / TILE;
+  T pv[VPT];
+  int pr0[VPT], pr1[VPT];
+  double ph[VPT];
+  float plo[VPT];
+  auto load_tile = [&](int tile) {
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) {
+      const int i = tile * TILE + q * BLOCK + threadIdx.x;
+      const bool in = i < n;
+      pv[q] = in ? C[i] : T(0);
+      pr0[q] = in ? d.rowptr[i] : 0;
+      pr1[q] = in ? d.rowptr[i + 1] : 0;
+      if (HK == 0) {
+        ph[q] = in ? ((const double *)d.hist)[i] : 0.0;
+        plo[q] = 0.f;
+      } else {
+        ph[q] = in ? (double)((const float *)d.hist)[i] : 0.0;
+        plo[q] = in ? d.hist_lo[i] : 0.f;
+      }
+    }
+  };
+  if ((int)blockIdx.x < ntiles) load_tile(blockIdx.x);
+  if (g->status != 0) return;
 
   const Tot tot = read_totals(cur, &sh_tot);
   const double l1 = tot.l1, hsum = cur->hsum, hnorm = cur->hnorm;
@@ -317,16 +345,14 @@ __global__ __launch_bounds__(BLOCK) void k_select(Dev d, long long s, double eps
     clear_stripes(nxt);
   }
 
-  T *C = (T *)d.cash[cur->buf];
-  const int n = d.n;
   const double c = d.c;
-  const int ntiles = (n + TILE - 1) / TILE;
 
   double accT = 0.0, accM = 0.0, accDH = 0.0;
   long long accG = 0, accE = 0;
 
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int base = tile * TILE;
+    if (tile != (int)blockIdx.x) load_tile(tile);
     T v[VPT];
     int rs[VPT], deg[VPT];
     bool fr[VPT];
@@ -338,7 +364,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(Dev d, long long s, double eps
       deg[q] = 0;
       rs[q] = 0;
       v[q] = T(0);
-      const T x = (i < n) ? C[i] : T(0);
+      const T x = pv[q];
       const bool gr = (i < n) && is_green(x, i, sched, theta, maxabs, tau, tie_id, d.seed, s);
       if (i < n) {
         if (d.green_mask) d.green_mask[i] = gr ? 1 : 0;
@@ -346,21 +372,21 @@ __global__ __launch_bounds__(BLOCK) void k_select(Dev d, long long s, double eps
         if (gr) {
           ++accG;
           if (x != T(0)) {
-            const int r0 = d.rowptr[i];
-            const int dg = d.rowptr[i + 1] - r0;
+            const int r0 = pr0[q];
+            const int dg = pr1[q] - r0;
             if (d.cval) sent = x;
             else if (dg > 0) sent = (T)((double)x / (double)dg);
             // history: H_{t+1} = H_t + M_t (eq. (5))
             if (HK == 0) {
               double *H = (double *)d.hist;
-              const double h = H[i];
+              const double h = ph[q];
               const double hn = h + (double)x;
               H[i] = hn;
               accDH += fabs(hn) - fabs(h);
             } else {
               float *Hh = (float *)d.hist;
               float *Hl = d.hist_lo;
-              const float hi = Hh[i], lo = Hl[i], xf = (float)x;
+              const float hi = (float)ph[q], lo = plo[q], xf = (float)x;
               const float sum = hi + xf;
               const float comp = (fabsf(hi) >= fabsf(xf)) ? ((hi - sum) + xf) : ((xf - sum) + hi);
               const float lo2 = lo + comp;
@@ -567,56 +593,13 @@ struct ColLds {
   double red[4 * (NT / 64)];
 };
 
-// LDS staging of a run item's CSC sources (and FP32 link values), filled by
-// direct global-to-LDS loads while the previous item is being summed.
-template <class T, int IC, int IK>
-struct ColStage {
-  int row[IC];
-  T val[sizeof(T) == 4 ? IC : 1];
-  int cp[IK + 64];  // the run's column pointers (absolute), IK + 1 used
-};
-
-// Issues the direct-to-LDS loads of a run item's sources (and values) into S:
-// lane l of the wave with base thread b writes the entry u*NT + b + l.
-template <class T, int NT, int IC, int IK>
-__device__ __forceinline__ void stage_item(const ColView &g, int4 item, ColStage<T, IC, IK> &S) {
-  if (item.x < 0) return;
-  const int k0 = item.x, ncol = item.y - item.x;
-  const int p0 = item.z, ne = item.w - item.z;
-  if (ne < 0 || ne > IC || ncol < 0 || ncol > IK) return;
-  const int wb = threadIdx.x & ~63;
-  for (int q0 = 0; q0 <= ncol; q0 += NT) {
-    const int q = q0 + (int)threadIdx.x;
-    if (q <= ncol)
-      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(g.colptr + k0 + q),
-                                       (void __attribute__((address_space(3))) *)(&S.cp[q0 + wb]), 4, 0, 0);
-  }
-  const bool vals = sizeof(T) == 4 && g.cval != nullptr && !g.unit;
-#pragma unroll
-  for (int u = 0; u < IC / NT; ++u) {
-    const int e = u * NT + (int)threadIdx.x;
-    if (e < ne) {
-      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(g.crow + p0 + e),
-                                       (void __attribute__((address_space(3))) *)(&S.row[u * NT + wb]), 4, 0, 0);
-      if (vals)
-        __builtin_amdgcn_global_load_lds(
-            (const void __attribute__((address_space(1))) *)((const T *)g.cval + p0 + e),
-            (void __attribute__((address_space(3))) *)(&S.val[u * NT + wb]), 4, 0, 0);
-    }
-  }
-}
-
 // One plan item: adds c * sum_j moved(j) P'_jk + kept(k) + off into out[k]
-// for the item's columns and folds the statistics of those values.  With
-// STAGED, a run item's sources (and FP32 values) come from the stage S, filled
-// by stage_item for this item beforehand, and the loads of `next` are issued
-// into S as soon as this item has read it.
-template <class T, int NT, int IC = CH, int IK = RUN_MAX_COLS, bool STAGED = false, class Moved, class Kept>
+// for the item's columns and folds the statistics of those values.
+template <class T, int NT, int IC = CH, int IK = RUN_MAX_COLS, class Moved, class Kept>
 __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved moved, Kept kept, double c,
                                             double off, double rr, T *__restrict__ out, double *long_acc,
                                             ColLds<NT, IC, IK> &L, double &l1, double &cs, double &sr,
-                                            double &mx, ColStage<T, IC, IK> *S = nullptr,
-                                            int4 next = make_int4(-1, 0, 0, 0)) {
+                                            double &mx) {
   constexpr int NW = NT / 64;
   constexpr int U = IC / NT;                 // links per thread
   constexpr int KC = IK / NT;                // columns per thread
@@ -634,25 +617,14 @@ __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved m
     const int k0 = item.x, k1 = item.y, p0 = item.z, p1 = item.w;
     const int ne = p1 - p0, ncol = k1 - k0;
     if (ne > IC || ne < 0 || ncol > IK || ncol < 0) return;  // the plan never builds such an item
-    if (STAGED) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's loads into the stage
     __syncthreads();
     int jj[U];
     double ww[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = u * NT + tid;
-      if (STAGED) {
-        jj[u] = (e < ne) ? S->row[e] : -1;
-        ww[u] = (e < ne && cval && !unit) ? (sizeof(T) == 4 ? (double)S->val[e] : (double)cval[p0 + e]) : 0.0;
-      } else {
-        jj[u] = (e < ne) ? crow[p0 + e] : -1;
-        ww[u] = (e < ne && cval && !unit) ? (double)cval[p0 + e] : 0.0;
-      }
-    }
-    if (STAGED) {
-      for (int q = tid; q <= ncol; q += NT) L.cp[q] = S->cp[q] - p0;
-      __syncthreads();  // every wave has read the stage
-      stage_item<T, NT, IC, IK>(g, next, *S);
+      jj[u] = (e < ne) ? crow[p0 + e] : -1;
+      ww[u] = (e < ne && cval && !unit) ? (double)cval[p0 + e] : 0.0;
     }
     double kv[KC];
 #pragma unroll
@@ -660,8 +632,7 @@ __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved m
       const int q = m * NT + tid;
       kv[m] = (q < ncol) ? kept(k0 + q) : 0.0;
     }
-    if (!STAGED)
-      for (int q = tid; q <= ncol; q += NT) L.cp[q] = colptr[k0 + q] - p0;
+    for (int q = tid; q <= ncol; q += NT) L.cp[q] = colptr[k0 + q] - p0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = u * NT + tid;
@@ -725,11 +696,6 @@ __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved m
     }
   } else {
     // PIECE or WHOLE: a strided walk over [p0, p1) of one column
-    if (STAGED) {
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      __syncthreads();
-      stage_item<T, NT, IC, IK>(g, next, *S);
-    }
     const int k = item.y, pb = item.z, pe = item.w;
     double acc = 0.0;
     for (int p0 = pb; p0 < pe; p0 += IC) {
