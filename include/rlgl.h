@@ -128,6 +128,30 @@ typedef struct {
   int32_t last_route;         /* rlgl_route used by the last step (PUSH or PULL) */
 } rlgl_step_info;
 
+/* Debug check of a graph against the contract above (Sec. 2: P must be
+ * stochastic, so every row of W with a stored link sums to one), run on
+ * `stream` over the device arrays; waits for the stream.  Checks:
+ *   - csr_rowptr runs from 0 to nnz without decreasing; every csr_col is in
+ *     [0, n);
+ *   - with csr_val: no value is negative or non-finite, and every row with a
+ *     stored link sums to 1 within 1e-12 (precision RLGL_FP64, double values)
+ *     or 1e-6 (float values);
+ *   - with the CSC: csc_colptr runs from 0 to nnz without decreasing, every
+ *     csc_row is in [0, n), and the CSC holds exactly the CSR's links (i, j),
+ *     with bit-identical values when both value arrays are given.  The links
+ *     are compared as multisets, through every column's length against the
+ *     CSR in-degree and a 64-bit sum of link hashes (a difference goes
+ *     unnoticed with probability about 2^-64).
+ * dev_scratch: caller-owned device memory of at least
+ * rlgl_validate_scratch_bytes(g) bytes (about 4n), overwritten.
+ * *max_row_dev (host, may be NULL): max |row sum - 1| over the rows with a
+ * link (0 without csr_val).  Every array read is bounds-checked against n
+ * and nnz.  Returns RLGL_OK, or RLGL_EINVAL with the first failed check in
+ * rlgl_last_error(). */
+size_t rlgl_validate_scratch_bytes(const rlgl_graph *g);
+rlgl_status rlgl_validate(const rlgl_graph *g, int32_t precision, void *dev_scratch, size_t scratch_bytes,
+                          void *stream, double *max_row_dev);
+
 /* Fills *opt with the defaults: THRESHOLD, r = 1, k = 1, theta_period = 1,
  * FP32C_FP64H, AUTO, pull_alpha = 0.15, check_period = 0, record_green = 0,
  * refresh = 1, relabel = 0, seed = 0. */

@@ -101,7 +101,8 @@ EXPORTED = ["rlgl_default_options", "rlgl_workspace_bytes", "rlgl_create", "rlgl
             "rlgl_batch_autotune", "rlgl_batch_destroy",
             "rlgl_pool_default_options", "rlgl_pool_workspace_bytes", "rlgl_pool_footprint", "rlgl_pool_create",
             "rlgl_pool_admit", "rlgl_pool_advance", "rlgl_pool_launch", "rlgl_pool_wait", "rlgl_pool_poll",
-            "rlgl_pool_result", "rlgl_pool_release", "rlgl_pool_destroy"]
+            "rlgl_pool_result", "rlgl_pool_release", "rlgl_pool_destroy", "rlgl_validate_scratch_bytes",
+            "rlgl_validate"]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -114,6 +115,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rlgl_default_options.restype = None
     lib.rlgl_workspace_bytes.argtypes = [G, O]
     lib.rlgl_workspace_bytes.restype = ctypes.c_size_t
+    lib.rlgl_validate_scratch_bytes.argtypes = [G]
+    lib.rlgl_validate_scratch_bytes.restype = ctypes.c_size_t
+    lib.rlgl_validate.argtypes = [G, i32, vp, ctypes.c_size_t, vp, ctypes.POINTER(f64)]
+    lib.rlgl_validate.restype = i32
     lib.rlgl_create.argtypes = [G, O, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
     lib.rlgl_create.restype = i32
     lib.rlgl_step.argtypes = [vp, i32, I]
@@ -218,6 +223,19 @@ def rlgl_last_error() -> str:
 
 def rlgl_workspace_bytes(graph: rlgl_graph, opt: rlgl_options) -> int:
     return int(_lib.rlgl_workspace_bytes(ctypes.byref(graph), ctypes.byref(opt)))
+
+
+def rlgl_validate_scratch_bytes(graph: rlgl_graph) -> int:
+    return int(_lib.rlgl_validate_scratch_bytes(ctypes.byref(graph)))
+
+
+def rlgl_validate(graph: rlgl_graph, precision: int, scratch, scratch_bytes: int, stream=None) -> float:
+    """Raises RlglError when the graph breaks the contract; returns max |row sum - 1|."""
+    dev = ctypes.c_double(0.0)
+    st = _lib.rlgl_validate(ctypes.byref(graph), int(precision), _ptr(scratch), int(scratch_bytes),
+                            _stream_handle(stream), ctypes.byref(dev))
+    _check(st, "rlgl_validate")
+    return dev.value
 
 
 def rlgl_create(graph: rlgl_graph, opt: rlgl_options, workspace, ws_bytes: int, stream=None):
@@ -440,6 +458,13 @@ class DeviceGraph:
         else:
             colptr = row = perm = None
         return cls(g.n, g.rowptr, g.col, g.c, val, colptr, row, perm, precision, device)
+
+    def validate(self, stream=None) -> float:
+        """rlgl_validate on these arrays (scratch from torch); returns max |row sum - 1|."""
+        g = self.struct()
+        nbytes = rlgl_validate_scratch_bytes(g)
+        scratch = torch.empty(nbytes, dtype=torch.uint8, device=self.rowptr.device)
+        return rlgl_validate(g, self.precision, scratch, nbytes, stream)
 
     def struct(self) -> rlgl_graph:
         return rlgl_graph(self.n, self.nnz, _ptr(self.rowptr), _ptr(self.col), _ptr(self.val),

@@ -22,6 +22,7 @@
 #include "rlgl_kernels.hip"
 #include "rlgl_batch.hip"
 #include "rlgl_lockstep.hip"
+#include "rlgl_validate.hip"
 
 using namespace rlgl;
 
@@ -549,6 +550,66 @@ void rlgl_default_options(rlgl_options *o) {
 }
 
 const char *rlgl_last_error(void) { return g_err.c_str(); }
+
+size_t rlgl_validate_scratch_bytes(const rlgl_graph *g) {
+  if (!g || g->n < 1) return 0;
+  return sizeof(VHead) + align_up(4 * (size_t)g->n, 256);
+}
+
+rlgl_status rlgl_validate(const rlgl_graph *g, int32_t precision, void *dev_scratch, size_t scratch_bytes,
+                          void *stream, double *max_row_dev) {
+  if (!g) return fail(RLGL_EINVAL, "null graph");
+  if (precision < 0 || precision > 2) return fail(RLGL_EINVAL, "precision out of range");
+  const int n = g->n;
+  const long long nnz = g->nnz;
+  if (n < 1 || nnz < 0 || nnz >= (1ll << 31)) return fail(RLGL_EINVAL, "n or nnz out of range");
+  if (!g->csr_rowptr || (nnz > 0 && !g->csr_col)) return fail(RLGL_EINVAL, "CSR arrays are NULL");
+  if (g->csc_colptr && nnz > 0 && !g->csc_row) return fail(RLGL_EINVAL, "csc_row is NULL");
+  if (!dev_scratch || scratch_bytes < rlgl_validate_scratch_bytes(g))
+    return fail(RLGL_ENOMEM, "scratch smaller than rlgl_validate_scratch_bytes()");
+  hipStream_t st = (hipStream_t)stream;
+  VHead *h = (VHead *)dev_scratch;
+  int *indeg = (int *)((char *)dev_scratch + sizeof(VHead));
+  const int grid = std::max(1, std::min((n + BLOCK - 1) / BLOCK, MAX_GRID));
+  const bool dbl = precision == RLGL_FP64;
+  // values enter the link hashes only when both sides store them
+  const int hv = (g->csr_val && g->csc_val) ? 1 : 0;
+  const double tol = dbl ? 1e-12 : 1e-6;
+  k_v_clear<<<grid, BLOCK, 0, st>>>(h, indeg, n);
+  if (dbl)
+    k_v_rows<double><<<grid, BLOCK, 0, st>>>(n, nnz, g->csr_rowptr, g->csr_col, (const double *)g->csr_val, hv, tol,
+                                            h, indeg);
+  else
+    k_v_rows<float><<<grid, BLOCK, 0, st>>>(n, nnz, g->csr_rowptr, g->csr_col, (const float *)g->csr_val, hv, tol, h,
+                                           indeg);
+  if (g->csc_colptr) {
+    if (dbl)
+      k_v_cols<double><<<grid, BLOCK, 0, st>>>(n, nnz, g->csc_colptr, g->csc_row, (const double *)g->csc_val, hv, h,
+                                              indeg);
+    else
+      k_v_cols<float><<<grid, BLOCK, 0, st>>>(n, nnz, g->csc_colptr, g->csc_row, (const float *)g->csc_val, hv, h,
+                                             indeg);
+  }
+  HIP_TRY(hipGetLastError());
+  VHead r{};
+  HIP_TRY(hipMemcpyAsync(&r, h, sizeof(VHead), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (max_row_dev) *max_row_dev = __builtin_bit_cast(double, r.dev_bits);
+  const unsigned int f = r.flags;
+  if (f & VF_ROWPTR) return fail(RLGL_EINVAL, "csr_rowptr does not run from 0 to nnz without decreasing");
+  if (f & VF_COL) return fail(RLGL_EINVAL, "a csr_col entry is outside [0, n)");
+  if (f & VF_VAL) return fail(RLGL_EINVAL, "a csr_val entry is negative or not finite");
+  if (f & VF_ROWSUM)
+    return fail(RLGL_EINVAL, "a row of csr_val does not sum to 1 (max deviation %.3g, tolerance %.1g)",
+                __builtin_bit_cast(double, r.dev_bits), tol);
+  if (f & VF_COLPTR) return fail(RLGL_EINVAL, "csc_colptr does not run from 0 to nnz without decreasing");
+  if (f & VF_ROW) return fail(RLGL_EINVAL, "a csc_row entry is outside [0, n)");
+  if (f & VF_CVAL) return fail(RLGL_EINVAL, "a csc_val entry is negative or not finite");
+  if (f & VF_INDEG) return fail(RLGL_EINVAL, "the CSC column lengths differ from the CSR in-degrees");
+  if (g->csc_colptr && r.h_csr != r.h_csc)
+    return fail(RLGL_EINVAL, "the CSC does not hold the same links%s as the CSR", hv ? " and values" : "");
+  return RLGL_OK;
+}
 
 size_t rlgl_workspace_bytes(const rlgl_graph *g, const rlgl_options *o) {
   if (!g || !o || g->n < 1 || g->nnz < 0 || o->precision < 0 || o->precision > 2) return 0;
