@@ -924,7 +924,7 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
 // ----------------------------------------------------------------- complete
 
 template <class T, bool VAL, bool RP>
-__global__ __launch_bounds__(BLOCK, 4) void k_complete(Dev d, long long s, int init) {
+__global__ __launch_bounds__(BLOCK, 5) void k_complete(Dev d, long long s, int init) {
   Glob *g = d.glob;
   if (g->status != 0) return;
   Rec *cur = &d.rec[s % 3];
@@ -996,6 +996,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_complete(Dev d, long long s, int i
 // Completes the columns with more than CH in-links once all their pieces
 // have been added to long_acc: x_k = kept(k) + c * acc + off, then resets
 // long_acc for the next pass and folds the statistics of the x_k.
+// kept(k, q) may use what the caller loaded ahead for the column at q.
 template <class T, class Kept>
 __device__ __forceinline__ void long_finish(const Dev &d, Kept kept, double off, T *__restrict__ out, Rec *r) {
   __shared__ double sh_red[4 * NWAVE];
@@ -1004,7 +1005,7 @@ __device__ __forceinline__ void long_finish(const Dev &d, Kept kept, double off,
     const int k = d.long_cols[q];
     const double acc = d.long_acc[q];
     d.long_acc[q] = 0.0;
-    const T x = (T)(kept(k) + d.c * acc + off);
+    const T x = (T)(kept(k, q) + d.c * acc + off);
     out[k] = x;
     fold_stats((double)x, d.r, l1, cs, sr, mx);
   }
@@ -1013,8 +1014,13 @@ __device__ __forceinline__ void long_finish(const Dev &d, Kept kept, double off,
 
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_complete_long(Dev d, long long s, int init) {
-  if (d.glob->status != 0) return;
   Rec *cur = &d.rec[s % 3];
+  // the cash of this thread's first long column is loaded before the step's
+  // records are read (it depends on none of their values)
+  const T *__restrict__ Cc = (const T *)d.cash[cur->buf];
+  const int q0 = blockIdx.x * BLOCK + threadIdx.x;
+  const T v0 = (q0 < d.n_long) ? Cc[d.long_cols[q0]] : T(0);
+  if (d.glob->status != 0) return;
   if (cur->mode != 1) return;
   Rec *nxt = &d.rec[(s + 1) % 3];
   __shared__ Tot sh_tot;
@@ -1022,9 +1028,8 @@ __global__ __launch_bounds__(BLOCK) void k_complete_long(Dev d, long long s, int
   const int sched = init ? SCHED_ALL : d.sched;
   const double theta = cur->theta, tau = cur->topk_tau, maxabs = tot.maxabs;
   const int tie_id = cur->topk_tie_id;
-  const T *__restrict__ Cc = (const T *)d.cash[cur->buf];
-  auto kept = [&](int k) -> double {
-    const T v = Cc[k];
+  auto kept = [&](int k, int q) -> double {
+    const T v = (q == q0) ? v0 : Cc[k];
     if (init) return -(double)v;
     return is_green(v, k, sched, theta, maxabs, tau, tie_id, d.seed, s) ? 0.0 : (double)v;
   };
@@ -1033,7 +1038,7 @@ __global__ __launch_bounds__(BLOCK) void k_complete_long(Dev d, long long s, int
 
 template <class T, int HK>
 __global__ __launch_bounds__(BLOCK) void k_refresh_long(Dev d, long long t, int out_buf) {
-  auto kept = [&](int k) -> double { return -hist_at<HK>(d, k); };
+  auto kept = [&](int k, int) -> double { return -hist_at<HK>(d, k); };
   long_finish<T>(d, kept, d.glob->rpool / (double)d.n, (T *)d.cash[out_buf], &d.rec[t % 3]);
 }
 
