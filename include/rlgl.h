@@ -99,7 +99,7 @@ typedef struct {
   int32_t theta_period;       /* recompute theta every theta_period steps (>= 1, default 1) */
   int32_t precision;          /* rlgl_precision */
   int32_t route;              /* rlgl_route */
-  double pull_alpha;          /* AUTO switch point as a fraction of nnz (default 0.15) */
+  double pull_alpha;          /* AUTO switch point as a fraction of nnz (default 0.05) */
   int32_t check_period;       /* rlgl_solve: steps enqueued between host reads of the stop flag; 0 = adaptive */
   int32_t record_green;       /* non-zero: keep the green mask of the last step for rlgl_get_green */
   int32_t refresh;            /* rebuild C_t = H_t P - H_t in FP64 (needs the CSC; see rlgl_refresh):
@@ -153,7 +153,7 @@ rlgl_status rlgl_validate(const rlgl_graph *g, int32_t precision, void *dev_scra
                           void *stream, double *max_row_dev);
 
 /* Fills *opt with the defaults: THRESHOLD, r = 1, k = 1, theta_period = 1,
- * FP32C_FP64H, AUTO, pull_alpha = 0.15, check_period = 0, record_green = 0,
+ * FP32C_FP64H, AUTO, pull_alpha = 0.05, check_period = 0, record_green = 0,
  * refresh = 1, relabel = 0, seed = 0. */
 void rlgl_default_options(rlgl_options *opt);
 

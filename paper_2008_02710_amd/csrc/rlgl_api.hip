@@ -543,7 +543,7 @@ void rlgl_default_options(rlgl_options *o) {
   o->theta_period = 1;
   o->precision = RLGL_FP32C_FP64H;
   o->route = RLGL_ROUTE_AUTO;
-  o->pull_alpha = 0.15;
+  o->pull_alpha = 0.05;
   o->check_period = 0;
   o->record_green = 0;
   o->refresh = 1;
