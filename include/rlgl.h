@@ -182,6 +182,15 @@ rlgl_status rlgl_step(rlgl_ctx *ctx, int32_t nsteps, rlgl_step_info *info);
  * pi_hat to pi* is at most resid / (1 - c). */
 rlgl_status rlgl_solve(rlgl_ctx *ctx, double eps, int64_t max_steps, double *dev_pi, rlgl_step_info *info);
 
+/* One green-light step (Algorithm 1, steps (4)-(6); eqs. (4)-(6)) whose green
+ * set G_t is given by the caller instead of the schedule: node i is green
+ * when dev_mask[i] != 0 (device memory, n bytes, caller's numbering; a green
+ * node with zero cash moves nothing).  This runs any rule for G_t, e.g. the
+ * block schedules of the mean-field SBM (Sec. 5).  No stop test; the route
+ * follows opt.route.  RLGL_EINVAL when the context was created with relabel.
+ * *info (may be NULL) as for rlgl_step. */
+rlgl_status rlgl_step_mask(rlgl_ctx *ctx, const uint8_t *dev_mask, rlgl_step_info *info);
+
 /* Releases the host context.  Does not touch the caller's device memory. */
 void rlgl_destroy(rlgl_ctx *ctx);
 

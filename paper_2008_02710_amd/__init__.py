@@ -102,7 +102,7 @@ EXPORTED = ["rlgl_default_options", "rlgl_workspace_bytes", "rlgl_create", "rlgl
             "rlgl_pool_default_options", "rlgl_pool_workspace_bytes", "rlgl_pool_footprint", "rlgl_pool_create",
             "rlgl_pool_admit", "rlgl_pool_advance", "rlgl_pool_launch", "rlgl_pool_wait", "rlgl_pool_poll",
             "rlgl_pool_result", "rlgl_pool_release", "rlgl_pool_destroy", "rlgl_validate_scratch_bytes",
-            "rlgl_validate"]
+            "rlgl_validate", "rlgl_step_mask"]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -123,6 +123,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rlgl_create.restype = i32
     lib.rlgl_step.argtypes = [vp, i32, I]
     lib.rlgl_step.restype = i32
+    lib.rlgl_step_mask.argtypes = [vp, vp, I]
+    lib.rlgl_step_mask.restype = i32
     lib.rlgl_solve.argtypes = [vp, f64, i64, vp, I]
     lib.rlgl_solve.restype = i32
     lib.rlgl_destroy.argtypes = [vp]
@@ -249,6 +251,13 @@ def rlgl_create(graph: rlgl_graph, opt: rlgl_options, workspace, ws_bytes: int, 
 def rlgl_step(ctx, nsteps: int) -> rlgl_step_info:
     info = rlgl_step_info()
     _check(_lib.rlgl_step(ctx, int(nsteps), ctypes.byref(info)), "rlgl_step")
+    return info
+
+
+def rlgl_step_mask(ctx, mask) -> rlgl_step_info:
+    """One step with the green set {i : mask[i] != 0} (device uint8 tensor or pointer)."""
+    info = rlgl_step_info()
+    _check(_lib.rlgl_step_mask(ctx, _ptr(mask), ctypes.byref(info)), "rlgl_step_mask")
     return info
 
 
@@ -490,6 +499,12 @@ class Solver:
 
     def step(self, nsteps: int = 1) -> dict:
         return rlgl_step(self.ctx, nsteps).as_dict()
+
+    def step_mask(self, mask) -> dict:
+        """One step whose green set is {i : mask[i] != 0} (uint8 tensor of n on the device)."""
+        if mask.dtype != torch.uint8 or mask.numel() != self.dg.n or not mask.is_cuda:
+            raise ValueError("mask must be a device uint8 tensor of n entries")
+        return rlgl_step_mask(self.ctx, mask.contiguous()).as_dict()
 
     def solve(self, eps: float, max_steps: int = 1_000_000, raise_on_error: bool = True):
         st, info = rlgl_solve(self.ctx, eps, max_steps, self.pi, raise_on_error)

@@ -660,6 +660,7 @@ rlgl_status rlgl_create(const rlgl_graph *g, const rlgl_options *o, void *ws, si
   d.route = g->csc_colptr ? o->route : RLGL_ROUTE_PUSH;
   d.pull_alpha = o->pull_alpha;
   d.seed = o->seed;
+  d.green_in = nullptr;
   d.cash[0] = w + L.cash0;
   d.cash[1] = w + L.cash1;
   d.hist = w + L.hist;
@@ -757,6 +758,30 @@ rlgl_status rlgl_step(rlgl_ctx *c, int32_t nsteps, rlgl_step_info *info) {
   HIP_TRY(hipGetLastError());
   const long long s0 = c->t;
   for (long long s = s0; s < s0 + nsteps; ++s) HIP_TRY(enqueue_step(c, s, -1.0, s0 + nsteps, 0));
+  rlgl_status st = read_back(c);
+  if (st != RLGL_OK) return st;
+  const int ds = c->host_glob->status;
+  const rlgl_status rs = (ds == ST_ZERO_HISTORY || ds == ST_NONFINITE) ? status_of(ds) : RLGL_OK;
+  fill_info(c, info, rs);
+  if (rs != RLGL_OK) return fail(rs, "stopped at t = %lld (device status %d)", c->t, ds);
+  return RLGL_OK;
+}
+
+rlgl_status rlgl_step_mask(rlgl_ctx *c, const uint8_t *dev_mask, rlgl_step_info *info) {
+  if (!c || !dev_mask) return fail(RLGL_EINVAL, "null argument");
+  if (c->d.perm) return fail(RLGL_EINVAL, "a caller-given green set needs the caller's numbering (relabel = 0)");
+  k_set_status<<<1, 64, 0, c->stream>>>(c->d.glob, 0);
+  HIP_TRY(hipGetLastError());
+  // the kernels take the descriptor by value at launch, so the mask
+  // schedule lives for this one step only
+  const int sched = c->d.sched;
+  c->d.sched = SCHED_MASK;
+  c->d.green_in = (const unsigned char *)dev_mask;
+  const long long s0 = c->t;
+  const hipError_t e = enqueue_step(c, s0, -1.0, s0 + 1, 0);
+  c->d.sched = sched;
+  c->d.green_in = nullptr;
+  HIP_TRY(e);
   rlgl_status st = read_back(c);
   if (st != RLGL_OK) return st;
   const int ds = c->host_glob->status;

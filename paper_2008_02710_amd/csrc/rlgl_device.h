@@ -27,6 +27,8 @@ constexpr int PUSH_GRID = 512;      // push launches (hot partials flushed once 
 constexpr int NSTRIPE = 32;
 
 enum { SCHED_ALL = 0, SCHED_THRESHOLD = 1, SCHED_TOPK = 2, SCHED_MAXC = 3, SCHED_PC = 4 };
+// a step whose green set the caller gives as a byte mask (rlgl_step_mask)
+constexpr int SCHED_MASK = 5;
 enum { ROUTE_PUSH = 0, ROUTE_PULL = 1, ROUTE_AUTO = 2 };
 enum { ST_RUNNING = 0, ST_CONVERGED = 1, ST_LIMIT = 2, ST_ZERO_HISTORY = -4, ST_NONFINITE = -6 };
 
@@ -105,6 +107,7 @@ struct Dev {
   int route;
   double pull_alpha;
   unsigned long long seed;  // SCHED_PC draws
+  const unsigned char *green_in;  // SCHED_MASK: the caller's green set, one byte per node
   // workspace
   void *cash[2];
   void *hist;        // double[n], or float[n] (hi part) for the compensated history

@@ -229,9 +229,11 @@ __device__ __forceinline__ unsigned long long splitmix64_at(unsigned long long s
 // the uniform draw being splitmix64 output t 2^32 + id, top 53 bits.
 template <class T>
 __device__ __forceinline__ bool is_green(T v, int id, int sched, double theta, double maxabs, double tau, int tie_id,
-                                         unsigned long long seed = 0ull, long long t = 0) {
+                                         unsigned long long seed = 0ull, long long t = 0,
+                                         const unsigned char *mask = nullptr) {
   const double a = fabs((double)v);
   if (sched == SCHED_ALL) return true;
+  if (sched == SCHED_MASK) return mask[id] != 0;  // the caller's green set
   if (sched == SCHED_THRESHOLD) return a >= theta;
   if (sched == SCHED_MAXC) return a == maxabs;
   if (sched == SCHED_PC) {
@@ -365,7 +367,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(Dev d, long long s, double eps
       rs[q] = 0;
       v[q] = T(0);
       const T x = pv[q];
-      const bool gr = (i < n) && is_green(x, i, sched, theta, maxabs, tau, tie_id, d.seed, s);
+      const bool gr = (i < n) && is_green(x, i, sched, theta, maxabs, tau, tie_id, d.seed, s, d.green_in);
       if (i < n) {
         if (d.green_mask) d.green_mask[i] = gr ? 1 : 0;
         T sent = T(0);  // pull: M_i P'_ij for each link i -> j (M_i itself with stored link values)
@@ -970,7 +972,7 @@ __global__ __launch_bounds__(BLOCK, 5) void k_complete(Dev d, long long s, int i
     // the kept part C_t - M_t of node k from its cash v
     auto keep = [&](T v, int k) -> double {
       if (init) return -(double)v;  // step 0: C_0 - M_0 with C_0 = 0
-      return is_green(v, k, sched, theta, maxabs, tau, tie_id, d.seed, s) ? 0.0 : (double)v;
+      return is_green(v, k, sched, theta, maxabs, tau, tie_id, d.seed, s, d.green_in) ? 0.0 : (double)v;
     };
     // what the sources send was written by select (zero off the green set;
     // links outside [0, N) are ignored)
@@ -1031,7 +1033,7 @@ __global__ __launch_bounds__(BLOCK) void k_complete_long(Dev d, long long s, int
   auto kept = [&](int k, int q) -> double {
     const T v = (q == q0) ? v0 : Cc[k];
     if (init) return -(double)v;
-    return is_green(v, k, sched, theta, maxabs, tau, tie_id, d.seed, s) ? 0.0 : (double)v;
+    return is_green(v, k, sched, theta, maxabs, tau, tie_id, d.seed, s, d.green_in) ? 0.0 : (double)v;
   };
   long_finish<T>(d, kept, tot.T / (double)d.n, (T *)d.cash[cur->buf ^ 1], nxt);
 }

@@ -422,3 +422,93 @@ def test_gso_pr_is_rlgl_on_the_auxiliary_chain():
         assert steps == t + 1
         assert np.abs(st0.H[1:] - H).max() < 1e-15
         assert np.abs(st0.C[1:] - C).max() < 1e-15
+
+
+# ------------------------------------------------ block schedules (Sec. 5.3)
+
+from oracle import blocks  # noqa: E402
+
+SBM3 = ((50, 20, 10), 0.1, 0.01)
+
+
+def _block_vector(c, N):
+    return np.repeat(np.asarray(c, dtype=np.float64), N)
+
+
+def test_block_step_equals_the_dense_step():
+    """The three-number block dynamics is the RLGL step of the dense SBM chain
+    with every state of the green blocks green, for all seven actions."""
+    N, p, q = SBM3
+    P = blocks.dense_chain(N, p, q)
+    ch = chain_from_dense(P)
+    blk = np.repeat(np.arange(3), N)
+    rng = np.random.default_rng(5)
+    for trial in range(6):
+        c = rng.standard_normal(3)
+        c[2] = -(N[0] * c[0] + N[1] * c[1]) / N[2]  # cash balance
+        for a in blocks.ACTIONS:
+            s = oracle.State.from_arrays(ch, _block_vector(c, N), np.zeros(P.shape[0]), 1.0)
+            s.step_mask(np.isin(blk, a))
+            want = blocks.step(c, a, N, p, q)
+            scale = np.abs(c).max()  # the dense step adds up to 80 terms of this size
+            assert np.abs(s.C - _block_vector(want, N)).max() < 1e-14 * scale
+            assert abs(float(np.dot(N, want))) < 1e-13 * scale
+
+
+def test_block_initial_cash_closed_form():
+    """One power-iteration step from the uniform M_0 gives the block cash of
+    the closed form of Sec. 5.3 (there written with the opposite sign of C)."""
+    for N, p, q in (SBM3, ((30, 30, 5), 0.2, 0.05), ((7, 5, 3), 0.5, 0.1)):
+        P = blocks.dense_chain(N, p, q)
+        n = P.shape[0]
+        M0 = np.full(n, 1.0 / n)
+        C1 = oracle.route(chain_from_dense(P), M0) - M0
+        blk = np.repeat(np.arange(3), N)
+        c0 = np.array([C1[blk == j].mean() for j in range(3)])
+        zeta = p / q - 1.0
+        Na = np.asarray(N, dtype=np.float64)
+        closed = np.array([zeta / n * sum(Na[j] * (Na[j] - Na[i]) / ((Na[i] * zeta + n) * (Na[j] * zeta + n))
+                                          for j in range(3)) for i in range(3)])
+        assert np.abs(c0 + closed).max() < 1e-16
+        assert np.abs(C1 - _block_vector(c0, N)).max() < 1e-16
+
+
+def test_block_shape_covers_the_half_space():
+    """z_2 in [-2, 2] and (y_2, y_3) correspond one to one (the three cases of
+    Sec. 5.3): the shape has unit L1 norm, zero balance and c_1 >= 0."""
+    N = np.array(SBM3[0], dtype=np.float64)
+    z2 = np.linspace(-2.0, 2.0, 401)
+    c = blocks.shape_from_z2(z2, N)
+    assert np.allclose((np.abs(c) * N).sum(axis=1), 1.0, atol=1e-15)
+    assert np.allclose((c * N).sum(axis=1), 0.0, atol=1e-15)
+    assert np.all(c[:, 0] >= -1e-18)
+    back = np.array([blocks.z_of(ci, N, 1.0)[1] for ci in c])
+    assert np.abs(back - z2).max() < 1e-12
+
+
+def test_optimal_block_schedule():
+    """Sec. 5.3 on the mean-field SBM (N = 50, 20, 10; p = 0.1, q = 0.01;
+    eps = 1e-14) from the power-iteration start: the dynamic-programming
+    schedule routes mostly the two small blocks, never all three (power
+    iteration), needs fewer steps than power iteration at a fraction of its
+    cost, is no worse than simple fixed schedules, and its value function
+    predicts the cost it pays."""
+    N, p, q = SBM3
+    eps = 1e-14
+    pol = blocks.Policy(N, p, q, eps, n1=1400, n2=81)
+    assert np.all(pol.V[0] == 0.0) and np.all(pol.V >= 0.0)
+    P = blocks.dense_chain(N, p, q)
+    n = P.shape[0]
+    C1 = oracle.route(chain_from_dense(P), np.full(n, 1.0 / n)) - 1.0 / n
+    blk = np.repeat(np.arange(3), N)
+    c0 = np.array([C1[blk == j].mean() for j in range(3)])
+    cost, steps, acts = blocks.run(c0, pol.action, N, p, q, eps)
+    pi_cost, pi_steps, _ = blocks.run(c0, lambda c: 6, N, p, q, eps)
+    assert np.isfinite(cost) and cost < pi_cost / 5 and steps < pi_steps
+    hist = np.bincount(acts, minlength=7)
+    assert hist[6] == 0 and hist[1] + hist[2] >= 0.75 * steps
+    assert abs(pol.value(c0) - cost) <= 0.1 * cost
+    for cycle in ((2, 2, 2, 4), (1, 2), (0, 1, 2), (4,), (3, 4, 5)):
+        it = iter(range(10 ** 9))
+        fixed, _, _ = blocks.run(c0, lambda c: cycle[next(it) % len(cycle)], N, p, q, eps)
+        assert cost <= fixed * 1.001, (cycle, fixed, cost)
