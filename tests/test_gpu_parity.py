@@ -482,3 +482,54 @@ def test_topk_with_heavy_ties(prec, k):
     assert int(mask.sum()) == min(k, g.n)
     assert np.array_equal(mask, want)
     s.close()
+
+
+# ------------------------------------------------------- pull plan edges
+
+def _boundary_graph():
+    """Columns whose in-degrees sit on the pull plan's limits (512 links per
+    item, 64 columns per item): exactly 511, 512 and 513 in-links, 1024 and
+    1025, runs of empty columns at item starts and ends, 64 and 65 one-link
+    columns in a row, a column fed only by dangling-free sources."""
+    rng = np.random.default_rng(123)
+    n = 3000
+    indeg = np.zeros(n, dtype=np.int64)
+    spec = [0, 0, 512, 0, 513, 511, 0, 1, 1024, 1025, 0, 0, 0, 512, 512, 2, 0]
+    indeg[:len(spec)] = spec
+    pos = len(spec)
+    indeg[pos:pos + 64] = 1
+    pos += 64 + 3
+    indeg[pos:pos + 65] = 1
+    pos += 65
+    indeg[pos:pos + 200] = 8
+    pos += 200
+    indeg[pos:] = rng.integers(0, 12, n - pos)
+    dst = np.repeat(np.arange(n), indeg)
+    src = rng.integers(0, n, dst.size)
+    return workloads.from_edges(n, src, dst, 0.85, name="plan_edges")
+
+
+@pytest.mark.parametrize("prec", [rl.FP64, rl.FP32C_FP64H], ids=PREC_NAMES.get)
+@pytest.mark.parametrize("relabel", [0, 1])
+def test_pull_plan_boundaries(prec, relabel):
+    g = _boundary_graph()
+    cp = g.csc()[0]
+    deg = np.diff(cp)
+    assert {511, 512, 513, 1024, 1025} <= set(deg.tolist())
+    say("case plan_edges", PREC_NAMES[prec], relabel)
+    s = solver(g, prec, route=rl.ROUTE_PULL, sched=rl.SCHED_ALL, record_green=1, relabel=relabel)
+    C0, H0, hs0 = _nontrivial_state(g, prec)
+    s.set_state(torch.from_numpy(C0).cuda(), torch.from_numpy(H0).cuda(), hs0, t=4)
+    Cg, Hg, info0 = s.state()
+    Cg, Hg = to_np(Cg), to_np(Hg)
+    s.step(1)
+    ost = oracle.State.from_arrays(oracle_chain(g), Cg, Hg, info0["h_sum"], t=4)
+    moved = float(np.abs(Cg).sum())
+    ost.step_mask(np.ones(g.n, dtype=bool))
+    C1, H1, info2 = s.state()
+    err = np.abs(to_np(C1) - ost.C)
+    assert err.sum() <= tol_step(prec) * moved + 1e-300, np.argsort(err)[-5:]
+    st, info = s.solve((1 - g.c) * tol_solve(prec) * 0.5)
+    assert st == rl.RLGL_OK
+    assert l1(to_np(s.pi), reference(g)) <= tol_solve(prec)
+    s.close()
