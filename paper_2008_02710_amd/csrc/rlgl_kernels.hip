@@ -739,15 +739,44 @@ __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved m
 // wave's LDS.
 //
 // In a RUN, lane l owns the WU consecutive links [l*WU, l*WU + WU) of the
-// item and gathers what their sources send.  A lane finds the column of its
-// first link by a binary search of the staged column pointers, then walks its
-// links: a column that both starts and ends among them stores its sum at
-// once; the sum of the leading part of its first column (which may have
-// started in an earlier lane) waits for the carry, the sum of the trailing
-// part goes into a segmented scan across the lanes, whose exclusive value is
-// that carry.  Then the lanes write the item's columns, consecutive lanes to
+// item and gathers what their sources send.  Lane q marks the last link of
+// column q in LDS, so each lane reads which of its links end a column (and
+// which column) with two LDS loads, then walks its links: a column that both
+// starts and ends among them stores its sum at once; the sum of the leading
+// part of its first column (which may have started in an earlier lane) waits
+// for the carry, the sum of the trailing part goes into a segmented scan
+// across the lanes, whose exclusive value is that carry.  Then the lanes write the item's columns, consecutive lanes to
 // consecutive columns: x_k = kept(k) + c * sum_k + off (columns without
 // in-links have sum 0).
+// Lane moves through DPP (the GFX9 encodings): row_shr:n shifts inside each
+// row of 16 lanes, row_bcast:15 hands a row's last lane to the next row,
+// row_bcast:31 hands lane 31 to rows 2 and 3, wave_shr:1 shifts the whole
+// wave by one lane.  A lane with no source, or in a row the mask leaves out,
+// reads 0.
+constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114, DPP_ROW_SHR8 = 0x118;
+constexpr int DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143, DPP_WAVE_SHR1 = 0x138;
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, true);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned int lo = (unsigned int)dpp_i32<CTRL, ROWS>((int)(unsigned int)b);
+  const unsigned int hi = (unsigned int)dpp_i32<CTRL, ROWS>((int)(unsigned int)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// One step of a segmented inclusive sum over the wave: the value from the
+// lane the move names is added unless this lane already starts a segment.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_scan_step(double &v, int &f) {
+  const double yv = dpp_f64<CTRL, ROWS>(v);
+  const int yf = dpp_i32<CTRL, ROWS>(f);
+  if (!f) v += yv;
+  f |= yf;
+}
+
 __device__ __forceinline__ void wave_lds_fence() {
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
   __builtin_amdgcn_wave_barrier();
@@ -856,50 +885,57 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
     for (int u = 0; u < WU; ++u) w[u] = (VAL && e0 + u < ne) ? (double)vals[(unsigned)(e0 + u)] : 1.0;
     if (item.x >= 0) {
       const int k0 = item.x, ncol = item.y - item.x;
-      for (int q = lane; q < ncol; q += 64) sum[q] = 0.0;
+      // Mark the last link of every column that has one with the column's
+      // index (row[] is free once jj holds this lane's sources; LDS
+      // operations of one wave take effect in program order).
+      static_assert(WCOLS <= 64, "one lane per column of a run");
+      *(int4 *)&row[e0] = make_int4(-1, -1, -1, -1);
+      *(int4 *)&row[e0 + 4] = make_int4(-1, -1, -1, -1);
+      if (lane < ncol) {
+        sum[lane] = 0.0;  // stays 0 for a column without in-links
+        const int b0 = cp[lane], b1 = cp[lane + 1];
+        if (b1 > b0) row[b1 - 1] = lane;
+      }
+      wave_lds_fence();
+      int ec[WU];
+      {
+        const int4 a = *(const int4 *)&row[e0];
+        const int4 b = *(const int4 *)&row[e0 + 4];
+        ec[0] = a.x; ec[1] = a.y; ec[2] = a.z; ec[3] = a.w;
+        ec[4] = b.x; ec[5] = b.y; ec[6] = b.z; ec[7] = b.w;
+      }
+      // Walk the lane's links: the sum up to its first column end is the
+      // head of that column (f), later ends close columns that lie wholly in
+      // the lane; links past ne send 0 and end no column.
       double acc = 0.0, head = 0.0;
       int ended = 0, f = 0;
-      if (e0 < ne) {
-        // the last column starting at or before this lane's first link
-        int lo = 0, hi = ncol;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (cp[mid] <= e0) lo = mid;
-          else hi = mid - 1;
-        }
-        f = lo;
-        int q = f, nb = cp[f + 1];
 #pragma unroll
-        for (int u = 0; u < WU; ++u) {
-          if (e0 + u < ne) {
-            acc += (double)x[u] * w[u];
-            if (e0 + u + 1 == nb) {
-              if (ended) sum[q] = acc;
-              else head = acc;
-              ended = 1;
-              acc = 0.0;
-              ++q;
-              while (q < ncol && cp[q + 1] == cp[q]) ++q;  // columns without in-links
-              nb = (q < ncol) ? cp[q + 1] : 0x7fffffff;
-            }
+      for (int u = 0; u < WU; ++u) {
+        acc += (double)x[u] * w[u];
+        const int q = ec[u];
+        if (q >= 0) {
+          if (ended) {
+            sum[q] = acc;
+          } else {
+            head = acc;
+            f = q;
           }
+          ended = 1;
+          acc = 0.0;
         }
       }
       // inclusive segmented scan of the trailing sums (a lane with a column
       // end starts a segment); its exclusive value is the carry
       double iv = acc;
       int fl = ended;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const double yv = __shfl_up(iv, o, 64);
-        const int yf = __shfl_up(fl, o, 64);
-        if (lane >= o) {
-          if (!fl) iv += yv;
-          fl |= yf;
-        }
-      }
-      const double carry = __shfl_up(iv, 1, 64);
-      if (ended) sum[f] = (lane > 0 ? carry : 0.0) + head;
+      seg_scan_step<DPP_ROW_SHR1, 0xF>(iv, fl);
+      seg_scan_step<DPP_ROW_SHR2, 0xF>(iv, fl);
+      seg_scan_step<DPP_ROW_SHR4, 0xF>(iv, fl);
+      seg_scan_step<DPP_ROW_SHR8, 0xF>(iv, fl);
+      seg_scan_step<DPP_ROW_BCAST15, 0xA>(iv, fl);
+      seg_scan_step<DPP_ROW_BCAST31, 0xC>(iv, fl);
+      const double carry = dpp_f64<DPP_WAVE_SHR1, 0xF>(iv);
+      if (ended) sum[f] = carry + head;
       wave_lds_fence();
       T *__restrict__ outs = out + k0;
       for (int q = lane; q < ncol; q += 64) {
