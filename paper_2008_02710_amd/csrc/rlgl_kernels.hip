@@ -813,36 +813,61 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
   // registers of the item fetched ahead
   int pr[WU], pc[NCP];
   unsigned int pk[NK];
+  // The item is the same for the whole wave (scalar registers); every lane
+  // loads at an index clamped into the item, then lanes past its end take
+  // the fill value, so no load sits behind a per-lane branch.
   auto fetch = [&](int4 item) {
     // item-relative bases (uniform) keep the per-lane offsets 32-bit
     const int p0 = item.z, ne = item.w - item.z;
-    const int *__restrict__ rows = crow + p0;
+    if (ne > 0) {
+      const int *__restrict__ rows = crow + p0;
 #pragma unroll
-    for (int u = 0; u < WU; ++u) {
-      const unsigned int e = (unsigned int)(u * 64 + lane);
-      pr[u] = ((int)e < ne) ? rows[e] : -1;
+      for (int u = 0; u < WU; ++u) {
+        const int e = u * 64 + lane;
+        const int v = rows[(unsigned int)min(e, ne - 1)];
+        pr[u] = (e < ne) ? v : -1;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < WU; ++u) pr[u] = -1;
     }
     const int k0 = item.x, ncol = item.y - item.x;
-    const bool run = item.x >= 0;
-    const int *__restrict__ cps = colptr + (run ? k0 : 0);
+    if (item.x >= 0) {  // a run: 1 <= ncol <= WCOLS
+      const int *__restrict__ cps = colptr + k0;
 #pragma unroll
-    for (int q = 0; q < NCP; ++q) {
-      const unsigned int j = (unsigned int)(q * 64 + lane);
-      pc[q] = (run && (int)j <= ncol) ? cps[j] - p0 : 0;
-    }
-    if (STAGEK) {
-      const unsigned int *__restrict__ kws = kw + (run ? (size_t)k0 * KW : 0);
+      for (int q = 0; q < NCP; ++q) {
+        const int j = q * 64 + lane;
+        const int v = cps[(unsigned int)min(j, ncol)];
+        pc[q] = (j <= ncol) ? v - p0 : 0;
+      }
+      if (STAGEK) {
+        const unsigned int *__restrict__ kws = kw + (size_t)k0 * KW;
 #pragma unroll
-      for (int q = 0; q < NK; ++q) {
-        const unsigned int j = (unsigned int)(q * 64 + lane);
-        pk[q] = (run && (int)j < ncol * KW) ? kws[j] : 0u;
+        for (int q = 0; q < NK; ++q) {
+          const int j = q * 64 + lane;
+          const unsigned int v = kws[(unsigned int)min(j, ncol * KW - 1)];
+          pk[q] = (j < ncol * KW) ? v : 0u;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NCP; ++q) pc[q] = 0;
+      if (STAGEK) {
+#pragma unroll
+        for (int q = 0; q < NK; ++q) pk[q] = 0u;
       }
     }
   };
+  auto item_at = [&](int i) -> int4 {
+    if (i >= n_items) return none;
+    const int4 v = d.items[i];
+    return make_int4(__builtin_amdgcn_readfirstlane(v.x), __builtin_amdgcn_readfirstlane(v.y),
+                     __builtin_amdgcn_readfirstlane(v.z), __builtin_amdgcn_readfirstlane(v.w));
+  };
 
   int it = (int)blockIdx.x * NWAVE + wv;
-  int4 cur = (it < n_items) ? d.items[it] : none;
-  int4 nxt = (it + stride < n_items) ? d.items[it + stride] : none;
+  int4 cur = item_at(it);
+  int4 nxt = item_at(it + stride);
   // an item the plan cannot have built is skipped whole
   auto valid = [&](int4 item) {
     const int ne = item.w - item.z;
@@ -862,7 +887,7 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
     }
     const int4 item = valid(cur) ? cur : none;
     if (it + stride < n_items) fetch(valid(nxt) ? nxt : none);
-    const int4 nx2 = (it + 2 * stride < n_items) ? d.items[it + 2 * stride] : none;
+    const int4 nx2 = item_at(it + 2 * stride);
     wave_lds_fence();
     const int ne = item.w - item.z;
     int jj[WU];
@@ -876,13 +901,22 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
     S x[WU];
 #pragma unroll
     for (int u = 0; u < WU; ++u) {
-      const bool ok = e0 + u < ne && (unsigned)jj[u] < (unsigned)n;
-      x[u] = ok ? src[(unsigned)jj[u]] : S(0);
+      // jj is -1 past the item's end; links outside [0, N) send nothing
+      const unsigned int j = (unsigned int)jj[u];
+      const bool ok = j < (unsigned int)n;
+      const S v = src[ok ? j : 0u];
+      x[u] = ok ? v : S(0);
     }
     double w[WU];
     const T *__restrict__ vals = cval + (VAL ? item.z : 0);
 #pragma unroll
-    for (int u = 0; u < WU; ++u) w[u] = (VAL && e0 + u < ne) ? (double)vals[(unsigned)(e0 + u)] : 1.0;
+    for (int u = 0; u < WU; ++u) {
+      w[u] = 1.0;
+      if (VAL && ne > 0) {
+        const double v = (double)vals[(unsigned int)min(e0 + u, ne - 1)];
+        w[u] = (e0 + u < ne) ? v : 1.0;
+      }
+    }
     if (item.x >= 0) {
       const int k0 = item.x, ncol = item.y - item.x;
       // Mark the last link of every column that has one with the column's
