@@ -51,7 +51,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 struct Layout {
   size_t cash0, cash1, hist, hist_lo, fr_rowstart, fr_eoff, fr_id, fr_scale, chunk_first, green_mask, delta, colt,
       hot_nodes, rec, glob,
-      log, items, long_cols, long_acc, total;
+      log, items, long_cols, long_acc, long_cnt, total;
   size_t max_items, max_long;
   // relabelled layout
   size_t perm, old2new, nrowptr, ncol, nval, ncolptr, nrow, ncval;
@@ -92,6 +92,7 @@ Layout make_layout(long long n, long long nnz, int prec, bool has_csc, bool rela
     L.items = take(sizeof(int4) * L.max_items);
     L.long_cols = take(4 * L.max_long);
     L.long_acc = take(8 * L.max_long);
+    L.long_cnt = take(4 * L.max_long);
   }
   if (relabel) {
     const size_t vs = (prec == RLGL_FP64) ? 8 : 4;
@@ -127,8 +128,8 @@ bool valid_options(const rlgl_options *o, std::string &why) {
   return true;
 }
 
-const char *kernel_names[] = {"select", "push", "complete", "topk", "complete_long"};
-enum { KS_SELECT = 0, KS_PUSH = 1, KS_COMPLETE = 2, KS_TOPK = 3, KS_LONG = 4, KS_N = 5 };
+const char *kernel_names[] = {"select", "push", "complete", "topk"};
+enum { KS_SELECT = 0, KS_PUSH = 1, KS_COMPLETE = 2, KS_TOPK = 3, KS_N = 4 };
 
 struct Launch {
   int kind;
@@ -258,12 +259,6 @@ hipError_t enqueue_step(rlgl_ctx *c, long long s, double eps, long long s_limit,
   e = timed(c, KS_COMPLETE, s, [&] {
     if (c->prec == RLGL_FP64) launch_complete<double>(c, s, force_all);
     else launch_complete<float>(c, s, force_all);
-  });
-  if (e != hipSuccess || d.n_long == 0) return e;
-  const int gl = std::max(1, std::min((d.n_long + BLOCK - 1) / BLOCK, NODE_GRID));
-  e = timed(c, KS_LONG, s, [&] {
-    if (c->prec == RLGL_FP64) k_complete_long<double><<<gl, blk, 0, c->stream>>>(d, s, force_all);
-    else k_complete_long<float><<<gl, blk, 0, c->stream>>>(d, s, force_all);
   });
   return e;
 }
@@ -457,7 +452,7 @@ rlgl_status build_plan(rlgl_ctx *c, const rlgl_graph *g, const Layout &L, char *
     const int dg = cp[k + 1] - cp[k];
     if (dg < 0) return fail(RLGL_EINVAL, "csc_colptr is not non-decreasing at %d", k);
     if (dg > WL) {
-      // a long column: pieces of WL links, completed by k_complete_long
+      // a long column: pieces of WL links; the last one summed writes the column
       flush(k);
       const int slot = (int)lng.size();
       lng.push_back(k);
@@ -470,8 +465,24 @@ rlgl_status build_plan(rlgl_ctx *c, const rlgl_graph *g, const Layout &L, char *
     run_e += dg;
   }
   flush(n);
-  // long pieces first: their partial sums are the longest dependency chain
-  std::stable_partition(items.begin(), items.end(), [](const int4 &a) { return a.x < 0; });
+  // The pieces are spread evenly over the first three quarters of the runs:
+  // a wave that sums a piece has two device-scope atomics in flight, which
+  // costs little while the other waves keep their gathers going, but stalls
+  // the pass when every wave takes a piece at once; the last column finished
+  // leaves a quarter of the pass to hide behind.
+  {
+    std::vector<int4> runs, pieces;
+    for (const int4 &it : items) (it.x < 0 ? pieces : runs).push_back(it);
+    const size_t span = (runs.size() * 3) / 4;
+    items.clear();
+    size_t r = 0;
+    for (size_t j = 0; j < pieces.size(); ++j) {
+      const size_t upto = span * (j + 1) / (pieces.size() + 1);
+      while (r < upto) items.push_back(runs[r++]);
+      items.push_back(pieces[j]);
+    }
+    while (r < runs.size()) items.push_back(runs[r++]);
+  }
   if (items.size() > L.max_items || lng.size() > L.max_long)
     return fail(RLGL_EINVAL, "pull plan exceeds its bound (internal)");
   if (!items.empty())
@@ -483,6 +494,7 @@ rlgl_status build_plan(rlgl_ctx *c, const rlgl_graph *g, const Layout &L, char *
   c->d.n_items = (int)items.size();
   c->d.long_cols = (const int *)(ws + L.long_cols);
   c->d.long_acc = (double *)(ws + L.long_acc);
+  c->d.long_cnt = (int *)(ws + L.long_cnt);
   c->d.n_long = (int)lng.size();
   return RLGL_OK;
 }
@@ -690,6 +702,7 @@ rlgl_status rlgl_create(const rlgl_graph *g, const rlgl_options *o, void *ws, si
   d.n_items = 0;
   d.long_cols = nullptr;
   d.long_acc = nullptr;
+  d.long_cnt = nullptr;
   d.n_long = 0;
   d.perm = nullptr;
 
@@ -933,9 +946,6 @@ int32_t rlgl_profile_read(rlgl_ctx *c, rlgl_kernel_stat *out, int32_t max_entrie
       b = (double)lg.gedges * (4.0 + vs + 2.0 * cs) + (double)lg.nfront * (8.0 + cs);
     } else if (L.kind == KS_COMPLETE) {
       b = push ? 2.0 * cs * n : (4.0 * n + nnz * (4.0 + vs + cs) + 2.0 * cs * n);
-    } else if (L.kind == KS_LONG) {
-      if (push) continue;
-      b = (double)c->d.n_long * (4.0 + 8.0 + 8.0 + 2.0 * cs);
     } else {
       b = 0.0;
     }

@@ -132,6 +132,7 @@ struct Dev {
   int n_items;
   const int *long_cols;
   double *long_acc;
+  int *long_cnt;  // links of each long column summed so far in the running pass (0 between passes)
   int n_long;
   // relabelled layout: internal index -> caller's id (NULL: the caller's numbering)
   const int *perm;

@@ -562,8 +562,8 @@ __global__ void k_indegree(Dev d, int *indeg) {
 // per thread) and adds them up per column with a block-wide segmented scan,
 // so every workgroup moves the same number of links whatever the degrees.
 // A column with more than CH in-links is cut into PIECEs of CH links whose
-// sums meet in long_acc; k_long_finish completes those columns afterwards
-// (a last-workgroup ticket would cost every workgroup a device-scope fence).
+// sums meet in long_acc; a later pass completes those columns (a
+// last-workgroup ticket would cost every workgroup a device-scope fence).
 
 struct Seg {
   double v;
@@ -730,7 +730,8 @@ __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved m
 // own (no workgroup barrier inside the item loop): a RUN {k0, k1, p0, p1} of
 // whole columns holding at most WL links and WCOLS columns, or a PIECE
 // {-1 - slot, k, p0, p1} of at most WL links of a longer column, whose sum
-// goes to long_acc[slot] (k_complete_long finishes those columns).
+// goes to long_acc[slot]: with FUSE the piece that completes the column's
+// link count writes the column, otherwise a later pass does (long_finish).
 //
 // The loads of an item (its CSC sources, column pointers and, with STAGEK,
 // the raw cash values its kept part needs) are issued coalesced into
@@ -782,9 +783,11 @@ __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_wave_barrier();
 }
 
-template <class T, class S, bool VAL, bool STAGEK, bool RP, class Keep>
+template <class T, class S, bool VAL, bool STAGEK, bool RP, bool FUSE, class Keep>
 __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ src, const T *__restrict__ kraw,
                                           Keep keep, double off, T *__restrict__ out, Rec *r) {
+  static_assert(!FUSE || STAGEK, "finishing long columns reads their raw values");
+  const T *__restrict__ kraw_t = kraw;
   constexpr int KW = STAGEK ? (int)(sizeof(T) / 4) : 0;      // dwords per staged raw value
   constexpr int NCP = (WCOLS + 1 + 63) / 64;                 // column pointers per lane
   constexpr int NK = STAGEK ? (WCOLS * KW + 63) / 64 : 1;    // staged raw dwords per lane
@@ -863,6 +866,43 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
     const int4 v = d.items[i];
     return make_int4(__builtin_amdgcn_readfirstlane(v.x), __builtin_amdgcn_readfirstlane(v.y),
                      __builtin_amdgcn_readfirstlane(v.z), __builtin_amdgcn_readfirstlane(v.w));
+  };
+
+  // FUSE: the piece that brings its column's link count (long_cnt) to the
+  // column's in-degree finishes the column.  Device-scope atomics on one
+  // address are carried out at one place for the whole device; a piece takes
+  // its count only after its add has returned, and the finishing piece swaps
+  // the sum out only after its count has returned, so the swap comes after
+  // every piece's add.  Each of the two round trips overlaps the wave's next
+  // item: piece pa has its add in flight, piece pb its count.
+  struct Piece {
+    int slot, k, ne, deg;
+    T raw;
+    double before;
+    int seen;
+  } pa{}, pb{};
+  bool has_a = false, has_b = false;
+  double piece_sum = 0.0;
+  auto advance = [&]() {
+    if (has_b) {
+      if (lane == 0 && pb.seen + pb.ne == pb.deg) {
+        const double sum = __hip_atomic_exchange(&d.long_acc[pb.slot], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&d.long_cnt[pb.slot], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const T y = (T)(keep(pb.raw, pb.k) + c * sum + off);
+        out[pb.k] = y;
+        fold_stats<RP>((double)y, rr, l1, cs, sr, mx);
+      }
+      has_b = false;
+    }
+    if (has_a) {
+      pb = pa;
+      if (lane == 0) {
+        asm volatile("" ::"v"(pa.before) : "memory");
+        pb.seen = __hip_atomic_fetch_add(&d.long_cnt[pa.slot], pa.ne, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      has_a = false;
+      has_b = true;
+    }
   };
 
   int it = (int)blockIdx.x * NWAVE + wv;
@@ -984,11 +1024,35 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
       for (int u = 0; u < WU; ++u) acc += (double)x[u] * w[u];
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-      if (lane == 0) atomic_add_f64(&d.long_acc[-1 - item.x], acc);
+      if (!FUSE) {
+        if (lane == 0) atomic_add_f64(&d.long_acc[-1 - item.x], acc);
+      } else {
+        piece_sum = acc;
+      }
+    }
+    if (FUSE) {
+      advance();
+      if (item.x < 0 && ne > 0) {
+        // the piece's add goes out now; its count follows one item later
+        pa.slot = -1 - item.x;
+        pa.k = item.y;
+        pa.ne = ne;
+        pa.deg = colptr[pa.k + 1] - colptr[pa.k];
+        if (lane == 0) {
+          pa.raw = kraw_t[pa.k];
+          pa.before =
+              __hip_atomic_fetch_add(&d.long_acc[pa.slot], piece_sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        has_a = true;
+      }
     }
     wave_lds_fence();  // this item's LDS reads are done before the next park
     cur = nxt;
     nxt = nx2;
+  }
+  if (FUSE) {
+    advance();
+    advance();
   }
   fold_block_stats(r, l1, cs, sr, mx, sh_red);
 }
@@ -1046,7 +1110,7 @@ __global__ __launch_bounds__(BLOCK, 5) void k_complete(Dev d, long long s, int i
     };
     // what the sources send was written by select (zero off the green set;
     // links outside [0, N) are ignored)
-    wave_pull<T, T, VAL, true, RP>(d, (const T *)d.src, Cc, keep, off, Cn, nxt);
+    wave_pull<T, T, VAL, true, RP, true>(d, (const T *)d.src, Cc, keep, off, Cn, nxt);
   }
 
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1065,8 +1129,8 @@ __global__ __launch_bounds__(BLOCK, 5) void k_complete(Dev d, long long s, int i
   }
 }
 
-// Completes the columns with more than CH in-links once all their pieces
-// have been added to long_acc: x_k = kept(k) + c * acc + off, then resets
+// Completes the long columns once all their pieces have been added to
+// long_acc: x_k = kept(k) + c * acc + off, then resets
 // long_acc for the next pass and folds the statistics of the x_k.
 // kept(k, q) may use what the caller loaded ahead for the column at q.
 template <class T, class Kept>
@@ -1082,30 +1146,6 @@ __device__ __forceinline__ void long_finish(const Dev &d, Kept kept, double off,
     fold_stats((double)x, d.r, l1, cs, sr, mx);
   }
   fold_block_stats(r, l1, cs, sr, mx, sh_red);
-}
-
-template <class T>
-__global__ __launch_bounds__(BLOCK) void k_complete_long(Dev d, long long s, int init) {
-  Rec *cur = &d.rec[s % 3];
-  // the cash of this thread's first long column is loaded before the step's
-  // records are read (it depends on none of their values)
-  const T *__restrict__ Cc = (const T *)d.cash[cur->buf];
-  const int q0 = blockIdx.x * BLOCK + threadIdx.x;
-  const T v0 = (q0 < d.n_long) ? Cc[d.long_cols[q0]] : T(0);
-  if (d.glob->status != 0) return;
-  if (cur->mode != 1) return;
-  Rec *nxt = &d.rec[(s + 1) % 3];
-  __shared__ Tot sh_tot;
-  const Tot tot = read_totals(cur, &sh_tot);
-  const int sched = init ? SCHED_ALL : d.sched;
-  const double theta = cur->theta, tau = cur->topk_tau, maxabs = tot.maxabs;
-  const int tie_id = cur->topk_tie_id;
-  auto kept = [&](int k, int q) -> double {
-    const T v = (q == q0) ? v0 : Cc[k];
-    if (init) return -(double)v;
-    return is_green(v, k, sched, theta, maxabs, tau, tie_id, d.seed, s, d.green_in) ? 0.0 : (double)v;
-  };
-  long_finish<T>(d, kept, tot.T / (double)d.n, (T *)d.cash[cur->buf ^ 1], nxt);
 }
 
 template <class T, int HK>
@@ -1257,7 +1297,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_refresh(Dev d, long long t, int ou
   const int n = d.n;
   const double off = d.glob->rpool / (double)n;
   auto keep = [&](T, int k) -> double { return -hist_at<HK>(d, k); };
-  wave_pull<T, double, VAL, false, RP>(d, d.rsrc, (const T *)nullptr, keep, off, (T *)d.cash[out_buf], cur);
+  wave_pull<T, double, VAL, false, RP, false>(d, d.rsrc, (const T *)nullptr, keep, off, (T *)d.cash[out_buf], cur);
 }
 
 // Clears an FP64 array (the push accumulators after the refresh used them).
@@ -1311,7 +1351,10 @@ __global__ __launch_bounds__(BLOCK) void k_reset(Dev d) {
     d.glob->ticket = 0u;
     d.glob->rpool = 0.0;
   }
-  for (int q = blockIdx.x * BLOCK + threadIdx.x; q < d.n_long; q += gridDim.x * BLOCK) d.long_acc[q] = 0.0;
+  for (int q = blockIdx.x * BLOCK + threadIdx.x; q < d.n_long; q += gridDim.x * BLOCK) {
+    d.long_acc[q] = 0.0;
+    if (d.long_cnt) d.long_cnt[q] = 0;
+  }
   for (int q = blockIdx.x * BLOCK + threadIdx.x; q < LOG_STEPS; q += gridDim.x * BLOCK) {
     d.log[q].s = -1;
     d.log[q].gedges = 0;
@@ -1462,8 +1505,6 @@ template __global__ void k_complete<double, false, false>(Dev, long long, int);
 template __global__ void k_complete<double, false, true>(Dev, long long, int);
 template __global__ void k_complete<double, true, false>(Dev, long long, int);
 template __global__ void k_complete<double, true, true>(Dev, long long, int);
-template __global__ void k_complete_long<float>(Dev, long long, int);
-template __global__ void k_complete_long<double>(Dev, long long, int);
 template __global__ void k_refresh_long<float, 0>(Dev, long long, int);
 template __global__ void k_refresh_long<float, 1>(Dev, long long, int);
 template __global__ void k_refresh_long<double, 0>(Dev, long long, int);
