@@ -814,58 +814,54 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
   const int4 none = make_int4(-1, 0, 0, 0);
 
   // registers of the item fetched ahead
-  int pr[WU], pc[NCP];
-  unsigned int pk[NK];
+  int pr[WU] = {}, pc[NCP] = {};
+  unsigned int pk[NK] = {};
   // The item is the same for the whole wave (scalar registers); every lane
-  // loads at an index clamped into the item, then lanes past its end take
-  // the fill value, so no load sits behind a per-lane branch.
+  // loads at an index clamped into the item, so no load sits behind a
+  // per-lane branch, and the lanes past the item's end take their fill
+  // value only when the item is parked (a select at fetch time would wait
+  // for the loads there).
+  // Every fetch sends the same loads whatever the item (an empty item reads
+  // the first column pointer, which every graph has), so the waits below
+  // count exactly the loads sent after the ones they wait for.
   auto fetch = [&](int4 item) {
     // item-relative bases (uniform) keep the per-lane offsets 32-bit
-    const int p0 = item.z, ne = item.w - item.z;
-    if (ne > 0) {
-      const int *__restrict__ rows = crow + p0;
+    const int ne = item.w - item.z;
+    const int *__restrict__ rows = (ne > 0) ? crow + item.z : colptr;
+    const int elast = max(ne - 1, 0);
 #pragma unroll
-      for (int u = 0; u < WU; ++u) {
-        const int e = u * 64 + lane;
-        const int v = rows[(unsigned int)min(e, ne - 1)];
-        pr[u] = (e < ne) ? v : -1;
-      }
-    } else {
+    for (int u = 0; u < WU; ++u) pr[u] = rows[(unsigned int)min(u * 64 + lane, elast)];
+    const bool run = item.x >= 0;  // a run: 1 <= ncol <= WCOLS
+    const int k0 = run ? item.x : 0, ncol = run ? item.y - item.x : 0;
+    const int *__restrict__ cps = colptr + k0;
 #pragma unroll
-      for (int u = 0; u < WU; ++u) pr[u] = -1;
-    }
-    const int k0 = item.x, ncol = item.y - item.x;
-    if (item.x >= 0) {  // a run: 1 <= ncol <= WCOLS
-      const int *__restrict__ cps = colptr + k0;
+    for (int q = 0; q < NCP; ++q) pc[q] = cps[(unsigned int)min(q * 64 + lane, ncol)];
+    if (STAGEK) {
+      const unsigned int *__restrict__ kws = kw + (size_t)k0 * KW;
+      const int klast = max(ncol * KW - 1, 0);
 #pragma unroll
-      for (int q = 0; q < NCP; ++q) {
-        const int j = q * 64 + lane;
-        const int v = cps[(unsigned int)min(j, ncol)];
-        pc[q] = (j <= ncol) ? v - p0 : 0;
-      }
-      if (STAGEK) {
-        const unsigned int *__restrict__ kws = kw + (size_t)k0 * KW;
-#pragma unroll
-        for (int q = 0; q < NK; ++q) {
-          const int j = q * 64 + lane;
-          const unsigned int v = kws[(unsigned int)min(j, ncol * KW - 1)];
-          pk[q] = (j < ncol * KW) ? v : 0u;
-        }
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < NCP; ++q) pc[q] = 0;
-      if (STAGEK) {
-#pragma unroll
-        for (int q = 0; q < NK; ++q) pk[q] = 0u;
-      }
+      for (int q = 0; q < NK; ++q) pk[q] = kws[(unsigned int)min(q * 64 + lane, klast)];
     }
   };
-  auto item_at = [&](int i) -> int4 {
-    if (i >= n_items) return none;
-    const int4 v = d.items[i];
-    return make_int4(__builtin_amdgcn_readfirstlane(v.x), __builtin_amdgcn_readfirstlane(v.y),
-                     __builtin_amdgcn_readfirstlane(v.z), __builtin_amdgcn_readfirstlane(v.w));
+  // The wave's items of 64 consecutive rounds are loaded at once, lane r
+  // holding round base + r, and each round's item is read out of its lane
+  // into scalar registers: no round waits for an item load (a per-round load
+  // would have to be waited for together with the vector loads before it).
+  const int it0 = (int)blockIdx.x * NWAVE + wv;
+  int4 ilist = none;
+  int ibase = 0;
+  auto load_items = [&](int round0) {
+    const int i = it0 + (round0 + lane) * stride;
+    ilist = (i < n_items) ? d.items[i] : none;
+    ibase = round0;
+    // wait here, on this rare path, not where the rounds read the list
+    asm volatile("" : "+v"(ilist.x), "+v"(ilist.y), "+v"(ilist.z), "+v"(ilist.w));
+  };
+  auto item_of = [&](int round) -> int4 {
+    if (round - ibase >= 64) load_items(round);
+    const int r = round - ibase;
+    return make_int4(__builtin_amdgcn_readlane(ilist.x, r), __builtin_amdgcn_readlane(ilist.y, r),
+                     __builtin_amdgcn_readlane(ilist.z, r), __builtin_amdgcn_readlane(ilist.w, r));
   };
 
   // FUSE: the piece that brings its column's link count (long_cnt) to the
@@ -905,9 +901,9 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
     }
   };
 
-  int it = (int)blockIdx.x * NWAVE + wv;
-  int4 cur = item_at(it);
-  int4 nxt = item_at(it + stride);
+  int it = it0, round = 0;
+  load_items(0);
+  int4 cur = item_of(0);
   // an item the plan cannot have built is skipped whole
   auto valid = [&](int4 item) {
     const int ne = item.w - item.z;
@@ -915,19 +911,21 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
     return item.x < 0 || (item.y - item.x >= 1 && item.y - item.x <= WCOLS);
   };
   if (it < n_items) fetch(valid(cur) ? cur : none);
-  for (; it < n_items; it += stride) {
+  for (; it < n_items; it += stride, ++round) {
     // park the fetched item in LDS, then send the next one's loads
-#pragma unroll
-    for (int u = 0; u < WU; ++u) row[u * 64 + lane] = pr[u];
-#pragma unroll
-    for (int q = 0; q < NCP; ++q) cp[q * 64 + lane] = pc[q];
-    if (STAGEK) {
-#pragma unroll
-      for (int q = 0; q < NK; ++q) kr[q * 64 + lane] = pk[q];
-    }
     const int4 item = valid(cur) ? cur : none;
-    if (it + stride < n_items) fetch(valid(nxt) ? nxt : none);
-    const int4 nx2 = item_at(it + 2 * stride);
+    {
+      const int p0 = item.z, ne = item.w - item.z, ncol = item.y - item.x;
+      const bool run = item.x >= 0;
+#pragma unroll
+      for (int u = 0; u < WU; ++u) row[u * 64 + lane] = (u * 64 + lane < ne) ? pr[u] : -1;
+#pragma unroll
+      for (int q = 0; q < NCP; ++q) cp[q * 64 + lane] = (run && q * 64 + lane <= ncol) ? pc[q] - p0 : 0;
+      if (STAGEK) {
+#pragma unroll
+        for (int q = 0; q < NK; ++q) kr[q * 64 + lane] = (run && q * 64 + lane < ncol * KW) ? pk[q] : 0u;
+      }
+    }
     wave_lds_fence();
     const int ne = item.w - item.z;
     int jj[WU];
@@ -938,23 +936,38 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
       jj[4] = b.x; jj[5] = b.y; jj[6] = b.z; jj[7] = b.w;
     }
     static_assert(WU == 8, "lane loads below assume 8 links per lane");
-    S x[WU];
+    // The item's gathers (and stored link values) are sent before the next
+    // item's loads: loads complete in the order they were sent, so waiting
+    // for the gathers then never waits for the next item's stream.
+    S xr[WU];
+    bool ok[WU];
 #pragma unroll
     for (int u = 0; u < WU; ++u) {
       // jj is -1 past the item's end; links outside [0, N) send nothing
       const unsigned int j = (unsigned int)jj[u];
-      const bool ok = j < (unsigned int)n;
-      const S v = src[ok ? j : 0u];
-      x[u] = ok ? v : S(0);
+      ok[u] = j < (unsigned int)n;
+      xr[u] = src[ok[u] ? j : 0u];
     }
-    double w[WU];
+    T wr[WU];
     const T *__restrict__ vals = cval + (VAL ? item.z : 0);
+    if (VAL && ne > 0) {
+#pragma unroll
+      for (int u = 0; u < WU; ++u) wr[u] = vals[(unsigned int)min(e0 + u, ne - 1)];
+    }
+    asm volatile("" ::: "memory");
+    // the next round's item (none past the end: its loads read element 0)
+    const int4 nxt = item_of(round + 1);
+    fetch(valid(nxt) ? nxt : none);
+    S x[WU];
+    double w[WU];
 #pragma unroll
     for (int u = 0; u < WU; ++u) {
+      asm volatile("" : "+v"(xr[u]));  // the wait for the gather stays here
+      x[u] = ok[u] ? xr[u] : S(0);
       w[u] = 1.0;
       if (VAL && ne > 0) {
-        const double v = (double)vals[(unsigned int)min(e0 + u, ne - 1)];
-        w[u] = (e0 + u < ne) ? v : 1.0;
+        asm volatile("" : "+v"(wr[u]));
+        w[u] = (e0 + u < ne) ? (double)wr[u] : 1.0;
       }
     }
     if (item.x >= 0) {
@@ -1048,7 +1061,6 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
     }
     wave_lds_fence();  // this item's LDS reads are done before the next park
     cur = nxt;
-    nxt = nx2;
   }
   if (FUSE) {
     advance();
