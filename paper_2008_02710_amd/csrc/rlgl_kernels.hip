@@ -778,6 +778,21 @@ __device__ __forceinline__ void seg_scan_step(double &v, int &f) {
   f |= yf;
 }
 
+// Sum over the wave through DPP moves, the same in every lane.
+__device__ __forceinline__ double wave_total_f64(double v) {
+  v += dpp_f64<DPP_ROW_SHR1, 0xF>(v);
+  v += dpp_f64<DPP_ROW_SHR2, 0xF>(v);
+  v += dpp_f64<DPP_ROW_SHR4, 0xF>(v);
+  v += dpp_f64<DPP_ROW_SHR8, 0xF>(v);
+  v += dpp_f64<DPP_ROW_BCAST15, 0xA>(v);
+  v += dpp_f64<DPP_ROW_BCAST31, 0xC>(v);
+  // lane 63 now holds the total
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned int lo = (unsigned int)__builtin_amdgcn_readlane((int)(unsigned int)b, 63);
+  const unsigned int hi = (unsigned int)__builtin_amdgcn_readlane((int)(unsigned int)(b >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __device__ __forceinline__ void wave_lds_fence() {
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
   __builtin_amdgcn_wave_barrier();
@@ -794,7 +809,7 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
   __shared__ int s_row[NWAVE][WL];
   __shared__ int s_cp[NWAVE][NCP * 64];
   __shared__ unsigned int s_kr[NWAVE][NK * 64];
-  __shared__ double s_sum[NWAVE][WCOLS];
+  __shared__ double s_sum[NWAVE][WCOLS + 64];
   __shared__ double sh_red[4 * NWAVE];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
@@ -994,22 +1009,21 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
       // Walk the lane's links: the sum up to its first column end is the
       // head of that column (f), later ends close columns that lie wholly in
       // the lane; links past ne send 0 and end no column.
+      // Branch-free: a link that closes no column inside the lane stores to
+      // the lane's own spare slot (sum[WCOLS + lane]).
       double acc = 0.0, head = 0.0;
       int ended = 0, f = 0;
 #pragma unroll
       for (int u = 0; u < WU; ++u) {
         acc += (double)x[u] * w[u];
         const int q = ec[u];
-        if (q >= 0) {
-          if (ended) {
-            sum[q] = acc;
-          } else {
-            head = acc;
-            f = q;
-          }
-          ended = 1;
-          acc = 0.0;
-        }
+        const bool e = q >= 0;
+        sum[(e && ended) ? q : WCOLS + lane] = acc;
+        const bool first = e && !ended;
+        head = first ? acc : head;
+        f = first ? q : f;
+        ended |= (int)e;
+        acc = e ? 0.0 : acc;
       }
       // inclusive segmented scan of the trailing sums (a lane with a column
       // end starts a segment); its exclusive value is the carry
@@ -1035,8 +1049,7 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
       double acc = 0.0;
 #pragma unroll
       for (int u = 0; u < WU; ++u) acc += (double)x[u] * w[u];
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+      acc = wave_total_f64(acc);
       if (!FUSE) {
         if (lane == 0) atomic_add_f64(&d.long_acc[-1 - item.x], acc);
       } else {
@@ -1072,7 +1085,7 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
 // ----------------------------------------------------------------- complete
 
 template <class T, bool VAL, bool RP>
-__global__ __launch_bounds__(BLOCK, 5) void k_complete(Dev d, long long s, int init) {
+__global__ __launch_bounds__(BLOCK, 4) void k_complete(Dev d, long long s, int init) {
   Glob *g = d.glob;
   if (g->status != 0) return;
   Rec *cur = &d.rec[s % 3];
