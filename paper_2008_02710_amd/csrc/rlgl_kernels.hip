@@ -1039,7 +1039,8 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
       if (ended) sum[f] = carry + head;
       wave_lds_fence();
       T *__restrict__ outs = out + k0;
-      for (int q = lane; q < ncol; q += 64) {
+      if (lane < ncol) {  // ncol <= WCOLS <= 64: one column per lane
+        const int q = lane;
         const double kv = STAGEK ? keep(((const T *)kr)[q], k0 + q) : keep(T(0), k0 + q);
         const T y = (T)(kv + c * sum[q] + off);
         outs[(unsigned)q] = y;
