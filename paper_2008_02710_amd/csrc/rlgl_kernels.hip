@@ -943,14 +943,13 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
     }
     wave_lds_fence();
     const int ne = item.w - item.z;
+    static_assert(WU % 4 == 0, "lanes read their links four at a time");
     int jj[WU];
-    {
-      const int4 a = *(const int4 *)&row[e0];
-      const int4 b = *(const int4 *)&row[e0 + 4];
-      jj[0] = a.x; jj[1] = a.y; jj[2] = a.z; jj[3] = a.w;
-      jj[4] = b.x; jj[5] = b.y; jj[6] = b.z; jj[7] = b.w;
+#pragma unroll
+    for (int h = 0; h < WU; h += 4) {
+      const int4 a = *(const int4 *)&row[e0 + h];
+      jj[h] = a.x; jj[h + 1] = a.y; jj[h + 2] = a.z; jj[h + 3] = a.w;
     }
-    static_assert(WU == 8, "lane loads below assume 8 links per lane");
     // The item's gathers (and stored link values) are sent before the next
     // item's loads: loads complete in the order they were sent, so waiting
     // for the gathers then never waits for the next item's stream.
@@ -991,8 +990,8 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
       // index (row[] is free once jj holds this lane's sources; LDS
       // operations of one wave take effect in program order).
       static_assert(WCOLS <= 64, "one lane per column of a run");
-      *(int4 *)&row[e0] = make_int4(-1, -1, -1, -1);
-      *(int4 *)&row[e0 + 4] = make_int4(-1, -1, -1, -1);
+#pragma unroll
+      for (int h = 0; h < WU; h += 4) *(int4 *)&row[e0 + h] = make_int4(-1, -1, -1, -1);
       if (lane < ncol) {
         sum[lane] = 0.0;  // stays 0 for a column without in-links
         const int b0 = cp[lane], b1 = cp[lane + 1];
@@ -1000,11 +999,10 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
       }
       wave_lds_fence();
       int ec[WU];
-      {
-        const int4 a = *(const int4 *)&row[e0];
-        const int4 b = *(const int4 *)&row[e0 + 4];
-        ec[0] = a.x; ec[1] = a.y; ec[2] = a.z; ec[3] = a.w;
-        ec[4] = b.x; ec[5] = b.y; ec[6] = b.z; ec[7] = b.w;
+#pragma unroll
+      for (int h = 0; h < WU; h += 4) {
+        const int4 a = *(const int4 *)&row[e0 + h];
+        ec[h] = a.x; ec[h + 1] = a.y; ec[h + 2] = a.z; ec[h + 3] = a.w;
       }
       // Walk the lane's links: the sum up to its first column end is the
       // head of that column (f), later ends close columns that lie wholly in
