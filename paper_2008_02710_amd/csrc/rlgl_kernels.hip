@@ -565,6 +565,50 @@ __global__ void k_indegree(Dev d, int *indeg) {
 // sums meet in long_acc; a later pass completes those columns (a
 // last-workgroup ticket would cost every workgroup a device-scope fence).
 
+// Lane moves through DPP (the GFX9 encodings): row_shr:n shifts inside each
+// row of 16 lanes, row_bcast:15 hands a row's last lane to the next row,
+// row_bcast:31 hands lane 31 to rows 2 and 3, wave_shr:1 shifts the whole
+// wave by one lane.  A lane with no source, or in a row the mask leaves out,
+// reads 0.
+constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114, DPP_ROW_SHR8 = 0x118;
+constexpr int DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143, DPP_WAVE_SHR1 = 0x138;
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, true);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned int lo = (unsigned int)dpp_i32<CTRL, ROWS>((int)(unsigned int)b);
+  const unsigned int hi = (unsigned int)dpp_i32<CTRL, ROWS>((int)(unsigned int)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// One step of a segmented inclusive sum over the wave: the value from the
+// lane the move names is added unless this lane already starts a segment.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_scan_step(double &v, int &f) {
+  const double yv = dpp_f64<CTRL, ROWS>(v);
+  const int yf = dpp_i32<CTRL, ROWS>(f);
+  if (!f) v += yv;
+  f |= yf;
+}
+
+// Sum over the wave through DPP moves, the same in every lane.
+__device__ __forceinline__ double wave_total_f64(double v) {
+  v += dpp_f64<DPP_ROW_SHR1, 0xF>(v);
+  v += dpp_f64<DPP_ROW_SHR2, 0xF>(v);
+  v += dpp_f64<DPP_ROW_SHR4, 0xF>(v);
+  v += dpp_f64<DPP_ROW_SHR8, 0xF>(v);
+  v += dpp_f64<DPP_ROW_BCAST15, 0xA>(v);
+  v += dpp_f64<DPP_ROW_BCAST31, 0xC>(v);
+  // lane 63 now holds the total
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned int lo = (unsigned int)__builtin_amdgcn_readlane((int)(unsigned int)b, 63);
+  const unsigned int hi = (unsigned int)__builtin_amdgcn_readlane((int)(unsigned int)(b >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 struct Seg {
   double v;
   int f;  // a column starts inside the span
@@ -614,6 +658,9 @@ __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved m
   auto weight = [&](int p, int j) -> double {
     return unit ? 1.0 : (cval ? (double)cval[p] : inv_outdeg(g.rowptr, g.n, j));
   };
+  // the item is the same for the whole workgroup: scalar registers
+  item = make_int4(__builtin_amdgcn_readfirstlane(item.x), __builtin_amdgcn_readfirstlane(item.y),
+                   __builtin_amdgcn_readfirstlane(item.z), __builtin_amdgcn_readfirstlane(item.w));
   if (item.x >= 0) {
     // RUN: every load below depends on the item alone
     const int k0 = item.x, k1 = item.y, p0 = item.z, p1 = item.w;
@@ -664,17 +711,15 @@ __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved m
       loc[u] = run.v;
     }
     Seg inc = run;
-    for (int o = 1; o < 64; o <<= 1) {
-      Seg y;
-      y.v = __shfl_up(inc.v, o, 64);
-      y.f = __shfl_up(inc.f, o, 64);
-      if (lane >= o) inc = seg_op(y, inc);
-    }
+    seg_scan_step<DPP_ROW_SHR1, 0xF>(inc.v, inc.f);
+    seg_scan_step<DPP_ROW_SHR2, 0xF>(inc.v, inc.f);
+    seg_scan_step<DPP_ROW_SHR4, 0xF>(inc.v, inc.f);
+    seg_scan_step<DPP_ROW_SHR8, 0xF>(inc.v, inc.f);
+    seg_scan_step<DPP_ROW_BCAST15, 0xA>(inc.v, inc.f);
+    seg_scan_step<DPP_ROW_BCAST31, 0xC>(inc.v, inc.f);
     if (lane == 63) L.wave[wv] = inc;
-    Seg ex;
-    ex.v = __shfl_up(inc.v, 1, 64);
-    ex.f = __shfl_up(inc.f, 1, 64);
-    if (lane == 0) ex = Seg{0.0, 0};
+    // exclusive value: the inclusive one of the lane before (lane 0 reads 0)
+    const Seg ex{dpp_f64<DPP_WAVE_SHR1, 0xF>(inc.v), dpp_i32<DPP_WAVE_SHR1, 0xF>(inc.f)};
     __syncthreads();
     Seg wbase{0.0, 0};
     for (int q = 0; q < wv; ++q) wbase = seg_op(wbase, L.wave[q]);
@@ -749,50 +794,6 @@ __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved m
 // across the lanes, whose exclusive value is that carry.  Then the lanes write the item's columns, consecutive lanes to
 // consecutive columns: x_k = kept(k) + c * sum_k + off (columns without
 // in-links have sum 0).
-// Lane moves through DPP (the GFX9 encodings): row_shr:n shifts inside each
-// row of 16 lanes, row_bcast:15 hands a row's last lane to the next row,
-// row_bcast:31 hands lane 31 to rows 2 and 3, wave_shr:1 shifts the whole
-// wave by one lane.  A lane with no source, or in a row the mask leaves out,
-// reads 0.
-constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114, DPP_ROW_SHR8 = 0x118;
-constexpr int DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143, DPP_WAVE_SHR1 = 0x138;
-
-template <int CTRL, int ROWS>
-__device__ __forceinline__ int dpp_i32(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, true);
-}
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const unsigned int lo = (unsigned int)dpp_i32<CTRL, ROWS>((int)(unsigned int)b);
-  const unsigned int hi = (unsigned int)dpp_i32<CTRL, ROWS>((int)(unsigned int)(b >> 32));
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-// One step of a segmented inclusive sum over the wave: the value from the
-// lane the move names is added unless this lane already starts a segment.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ void seg_scan_step(double &v, int &f) {
-  const double yv = dpp_f64<CTRL, ROWS>(v);
-  const int yf = dpp_i32<CTRL, ROWS>(f);
-  if (!f) v += yv;
-  f |= yf;
-}
-
-// Sum over the wave through DPP moves, the same in every lane.
-__device__ __forceinline__ double wave_total_f64(double v) {
-  v += dpp_f64<DPP_ROW_SHR1, 0xF>(v);
-  v += dpp_f64<DPP_ROW_SHR2, 0xF>(v);
-  v += dpp_f64<DPP_ROW_SHR4, 0xF>(v);
-  v += dpp_f64<DPP_ROW_SHR8, 0xF>(v);
-  v += dpp_f64<DPP_ROW_BCAST15, 0xA>(v);
-  v += dpp_f64<DPP_ROW_BCAST31, 0xC>(v);
-  // lane 63 now holds the total
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const unsigned int lo = (unsigned int)__builtin_amdgcn_readlane((int)(unsigned int)b, 63);
-  const unsigned int hi = (unsigned int)__builtin_amdgcn_readlane((int)(unsigned int)(b >> 32), 63);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
 __device__ __forceinline__ void wave_lds_fence() {
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
   __builtin_amdgcn_wave_barrier();
