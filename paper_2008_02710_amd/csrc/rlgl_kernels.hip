@@ -669,11 +669,20 @@ __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved m
     __syncthreads();
     int jj[U];
     double ww[U];
+    // loads clamped into the item (no per-thread branch); past its end the
+    // source is -1 and the weight 0
+    const int elast = max(ne - 1, 0);
+    const int *__restrict__ rows = (ne > 0) ? crow + p0 : colptr;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = u * NT + tid;
-      jj[u] = (e < ne) ? crow[p0 + e] : -1;
-      ww[u] = (e < ne && cval && !unit) ? (double)cval[p0 + e] : 0.0;
+      const int j = rows[min(e, elast)];
+      jj[u] = (e < ne) ? j : -1;
+      ww[u] = 0.0;
+      if (cval && !unit && ne > 0) {
+        const double v = (double)cval[p0 + min(e, elast)];
+        ww[u] = (e < ne) ? v : 0.0;
+      }
     }
     double kv[KC];
 #pragma unroll

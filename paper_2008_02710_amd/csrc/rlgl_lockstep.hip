@@ -209,8 +209,11 @@ __device__ __forceinline__ void ls_item(const LsArgs &a, int k, int mode, int lo
   column_item<T, NT>(
       g, item,
       [&](int j) -> double {
-        if ((unsigned)j >= (unsigned)n) return 0.0;
-        return refresh ? hs[j] : (double)src[j];
+        // a load at a clamped index and a select, not a branch per link
+        const bool ok = (unsigned)j < (unsigned)n;
+        const unsigned int jc = ok ? (unsigned int)j : 0u;
+        const double v = refresh ? hs[jc] : (double)src[jc];
+        return ok ? v : 0.0;
       },
       [&](int kk) -> double {
         if (init) return -m0;
