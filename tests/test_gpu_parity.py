@@ -533,3 +533,42 @@ def test_pull_plan_boundaries(prec, relabel):
     assert st == rl.RLGL_OK
     assert l1(to_np(s.pi), reference(g)) <= tol_solve(prec)
     s.close()
+
+
+def _many_piece_graph():
+    """Long columns cut into many pull pieces: 20000, 5000 and 1537 in-links
+    (40, 10 and 4 pieces, the last one a single link), beside ordinary ones."""
+    rng = np.random.default_rng(7)
+    n = 25000
+    indeg = rng.integers(0, 10, n)
+    indeg[0], indeg[1], indeg[7] = 20000, 5000, 1537
+    dst = np.repeat(np.arange(n), indeg)
+    src = rng.integers(0, n, dst.size)
+    return workloads.from_edges(n, src, dst, 0.85, name="many_pieces")
+
+
+@pytest.mark.parametrize("prec", [rl.FP64, rl.FP32C_FP64H], ids=PREC_NAMES.get)
+@pytest.mark.parametrize("relabel", [0, 1])
+def test_long_columns_many_pieces(prec, relabel):
+    """The column a piece completes is written in the same pass: every step
+    of several in a row against the oracle (a count or sum left over from one
+    pass would show in the next)."""
+    g = _many_piece_graph()
+    deg = np.diff(g.csc()[0])
+    assert deg.max() == 20000 and (deg > 512).sum() >= 3
+    say("case many_pieces", PREC_NAMES[prec], relabel)
+    s = solver(g, prec, route=rl.ROUTE_PULL, sched=rl.SCHED_ALL, record_green=1, relabel=relabel)
+    C0, H0, hs0 = _nontrivial_state(g, prec)
+    s.set_state(torch.from_numpy(C0).cuda(), torch.from_numpy(H0).cuda(), hs0, t=4)
+    for _ in range(4):
+        Cg, Hg, info0 = s.state()
+        Cg, Hg = to_np(Cg), to_np(Hg)
+        ost = oracle.State.from_arrays(oracle_chain(g), Cg, Hg, info0["h_sum"], t=info0["t"])
+        moved = float(np.abs(Cg).sum())
+        s.step(1)
+        ost.step_mask(np.ones(g.n, dtype=bool))
+        C1, _, _ = s.state()
+        err = np.abs(to_np(C1) - ost.C)
+        assert err.sum() <= tol_step(prec) * moved + 1e-300, np.argsort(err)[-5:]
+        assert err[[0, 1, 7]].max() <= tol_step(prec) * moved
+    s.close()
