@@ -32,17 +32,76 @@ namespace rlgl {
 
 // ---------------------------------------------------------------- helpers
 
+// Lane moves through DPP (the GFX9 encodings): row_shr:n shifts inside each
+// row of 16 lanes, row_bcast:15 hands a row's last lane to the next row,
+// row_bcast:31 hands lane 31 to rows 2 and 3, wave_shr:1 shifts the whole
+// wave by one lane.  A lane with no source, or in a row the mask leaves out,
+// reads 0.
+constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114, DPP_ROW_SHR8 = 0x118;
+constexpr int DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143, DPP_WAVE_SHR1 = 0x138;
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, true);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned int lo = (unsigned int)dpp_i32<CTRL, ROWS>((int)(unsigned int)b);
+  const unsigned int hi = (unsigned int)dpp_i32<CTRL, ROWS>((int)(unsigned int)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// One step of a segmented inclusive sum over the wave: the value from the
+// lane the move names is added unless this lane already starts a segment.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_scan_step(double &v, int &f) {
+  const double yv = dpp_f64<CTRL, ROWS>(v);
+  const int yf = dpp_i32<CTRL, ROWS>(f);
+  if (!f) v += yv;
+  f |= yf;
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ long long dpp_i64(long long v) {
+  const unsigned long long b = (unsigned long long)v;
+  const unsigned int lo = (unsigned int)dpp_i32<CTRL, ROWS>((int)(unsigned int)b);
+  const unsigned int hi = (unsigned int)dpp_i32<CTRL, ROWS>((int)(unsigned int)(b >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ unsigned long long lane63_u64(unsigned long long b) {
+  const unsigned int lo = (unsigned int)__builtin_amdgcn_readlane((int)(unsigned int)b, 63);
+  const unsigned int hi = (unsigned int)__builtin_amdgcn_readlane((int)(unsigned int)(b >> 32), 63);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Wave reductions through DPP moves (a lane with no source reads 0, so
+// wave_max is for non-negative values); every lane receives the result.
 __device__ __forceinline__ double wave_sum(double x) {
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
+  x += dpp_f64<DPP_ROW_SHR1, 0xF>(x);
+  x += dpp_f64<DPP_ROW_SHR2, 0xF>(x);
+  x += dpp_f64<DPP_ROW_SHR4, 0xF>(x);
+  x += dpp_f64<DPP_ROW_SHR8, 0xF>(x);
+  x += dpp_f64<DPP_ROW_BCAST15, 0xA>(x);
+  x += dpp_f64<DPP_ROW_BCAST31, 0xC>(x);
+  return __longlong_as_double((long long)lane63_u64((unsigned long long)__double_as_longlong(x)));
 }
 __device__ __forceinline__ double wave_max(double x) {
-  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
-  return x;
+  x = fmax(x, dpp_f64<DPP_ROW_SHR1, 0xF>(x));
+  x = fmax(x, dpp_f64<DPP_ROW_SHR2, 0xF>(x));
+  x = fmax(x, dpp_f64<DPP_ROW_SHR4, 0xF>(x));
+  x = fmax(x, dpp_f64<DPP_ROW_SHR8, 0xF>(x));
+  x = fmax(x, dpp_f64<DPP_ROW_BCAST15, 0xA>(x));
+  x = fmax(x, dpp_f64<DPP_ROW_BCAST31, 0xC>(x));
+  return __longlong_as_double((long long)lane63_u64((unsigned long long)__double_as_longlong(x)));
 }
 __device__ __forceinline__ long long wave_sum_ll(long long x) {
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
+  x += dpp_i64<DPP_ROW_SHR1, 0xF>(x);
+  x += dpp_i64<DPP_ROW_SHR2, 0xF>(x);
+  x += dpp_i64<DPP_ROW_SHR4, 0xF>(x);
+  x += dpp_i64<DPP_ROW_SHR8, 0xF>(x);
+  x += dpp_i64<DPP_ROW_BCAST15, 0xA>(x);
+  x += dpp_i64<DPP_ROW_BCAST31, 0xC>(x);
+  return (long long)lane63_u64((unsigned long long)x);
 }
 
 // Block-wide sums of four doubles; every thread receives the result.
@@ -565,50 +624,6 @@ __global__ void k_indegree(Dev d, int *indeg) {
 // sums meet in long_acc; a later pass completes those columns (a
 // last-workgroup ticket would cost every workgroup a device-scope fence).
 
-// Lane moves through DPP (the GFX9 encodings): row_shr:n shifts inside each
-// row of 16 lanes, row_bcast:15 hands a row's last lane to the next row,
-// row_bcast:31 hands lane 31 to rows 2 and 3, wave_shr:1 shifts the whole
-// wave by one lane.  A lane with no source, or in a row the mask leaves out,
-// reads 0.
-constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114, DPP_ROW_SHR8 = 0x118;
-constexpr int DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143, DPP_WAVE_SHR1 = 0x138;
-
-template <int CTRL, int ROWS>
-__device__ __forceinline__ int dpp_i32(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, true);
-}
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const unsigned int lo = (unsigned int)dpp_i32<CTRL, ROWS>((int)(unsigned int)b);
-  const unsigned int hi = (unsigned int)dpp_i32<CTRL, ROWS>((int)(unsigned int)(b >> 32));
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-// One step of a segmented inclusive sum over the wave: the value from the
-// lane the move names is added unless this lane already starts a segment.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ void seg_scan_step(double &v, int &f) {
-  const double yv = dpp_f64<CTRL, ROWS>(v);
-  const int yf = dpp_i32<CTRL, ROWS>(f);
-  if (!f) v += yv;
-  f |= yf;
-}
-
-// Sum over the wave through DPP moves, the same in every lane.
-__device__ __forceinline__ double wave_total_f64(double v) {
-  v += dpp_f64<DPP_ROW_SHR1, 0xF>(v);
-  v += dpp_f64<DPP_ROW_SHR2, 0xF>(v);
-  v += dpp_f64<DPP_ROW_SHR4, 0xF>(v);
-  v += dpp_f64<DPP_ROW_SHR8, 0xF>(v);
-  v += dpp_f64<DPP_ROW_BCAST15, 0xA>(v);
-  v += dpp_f64<DPP_ROW_BCAST31, 0xC>(v);
-  // lane 63 now holds the total
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const unsigned int lo = (unsigned int)__builtin_amdgcn_readlane((int)(unsigned int)b, 63);
-  const unsigned int hi = (unsigned int)__builtin_amdgcn_readlane((int)(unsigned int)(b >> 32), 63);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
 struct Seg {
   double v;
   int f;  // a column starts inside the span
@@ -1058,7 +1073,7 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
       double acc = 0.0;
 #pragma unroll
       for (int u = 0; u < WU; ++u) acc += (double)x[u] * w[u];
-      acc = wave_total_f64(acc);
+      acc = wave_sum(acc);
       if (!FUSE) {
         if (lane == 0) atomic_add_f64(&d.long_acc[-1 - item.x], acc);
       } else {
