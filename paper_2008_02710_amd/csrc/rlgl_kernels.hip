@@ -804,20 +804,21 @@ __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved m
 //
 // The loads of an item (its CSC sources, column pointers and, with STAGEK,
 // the raw cash values its kept part needs) are issued coalesced into
-// registers one item ahead, so they travel while the wave gathers and sums
-// the item before; at the top of the next round they are parked in the
-// wave's LDS.
+// registers one item ahead, right after the current item's gathers, so they
+// travel while the wave sums that item and the wait for the gathers does not
+// include them; at the top of the next round they are parked in the wave's
+// LDS.
 //
 // In a RUN, lane l owns the WU consecutive links [l*WU, l*WU + WU) of the
 // item and gathers what their sources send.  Lane q marks the last link of
 // column q in LDS, so each lane reads which of its links end a column (and
-// which column) with two LDS loads, then walks its links: a column that both
-// starts and ends among them stores its sum at once; the sum of the leading
-// part of its first column (which may have started in an earlier lane) waits
-// for the carry, the sum of the trailing part goes into a segmented scan
-// across the lanes, whose exclusive value is that carry.  Then the lanes write the item's columns, consecutive lanes to
-// consecutive columns: x_k = kept(k) + c * sum_k + off (columns without
-// in-links have sum 0).
+// which column) with WU/4 LDS loads, then walks its links without branches:
+// a column that both starts and ends among them stores its sum at once; the
+// sum of the leading part of its first column (which may have started in an
+// earlier lane) waits for the carry, the sum of the trailing part goes into
+// a segmented scan across the lanes, whose exclusive value is that carry.
+// Then lane q writes column q of the item: x_k = kept(k) + c * sum_k + off
+// (columns without in-links have sum 0).
 __device__ __forceinline__ void wave_lds_fence() {
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
   __builtin_amdgcn_wave_barrier();
