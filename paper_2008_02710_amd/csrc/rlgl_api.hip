@@ -809,7 +809,7 @@ rlgl_status rlgl_solve(rlgl_ctx *c, double eps, int64_t max_steps, double *dev_p
   k_set_status<<<1, 64, 0, c->stream>>>(c->d.glob, 0);
   HIP_TRY(hipGetLastError());
   const long long s_limit = c->t + max_steps;
-  long long batch = c->check_period > 0 ? c->check_period : (c->d.sched == SCHED_MAXC ? 64 : 4);
+  long long batch = c->check_period > 0 ? c->check_period : (c->d.sched == SCHED_MAXC ? 64 : 8);
   double prev_resid = -1.0;
   long long prev_t = c->t, refreshed_at = -1, last_refresh = c->t;
   int ds = 0;
