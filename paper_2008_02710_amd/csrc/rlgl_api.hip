@@ -47,6 +47,9 @@ rlgl_status fail(rlgl_status st, const char *fmt, ...) {
   } while (0)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+// The workspace places the status word right after the three step records.
+size_t records_bytes() { return align_up(sizeof(Rec) * 3, 256); }
+size_t record_span() { return records_bytes() + sizeof(Glob); }
 
 struct Layout {
   size_t cash0, cash1, hist, hist_lo, fr_rowstart, fr_eoff, fr_id, fr_scale, chunk_first, green_mask, delta, colt,
@@ -264,8 +267,12 @@ hipError_t enqueue_step(rlgl_ctx *c, long long s, double eps, long long s_limit,
 }
 
 rlgl_status read_back(rlgl_ctx *c) {
-  HIP_TRY(hipMemcpyAsync(c->host_glob, c->d.glob, sizeof(Glob), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipMemcpyAsync(c->host_rec, c->d.rec, sizeof(Rec) * 3, hipMemcpyDeviceToHost, c->stream));
+  if ((const char *)c->d.glob == (const char *)c->d.rec + records_bytes()) {
+    HIP_TRY(hipMemcpyAsync(c->host_rec, c->d.rec, record_span(), hipMemcpyDeviceToHost, c->stream));
+  } else {
+    HIP_TRY(hipMemcpyAsync(c->host_glob, c->d.glob, sizeof(Glob), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->host_rec, c->d.rec, sizeof(Rec) * 3, hipMemcpyDeviceToHost, c->stream));
+  }
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->t = c->host_glob->t;
   return RLGL_OK;
@@ -712,9 +719,14 @@ rlgl_status rlgl_create(const rlgl_graph *g, const rlgl_options *o, void *ws, si
   c->grid_misc = std::max(1, std::min((g->n + BLOCK - 1) / BLOCK, NODE_GRID));
 
   rlgl_status st = RLGL_OK;
-  if (hipHostMalloc((void **)&c->host_glob, sizeof(Glob), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void **)&c->host_rec, sizeof(Rec) * 3, hipHostMallocDefault) != hipSuccess) {
+  // one pinned block mirrors the device's records followed by the status
+  // word (their order in the workspace), so a read-back is one copy
+  void *stage = nullptr;
+  if (hipHostMalloc(&stage, record_span(), hipHostMallocDefault) != hipSuccess) {
     st = fail(RLGL_EHIP, "pinned host allocation failed");
+  } else {
+    c->host_rec = (Rec *)stage;
+    c->host_glob = (Glob *)((char *)stage + records_bytes());
   }
   if (st == RLGL_OK) {
     int last = 0;
@@ -755,8 +767,7 @@ void rlgl_destroy(rlgl_ctx *c) {
     (void)hipEventDestroy(L.b);
   }
   for (auto e : c->free_events) (void)hipEventDestroy(e);
-  if (c->host_glob) (void)hipHostFree(c->host_glob);
-  if (c->host_rec) (void)hipHostFree(c->host_rec);
+  if (c->host_rec) (void)hipHostFree(c->host_rec);  // holds host_glob too
   delete c;
 }
 
