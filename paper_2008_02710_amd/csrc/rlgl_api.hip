@@ -159,6 +159,7 @@ struct rlgl_ctx {
   int check_period;
   int refresh;
   long long refreshes;
+  bool stale;  // host_rec / host_glob older than the device's (after a reset)
 };
 
 namespace {
@@ -274,6 +275,7 @@ rlgl_status read_back(rlgl_ctx *c) {
     HIP_TRY(hipMemcpyAsync(c->host_rec, c->d.rec, sizeof(Rec) * 3, hipMemcpyDeviceToHost, c->stream));
   }
   HIP_TRY(hipStreamSynchronize(c->stream));
+  c->stale = false;
   c->t = c->host_glob->t;
   return RLGL_OK;
 }
@@ -305,11 +307,19 @@ rlgl_status reset_device(rlgl_ctx *c) {
   else k_reset<float, 0><<<gr, BLOCK, 0, c->stream>>>(d);
   HIP_TRY(hipGetLastError());
   HIP_TRY(enqueue_step(c, 0, -1.0, 1, 1));  // step 0: all green, M_0 = (1/N) 1
-  return read_back(c);
+  // step 0 always leaves t = 1; the host copies of the records are read
+  // when a call first needs them
+  c->t = 1;
+  c->stale = true;
+  return RLGL_OK;
 }
 
 rlgl_status do_refresh(rlgl_ctx *c) {
   if (!c->d.colptr) return fail(RLGL_EINVAL, "refresh needs the CSC arrays");
+  if (c->stale) {
+    const rlgl_status st = read_back(c);
+    if (st != RLGL_OK) return st;
+  }
   const long long t = c->t;
   const int out = c->host_rec[t % 3].buf ^ 1;
   const Dev &d = c->d;
