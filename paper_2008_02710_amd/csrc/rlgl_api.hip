@@ -314,7 +314,8 @@ rlgl_status reset_device(rlgl_ctx *c) {
   return RLGL_OK;
 }
 
-rlgl_status do_refresh(rlgl_ctx *c) {
+// sync = false leaves the host copies stale (the caller reads back next).
+rlgl_status do_refresh(rlgl_ctx *c, bool sync = true) {
   if (!c->d.colptr) return fail(RLGL_EINVAL, "refresh needs the CSC arrays");
   if (c->stale) {
     const rlgl_status st = read_back(c);
@@ -340,6 +341,10 @@ rlgl_status do_refresh(rlgl_ctx *c) {
   k_refresh_done<<<1, 64, 0, c->stream>>>(d, t, out);
   HIP_TRY(hipGetLastError());
   ++c->refreshes;
+  if (!sync) {
+    c->stale = true;  // the refresh keeps t; the next read-back renews the copies
+    return RLGL_OK;
+  }
   return read_back(c);
 }
 
@@ -845,8 +850,8 @@ rlgl_status rlgl_solve(rlgl_ctx *c, double eps, int64_t max_steps, double *dev_p
     ds = c->host_glob->status;
     if (ds == ST_CONVERGED && c->refresh > 0 && refreshed_at != c->t) {
       // accept the stop only on the cash rebuilt from the history; one step
-      // is enqueued to re-run the stop test on it
-      st = do_refresh(c);
+      // is enqueued to re-run the stop test on it, and read back with it
+      st = do_refresh(c, false);
       if (st != RLGL_OK) return st;
       refreshed_at = last_refresh = c->t;
       batch = 1;
