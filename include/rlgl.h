@@ -191,6 +191,40 @@ rlgl_status rlgl_solve(rlgl_ctx *ctx, double eps, int64_t max_steps, double *dev
  * *info (may be NULL) as for rlgl_step. */
 rlgl_status rlgl_step_mask(rlgl_ctx *ctx, const uint8_t *dev_mask, rlgl_step_info *info);
 
+/* ---- one-workgroup solves --------------------------------------------
+ *
+ * Algorithm 1 from step 0 to its stop test (step (7)) and pi_hat = H / (H 1)
+ * (eq. (2)), for a chain small enough that one workgroup's LDS holds its cash
+ * vector, in ONE kernel launch on `stream`.  Meant for latency-bound chains
+ * (one green node per step in RLGL_MaxC, Sec. 6, takes N-scale step counts).
+ * Rules: RLGL_SCHED_ALL, _THRESHOLD (r, theta_period), _MAXC and _PC; TOPK is
+ * RLGL_EINVAL.  Precision: RLGL_FP64, or FP32 cash (either FP32 option) with
+ * an FP64 history.  With FP64 cash and RLGL_MaxC the cash moves in the order
+ * of the plain serial method (C -= M for the green nodes, their links in
+ * increasing node order, then the uniform restart share), so every green set
+ * and every cash value equal the serial method's.  With FP32 cash and
+ * opt->refresh > 0 a stop is accepted only on C_t = H_t P - H_t rebuilt in
+ * FP64 (eq. (7)).  opt->route, pull_alpha, check_period, record_green and
+ * relabel are ignored.
+ *
+ * g: both the CSR and the CSC are required (device arrays, as for
+ * rlgl_create); n <= rlgl_small_max_n(precision).
+ * dev_workspace: caller-owned device memory of at least
+ * rlgl_small_workspace_bytes(n) bytes (history, moved cash, result record),
+ * overwritten.  dev_pi: n doubles (device, may be NULL), written when the
+ * solve stops on eps (RLGL_OK) or at max_steps (RLGL_ENOT_CONVERGED).
+ * Synchronises `stream` before returning; *info (host, may be NULL) as for
+ * rlgl_solve, with last_route PUSH for a step routed from the green list and
+ * PULL for a column step.  Errors: RLGL_EINVAL (arguments, n above the
+ * capacity, csr_rowptr[n] or csc_colptr[n] != nnz; nothing launched),
+ * RLGL_ENOMEM (workspace too small), RLGL_EHIP, and the solve outcomes
+ * RLGL_ENOT_CONVERGED, RLGL_EZERO_HISTORY, RLGL_ENONFINITE. */
+int32_t rlgl_small_max_n(int32_t precision);
+size_t rlgl_small_workspace_bytes(int32_t n);
+rlgl_status rlgl_solve_small(const rlgl_graph *g, const rlgl_options *opt, double eps, int64_t max_steps,
+                             double *dev_pi, void *dev_workspace, size_t ws_bytes, void *stream,
+                             rlgl_step_info *info);
+
 /* Releases the host context.  Does not touch the caller's device memory. */
 void rlgl_destroy(rlgl_ctx *ctx);
 

@@ -102,7 +102,8 @@ EXPORTED = ["rlgl_default_options", "rlgl_workspace_bytes", "rlgl_create", "rlgl
             "rlgl_pool_default_options", "rlgl_pool_workspace_bytes", "rlgl_pool_footprint", "rlgl_pool_create",
             "rlgl_pool_admit", "rlgl_pool_advance", "rlgl_pool_launch", "rlgl_pool_wait", "rlgl_pool_poll",
             "rlgl_pool_result", "rlgl_pool_release", "rlgl_pool_destroy", "rlgl_validate_scratch_bytes",
-            "rlgl_validate", "rlgl_step_mask"]
+            "rlgl_validate", "rlgl_step_mask", "rlgl_small_max_n", "rlgl_small_workspace_bytes",
+            "rlgl_solve_small"]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -127,6 +128,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rlgl_step_mask.restype = i32
     lib.rlgl_solve.argtypes = [vp, f64, i64, vp, I]
     lib.rlgl_solve.restype = i32
+    lib.rlgl_small_max_n.argtypes = [i32]
+    lib.rlgl_small_max_n.restype = i32
+    lib.rlgl_small_workspace_bytes.argtypes = [i32]
+    lib.rlgl_small_workspace_bytes.restype = ctypes.c_size_t
+    lib.rlgl_solve_small.argtypes = [G, O, f64, i64, vp, vp, ctypes.c_size_t, vp, I]
+    lib.rlgl_solve_small.restype = i32
     lib.rlgl_destroy.argtypes = [vp]
     lib.rlgl_destroy.restype = None
     lib.rlgl_last_error.argtypes = []
@@ -266,6 +273,24 @@ def rlgl_solve(ctx, eps: float, max_steps: int, pi_out=None, raise_on_error: boo
     st = _lib.rlgl_solve(ctx, float(eps), int(max_steps), _ptr(pi_out), ctypes.byref(info))
     if raise_on_error:
         _check(st, "rlgl_solve")
+    return st, info
+
+
+def rlgl_small_max_n(precision: int) -> int:
+    return int(_lib.rlgl_small_max_n(int(precision)))
+
+
+def rlgl_small_workspace_bytes(n: int) -> int:
+    return int(_lib.rlgl_small_workspace_bytes(int(n)))
+
+
+def rlgl_solve_small(graph: rlgl_graph, opt: rlgl_options, eps: float, max_steps: int, pi_out, workspace,
+                     ws_bytes: int, stream=None, raise_on_error: bool = True):
+    info = rlgl_step_info()
+    st = _lib.rlgl_solve_small(ctypes.byref(graph), ctypes.byref(opt), float(eps), int(max_steps), _ptr(pi_out),
+                               _ptr(workspace), int(ws_bytes), _stream_handle(stream), ctypes.byref(info))
+    if raise_on_error:
+        _check(st, "rlgl_solve_small")
     return st, info
 
 
@@ -541,6 +566,27 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+class SmallSolver:
+    """One-workgroup solves of a small chain (rlgl_solve_small): the options,
+    a workspace tensor and an output buffer."""
+
+    def __init__(self, dg: DeviceGraph, stream=None, **options):
+        options.setdefault("precision", dg.precision)
+        self.dg = dg
+        self.graph = dg.struct()
+        self.opt = rlgl_default_options(**options)
+        self.ws_bytes = rlgl_small_workspace_bytes(dg.n)
+        dev = dg.rowptr.device
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        self.stream = stream
+        self.pi = torch.empty(dg.n, dtype=torch.float64, device=dev)
+
+    def solve(self, eps: float, max_steps: int = 1_000_000, raise_on_error: bool = True):
+        st, info = rlgl_solve_small(self.graph, self.opt, eps, max_steps, self.pi, self.workspace, self.ws_bytes,
+                                    self.stream, raise_on_error)
+        return st, info.as_dict()
 
 
 class DeviceBatch:

@@ -23,6 +23,7 @@
 #include "rlgl_batch.hip"
 #include "rlgl_lockstep.hip"
 #include "rlgl_validate.hip"
+#include "rlgl_small.hip"
 
 using namespace rlgl;
 
@@ -353,6 +354,7 @@ rlgl_status status_of(int dev_status) {
     case ST_ZERO_HISTORY: return RLGL_EZERO_HISTORY;
     case ST_NONFINITE: return RLGL_ENONFINITE;
     case ST_LIMIT: return RLGL_ENOT_CONVERGED;
+    case ST_BAD_GRAPH: return RLGL_EINVAL;
     default: return RLGL_OK;
   }
 }
@@ -2100,6 +2102,146 @@ void rlgl_pool_destroy(rlgl_pool *p) {
   if (p->launched) (void)hipEventDestroy(p->launched);
   ls_free(p->E);
   delete p;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------ one-workgroup solves
+
+namespace {
+
+struct SmallLayout {
+  size_t rec, H, Q, total;
+};
+
+SmallLayout small_layout(long long n) {
+  SmallLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes, 256);
+    return at;
+  };
+  L.rec = take(sizeof(SmallRec));
+  L.H = take(8 * (size_t)n);
+  L.Q = take(8 * (size_t)n);
+  L.total = off + 256;  // room to align the caller's pointer
+  return L;
+}
+
+const void *small_kernel(int prec) {
+  return prec == RLGL_FP64 ? (const void *)k_small<double> : (const void *)k_small<float>;
+}
+
+// Largest n whose cash fits in the LDS one workgroup may take on the current
+// device, next to the kernel's own static LDS; 0 when the query fails.
+int small_capacity(int prec) {
+  int dev = 0, lds = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
+  hipFuncAttributes fa{};
+  if (hipFuncGetAttributes(&fa, small_kernel(prec)) != hipSuccess) return 0;
+  const long long dyn = (long long)lds - (long long)fa.sharedSizeBytes - 16;
+  const int cs = prec == RLGL_FP64 ? 8 : 4;
+  return dyn > 0 ? (int)(dyn / cs) : 0;
+}
+
+rlgl_status small_solve(const rlgl_graph *g, const rlgl_options *o, double eps, int64_t max_steps, double *dev_pi,
+                        char *ws, size_t ws_bytes, hipStream_t stream, rlgl_step_info *info) {
+  if (!g || !o) return fail(RLGL_EINVAL, "null argument");
+  std::string why;
+  if (!valid_options(o, why)) return fail(RLGL_EINVAL, "options: %s", why.c_str());
+  if (o->sched == RLGL_SCHED_TOPK) return fail(RLGL_EINVAL, "the one-workgroup solve has no top-k rule");
+  if (g->n < 1) return fail(RLGL_EINVAL, "n must be >= 1");
+  if (g->nnz < 0 || g->nnz >= (1ll << 31)) return fail(RLGL_EINVAL, "nnz must be in [0, 2^31)");
+  if (!(g->damping > 0.0 && g->damping <= 1.0)) return fail(RLGL_EINVAL, "damping must be in (0, 1]");
+  if (!g->csr_rowptr || !g->csc_colptr) return fail(RLGL_EINVAL, "the one-workgroup solve needs the CSR and the CSC");
+  if (g->nnz > 0 && (!g->csr_col || !g->csc_row)) return fail(RLGL_EINVAL, "link arrays missing");
+  if ((g->csr_val == nullptr) != (g->csc_val == nullptr))
+    return fail(RLGL_EINVAL, "csr_val and csc_val must both be given or both be NULL");
+  if (!(eps >= 0.0) || max_steps < 0) return fail(RLGL_EINVAL, "eps must be >= 0 and max_steps >= 0");
+  const int cap = small_capacity(o->precision);
+  if (g->n > cap) return fail(RLGL_EINVAL, "n = %d exceeds the one-workgroup capacity %d", g->n, cap);
+  const SmallLayout L = small_layout(g->n);
+  if (!ws) return fail(RLGL_EINVAL, "workspace is NULL");
+  if (ws_bytes < L.total) return fail(RLGL_ENOMEM, "workspace too small: %zu < %zu", ws_bytes, L.total);
+  char *w = (char *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+  int ends[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(&ends[0], g->csr_rowptr + g->n, sizeof(int), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(&ends[1], g->csc_colptr + g->n, sizeof(int), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  if ((long long)ends[0] != g->nnz || (long long)ends[1] != g->nnz)
+    return fail(RLGL_EINVAL, "csr_rowptr[n] = %d and csc_colptr[n] = %d must equal nnz = %lld", ends[0], ends[1],
+                (long long)g->nnz);
+
+  SmallArgs a{};
+  a.n = g->n;
+  a.nnz = g->nnz;
+  a.c = g->damping;
+  a.rowptr = g->csr_rowptr;
+  a.col = g->csr_col;
+  a.colptr = g->csc_colptr;
+  a.crow = g->csc_row;
+  a.val = g->csr_val;
+  a.cval = g->csc_val;
+  a.sched = o->sched;
+  a.r = o->r;
+  a.theta_period = o->theta_period;
+  a.seed = o->seed;
+  a.refresh = o->refresh > 0 ? 1 : 0;
+  a.eps = eps;
+  a.max_steps = max_steps;
+  a.H = (double *)(w + L.H);
+  a.Q = (double *)(w + L.Q);
+  a.rec = (SmallRec *)(w + L.rec);
+  a.pi = dev_pi;
+  const int cs = o->precision == RLGL_FP64 ? 8 : 4;
+  const size_t dyn = align_up((size_t)g->n * cs, 16);
+  HIP_TRY(hipFuncSetAttribute(small_kernel(o->precision), hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+  if (o->precision == RLGL_FP64) k_small<double><<<1, SM_BLOCK, dyn, stream>>>(a);
+  else k_small<float><<<1, SM_BLOCK, dyn, stream>>>(a);
+  HIP_TRY(hipGetLastError());
+  SmallRec r{};
+  HIP_TRY(hipMemcpyAsync(&r, a.rec, sizeof r, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  const rlgl_status rs = (r.status == ST_CONVERGED) ? RLGL_OK : status_of(r.status);
+  if (info) {
+    info->t = r.t;
+    info->green = r.green;
+    info->green_total = r.green_total;
+    info->edges_pushed = r.edges;
+    info->l1_cash = r.l1;
+    info->h_sum = r.hsum;
+    info->resid = r.hsum != 0.0 ? r.l1 / std::fabs(r.hsum) : INFINITY;
+    info->theta = r.theta;
+    info->cash_sum = r.csum;
+    info->status = rs;
+    info->last_route = r.last_route;
+  }
+  if (r.status == ST_BAD_GRAPH)
+    return fail(RLGL_EINVAL, "a row or column pointer or a link index of the graph is out of range");
+  if (rs != RLGL_OK) return fail(rs, "one-workgroup solve stopped at t = %lld (device status %d)", r.t, r.status);
+  return RLGL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t rlgl_small_max_n(int32_t precision) {
+  if (precision < 0 || precision > 2) return 0;
+  return small_capacity(precision);
+}
+
+size_t rlgl_small_workspace_bytes(int32_t n) {
+  if (n < 1) return 0;
+  return small_layout(n).total;
+}
+
+rlgl_status rlgl_solve_small(const rlgl_graph *g, const rlgl_options *opt, double eps, int64_t max_steps,
+                             double *dev_pi, void *dev_workspace, size_t ws_bytes, void *stream,
+                             rlgl_step_info *info) {
+  return small_solve(g, opt, eps, max_steps, dev_pi, (char *)dev_workspace, ws_bytes, (hipStream_t)stream, info);
 }
 
 }  // extern "C"

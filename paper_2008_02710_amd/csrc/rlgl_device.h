@@ -30,7 +30,9 @@ enum { SCHED_ALL = 0, SCHED_THRESHOLD = 1, SCHED_TOPK = 2, SCHED_MAXC = 3, SCHED
 // a step whose green set the caller gives as a byte mask (rlgl_step_mask)
 constexpr int SCHED_MASK = 5;
 enum { ROUTE_PUSH = 0, ROUTE_PULL = 1, ROUTE_AUTO = 2 };
-enum { ST_RUNNING = 0, ST_CONVERGED = 1, ST_LIMIT = 2, ST_ZERO_HISTORY = -4, ST_NONFINITE = -6 };
+// ST_BAD_GRAPH: a kernel met a row/column pointer or link index outside its
+// range (the caller's graph breaks the contract); reported as RLGL_EINVAL.
+enum { ST_RUNNING = 0, ST_CONVERGED = 1, ST_LIMIT = 2, ST_BAD_GRAPH = -1, ST_ZERO_HISTORY = -4, ST_NONFINITE = -6 };
 
 // One stripe of the FP64 accumulators of a record.
 struct alignas(128) Acc {

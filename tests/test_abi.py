@@ -38,12 +38,12 @@ def test_binding_names_match_header():
         assert hasattr(rl, name), name
 
 
-def test_struct_sizes_match_header():
+def test_struct_sizes_match_header(tmp_path):
     """The ctypes mirrors have the C layout (checked against offsets the
     compiler computes for the header)."""
     import paper_2008_02710_amd as rl
-    src = os.path.join(ROOT, "_sizes_probe.c")
-    exe = os.path.join(ROOT, "_sizes_probe")
+    src = str(tmp_path / "sizes_probe.c")
+    exe = str(tmp_path / "sizes_probe")
     open(src, "w").write(
         '#include <stdio.h>\n#include <stddef.h>\n#include "rlgl.h"\n'
         'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(rlgl_graph),'
@@ -53,14 +53,9 @@ def test_struct_sizes_match_header():
         ' sizeof(rlgl_chain_result), sizeof(rlgl_pool_options), sizeof(rlgl_request),'
         ' offsetof(rlgl_request, tol_l1), offsetof(rlgl_options, relabel), offsetof(rlgl_options, seed));'
         'return 0;}\n')
-    try:
-        import subprocess
-        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", exe, src])
-        out = subprocess.check_output([exe]).decode().split()
-    finally:
-        for p in (src, exe):
-            if os.path.exists(p):
-                os.remove(p)
+    import subprocess
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", exe, src])
+    out = subprocess.check_output([exe]).decode().split()
     got = [ctypes.sizeof(rl.rlgl_graph), ctypes.sizeof(rl.rlgl_options), ctypes.sizeof(rl.rlgl_step_info),
            ctypes.sizeof(rl.rlgl_kernel_stat), rl.rlgl_options.record_green.offset,
            rl.rlgl_step_info.last_route.offset, ctypes.sizeof(rl.rlgl_batch_graphs),
@@ -133,3 +128,30 @@ def test_pool_host_side_checks():
     assert lib.rlgl_pool_admit(None, ctypes.byref(req), ctypes.byref(slot)) == rl.RLGL_EINVAL
     assert lib.rlgl_pool_poll(None, None, 0) == rl.RLGL_EINVAL
     assert lib.rlgl_pool_release(None, 0) == rl.RLGL_EINVAL
+
+
+def test_small_solver_host_side_checks():
+    """rlgl_solve_small rejects bad arguments before any launch; its workspace
+    size follows n (history and moved cash, 8 bytes each per node)."""
+    import paper_2008_02710_amd as rl
+    lib = rl._lib
+    assert rl.rlgl_small_workspace_bytes(0) == 0
+    w1, w2 = rl.rlgl_small_workspace_bytes(1000), rl.rlgl_small_workspace_bytes(2000)
+    assert w2 - w1 >= 2 * (8 * 1000 - 256) and w1 >= 16 * 1000
+    assert rl.rlgl_small_max_n(9) == 0
+    g = rl.rlgl_graph(10, 0, 1, 0, None, 1, 0, None, 0.85)
+    info = rl.rlgl_step_info()
+    for field, value in (("sched", rl.SCHED_TOPK), ("r", 0.5), ("theta_period", 0), ("precision", 7)):
+        o = rl.rlgl_default_options(**{field: value})
+        assert lib.rlgl_solve_small(ctypes.byref(g), ctypes.byref(o), 1e-9, 10, None, 4096, 1 << 20, None,
+                                    ctypes.byref(info)) == rl.RLGL_EINVAL
+    o = rl.rlgl_default_options(sched=rl.SCHED_MAXC)
+    nocsc = rl.rlgl_graph(10, 0, 1, 0, None, None, None, None, 0.85)
+    assert lib.rlgl_solve_small(ctypes.byref(nocsc), ctypes.byref(o), 1e-9, 10, None, 4096, 1 << 20, None,
+                                ctypes.byref(info)) == rl.RLGL_EINVAL
+    assert "CSC" in rl.rlgl_last_error()
+    g0 = rl.rlgl_graph(10, 0, 1, 0, None, 1, 0, None, 1.5)
+    assert lib.rlgl_solve_small(ctypes.byref(g0), ctypes.byref(o), 1e-9, 10, None, 4096, 1 << 20, None,
+                                ctypes.byref(info)) == rl.RLGL_EINVAL
+    assert lib.rlgl_solve_small(ctypes.byref(g), ctypes.byref(o), -1.0, 10, None, 4096, 1 << 20, None,
+                                ctypes.byref(info)) == rl.RLGL_EINVAL
