@@ -225,6 +225,22 @@ rlgl_status rlgl_solve_small(const rlgl_graph *g, const rlgl_options *opt, doubl
                              double *dev_pi, void *dev_workspace, size_t ws_bytes, void *stream,
                              rlgl_step_info *info);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * rlgl_solve_small with its workspace taken from a static device array of
+ * RLGL_SMALL_STATIC_BYTES bytes that the library holds on every GPU it runs
+ * on until the process ends.  Same arguments, behaviour and errors as
+ * rlgl_solve_small without dev_workspace and ws_bytes; RLGL_EINVAL when
+ * rlgl_small_workspace_bytes(g->n) exceeds RLGL_SMALL_STATIC_BYTES (n above
+ * about 32,700).  Calls no hipMalloc, hipFree or other allocating routine.
+ * Every call on one GPU uses that GPU's array, which keeps the last call's
+ * contents (every solve writes its history and moved cash before reading
+ * them): calls whose work overlaps on one GPU (from several host threads,
+ * or on streams that run concurrently) race and must not be made. */
+#define RLGL_SMALL_STATIC_BYTES (512u * 1024u)
+rlgl_status rlgl_solve_small_static(const rlgl_graph *g, const rlgl_options *opt, double eps, int64_t max_steps,
+                                    double *dev_pi, void *stream, rlgl_step_info *info);
+
 /* Releases the host context.  Does not touch the caller's device memory. */
 void rlgl_destroy(rlgl_ctx *ctx);
 

@@ -103,7 +103,7 @@ EXPORTED = ["rlgl_default_options", "rlgl_workspace_bytes", "rlgl_create", "rlgl
             "rlgl_pool_admit", "rlgl_pool_advance", "rlgl_pool_launch", "rlgl_pool_wait", "rlgl_pool_poll",
             "rlgl_pool_result", "rlgl_pool_release", "rlgl_pool_destroy", "rlgl_validate_scratch_bytes",
             "rlgl_validate", "rlgl_step_mask", "rlgl_small_max_n", "rlgl_small_workspace_bytes",
-            "rlgl_solve_small"]
+            "rlgl_solve_small", "rlgl_solve_small_static"]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -134,6 +134,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rlgl_small_workspace_bytes.restype = ctypes.c_size_t
     lib.rlgl_solve_small.argtypes = [G, O, f64, i64, vp, vp, ctypes.c_size_t, vp, I]
     lib.rlgl_solve_small.restype = i32
+    lib.rlgl_solve_small_static.argtypes = [G, O, f64, i64, vp, vp, I]
+    lib.rlgl_solve_small_static.restype = i32
     lib.rlgl_destroy.argtypes = [vp]
     lib.rlgl_destroy.restype = None
     lib.rlgl_last_error.argtypes = []
@@ -291,6 +293,20 @@ def rlgl_solve_small(graph: rlgl_graph, opt: rlgl_options, eps: float, max_steps
                                _ptr(workspace), int(ws_bytes), _stream_handle(stream), ctypes.byref(info))
     if raise_on_error:
         _check(st, "rlgl_solve_small")
+    return st, info
+
+
+RLGL_SMALL_STATIC_BYTES = 512 * 1024
+
+
+def rlgl_solve_small_static(graph: rlgl_graph, opt: rlgl_options, eps: float, max_steps: int, pi_out, stream=None,
+                            raise_on_error: bool = True):
+    """rlgl_solve_small on the library's static device workspace (no allocation)."""
+    info = rlgl_step_info()
+    st = _lib.rlgl_solve_small_static(ctypes.byref(graph), ctypes.byref(opt), float(eps), int(max_steps),
+                                      _ptr(pi_out), _stream_handle(stream), ctypes.byref(info))
+    if raise_on_error:
+        _check(st, "rlgl_solve_small_static")
     return st, info
 
 

@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -2146,6 +2147,34 @@ int small_capacity(int prec) {
   return dyn > 0 ? (int)(dyn / cs) : 0;
 }
 
+
+// The workspace of rlgl_solve_small_static: a static device array of fixed
+// size, one copy on every GPU the library runs on, held until the process
+// ends.  Host code never passes the array's name to a kernel or a copy (on
+// the host it stands for no device address); it uses the address that
+// hipGetSymbolAddress returns, looked up once per device with that device
+// current.
+static __device__ __align__(256) unsigned char scratch[RLGL_SMALL_STATIC_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[MAX_DEVICES] = {};
+
+rlgl_status static_scratch(char **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(RLGL_EINVAL, "device %d beyond the library's table", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(RLGL_EHIP, "hipGetSymbolAddress returned no address for the static workspace");
+    g_scratch_ptr[dev] = (char *)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return RLGL_OK;
+}
+
 rlgl_status small_solve(const rlgl_graph *g, const rlgl_options *o, double eps, int64_t max_steps, double *dev_pi,
                         char *ws, size_t ws_bytes, hipStream_t stream, rlgl_step_info *info) {
   if (!g || !o) return fail(RLGL_EINVAL, "null argument");
@@ -2242,6 +2271,24 @@ rlgl_status rlgl_solve_small(const rlgl_graph *g, const rlgl_options *opt, doubl
                              double *dev_pi, void *dev_workspace, size_t ws_bytes, void *stream,
                              rlgl_step_info *info) {
   return small_solve(g, opt, eps, max_steps, dev_pi, (char *)dev_workspace, ws_bytes, (hipStream_t)stream, info);
+}
+
+}  // extern "C"
+
+extern "C" {
+
+rlgl_status rlgl_solve_small_static(const rlgl_graph *g, const rlgl_options *opt, double eps, int64_t max_steps,
+                                    double *dev_pi, void *stream, rlgl_step_info *info) {
+  if (!g) return fail(RLGL_EINVAL, "null argument");
+  if (g->n < 1) return fail(RLGL_EINVAL, "n must be >= 1");
+  const size_t need = small_layout(g->n).total;
+  if (need > (size_t)RLGL_SMALL_STATIC_BYTES)
+    return fail(RLGL_EINVAL, "n = %d needs %zu workspace bytes, beyond the static %zu", g->n, need,
+                (size_t)RLGL_SMALL_STATIC_BYTES);
+  char *ws = nullptr;
+  const rlgl_status st = static_scratch(&ws);
+  if (st != RLGL_OK) return st;
+  return small_solve(g, opt, eps, max_steps, dev_pi, ws, (size_t)RLGL_SMALL_STATIC_BYTES, (hipStream_t)stream, info);
 }
 
 }  // extern "C"

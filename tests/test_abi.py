@@ -155,3 +155,20 @@ def test_small_solver_host_side_checks():
                                 ctypes.byref(info)) == rl.RLGL_EINVAL
     assert lib.rlgl_solve_small(ctypes.byref(g), ctypes.byref(o), -1.0, 10, None, 4096, 1 << 20, None,
                                 ctypes.byref(info)) == rl.RLGL_EINVAL
+
+
+def test_static_workspace_size_matches_header():
+    import paper_2008_02710_amd as rl
+    text = open(HEADER).read()
+    m = re.search(r"#define\s+RLGL_SMALL_STATIC_BYTES\s+\((\d+)u\s*\*\s*(\d+)u\)", text)
+    assert m, "RLGL_SMALL_STATIC_BYTES not found"
+    assert int(m.group(1)) * int(m.group(2)) == rl.RLGL_SMALL_STATIC_BYTES
+    # the largest one-workgroup workspace the static array holds
+    assert rl.rlgl_small_workspace_bytes(32736) <= rl.RLGL_SMALL_STATIC_BYTES
+    assert rl.rlgl_small_workspace_bytes(32737) > rl.RLGL_SMALL_STATIC_BYTES
+    g = rl.rlgl_graph(40000, 0, 1, 0, None, 1, 0, None, 0.85)
+    o = rl.rlgl_default_options(precision=rl.FP32C_FP64H)
+    info = rl.rlgl_step_info()
+    assert rl._lib.rlgl_solve_small_static(ctypes.byref(g), ctypes.byref(o), 1e-9, 10, None, None,
+                                           ctypes.byref(info)) == rl.RLGL_EINVAL
+    assert "static" in rl.rlgl_last_error()
