@@ -2,10 +2,14 @@
 
 A "step" of this benchmark is one whole solve: step 0 of Algorithm 1, the
 green-light steps, the stop test and the normalisation pi_hat = H / (H 1),
-on a graph already resident in HBM.  The default workload is the Chung-Lu
-power-law digraph with 2^20 nodes (exponent 2.1, mean degree 16, 5% forced
-dangling nodes, damping 0.85), threshold schedule (r = 1), FP32 cash with
-FP64 history, push/pull chosen per step.
+on a graph already resident in HBM.  The default workload is the R-MAT graph
+of scale 24 (16.8M nodes, 268M links, (a, b, c) = (0.57, 0.19, 0.19), damping
+0.85) with FP32 link values stored per link, FP32 cash and FP64 history.  Its
+green-light schedule is the one with the shortest time to solution on these
+kernels: the all-green schedule (power iteration as RLGL's special case),
+measured beside the threshold schedule (r = 1) in the same run.  Also timed:
+the Chung-Lu 2^20 graph under both schedules, the CPU oracle, the batched
+engines and the serving pool.
 
 The solve stops at ||C_t||_1 / |H_t 1| < (1 - c) * 1e-6, which bounds the L1
 distance to pi* by 1e-6 (contraction of the Google matrix); the result is
@@ -57,25 +61,124 @@ def read_traffic(kernel: str, workload: str):
         return None
 
 
+# Per workload: the generator, the schedule timed for the headline, the
+# schedules timed beside it, and how the link values are held.
+WORKLOADS = {
+    # R-MAT scale 24 with FP32 P values stored per link.  All-green takes 21
+    # steps (5.9G edge-pushes) where the threshold rule takes 198 (46.6G): the
+    # threshold's green nodes are the hubs (about 80% of the links per step)
+    # and the equal cash of the nodes without in-links keeps the residual up
+    "rmat_s24": dict(sched="all", alt=["threshold"], link_values="stored"),
+    # Chung-Lu 2^20: the threshold schedule is the workload's own
+    "chung_lu_2p20": dict(sched="threshold", alt=["all"], link_values="implicit"),
+    "scc_c1_2p20": dict(sched="threshold", alt=[], link_values="implicit"),
+    "poisson_1e4": dict(sched="all", alt=["maxc"], link_values="stored"),
+}
+
+
 def make_workload(name: str):
     import workloads
     if name == "chung_lu_2p20":
-        g = workloads.chung_lu(1 << 20, 2.1, 16.0, 0.05, 0.85, seed=0, name=name)
-        return g, dict(sched="threshold", r=1.0)
+        return workloads.chung_lu(1 << 20, 2.1, 16.0, 0.05, 0.85, seed=0, name=name)
     if name == "rmat_s24":
         g = workloads.rmat(24, 16, 0.57, 0.19, 0.19, 0.85, seed=0)
         g.name = name
-        return g, dict(sched="threshold", r=1.0)
+        return g
     if name == "scc_c1_2p20":
         # the undamped chain (c = 1) on the largest strongly connected component
         base = workloads.chung_lu(1 << 20, 2.1, 16.0, 0.0, 1.0, seed=0, name="chung_lu_2p20_nodangle")
-        g = workloads.largest_scc(base, c=1.0, name=name)
-        return g, dict(sched="threshold", r=1.0)
+        return workloads.largest_scc(base, c=1.0, name=name)
     if name == "poisson_1e4":
         g = workloads.poisson_uniform(10000, 8.0, 0.85, seed=0)
         g.name = name
-        return g, dict(sched="all", r=1.0)
+        return g
     raise SystemExit(f"unknown workload {name}")
+
+
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def log(*a):
+    print("#", *a, file=sys.stderr, flush=True)
+
+
+def time_solves(rl, torch, s, eps, max_steps, steps, warmup, stream):
+    """Warm-up solves, then `steps` timed solves (reset + solve each), with a
+    device synchronisation on both sides of the timed region."""
+    def one():
+        s.reset()
+        st, info = s.solve(eps, max_steps)
+        return info
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    infos, wall = [], []
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a = time.perf_counter()
+        infos.append(one())
+        wall.append(time.perf_counter() - a)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    return infos, wall, total, ev0.elapsed_time(ev1)
+
+
+def roofline_of(prof, copy_gbps, traffic):
+    """Roofline of the dominant kernel from one profiled solve: algorithmic
+    bytes (links of green nodes that moved cash and the per-node terms, the
+    work the method does) over the launches' event-timed duration, against
+    the 8 TB/s HBM peak; the bytes its access pattern touches beside them."""
+    dom_name, st = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    launches = max(st["launches"], 1)
+    achieved = st["bytes"] / (st["ms"] * 1e-3) / 1e9
+    touched = st["bytes_touched"] / (st["ms"] * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": f"k_{dom_name}", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "algorithmic_bytes_per_launch": round(st["bytes"] / launches),
+            "touched_bytes_per_launch": round(st["bytes_touched"] / launches),
+            "touched_GBps": round(touched, 1), "touched_frac": round(touched / HBM_PEAK_GBS, 4),
+            "green_links_per_launch": round(st["green_links"] / launches),
+            "avg_launch_us": round(1000.0 * st["ms"] / launches, 2), "launches_per_solve": st["launches"],
+            "stream_copy_GBps": round(copy_gbps, 1), "frac_of_copy": round(achieved / copy_gbps, 4),
+            "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 4),
+                            "GBps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1),
+                            "touched_GBps": round(v["bytes_touched"] / max(v["ms"], 1e-9) / 1e6, 1)}
+                        for k, v in prof.items()}}
+
+
+def schedule_leg(rl, torch, oracle, g, dg, sched_name, args, prec, route, stream, eps, steps, warmup, r=1.0):
+    """Times one schedule on a resident graph and certifies its result."""
+    import numpy as np
+    sched = SCHED_IDS[sched_name]
+    relabel = args.relabel if sched not in (rl.SCHED_PC, rl.SCHED_TOPK) else 0
+    max_steps = 100000 if sched != rl.SCHED_MAXC else 10_000_000
+    s = rl.Solver(dg, stream=stream, sched=sched, r=r, route=route, precision=prec, relabel=relabel)
+    infos, wall, total, _ = time_solves(rl, torch, s, eps, max_steps, steps, warmup, stream)
+    last = infos[-1]
+    pi = s.pi.detach().cpu().numpy()
+    s.close()
+    ch = oracle.Chain(g.rowptr, g.col, g.val(), g.c)
+    resid = oracle.residual(ch, pi)
+    ms = 1000.0 * total / steps
+    out = {"ms_per_solve": round(ms, 4), "solve_ms_min": round(1000 * min(wall), 4),
+           "steps": last["t"] - 1, "edge_pushes": last["edges_pushed"],
+           "normalized_iterations": round(last["edges_pushed"] / g.nnz, 3),
+           "gteps": round(sum(i["edges_pushed"] for i in infos) / total / 1e9, 3),
+           "fp64_residual": resid, "l1_certified_bound": resid / (1.0 - g.c) if g.c < 1.0 else None}
+    log(f"schedule {sched_name} on {g.name}: {json.dumps(out)}")
+    return out
 
 
 def batched_leg(args, rl, torch, oracle):
@@ -170,23 +273,32 @@ def serving_leg(args, rl, torch, oracle):
     uniformly from a pool of pre-generated chains (n log-uniform in
     [1e3, 1e6], Chung-Lu exponent 2.3, mean degree 12, damping 0.85) held in
     page-locked host memory, tolerance 1e-6 L1.  The upload counts toward the
-    latency.  Run under three arena budgets: one that never binds, 4 GB, and
-    256 MB, where admission waits for memory (a 1e6-node chain takes ~90 MB)."""
+    latency.  The first seconds of requests warm the pool up; the measured
+    requests follow.  Run under an arena budget that never binds and under
+    one of 1.25 times the largest request's footprint, where a large request
+    holds most of the arena and the admissions after it wait for memory."""
     import numpy as np
     import workloads
     from paper_2008_02710_amd.serving import serve
     t0 = time.time()
     pool_graphs = workloads.serving_pool(args.serve_pool, seed=5)
     hcs = [rl.HostChain(g, tol_l1=1e-6) for g in pool_graphs]
-    print(f"# serving pool: {len(hcs)} chains, {sum(g.n for g in pool_graphs)} nodes, "
-          f"{sum(g.nnz for g in pool_graphs)} links, gen {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
-    total = args.serve_requests + args.serve_warmup
-    draws = workloads.request_draws(total, len(hcs), seed=5)
+    log(f"serving pool: {len(hcs)} chains, {sum(g.n for g in pool_graphs)} nodes, "
+        f"{sum(g.nnz for g in pool_graphs)} links, gen {time.time() - t0:.1f}s")
+    total = args.serve_requests + int(args.serve_rate * args.serve_warmup_s * 1.5) + 16
     arrivals = workloads.poisson_arrivals(total, args.serve_rate, seed=5)
+    warm = int(np.searchsorted(arrivals, args.serve_warmup_s))
+    total = warm + args.serve_requests
+    arrivals = list(arrivals[:total])
+    draws = workloads.request_draws(total, len(hcs), seed=5)
     reqs = [hcs[d] for d in draws]
-    sample = set(range(args.serve_warmup, total, max(1, args.serve_requests // 16)))
+    sample = set(range(warm, total, max(1, args.serve_requests // 16)))
+    probe = rl.Pool(1 << 20, max_chains=1, precision=rl.FP32C_KAHANH)
+    foot = [probe.footprint(h.n, h.nnz) for h in hcs]
+    probe.close()
+    tight = int(1.25 * max(foot))
     out = {}
-    for label, arena in (("unbounded", 48 << 30), ("4GB", 4 << 30), ("256MB", 256 << 20)):
+    for label, arena in (("unbounded", 48 << 30), ("tight", tight)):
         pool = rl.Pool(arena, max_chains=256, precision=rl.FP32C_KAHANH)
         kept = {}
 
@@ -194,10 +306,9 @@ def serving_leg(args, rl, torch, oracle):
             if i in sample:
                 kept[i] = pi.detach().cpu().numpy().copy()
 
-        peak = [0]
-        recs = serve(pool, reqs, list(arrivals), iterations=args.serve_iters, on_result=on_result)
+        recs = serve(pool, reqs, arrivals, iterations=args.serve_iters, on_result=on_result)
         pool.close()
-        meas = recs[args.serve_warmup:]
+        meas = recs[warm:]
         lat = np.array([r["latency"] for r in meas]) * 1000.0
         wait = np.array([r["admitted"] - r["arrival"] for r in meas]) * 1000.0
         span = max(r["finished"] for r in meas) - min(r["arrival"] for r in meas)
@@ -208,25 +319,33 @@ def serving_leg(args, rl, torch, oracle):
             g = pool_graphs[draws[i]]
             ch = oracle.Chain(g.rowptr, g.col, g.val(), g.c)
             worst = max(worst, oracle.residual(ch, pi) / (1.0 - g.c))
-        # requests in flight over time, from the admission and finish times
-        ev = sorted([(r["admitted"], 1) for r in meas] + [(r["finished"], -1) for r in meas])
-        cur = 0
-        for _, d in ev:
+        # requests and arena bytes in flight over time, from the admission and finish times
+        ev = sorted([(r["admitted"], 1, foot[draws[warm + k]]) for k, r in enumerate(meas)] +
+                    [(r["finished"], -1, -foot[draws[warm + k]]) for k, r in enumerate(meas)])
+        cur = cur_b = peak = peak_b = 0
+        for _, d, fb in ev:
             cur += d
-            peak[0] = max(peak[0], cur)
+            cur_b += fb
+            peak = max(peak, cur)
+            peak_b = max(peak_b, cur_b)
         out[label] = {"arena_bytes": arena, "requests": len(meas), "failed": bad,
                       "p50_ms": round(float(np.percentile(lat, 50)), 3),
                       "p99_ms": round(float(np.percentile(lat, 99)), 3),
                       "mean_ms": round(float(lat.mean()), 3),
+                      "admission_wait_p50_ms": round(float(np.percentile(wait, 50)), 3),
                       "admission_wait_p99_ms": round(float(np.percentile(wait, 99)), 3),
+                      "admissions_that_waited": int(sum(r["blocked"] for r in meas)),
                       "completed_per_s": round(len(meas) / span, 1),
                       "served_gteps": round(pushes / span / 1e9, 3),
-                      "peak_in_flight": peak[0],
+                      "peak_in_flight": peak, "peak_resident_bytes": int(peak_b),
                       "worst_certified_l1_sampled": worst, "sampled": len(kept)}
-        print(f"# serving {label}: {json.dumps(out[label])}", file=sys.stderr, flush=True)
+        log(f"serving {label}: {json.dumps(out[label])}")
     return {"workload": "chung_lu_serving", "rate_per_s": args.serve_rate, "pool_chains": len(hcs),
-            "warmup_requests": args.serve_warmup, "tol_l1": 1e-6, "iterations_per_poll": args.serve_iters,
-            "budgets": out}
+            "warmup_s": args.serve_warmup_s, "warmup_requests": warm, "tol_l1": 1e-6,
+            "largest_footprint_bytes": int(max(foot)), "iterations_per_poll": args.serve_iters, "budgets": out}
+
+
+SCHED_IDS = {}
 
 
 def main():
@@ -234,31 +353,35 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10, help="timed solves")
     ap.add_argument("--warmup", type=int, default=3, help="untimed solves")
-    ap.add_argument("--workload", default="chung_lu_2p20")
+    ap.add_argument("--workload", default="rmat_s24", choices=sorted(WORKLOADS))
     ap.add_argument("--route", default="auto", choices=["auto", "push", "pull"])
     ap.add_argument("--precision", default="fp32c_fp64h", choices=["fp64", "fp32c_fp64h", "fp32c_kahanh"])
     ap.add_argument("--tol", type=float, default=1e-6, help="certified L1 target")
     ap.add_argument("--sched", default=None, choices=["all", "threshold", "maxc", "pc"],
                     help="green-light schedule (default: the workload's)")
-    ap.add_argument("--r", type=float, default=None, help="threshold power-mean order (default: the workload's)")
+    ap.add_argument("--r", type=float, default=None, help="threshold power-mean order (default 1)")
     ap.add_argument("--theta-period", type=int, default=1, help="steps between threshold refreshes")
     ap.add_argument("--seed", type=int, default=1, help="seed of the PC draws")
-    ap.add_argument("--link-values", default="implicit", choices=["implicit", "stored"],
-                    help="link weights 1/outdeg implied by the CSR row pointers, or stored per link")
+    ap.add_argument("--link-values", default=None, choices=["implicit", "stored"],
+                    help="link weights 1/outdeg implied by the CSR row pointers, or stored per link "
+                         "(default: the workload's)")
     ap.add_argument("--relabel", type=int, default=1, choices=[0, 1],
                     help="renumber the states by decreasing out-degree inside the library (layout step)")
+    ap.add_argument("--small", action="store_true",
+                    help="solve with the one-workgroup solver (rlgl_solve_small; small chains)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-ref", action="store_true", help="skip the FP64 power-iteration reference")
+    ap.add_argument("--no-legs", action="store_true", help="skip the schedule and Chung-Lu comparison legs")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     ap.add_argument("--batch", type=int, default=512,
                     help="chains of the batched workload (0 skips the batched leg)")
-    ap.add_argument("--serve-requests", type=int, default=5000,
+    ap.add_argument("--serve-requests", type=int, default=20000,
                     help="measured requests of the serving leg (0 skips it)")
-    ap.add_argument("--serve-warmup", type=int, default=1000, help="requests before the measured ones")
+    ap.add_argument("--serve-warmup-s", type=float, default=2.0, help="seconds of requests before the measured ones")
     ap.add_argument("--serve-rate", type=float, default=500.0, help="Poisson arrival rate (requests/s)")
-    ap.add_argument("--serve-pool", type=int, default=64, help="pre-generated chains requests draw from")
+    ap.add_argument("--serve-pool", type=int, default=512, help="pre-generated chains requests draw from")
     ap.add_argument("--serve-iters", type=int, default=4, help="lockstep iterations between host polls")
     args = ap.parse_args()
 
@@ -283,65 +406,49 @@ def main():
 
     import paper_2008_02710_amd as rl
 
+    SCHED_IDS.update({"threshold": rl.SCHED_THRESHOLD, "all": rl.SCHED_ALL, "maxc": rl.SCHED_MAXC,
+                      "pc": rl.SCHED_PC})
     prec = {"fp64": rl.FP64, "fp32c_fp64h": rl.FP32C_FP64H, "fp32c_kahanh": rl.FP32C_KAHANH}[args.precision]
     route = {"auto": rl.ROUTE_AUTO, "push": rl.ROUTE_PUSH, "pull": rl.ROUTE_PULL}[args.route]
-    t0 = time.time()
-    g, wl = make_workload(args.workload)
+    wl = dict(WORKLOADS[args.workload])
     if args.sched:
         wl["sched"] = args.sched
-    if args.r is not None:
-        wl["r"] = args.r
-    sched = {"threshold": rl.SCHED_THRESHOLD, "all": rl.SCHED_ALL, "maxc": rl.SCHED_MAXC,
-             "pc": rl.SCHED_PC}[wl["sched"]]
+        wl["alt"] = [x for x in ("all", "threshold") if x != args.sched]
+    if args.link_values:
+        wl["link_values"] = args.link_values
+    r = 1.0 if args.r is None else args.r
+    t0 = time.time()
+    g = make_workload(args.workload)
+    sched = SCHED_IDS[wl["sched"]]
     if sched == rl.SCHED_PC and args.relabel:
         args.relabel = 0  # the PC draws are keyed by the caller's node ids
-    print(f"# workload {g.name}: n={g.n} nnz={g.nnz} dangling={g.n_dangling} gen={time.time() - t0:.1f}s",
-          file=sys.stderr, flush=True)
+    log(f"workload {g.name}: n={g.n} nnz={g.nnz} dangling={g.n_dangling} gen={time.time() - t0:.1f}s")
 
     dev = torch.device("cuda:0")
-    dg = rl.DeviceGraph.from_workload(g, precision=prec, with_csc=True, explicit_val=args.link_values == "stored",
-                                      device=dev)
+    stored = wl["link_values"] == "stored"
+    dg = rl.DeviceGraph.from_workload(g, precision=prec, with_csc=True, explicit_val=stored, device=dev)
     stream = torch.cuda.current_stream(dev)
-    s = rl.Solver(dg, stream=stream, sched=sched, r=wl["r"], route=route, precision=prec, relabel=args.relabel,
-                  theta_period=args.theta_period, seed=args.seed)
     # c < 1: the residual certifies the L1 error through 1/(1-c); c = 1 has no
     # such bound, so the stop is a tenth of the target and the error is
     # measured against FP64 power iteration
     eps = (1.0 - g.c) * args.tol if g.c < 1.0 else 0.1 * args.tol
     max_steps = 100000 if sched != rl.SCHED_MAXC else 10_000_000
 
-    def one_solve():
-        s.reset()
-        st, info = s.solve(eps, max_steps)
-        return info
-
-    for _ in range(args.warmup):
-        one_solve()
-    torch.cuda.synchronize()
-
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    infos = []
-    wall = []
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        a = time.perf_counter()
-        infos.append(one_solve())
-        wall.append(time.perf_counter() - a)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    t_total = time.perf_counter() - t_start
-    ev_ms = ev0.elapsed_time(ev1)
+    if args.small:
+        s = rl.SmallSolver(dg, stream=stream, sched=sched, r=r, precision=prec, theta_period=args.theta_period,
+                           seed=args.seed)
+        s.reset = lambda: None  # every one-workgroup solve starts from step 0
+    else:
+        s = rl.Solver(dg, stream=stream, sched=sched, r=r, route=route, precision=prec, relabel=args.relabel,
+                      theta_period=args.theta_period, seed=args.seed)
+    infos, wall, t_total, ev_ms = time_solves(rl, torch, s, eps, max_steps, args.steps, args.warmup, stream)
     pushes = sum(i["edges_pushed"] for i in infos)
     gteps = pushes / t_total / 1e9
     ms_per_solve = 1000.0 * t_total / args.steps
     last = infos[-1]
     pi = s.pi.detach().cpu().numpy()
-    print(f"# timed {args.steps} solves: {ms_per_solve:.3f} ms/solve (events {ev_ms / args.steps:.3f}), "
-          f"steps={last['t'] - 1} pushes/solve={last['edges_pushed']} GTEPS={gteps:.1f}",
-          file=sys.stderr, flush=True)
+    log(f"timed {args.steps} solves: {ms_per_solve:.3f} ms/solve (events {ev_ms / args.steps:.3f}), "
+        f"steps={last['t'] - 1} pushes/solve={last['edges_pushed']} GTEPS={gteps:.1f}")
 
     # ---- a plain device copy on the same GPU (STREAM-copy style): 2 x 1 GiB moved
     cbuf = torch.empty(1 << 28, dtype=torch.float32, device=dev)
@@ -357,26 +464,20 @@ def main():
     copy_gbps = 5 * 2 * cbuf.numel() * 4 / (ce0.elapsed_time(ce1) * 1e-3) / 1e9
     del cbuf, cdst
 
-    # ---- roofline of the dominant kernel: same solve, events around each launch
-    rl.rlgl_profile_enable(s.ctx, True)
-    one_solve()
-    torch.cuda.synchronize()
-    prof = rl.rlgl_profile_read(s.ctx)
-    rl.rlgl_profile_enable(s.ctx, False)
-    dom = max(prof.items(), key=lambda kv: kv[1]["ms"])
-    dom_name, dom_stat = dom
-    achieved = dom_stat["bytes"] / (dom_stat["ms"] * 1e-3) / 1e9
-    per_launch_bytes = dom_stat["bytes"] / max(dom_stat["launches"], 1)
-    traffic = read_traffic(dom_name, g.name)
-    roofline = {"bound": "hbm", "kernel": f"k_{dom_name}", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "algorithmic_bytes_per_launch": round(per_launch_bytes),
-                "avg_launch_us": round(1000.0 * dom_stat["ms"] / max(dom_stat["launches"], 1), 2),
-                "launches_per_solve": dom_stat["launches"],
-                "stream_copy_GBps": round(copy_gbps, 1), "frac_of_copy": round(achieved / copy_gbps, 4),
-                "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 4),
-                                "GBps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)} for k, v in prof.items()}}
-    print(f"# profile: {json.dumps(roofline['kernels'])}", file=sys.stderr, flush=True)
+    # ---- roofline of the dominant kernel: one more solve, HIP events around each launch
+    roofline = None
+    if not args.small:
+        rl.rlgl_profile_enable(s.ctx, True)
+        s.reset()
+        s.solve(eps, max_steps)
+        torch.cuda.synchronize()
+        prof = rl.rlgl_profile_read(s.ctx)
+        rl.rlgl_profile_enable(s.ctx, False)
+        dom = max(prof.items(), key=lambda kv: kv[1]["ms"])[0]
+        roofline = roofline_of(prof, copy_gbps, read_traffic(dom, g.name))
+        log(f"profile: {json.dumps(roofline['kernels'])}")
+    s.close() if hasattr(s, "close") else None
+    del s
 
     # ---- accuracy against FP64
     import oracle
@@ -384,70 +485,83 @@ def main():
     t_res = time.time()
     true_resid = oracle.residual(ch, pi)
     l1_bound = true_resid / (1.0 - g.c) if g.c < 1.0 else None
-    print(f"# FP64 residual of pi_hat {true_resid:.3e} -> certified L1 <= {l1_bound} "
-          f"({time.time() - t_res:.1f}s)", file=sys.stderr, flush=True)
+    log(f"FP64 residual of pi_hat {true_resid:.3e} -> certified L1 <= {l1_bound} ({time.time() - t_res:.1f}s)")
     l1_ref = None
     if not args.no_ref:
         t_ref = time.time()
-        if g.c < 1.0:
-            x, it = oracle.reference_pagerank(ch, 1e-10)
-        else:
-            pst, x, it = oracle.power_iteration(ch, 1e-13, 100000)
-            if pst != oracle.OK:
-                raise SystemExit("power iteration reference did not converge")
+        tol_pi = 1e-10 * (1.0 - g.c) if g.c < 1.0 else 1e-13
+        pst, x, it, _ = oracle.power_iteration_omp(ch, tol_pi, 100000)
+        if pst != oracle.OK:
+            raise SystemExit("power iteration reference did not converge")
         l1_ref = float(np.abs(pi - x).sum())
-        print(f"# L1 vs FP64 power iteration ({it} iterations, {time.time() - t_ref:.1f}s): {l1_ref:.3e}",
-              file=sys.stderr, flush=True)
+        del x
+        log(f"L1 vs FP64 power iteration ({it} iterations, {time.time() - t_ref:.1f}s): {l1_ref:.3e}")
 
-    # ---- CPU baseline: the oracle's own solve, same graph, same schedule and
-    # eps, stepped until the time budget is spent (full solves on small
-    # graphs, the first steps of one solve on large ones)
+    # ---- the other schedules on the same resident graph, and the Chung-Lu 2^20 graph under both
+    schedules = {wl["sched"]: {"ms_per_solve": round(ms_per_solve, 4), "steps": last["t"] - 1,
+                               "edge_pushes": last["edges_pushed"],
+                               "normalized_iterations": round(last["edges_pushed"] / g.nnz, 3),
+                               "gteps": round(gteps, 3), "fp64_residual": true_resid,
+                               "l1_certified_bound": l1_bound, "headline": True}}
+    chung_lu = None
+    if not args.no_legs and not args.small:
+        for alt in wl["alt"]:
+            schedules[alt] = schedule_leg(rl, torch, oracle, g, dg, alt, args, prec, route, stream, eps,
+                                          steps=max(1, min(args.steps, 3)), warmup=1, r=r)
+        if args.workload != "chung_lu_2p20":
+            g2 = make_workload("chung_lu_2p20")
+            dg2 = rl.DeviceGraph.from_workload(g2, precision=prec, with_csc=True, explicit_val=False, device=dev)
+            eps2 = (1.0 - g2.c) * args.tol
+            chung_lu = {"workload": g2.name, "n": g2.n, "nnz": g2.nnz, "link_values": "implicit",
+                        "schedules": {x: schedule_leg(rl, torch, oracle, g2, dg2, x, args, prec, route, stream,
+                                                      eps2, steps=max(1, min(args.steps, 5)), warmup=1)
+                                      for x in ("threshold", "all")}}
+            del dg2, g2
+            torch.cuda.empty_cache()
+
+    # ---- CPU baseline: the oracle's own serial solve loop (C, FP64, one core)
+    # on the same graph, schedule and eps: whole solves while they fit the time
+    # budget, else its first steps (step 0 included)
     cpu = None
     if not args.no_cpu:
         osched = {rl.SCHED_THRESHOLD: oracle.THRESHOLD, rl.SCHED_ALL: oracle.ALL, rl.SCHED_MAXC: oracle.MAXC,
                   rl.SCHED_PC: oracle.PC}[sched]
-        solves, steps, opushes, tcpu = 0, 0, 0, 0.0
         a = time.perf_counter()
-        t_print = a
-        st = oracle.State(ch)
-        while True:
-            if st.t >= 2 and st.resid < eps:
-                opushes += st.edges
+        ost, _, oinfo = oracle.solve(ch, osched, eps=eps, max_steps=1, r=r, seed=args.seed)
+        probe = time.perf_counter() - a
+        per_step = probe / 2.0
+        if ost == oracle.OK:
+            solves, opushes, tcpu = 0, 0, 0.0
+            while tcpu < args.cpu_seconds:
+                a = time.perf_counter()
+                ost, _, oinfo = oracle.solve(ch, osched, eps=eps, max_steps=10_000_000, r=r, seed=args.seed)
+                tcpu += time.perf_counter() - a
+                opushes += oinfo["edges_pushed"]
                 solves += 1
-                if time.perf_counter() - a >= args.cpu_seconds:
-                    st = None
-                    break
-                st = oracle.State(ch)
-            if time.perf_counter() - a >= args.cpu_seconds:
-                break
-            st.step(osched, r=wl["r"], seed=args.seed)
-            steps += 1
-            if time.perf_counter() - t_print >= 3.0:
-                t_print = time.perf_counter()
-                print(f"# cpu oracle: {steps} steps, {t_print - a:.1f}s", file=sys.stderr, flush=True)
-        if st is not None:
-            opushes += st.edges
-        tcpu = time.perf_counter() - a
-        sample = (f"{solves} full serial FP64 oracle solves of the same graph to the same eps ({steps} steps)"
-                  if st is None or st.t <= 1 else
-                  f"{solves} full solves and the first {st.t - 1} steps of another: serial FP64 oracle steps of "
-                  f"the same graph and schedule, {steps} steps in all")
+            sample = f"{solves} full solves of the serial FP64 oracle (C) on the same graph, schedule and eps"
+        else:
+            k = max(1, int(args.cpu_seconds / max(per_step, 1e-9)) - 1)
+            a = time.perf_counter()
+            ost, _, oinfo = oracle.solve(ch, osched, eps=eps, max_steps=k, r=r, seed=args.seed)
+            tcpu = time.perf_counter() - a
+            opushes = oinfo["edges_pushed"]
+            sample = (f"{'a full solve' if ost == oracle.OK else 'the first ' + str(oinfo['steps']) + ' steps'} "
+                      f"(step 0 included) of the serial FP64 oracle's solve loop (C) on the same graph and schedule")
         cpu = {"value": round(opushes / tcpu / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-               "sample": f"{sample} ({tcpu:.1f} s, step 0 included)",
-               "host": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
-        print(f"# cpu oracle: {cpu}", file=sys.stderr, flush=True)
+               "sample": f"{sample} ({tcpu:.1f} s)", "host": host_cpu_model(), "host_cpus": os.cpu_count()}
+        log(f"cpu oracle: {cpu}")
         # all host cores: FP64 power iteration (pull by columns, OpenMP) to the same L1 target
         if g.c < 1.0:
             a = time.perf_counter()
             pst, _, pit, threads = oracle.power_iteration_omp(ch, (1.0 - g.c) * args.tol, 100000)
             tpi = time.perf_counter() - a
-            links = int(g.nnz)
             cpu["power_iteration_all_cores"] = {
-                "value": round(pit * links / tpi / 1e9, 5), "unit": "GTEPS", "cores": threads,
+                "value": round(pit * int(g.nnz) / tpi / 1e9, 5), "unit": "GTEPS", "cores": threads,
                 "kind": "OpenMP FP64 power iteration", "iterations": pit, "seconds": round(tpi, 3),
                 "sample": "one full solve to the same L1 target, transpose built inside the timed region"}
-            print(f"# cpu power iteration, all cores: {cpu['power_iteration_all_cores']}", file=sys.stderr,
-                  flush=True)
+            log(f"cpu power iteration, all cores: {cpu['power_iteration_all_cores']}")
+    del ch, dg
+    torch.cuda.empty_cache()
 
     batched = batched_leg(args, rl, torch, oracle) if args.batch > 0 else None
     serving = serving_leg(args, rl, torch, oracle) if args.serve_requests > 0 else None
@@ -466,10 +580,12 @@ def main():
         "dtype": "f32" if prec != rl.FP64 else "f64",
         "data": "synthetic",
         "config": {"workload": g.name, "n": g.n, "nnz": g.nnz, "dangling": g.n_dangling, "damping": g.c,
-                   "schedule": wl["sched"], "r": wl["r"], "precision": args.precision, "route": args.route,
-                   "relabel": args.relabel, "link_values": args.link_values, "theta_period": args.theta_period,
+                   "schedule": wl["sched"], "r": r, "precision": args.precision, "route": args.route,
+                   "relabel": args.relabel, "link_values": wl["link_values"], "theta_period": args.theta_period,
+                   "solver": "one-workgroup" if args.small else "multi-launch",
                    "eps_resid": eps, "tol_l1": args.tol, "generator": g.params.get("generator"),
                    "seed": g.params.get("seed")},
+        "time_to_solution_ms": round(ms_per_solve, 4),
         "steps_per_solve": last["t"] - 1,
         "edge_pushes_per_solve": last["edges_pushed"],
         "normalized_iterations": round(last["edges_pushed"] / g.nnz, 3),
@@ -478,12 +594,13 @@ def main():
         "l1_vs_fp64_power_iteration": l1_ref,
         "fp64_residual": true_resid,
         "l1_certified_bound": l1_bound,
+        "schedules": schedules,
+        "chung_lu_2p20": chung_lu,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched": batched,
         "serving": serving,
     }
-    s.close()
     print(json.dumps(out), flush=True)
 
 

@@ -274,13 +274,25 @@ rlgl_status rlgl_get_green(rlgl_ctx *ctx, uint8_t *dev_mask);
 
 /* Per-kernel timing of the steps enqueued since the last call (HIP events on
  * the context's stream around every launch while enabled).  Fills up to 8
- * entries: name, launches, total milliseconds, algorithmic bytes moved.  The
- * return value is the number of entries (or a negative rlgl_status). */
+ * entries; the return value is the number of entries (or a negative
+ * rlgl_status).  `bytes` counts what the method itself must move (the cost
+ * of the links used, Sec. 6): a pull launch 4 B of source index, the link
+ * value when stored and the gathered moved cash per link of a green node
+ * that moved cash, plus 4 B of column pointer, the cash read and written and
+ * the moved cash per node; a push launch the link index, value and
+ * destination read-modify-write per such link plus the frontier entry per
+ * green row; a select launch the cash per node and the row pointers and
+ * history read-modify-write per green node (plus the frontier or the send
+ * values it writes).  `bytes_touched` counts what the launch's access
+ * pattern reads and writes: a pull reads every stored link, red or green,
+ * and a push adds into FP64 sums. */
 typedef struct {
   char name[24];
   int64_t launches;
   double ms;
-  double bytes;
+  double bytes;               /* algorithmic bytes */
+  double bytes_touched;       /* bytes of the access pattern */
+  int64_t green_links;        /* links of green nodes that moved cash, over the launches */
 } rlgl_kernel_stat;
 rlgl_status rlgl_profile_enable(rlgl_ctx *ctx, int32_t on);
 int32_t rlgl_profile_read(rlgl_ctx *ctx, rlgl_kernel_stat *out, int32_t max_entries);

@@ -53,7 +53,7 @@ class rlgl_step_info(ctypes.Structure):
 
 class rlgl_kernel_stat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
-                ("bytes", ctypes.c_double)]
+                ("bytes", ctypes.c_double), ("bytes_touched", ctypes.c_double), ("green_links", ctypes.c_int64)]
 
 
 BATCH_PERSISTENT, BATCH_LOCKSTEP = 0, 1
@@ -347,7 +347,8 @@ def rlgl_profile_read(ctx):
     m = _lib.rlgl_profile_read(ctx, buf, 8)
     if m < 0:
         raise RlglError(m, "rlgl_profile_read")
-    return {buf[i].name.decode(): {"launches": buf[i].launches, "ms": buf[i].ms, "bytes": buf[i].bytes}
+    return {buf[i].name.decode(): {"launches": buf[i].launches, "ms": buf[i].ms, "bytes": buf[i].bytes,
+                                   "bytes_touched": buf[i].bytes_touched, "green_links": buf[i].green_links}
             for i in range(m)}
 
 

@@ -959,29 +959,40 @@ int32_t rlgl_profile_read(rlgl_ctx *c, rlgl_kernel_stat *out, int32_t max_entrie
   const double vs = c->d.val ? cs : 0.0;
   const double hb = 16.0;  // history read-modify-write per green node
   const double n = (double)c->d.n, nnz = (double)c->d.nnz;
-  double ms[KS_N] = {0}, bytes[KS_N] = {0};
-  long long cnt[KS_N] = {0};
+  double ms[KS_N] = {0}, bytes[KS_N] = {0}, touched[KS_N] = {0};
+  long long cnt[KS_N] = {0}, links[KS_N] = {0};
   for (auto &L : c->launches) {
     const StepLog &lg = log[L.s % LOG_STEPS];
     if (lg.s != L.s) continue;  // launch of a step that never ran (after the stop) or fell off the ring
     const bool push = lg.mode == 0;
-    double b = 0.0;
+    const double ge = (double)lg.gedges;
+    double b = 0.0, bt = 0.0;
     if (L.kind == KS_SELECT) {
       b = cs * n + (double)lg.green * (8.0 + hb);
       if (push) b += (double)lg.nfront * (4 + 4 + 4 + cs) + (double)lg.green * cs;
       else b += cs * n;  // what each node sends along its links in the pull
+      bt = b;
     } else if (L.kind == KS_PUSH) {
       if (!push) continue;
-      b = (double)lg.gedges * (4.0 + vs + 2.0 * cs) + (double)lg.nfront * (8.0 + cs);
+      b = ge * (4.0 + vs + 2.0 * cs) + (double)lg.nfront * (8.0 + cs);
+      bt = ge * (4.0 + vs + (c->d.delta ? 16.0 : 2.0 * cs)) + (double)lg.nfront * (12.0 + cs);
     } else if (L.kind == KS_COMPLETE) {
-      b = push ? 2.0 * cs * n : (4.0 * n + nnz * (4.0 + vs + cs) + 2.0 * cs * n);
-    } else {
-      b = 0.0;
+      if (push) {
+        b = 2.0 * cs * n;
+        bt = b + (c->d.delta ? 16.0 * n : 0.0);
+      } else {
+        // per link of a green node: source index, stored value, gathered
+        // moved cash; per node: column pointer, cash read and write, moved cash
+        b = ge * (4.0 + vs + cs) + n * (4.0 + 3.0 * cs);
+        bt = nnz * (4.0 + vs + cs) + n * (4.0 + 3.0 * cs);
+      }
     }
     float e = 0.f;
     (void)hipEventElapsedTime(&e, L.a, L.b);
     ms[L.kind] += e;
     bytes[L.kind] += b;
+    touched[L.kind] += bt;
+    links[L.kind] += (L.kind == KS_SELECT || L.kind == KS_TOPK) ? 0 : lg.gedges;
     cnt[L.kind] += 1;
   }
   for (auto &L : c->launches) {
@@ -997,6 +1008,8 @@ int32_t rlgl_profile_read(rlgl_ctx *c, rlgl_kernel_stat *out, int32_t max_entrie
     out[m].launches = cnt[k];
     out[m].ms = ms[k];
     out[m].bytes = bytes[k];
+    out[m].bytes_touched = touched[k];
+    out[m].green_links = links[k];
     ++m;
   }
   return m;

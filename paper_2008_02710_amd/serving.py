@@ -28,7 +28,9 @@ def serve(pool, chains, arrivals, iterations: int = 4, on_result=None, clock=tim
     """Runs the request stream ``chains[i]`` arriving at ``arrivals[i]``
     seconds (non-decreasing) after the start and returns one record per
     request: arrival, admission and finish times (s), latency (s) and the
-    chain outcome of ``rlgl_pool_result``.  ``on_result(i, outcome, pi)``
+    chain outcome of ``rlgl_pool_result``; ``blocked`` says whether the request
+    once waited at the head of the queue because no slot or arena block was
+    free.  ``on_result(i, outcome, pi)``
     is called with the device pi_hat before the slot is released."""
     if any(b < a for a, b in zip(arrivals, arrivals[1:])):
         raise ValueError("arrival times must be non-decreasing")
@@ -48,6 +50,7 @@ def _serve(pool, chains, arrivals, iterations, on_result, clock, idle_sleep):
     queue: deque[int] = deque()
     slot_req: dict[int, int] = {}
     admitted = [0.0] * n
+    blocked = [False] * n  # the request once found no free slot or arena block at the head of the queue
     out = [None] * n
     done = 0
     while done < n:
@@ -63,6 +66,7 @@ def _serve(pool, chains, arrivals, iterations, on_result, clock, idle_sleep):
             i = queue[0]
             slot = pool.admit(chains[i])
             if slot is None:
+                blocked[i] = True
                 if not slot_req:
                     raise RuntimeError(f"request {i} does not fit an empty pool "
                                        f"(footprint {pool.footprint(chains[i].n, chains[i].nnz)} bytes)")
@@ -78,7 +82,8 @@ def _serve(pool, chains, arrivals, iterations, on_result, clock, idle_sleep):
                 res, pi = pool.result(slot)
                 if on_result is not None:
                     on_result(i, res, pi)
-                out[i] = dict(arrival=arrivals[i], admitted=admitted[i], finished=t, latency=t - arrivals[i], **res)
+                out[i] = dict(arrival=arrivals[i], admitted=admitted[i], finished=t, latency=t - arrivals[i],
+                              blocked=blocked[i], **res)
                 pool.release(slot)
                 done += 1
         elif nxt < n:
