@@ -279,6 +279,9 @@ rlgl_status read_back(rlgl_ctx *c) {
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->stale = false;
   c->t = c->host_glob->t;
+  if (c->host_glob->bad)
+    return fail(RLGL_EINVAL, "a kernel met a link index or plan entry outside its range: the graph breaks the "
+                             "contract of rlgl_graph (rlgl_validate names the first violation)");
   return RLGL_OK;
 }
 

@@ -63,8 +63,11 @@ __device__ void batch_chain(const BatchDev &b, int k, ColLds<NT> &L) {
   const double rr = b.r;
   const int tid = threadIdx.x;
   const int *__restrict__ rowptr = b.rowptr + cd.rp_off;
+  __shared__ int s_bad;  // a link index or plan item outside its range
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
   const ColView g{b.colptr + cd.rp_off, b.crow + cd.edge_off, rowptr,
-                  b.cval ? (const void *)((const T *)b.cval + cd.edge_off) : nullptr, n, 0};
+                  b.cval ? (const void *)((const T *)b.cval + cd.edge_off) : nullptr, n, 0, &s_bad};
   T *Ca = (T *)b.cash0 + cd.node_off;
   T *Cb = (T *)b.cash1 + cd.node_off;
   double *H64 = (double *)b.hist + cd.node_off;
@@ -103,7 +106,13 @@ __device__ void batch_chain(const BatchDev &b, int k, ColLds<NT> &L) {
   const Red4 s0 = block_sum4<NW>(Red4{accT, accM, 0, 0}, L.red);
   double hsum = s0.b, hnorm = s0.b;
   long long edges = cd.nnz;
-  route([&](int j) -> double { return ((unsigned)j < (unsigned)n) ? (double)m0 : 0.0; },
+  // a link outside [0, n) sends nothing and is reported
+  auto in_range = [&](int j) -> bool {
+    const bool ok = (unsigned)j < (unsigned)n;
+    if (!ok) s_bad = 1;
+    return ok;
+  };
+  route([&](int j) -> double { return in_range(j) ? (double)m0 : 0.0; },
         [&](int) -> double { return -(double)m0; }, s0.a / (double)n, Ca);
   T *cur = Ca, *oth = Cb;
   long long t = 1, refreshed = -1;
@@ -112,6 +121,7 @@ __device__ void batch_chain(const BatchDev &b, int k, ColLds<NT> &L) {
 
   for (;;) {
     resid = l1 / fabs(hsum);
+    if (s_bad) { status = ST_BAD_GRAPH; break; }
     if (!isfinite(l1) || !isfinite(hsum)) { status = ST_NONFINITE; break; }
     if (fabs(hsum) <= 1e-300 || fabs(hsum) <= 1e-12 * hnorm) { status = ST_ZERO_HISTORY; break; }
     // the rounding of FP32 cash leaves C_t 1 != 0; once that drift is half of
@@ -123,7 +133,7 @@ __device__ void batch_chain(const BatchDev &b, int k, ColLds<NT> &L) {
         double pool = 0.0;
         for (int i = tid; i < n; i += NT) pool += hist(i) * (deg(i) > 0 ? 1.0 - c : 1.0);
         pool = block_sum1<NW>(pool, L.red);
-        route([&](int j) -> double { return ((unsigned)j < (unsigned)n) ? hist(j) : 0.0; },
+        route([&](int j) -> double { return in_range(j) ? hist(j) : 0.0; },
               [&](int kk) -> double { return -hist(kk); }, pool / (double)n, oth);
         T *tmp = cur;
         cur = oth;
@@ -172,7 +182,7 @@ __device__ void batch_chain(const BatchDev &b, int k, ColLds<NT> &L) {
     // route (eq. (6)) by the CSC gather, M_j recomputed from the snapshot
     const T *cc = cur;
     route([&](int j) -> double {
-            if ((unsigned)j >= (unsigned)n) return 0.0;
+            if (!in_range(j)) return 0.0;
             const T v = cc[j];
             return green(v) ? (double)v : 0.0;
           },
@@ -186,7 +196,7 @@ __device__ void batch_chain(const BatchDev &b, int k, ColLds<NT> &L) {
     oth = tmp;
     ++t;
   }
-  if (status != ST_NONFINITE && hsum != 0.0)
+  if (status != ST_NONFINITE && status != ST_BAD_GRAPH && hsum != 0.0)
     for (int i = tid; i < n; i += NT) b.pi[cd.node_off + i] = hist(i) / hsum;  // eq. (2)
   if (tid == 0) {
     ChainOut o;

@@ -14,6 +14,7 @@ constexpr int RUN_MAX_COLS = 1024; // batched pull: columns per run item (4 per 
 constexpr int WU = 8;               // single-chain pull: links per lane of a wave item
 constexpr int WL = 64 * WU;         // single-chain pull: links per run item and per long-column piece
 constexpr int WCOLS = 64;           // single-chain pull: columns per run item
+constexpr int HOT_SRC = 6144;       // single-chain pull: send values of the lowest-numbered sources held in LDS
 constexpr int LOG_STEPS = 4096;     // ring of per-step records kept for profiling
 constexpr int MAX_GRID = 2048;      // edge-parallel launches
 constexpr int NODE_GRID = 512;      // node-parallel launches (2 workgroups per CU)
@@ -77,6 +78,8 @@ struct alignas(256) Rec {
 struct Glob {
   int status;
   unsigned int ticket;        // last-block detection in k_refresh
+  int bad;                    // a kernel met a link index or plan item outside its range (sticky)
+  int pad_;
   long long t;                // index of the current state
   double rpool;               // refresh: sum_j H_j (1 - c [outdeg_j > 0])
   // top-k radix select: bits fixed so far, entries still to take, the k-th key

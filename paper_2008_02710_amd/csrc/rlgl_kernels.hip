@@ -359,6 +359,13 @@ __global__ __launch_bounds__(BLOCK) void k_select(Dev d, long long s, double eps
   };
   if ((int)blockIdx.x < ntiles) load_tile(blockIdx.x);
   if (g->status != 0) return;
+  if (g->bad) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      g->status = ST_BAD_GRAPH;
+      g->t = s;
+    }
+    return;
+  }
 
   const Tot tot = read_totals(cur, &sh_tot);
   const double l1 = tot.l1, hsum = cur->hsum, hnorm = cur->hnorm;
@@ -555,8 +562,12 @@ __global__ __launch_bounds__(BLOCK) void k_push(Dev d, long long s) {
     const int e1 = min(tot, e0 + CH);
     const int j0 = d.chunk_first[b];
     const int j1 = (b + 1 < nchunks) ? d.chunk_first[b + 1] : nent - 1;
-    // a chunk overlaps at most CH + 1 frontier rows (every row has a link)
-    if (j0 < 0 || j1 >= nent || j1 < j0 || j1 - j0 + 1 > CH + 1) continue;
+    // a chunk overlaps at most CH + 1 frontier rows (every row has a link);
+    // anything else is a fault of the frontier, reported, never followed
+    if (j0 < 0 || j1 >= nent || j1 < j0 || j1 - j0 + 1 > CH + 1) {
+      d.glob->bad = 1;
+      continue;
+    }
     const int ne = j1 - j0 + 1;
     __syncthreads();
     for (int q = threadIdx.x; q < ne; q += BLOCK) {
@@ -573,13 +584,19 @@ __global__ __launch_bounds__(BLOCK) void k_push(Dev d, long long s) {
         else hi = mid - 1;
       }
       const int idx = s_rs[lo] + (e - s_eoff[lo]);
-      if ((unsigned long long)idx >= (unsigned long long)d.nnz) continue;
+      if ((unsigned long long)idx >= (unsigned long long)d.nnz) {
+        d.glob->bad = 1;
+        continue;
+      }
       const int dst = col[idx];
       const double amt = val ? (double)s_sc[lo] * (double)val[idx] : (double)s_sc[lo];
       if (dst >= 0) {
-        if (dst < d.n) atomic_add_f64(&D[dst], amt);  // links outside [0, N) are ignored
+        if (dst < d.n) atomic_add_f64(&D[dst], amt);
+        else d.glob->bad = 1;  // a link outside [0, N): reported, never followed
       } else if (-1 - dst < n_hot) {
         atomicAdd(&s_hot[-1 - dst], amt);
+      } else {
+        d.glob->bad = 1;
       }
     }
   }
@@ -642,6 +659,7 @@ struct ColView {
   const void *cval;
   int n;
   int unit;  // moved(j) already holds M_j P'_jk: every link weight is 1
+  int *bad;  // set when an item or a link index is out of range (may be null)
 };
 
 // LDS of the column pass over items of at most IC links and IK columns.
@@ -680,7 +698,10 @@ __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved m
     // RUN: every load below depends on the item alone
     const int k0 = item.x, k1 = item.y, p0 = item.z, p1 = item.w;
     const int ne = p1 - p0, ncol = k1 - k0;
-    if (ne > IC || ne < 0 || ncol > IK || ncol < 0) return;  // the plan never builds such an item
+    if (ne > IC || ne < 0 || ncol > IK || ncol < 0) {  // the plan never builds such an item
+      if (g.bad) *g.bad = 1;
+      return;
+    }
     __syncthreads();
     int jj[U];
     double ww[U];
@@ -837,6 +858,16 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
   __shared__ unsigned int s_kr[NWAVE][NK * 64];
   __shared__ double s_sum[NWAVE][WCOLS + 64];
   __shared__ double sh_red[4 * NWAVE];
+  // What the HOTK lowest-numbered sources send, staged once per workgroup:
+  // in the relabelled layout they are the states of largest out-degree, so
+  // their gathers (about a fifth of the links on R-MAT, half on the
+  // Chung-Lu graphs) read LDS instead of L2.  FP32 send values only (24 KB,
+  // four workgroups per CU still fit).
+  constexpr int HOTK = sizeof(S) == 4 ? HOT_SRC : 1;
+  __shared__ S s_hot[HOTK];
+  const int hk = sizeof(S) == 4 ? min(HOTK, d.n) : 0;
+  for (int q = threadIdx.x; q < hk; q += BLOCK) s_hot[q] = src[q];
+  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   int *row = s_row[wv];
@@ -945,11 +976,14 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
   int it = it0, round = 0;
   load_items(0);
   int4 cur = item_of(0);
-  // an item the plan cannot have built is skipped whole
+  // an item the plan cannot have built is not followed, and reported
+  int badl = 0;
   auto valid = [&](int4 item) {
     const int ne = item.w - item.z;
-    if (ne < 0 || ne > WL) return false;
-    return item.x < 0 || (item.y - item.x >= 1 && item.y - item.x <= WCOLS);
+    bool ok = ne >= 0 && ne <= WL;
+    ok = ok && (item.x < 0 || (item.y - item.x >= 1 && item.y - item.x <= WCOLS));
+    badl |= ok ? 0 : 1;
+    return ok;
   };
   if (it < n_items) fetch(valid(cur) ? cur : none);
   for (; it < n_items; it += stride, ++round) {
@@ -983,10 +1017,12 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
     bool ok[WU];
 #pragma unroll
     for (int u = 0; u < WU; ++u) {
-      // jj is -1 past the item's end; links outside [0, N) send nothing
+      // jj is -1 past the item's end; a link outside [0, N) sends nothing
+      // and is reported
       const unsigned int j = (unsigned int)jj[u];
       ok[u] = j < (unsigned int)n;
-      xr[u] = src[ok[u] ? j : 0u];
+      badl |= (e0 + u < item.w - item.z && !ok[u]) ? 1 : 0;
+      xr[u] = (j < (unsigned int)hk) ? s_hot[j] : src[ok[u] ? j : 0u];
     }
     T wr[WU];
     const T *__restrict__ vals = cval + (VAL ? item.z : 0);
@@ -1104,6 +1140,7 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
     advance();
     advance();
   }
+  if (badl) d.glob->bad = 1;
   fold_block_stats(r, l1, cs, sr, mx, sh_red);
 }
 
@@ -1358,7 +1395,7 @@ __global__ __launch_bounds__(BLOCK) void k_zero_f64(double *p, int n) {
 __global__ void k_refresh_done(Dev d, long long t, int out_buf) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   d.rec[t % 3].buf = out_buf;
-  d.glob->status = 0;
+  d.glob->status = d.glob->bad ? ST_BAD_GRAPH : 0;
 }
 
 // ------------------------------------------------------------ init / misc
@@ -1397,6 +1434,7 @@ __global__ __launch_bounds__(BLOCK) void k_reset(Dev d) {
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     d.glob->status = 0;
+    d.glob->bad = 0;
     d.glob->t = 0;
     d.glob->ticket = 0u;
     d.glob->rpool = 0.0;
@@ -1526,6 +1564,7 @@ __global__ void k_prepare_import(Dev d, long long t, int buf) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     d.log[(t + LOG_STEPS - 1) % LOG_STEPS].gedges = d.nnz;  // the AUTO router sees a dense previous step
     d.glob->status = 0;
+    d.glob->bad = 0;
     d.glob->t = t;
   }
 }

@@ -60,6 +60,7 @@ struct LsCtl {
   long long t, refreshed, edges, t0, t1;
   double theta, maxabs, hsum, hnorm, resid;
   int mode, buf, status, green_steps;
+  int bad, pad_;  // a route met a link index or plan item outside its range
 };
 
 struct alignas(128) LsStripe {
@@ -195,7 +196,8 @@ __device__ __forceinline__ void ls_item(const LsArgs &a, int k, int mode, int lo
   const LsChain ch = a.chains[k];
   const LsCtl *ctl = &a.ctl[k];
   const int n = ch.n;
-  const ColView g{ch.colptr, ch.crow, ch.rowptr, nullptr, n, 1};
+  int *bad = &a.ctl[k].bad;
+  const ColView g{ch.colptr, ch.crow, ch.rowptr, nullptr, n, 1, bad};
   const int buf = ctl->buf;
   const T *__restrict__ cur = (const T *)(buf ? ch.cash1 : ch.cash0);
   T *__restrict__ out = (T *)(buf ? ch.cash0 : ch.cash1);
@@ -209,8 +211,10 @@ __device__ __forceinline__ void ls_item(const LsArgs &a, int k, int mode, int lo
   column_item<T, NT>(
       g, item,
       [&](int j) -> double {
-        // a load at a clamped index and a select, not a branch per link
+        // a load at a clamped index and a select, not a branch per link; a
+        // link outside [0, n) sends nothing and is reported
         const bool ok = (unsigned)j < (unsigned)n;
+        if (!ok) *bad = 1;
         const unsigned int jc = ok ? (unsigned int)j : 0u;
         const double v = refresh ? hs[jc] : (double)src[jc];
         return ok ? v : 0.0;
@@ -404,7 +408,9 @@ __global__ __launch_bounds__(64) void k_ls_control(LsArgs a) {
   const double resid = l1 / fabs(hsum);
   ctl->resid = resid;
   int next = LS_STEP, status = 0;
-  if (!isfinite(l1) || !isfinite(hsum)) {
+  if (ctl->bad) {
+    status = ST_BAD_GRAPH;
+  } else if (!isfinite(l1) || !isfinite(hsum)) {
     status = ST_NONFINITE;
   } else if (fabs(hsum) <= 1e-300 || fabs(hsum) <= 1e-12 * hnorm) {
     status = ST_ZERO_HISTORY;
@@ -419,7 +425,7 @@ __global__ __launch_bounds__(64) void k_ls_control(LsArgs a) {
   }
   if (status != 0) {
     ctl->status = status;
-    if (status != ST_NONFINITE && hsum != 0.0) {
+    if (status != ST_NONFINITE && status != ST_BAD_GRAPH && hsum != 0.0) {
       next = LS_FINISH;
     } else {
       next = LS_DONE;
@@ -458,6 +464,8 @@ __global__ void k_ls_start(const LsChain *chains, LsCtl *ctl, LsStripe *stats, c
   z.mode = LS_INIT;
   z.buf = 0;
   z.status = 0;
+  z.bad = 0;
+  z.pad_ = 0;
   z.green_steps = 0;
   ctl[k] = z;
   for (int s = 0; s < LS_NS; ++s) {
@@ -492,6 +500,8 @@ __global__ void k_ls_admit(LsChain *chains, LsCtl *ctl, LsStripe *stats, int slo
   z.mode = LS_INIT;
   z.buf = 0;
   z.status = 0;
+  z.bad = 0;
+  z.pad_ = 0;
   z.green_steps = 0;
   ctl[slot] = z;
   for (int s = 0; s < LS_NS; ++s) {

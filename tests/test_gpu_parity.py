@@ -147,9 +147,62 @@ def _step_parity(prec, route, sched, which, relabel):
     C1, H1, info2 = s.state()
     assert info2["t"] == 5
     assert l1(to_np(C1), ost.C) <= tol_step(prec) * moved + 1e-300
+    # element by element: every node within the rounding its own terms allow
+    # (R_k bounds the sum of |terms| arriving at k: route of |M|)
+    M = np.where(want, Cg, 0.0)
+    R = oracle.route(oracle_chain(g), np.abs(M)) + np.abs(Cg)
+    indeg = np.diff(g.csc()[0]).astype(np.float64)
+    # the restart share T/N is summed over all green nodes in another order:
+    # its error is at most u sum |M| (N terms, divided by N) on every node
+    pool_err = 2.3e-16 * float(np.abs(M).sum())
+    if prec == rl.FP64:
+        bound = (indeg + 4.0) * 2.3e-16 * R + pool_err
+    else:
+        bound = 1.3e-7 * R + 6e-8 * np.abs(ost.C) + (indeg + 4.0) * 2.3e-16 * R + pool_err
+    err = np.abs(to_np(C1) - ost.C)
+    worst = int(np.argmax(err - bound))
+    assert np.all(err <= bound + 1e-300), (worst, err[worst], bound[worst])
     assert l1(to_np(H1), ost.H) <= (1e-15 * moved if prec == rl.FP64 else 1e-13 + 1e-7 * moved)
     assert abs(info2["h_sum"] - ost.hsum) <= 1e-14
     assert info2["l1_cash"] == pytest.approx(float(np.abs(to_np(C1)).sum()), rel=1e-12, abs=1e-300)
+    s.close()
+
+
+# ------------------------------------------------------------- refresh
+
+@pytest.mark.parametrize("prec", PRECS, ids=PREC_NAMES.get)
+@pytest.mark.parametrize("relabel", [0, 1])
+@pytest.mark.parametrize("which", ["small", "hub"])
+def test_refresh_matches_oracle(prec, relabel, which):
+    """rlgl_refresh rebuilds C_t = H_t P - H_t (eq. (7) with C_0 = 0): against
+    the oracle's route(H) - H in FP64, element by element, with long columns
+    (the hub graph has columns of more than 4096 in-links) and in the
+    relabelled layout; H itself is left unchanged."""
+    g = small_graph() if which == "small" else hub_graph()
+    say("case refresh", which, PREC_NAMES[prec], relabel)
+    s = solver(g, prec, sched=rl.SCHED_THRESHOLD, relabel=relabel)
+    s.step(6)
+    _, H, info = s.state()
+    H = to_np(H)
+    s.refresh()
+    C2, H2, info2 = s.state()
+    C2, H2 = to_np(C2), to_np(H2)
+    assert np.array_equal(H2, H) and info2["t"] == info["t"]
+    ch = oracle_chain(g)
+    want = oracle.route(ch, H) - H
+    R = oracle.route(ch, np.abs(H)) + np.abs(H)
+    indeg = np.diff(g.csc()[0]).astype(np.float64)
+    # the restart share is summed over all nodes in another order: at most
+    # u sum |H| on every node
+    bound = (indeg + 4.0) * 2.3e-16 * R + 2.3e-16 * float(np.abs(H).sum())
+    if prec != rl.FP64:
+        # FP32 link values (relative 2^-24 each) and one rounding of the result
+        bound = bound + 1.3e-7 * R + 6e-8 * np.abs(want)
+    err = np.abs(C2 - want)
+    worst = int(np.argmax(err - bound))
+    assert np.all(err <= bound + 1e-300), (worst, err[worst], bound[worst])
+    # the statistics the step records now describe the rebuilt cash
+    assert info2["l1_cash"] == pytest.approx(float(np.abs(C2).sum()), rel=1e-12)
     s.close()
 
 

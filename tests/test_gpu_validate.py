@@ -130,3 +130,65 @@ def test_scratch_and_arguments():
         rl.rlgl_validate(gs, 7, ok, need)
     assert e.value.status == rl.RLGL_EINVAL
     assert rl.rlgl_validate(gs, rl.FP32C_FP64H, ok, need) <= 1e-6
+
+
+# ------------------------------------------------ out-of-range links in the solvers
+#
+# A solver reads link indices only through its own range checks: a source or
+# destination outside [0, n) is never followed, and the call fails with
+# RLGL_EINVAL instead of returning a wrong pi_hat.
+
+
+def _broken(g, which, prec=rl.FP32C_FP64H):
+    dg = device(g, prec, stored=False)
+    # links 7 and nnz // 2 point past the last state
+    if which == "csc":
+        dg.row[7] = g.n + 3
+        dg.row[g.nnz // 2] = g.n
+    else:
+        dg.col[7] = g.n + 3
+        dg.col[g.nnz // 2] = g.n
+    torch.cuda.synchronize()
+    return dg
+
+
+@pytest.mark.parametrize("route", [rl.ROUTE_PULL, rl.ROUTE_PUSH])
+@pytest.mark.parametrize("relabel", [0, 1])
+def test_solver_reports_links_out_of_range(route, relabel):
+    g = graph()
+    which = "csc" if route == rl.ROUTE_PULL else "csr"
+    say("case broken_solve", which, relabel)
+    dg = _broken(g, which)
+    s = rl.Solver(dg, sched=rl.SCHED_ALL, route=route, relabel=relabel)
+    st, info = s.solve(1e-9, max_steps=50, raise_on_error=False)
+    assert st == rl.RLGL_EINVAL
+    assert "outside its range" in rl.rlgl_last_error()
+    s.close()
+
+
+def test_small_solver_reports_links_out_of_range():
+    g = graph()
+    say("case broken_small")
+    for which in ("csc", "csr"):
+        dg = _broken(g, which, rl.FP64)
+        s = rl.SmallSolver(dg, sched=rl.SCHED_MAXC if which == "csr" else rl.SCHED_ALL)
+        st, info = s.solve(1e-9, max_steps=200000, raise_on_error=False)
+        assert st == rl.RLGL_EINVAL and "out of range" in rl.rlgl_last_error()
+
+
+@pytest.mark.parametrize("engine", [rl.BATCH_LOCKSTEP, rl.BATCH_PERSISTENT])
+def test_batch_reports_links_out_of_range(engine):
+    gs = [workloads.chung_lu(n, 2.3, 6.0, 0.0, 0.85, seed=60 + k, name=f"b{k}")
+          for k, n in enumerate((3000, 1200, 5000))]
+    say("case broken_batch", engine)
+    db = rl.DeviceBatch(gs, precision=rl.FP32C_KAHANH, tol_l1=1e-6)
+    # one source of chain 1 points past its last state
+    db.row[int(db.edge_off[1]) + 5] = gs[1].n + 2
+    torch.cuda.synchronize()
+    bs = rl.BatchSolver(db, engine=engine, max_steps=1000,
+                        wg_size=256 if engine == rl.BATCH_LOCKSTEP else 512)
+    st, res, _ = bs.solve(raise_on_error=False)
+    assert res[1]["status"] == rl.RLGL_EINVAL
+    assert res[0]["status"] == rl.RLGL_OK and res[2]["status"] == rl.RLGL_OK
+    assert st == rl.RLGL_EINVAL
+    bs.close()
