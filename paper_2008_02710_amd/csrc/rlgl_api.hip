@@ -56,13 +56,14 @@ size_t record_span() { return records_bytes() + sizeof(Glob); }
 struct Layout {
   size_t cash0, cash1, hist, hist_lo, fr_rowstart, fr_eoff, fr_id, fr_scale, chunk_first, green_mask, delta, colt,
       hot_nodes, rec, glob,
-      log, items, long_cols, long_acc, long_cnt, total;
+      log, items, long_cols, long_acc, long_cnt, khist, tk_ckey, tk_cid, tk_hist, tk_cnt, total;
   size_t max_items, max_long;
   // relabelled layout
   size_t perm, old2new, nrowptr, ncol, nval, ncolptr, nrow, ncval;
 };
 
-Layout make_layout(long long n, long long nnz, int prec, bool has_csc, bool relabel = false, bool has_val = false) {
+Layout make_layout(long long n, long long nnz, int prec, bool has_csc, bool relabel = false, bool has_val = false,
+                   bool topk = false) {
   Layout L{};
   const size_t cs = (prec == RLGL_FP64) ? 8 : 4;
   size_t off = 0;
@@ -98,6 +99,13 @@ Layout make_layout(long long n, long long nnz, int prec, bool has_csc, bool rela
     L.long_cols = take(4 * L.max_long);
     L.long_acc = take(8 * L.max_long);
     L.long_cnt = take(4 * L.max_long);
+  }
+  if (topk) {
+    L.khist = take(4 * (size_t)3 * KH_STRIPES * KH_BINS);
+    L.tk_ckey = take(8 * (size_t)n);
+    L.tk_cid = take(4 * (size_t)n);
+    L.tk_hist = take(4 * (size_t)3 * KH_BINS);
+    L.tk_cnt = take(4 * (size_t)SEL_GRID);
   }
   if (relabel) {
     const size_t vs = (prec == RLGL_FP64) ? 8 : 4;
@@ -162,6 +170,7 @@ struct rlgl_ctx {
   int refresh;
   long long refreshes;
   bool stale;  // host_rec / host_glob older than the device's (after a reset)
+  bool khist_stale;  // the top-k histogram of the current record does not describe its cash
 };
 
 namespace {
@@ -194,14 +203,20 @@ hipError_t timed(rlgl_ctx *c, int kind, long long s, F launch) {
 
 // k_complete and k_refresh come in variants by stored or implied link values
 // and by whether the threshold's power mean needs sum |C|^r (r != 1).
-template <class T>
-void launch_complete(rlgl_ctx *c, long long s, int force_all) {
+template <class T, bool TK>
+void launch_complete_tk(rlgl_ctx *c, long long s, int force_all) {
   const Dev &d = c->d;
   const bool v = d.cval != nullptr, rp = d.r != 1.0;
-  if (v && rp) k_complete<T, true, true><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, s, force_all);
-  else if (v) k_complete<T, true, false><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, s, force_all);
-  else if (rp) k_complete<T, false, true><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, s, force_all);
-  else k_complete<T, false, false><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, s, force_all);
+  if (v && rp) k_complete<T, true, true, TK><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, s, force_all);
+  else if (v) k_complete<T, true, false, TK><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, s, force_all);
+  else if (rp) k_complete<T, false, true, TK><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, s, force_all);
+  else k_complete<T, false, false, TK><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, s, force_all);
+}
+// The top-k rule needs the histogram of the keys the pass writes.
+template <class T>
+void launch_complete(rlgl_ctx *c, long long s, int force_all) {
+  if (c->d.sched == SCHED_TOPK) launch_complete_tk<T, true>(c, s, force_all);
+  else launch_complete_tk<T, false>(c, s, force_all);
 }
 
 // Workgroups of the k_complete variant launch_complete picks that fit one CU together.
@@ -209,12 +224,21 @@ hipError_t complete_occupancy(const rlgl_ctx *c, int *per_cu) {
   const Dev &d = c->d;
   const bool v = d.cval != nullptr, rp = d.r != 1.0;
   const void *f;
-  if (c->prec == RLGL_FP64)
-    f = v ? (rp ? (const void *)k_complete<double, true, true> : (const void *)k_complete<double, true, false>)
-          : (rp ? (const void *)k_complete<double, false, true> : (const void *)k_complete<double, false, false>);
-  else
-    f = v ? (rp ? (const void *)k_complete<float, true, true> : (const void *)k_complete<float, true, false>)
-          : (rp ? (const void *)k_complete<float, false, true> : (const void *)k_complete<float, false, false>);
+  if (d.sched == SCHED_TOPK) {
+    if (c->prec == RLGL_FP64)
+      f = v ? (rp ? (const void *)k_complete<double, true, true, true> : (const void *)k_complete<double, true, false, true>)
+            : (rp ? (const void *)k_complete<double, false, true, true> : (const void *)k_complete<double, false, false, true>);
+    else
+      f = v ? (rp ? (const void *)k_complete<float, true, true, true> : (const void *)k_complete<float, true, false, true>)
+            : (rp ? (const void *)k_complete<float, false, true, true> : (const void *)k_complete<float, false, false, true>);
+  } else {
+    if (c->prec == RLGL_FP64)
+      f = v ? (rp ? (const void *)k_complete<double, true, true, false> : (const void *)k_complete<double, true, false, false>)
+            : (rp ? (const void *)k_complete<double, false, true, false> : (const void *)k_complete<double, false, false, false>);
+    else
+      f = v ? (rp ? (const void *)k_complete<float, true, true, false> : (const void *)k_complete<float, true, false, false>)
+            : (rp ? (const void *)k_complete<float, false, true, false> : (const void *)k_complete<float, false, false, false>);
+  }
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, f, BLOCK, 0);
 }
 
@@ -234,17 +258,37 @@ hipError_t enqueue_step(rlgl_ctx *c, long long s, double eps, long long s_limit,
   hipError_t e = hipSuccess;
   if (!force_all && d.sched == SCHED_TOPK) {
     e = timed(c, KS_TOPK, s, [&] {
-      // radix select of the k-th largest |C| and of the id bound among its ties
-      const int key_bits = (c->prec == RLGL_FP64) ? 64 : 32;
-      const int hg = std::max(1, std::min((d.n + BLOCK - 1) / BLOCK, 1024));
-      k_topk_init<<<1, 256, 0, c->stream>>>(d);
-      for (int ids = 0; ids < 2; ++ids) {
-        const int bits = ids ? 32 : key_bits;
-        for (int shift = bits - 8; shift >= 0; shift -= 8) {
-          if (c->prec == RLGL_FP64) k_topk_hist<double><<<hg, BLOCK, 0, c->stream>>>(d, s, shift, ids);
-          else k_topk_hist<float><<<hg, BLOCK, 0, c->stream>>>(d, s, shift, ids);
-          k_topk_pick<<<1, 64, 0, c->stream>>>(d, s, shift, ids, shift == 0, key_bits);
-        }
+      // the k-th largest |C| and the id bound among its ties: the bin of the
+      // histogram the previous complete pass counted, its candidates, then a
+      // one-workgroup radix select over them
+      const bool dbl = c->prec == RLGL_FP64;
+      if (c->khist_stale) {
+        k_topk_hist_zero<<<8, 256, 0, c->stream>>>(d, s);
+        if (dbl) k_topk_hist_full<double><<<c->grid_sel, BLOCK, 0, c->stream>>>(d, s);
+        else k_topk_hist_full<float><<<c->grid_sel, BLOCK, 0, c->stream>>>(d, s);
+        c->khist_stale = false;
+      }
+      // the digits below bin B, then those of the ids (ids < 2^31)
+      TkDigit dg[8];
+      int nd = 0;
+      for (int lo = (dbl ? 63 : 31) - KH_BITS; lo > 0;) {
+        const int w = std::min(lo, KH_BITS);
+        lo -= w;
+        dg[nd++] = TkDigit{0, lo, w};
+      }
+      for (int lo = 31; lo > 0;) {
+        const int w = std::min(lo, KH_BITS);
+        lo -= w;
+        dg[nd++] = TkDigit{1, lo, w};
+      }
+      const int pg = std::max(1, std::min(c->grid_sel, 256));
+      if (dbl) k_topk_collect<double><<<d.tk_grid, BLOCK, 0, c->stream>>>(d, s);
+      else k_topk_collect<float><<<d.tk_grid, BLOCK, 0, c->stream>>>(d, s);
+      for (int p = 0; p <= nd; ++p) {
+        const TkDigit prev = p > 0 ? dg[p - 1] : TkDigit{0, 0, 0};
+        const TkDigit cur = p < nd ? dg[p] : TkDigit{1, 0, 0};
+        if (dbl) k_topk_pass<double><<<p < nd ? pg : 1, BLOCK, 0, c->stream>>>(d, s, p, prev, cur);
+        else k_topk_pass<float><<<p < nd ? pg : 1, BLOCK, 0, c->stream>>>(d, s, p, prev, cur);
       }
     });
     if (e != hipSuccess) return e;
@@ -305,6 +349,7 @@ void fill_info(rlgl_ctx *c, rlgl_step_info *info, int status) {
 }
 
 rlgl_status reset_device(rlgl_ctx *c) {
+  c->khist_stale = false;  // step 0 counts the histogram of C_1
   const Dev &d = c->d;
   const int gr = std::max(3, c->grid_misc);  // blocks 0..2 clear the three records
   if (c->prec == RLGL_FP64) k_reset<double, 0><<<gr, BLOCK, 0, c->stream>>>(d);
@@ -346,6 +391,7 @@ rlgl_status do_refresh(rlgl_ctx *c, bool sync = true) {
   k_refresh_done<<<1, 64, 0, c->stream>>>(d, t, out);
   HIP_TRY(hipGetLastError());
   ++c->refreshes;
+  c->khist_stale = true;  // the rebuilt cash has no histogram of its own
   if (!sync) {
     c->stale = true;  // the refresh keeps t; the next read-back renews the copies
     return RLGL_OK;
@@ -653,7 +699,8 @@ rlgl_status rlgl_validate(const rlgl_graph *g, int32_t precision, void *dev_scra
 
 size_t rlgl_workspace_bytes(const rlgl_graph *g, const rlgl_options *o) {
   if (!g || !o || g->n < 1 || g->nnz < 0 || o->precision < 0 || o->precision > 2) return 0;
-  return make_layout(g->n, g->nnz, o->precision, g->csc_colptr != nullptr, o->relabel != 0, g->csr_val != nullptr)
+  return make_layout(g->n, g->nnz, o->precision, g->csc_colptr != nullptr, o->relabel != 0, g->csr_val != nullptr,
+                     o->sched == RLGL_SCHED_TOPK)
       .total;
 }
 
@@ -672,8 +719,8 @@ rlgl_status rlgl_create(const rlgl_graph *g, const rlgl_options *o, void *ws, si
   if ((g->csr_val == nullptr) != (g->csc_colptr ? g->csc_val == nullptr : g->csr_val == nullptr))
     return fail(RLGL_EINVAL, "csr_val and csc_val must both be given or both be NULL");
   if (!ws) return fail(RLGL_EINVAL, "workspace is NULL");
-  const Layout L =
-      make_layout(g->n, g->nnz, o->precision, g->csc_colptr != nullptr, o->relabel != 0, g->csr_val != nullptr);
+  const Layout L = make_layout(g->n, g->nnz, o->precision, g->csc_colptr != nullptr, o->relabel != 0,
+                               g->csr_val != nullptr, o->sched == RLGL_SCHED_TOPK);
   if (ws_bytes < L.total) return fail(RLGL_ENOMEM, "workspace too small: %zu < %zu", ws_bytes, L.total);
 
   rlgl_ctx *c = new (std::nothrow) rlgl_ctx();
@@ -733,9 +780,17 @@ rlgl_status rlgl_create(const rlgl_graph *g, const rlgl_options *o, void *ws, si
   d.long_cnt = nullptr;
   d.n_long = 0;
   d.perm = nullptr;
+  const bool topk = o->sched == RLGL_SCHED_TOPK;
+  d.khist = topk ? (unsigned int *)(w + L.khist) : nullptr;
+  d.tk_ckey = topk ? (unsigned long long *)(w + L.tk_ckey) : nullptr;
+  d.tk_cid = topk ? (int *)(w + L.tk_cid) : nullptr;
+  d.tk_hist = topk ? (unsigned int *)(w + L.tk_hist) : nullptr;
+  d.tk_cnt = topk ? (int *)(w + L.tk_cnt) : nullptr;
+  c->khist_stale = false;
 
   const int tiles = (g->n + TILE - 1) / TILE;
   c->grid_sel = std::max(1, std::min(tiles, SEL_GRID));
+  d.tk_grid = std::min(c->grid_sel, 256);  // workgroups of the collecting pass
   c->grid_push = (int)std::max<long long>(1, std::min<long long>((g->nnz + CH - 1) / CH, PUSH_GRID));
   c->grid_misc = std::max(1, std::min((g->n + BLOCK - 1) / BLOCK, NODE_GRID));
 
@@ -826,6 +881,7 @@ rlgl_status rlgl_step_mask(rlgl_ctx *c, const uint8_t *dev_mask, rlgl_step_info 
   const hipError_t e = enqueue_step(c, s0, -1.0, s0 + 1, 0);
   c->d.sched = sched;
   c->d.green_in = nullptr;
+  c->khist_stale = true;  // that step's complete pass counted no histogram
   HIP_TRY(e);
   rlgl_status st = read_back(c);
   if (st != RLGL_OK) return st;
@@ -930,6 +986,7 @@ rlgl_status rlgl_set_state(rlgl_ctx *c, const double *dC, const double *dH, doub
   else k_import<float, 0><<<c->grid_misc, BLOCK, 0, c->stream>>>(c->d, dC, dH, t, buf);
   k_finish_import<<<1, 64, 0, c->stream>>>(c->d, t, h_sum);
   HIP_TRY(hipGetLastError());
+  c->khist_stale = true;
   return read_back(c);
 }
 

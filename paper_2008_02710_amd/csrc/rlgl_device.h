@@ -15,6 +15,10 @@ constexpr int WU = 8;               // single-chain pull: links per lane of a wa
 constexpr int WL = 64 * WU;         // single-chain pull: links per run item and per long-column piece
 constexpr int WCOLS = 64;           // single-chain pull: columns per run item
 constexpr int HOT_SRC = 6144;       // single-chain pull: send values of the lowest-numbered sources held in LDS
+constexpr int HOT_SRC_TK = 4096;    // the same when the pull also counts the top-k histogram (LDS budget)
+constexpr int KH_BITS = 11;         // top-k: bits of the |C| key counted by the pass that writes C
+constexpr int KH_BINS = 1 << KH_BITS;
+constexpr int KH_STRIPES = 4;       // global copies of the top-k histogram
 constexpr int LOG_STEPS = 4096;     // ring of per-step records kept for profiling
 constexpr int MAX_GRID = 2048;      // edge-parallel launches
 constexpr int NODE_GRID = 512;      // node-parallel launches (2 workgroups per CU)
@@ -82,10 +86,13 @@ struct Glob {
   int pad_;
   long long t;                // index of the current state
   double rpool;               // refresh: sum_j H_j (1 - c [outdeg_j > 0])
-  // top-k radix select: bits fixed so far, entries still to take, the k-th key
-  unsigned long long tk_prefix, tk_key;
-  long long tk_rem;
-  unsigned int tk_hist[256];
+  // top-k: the histogram bin that holds the k-th key, the keys of that bin
+  // still to take, and the length of its candidate list
+  unsigned long long tk_pref[2];  // radix state of the passes (double-buffered by pass parity)
+  long long tk_rem[2];
+  unsigned long long tk_tau;      // the k-th key, once its digits are fixed
+  int tk_done;  // tau and the id bound of the running top-k select are written
+  unsigned int pad2_;
 };
 
 struct StepLog {
@@ -141,6 +148,13 @@ struct Dev {
   int n_long;
   // relabelled layout: internal index -> caller's id (NULL: the caller's numbering)
   const int *perm;
+  // top-k: histograms of the top key bits per record, candidate keys and ids
+  unsigned int *khist;         // [3][KH_STRIPES][KH_BINS]
+  unsigned long long *tk_ckey;  // [n]
+  int *tk_cid;                  // [n]
+  unsigned int *tk_hist;        // [3][KH_BINS] digit histograms of the passes over the candidates
+  int *tk_cnt;                  // [tk_grid] candidates each collecting workgroup found
+  int tk_grid;                  // workgroups of the collecting pass
 };
 
 // Host-side sum of the stripes (same order as the device).

@@ -411,6 +411,11 @@ __global__ __launch_bounds__(BLOCK) void k_select(Dev d, long long s, double eps
       nxt->ticket = 0u;
     }
     clear_stripes(nxt);
+    if (d.khist && d.sched == SCHED_TOPK) {
+      // the top-k histogram the complete pass of this step fills
+      unsigned int *kh = d.khist + (size_t)((s + 1) % 3) * KH_STRIPES * KH_BINS;
+      for (int q = threadIdx.x; q < KH_STRIPES * KH_BINS; q += BLOCK) kh[q] = 0u;
+    }
   }
 
   const double c = d.c;
@@ -624,6 +629,51 @@ __global__ void k_indegree(Dev d, int *indeg) {
     const int j = d.col[e];
     if ((unsigned)j < (unsigned)d.n) atomicAdd(&indeg[j], 1);
   }
+}
+
+// ------------------------------------------------------------ top-k keys
+
+template <class T>
+__device__ __forceinline__ unsigned long long topk_key(T v) {
+  if (sizeof(T) == 4) return (unsigned long long)__float_as_uint(fabsf((float)v));
+  return (unsigned long long)__double_as_longlong(fabs((double)v));
+}
+template <class T>
+__device__ __forceinline__ int kh_bin(T v) {
+  return (int)(topk_key(v) >> (sizeof(T) == 4 ? 31 - KH_BITS : 63 - KH_BITS));
+}
+// Positions of the candidate list each collecting workgroup owns: a multiple
+// of the workgroup size, so that the last one ends at or past n.
+__device__ __forceinline__ int tk_segment(int n, int grid) {
+  const int per = (n + grid - 1) / grid;
+  return (per + BLOCK - 1) / BLOCK * BLOCK;
+}
+__device__ __forceinline__ unsigned int *khist_of(const Dev &d, long long s) {
+  return d.khist + (size_t)(s % 3) * KH_STRIPES * KH_BINS;
+}
+// Adds one per active lane to h[bin] (bin < 2^BITS).  The lanes of a wave
+// that share a bin are found with BITS ballots and counted by one atomic, so
+// a histogram whose values crowd into a few bins costs one LDS atomic per
+// distinct bin per wave instead of up to 64 on one address.  Every lane of
+// the wave that is still executing must call it.
+template <int BITS>
+__device__ __forceinline__ void wave_hist_add(unsigned int *h, unsigned int bin, bool active) {
+  unsigned long long same = __ballot(active);
+#pragma unroll
+  for (int b = 0; b < BITS; ++b) {
+    const bool bit = (bin >> b) & 1u;
+    const unsigned long long m = __ballot(bit);
+    same &= bit ? m : ~m;
+  }
+  const int lane = threadIdx.x & 63;
+  if (active && (same & ((1ull << lane) - 1ull)) == 0ull) atomicAdd(&h[bin], (unsigned int)__popcll(same));
+}
+
+// Adds a workgroup's LDS histogram to stripe blockIdx mod KH_STRIPES.
+__device__ __forceinline__ void kh_flush(unsigned int *kh, const unsigned int *s_kh) {
+  unsigned int *dst = kh + (size_t)(blockIdx.x % KH_STRIPES) * KH_BINS;
+  for (int b = threadIdx.x; b < KH_BINS; b += blockDim.x)
+    if (s_kh[b]) atomicAdd(&dst[b], s_kh[b]);
 }
 
 // ------------------------------------------------------- column gather pass
@@ -845,9 +895,10 @@ __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_wave_barrier();
 }
 
-template <class T, class S, bool VAL, bool STAGEK, bool RP, bool FUSE, class Keep>
+template <class T, class S, bool VAL, bool STAGEK, bool RP, bool FUSE, bool KH = false, class Keep>
 __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ src, const T *__restrict__ kraw,
-                                          Keep keep, double off, T *__restrict__ out, Rec *r) {
+                                          Keep keep, double off, T *__restrict__ out, Rec *r,
+                                          unsigned int *s_kh = nullptr) {
   static_assert(!FUSE || STAGEK, "finishing long columns reads their raw values");
   const T *__restrict__ kraw_t = kraw;
   constexpr int KW = STAGEK ? (int)(sizeof(T) / 4) : 0;      // dwords per staged raw value
@@ -863,7 +914,7 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
   // their gathers (about a fifth of the links on R-MAT, half on the
   // Chung-Lu graphs) read LDS instead of L2.  FP32 send values only (24 KB,
   // four workgroups per CU still fit).
-  constexpr int HOTK = sizeof(S) == 4 ? HOT_SRC : 1;
+  constexpr int HOTK = sizeof(S) == 4 ? (KH ? HOT_SRC_TK : HOT_SRC) : 1;
   __shared__ S s_hot[HOTK];
   const int hk = sizeof(S) == 4 ? min(HOTK, d.n) : 0;
   for (int q = threadIdx.x; q < hk; q += BLOCK) s_hot[q] = src[q];
@@ -959,6 +1010,7 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
         const T y = (T)(keep(pb.raw, pb.k) + c * sum + off);
         out[pb.k] = y;
         fold_stats<RP>((double)y, rr, l1, cs, sr, mx);
+        if (KH) atomicAdd(&s_kh[kh_bin(y)], 1u);
       }
       has_b = false;
     }
@@ -1105,6 +1157,7 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
         const T y = (T)(kv + c * sum[q] + off);
         outs[(unsigned)q] = y;
         fold_stats<RP>((double)y, rr, l1, cs, sr, mx);
+        if (KH) atomicAdd(&s_kh[kh_bin(y)], 1u);
       }
     } else if (ne > 0) {
       double acc = 0.0;
@@ -1146,7 +1199,7 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
 
 // ----------------------------------------------------------------- complete
 
-template <class T, bool VAL, bool RP>
+template <class T, bool VAL, bool RP, bool TK>
 __global__ __launch_bounds__(BLOCK, 4) void k_complete(Dev d, long long s, int init) {
   Glob *g = d.glob;
   if (g->status != 0) return;
@@ -1154,6 +1207,12 @@ __global__ __launch_bounds__(BLOCK, 4) void k_complete(Dev d, long long s, int i
   Rec *nxt = &d.rec[(s + 1) % 3];
   __shared__ Tot sh_tot;
   __shared__ double sh_red[4 * NWAVE];
+  // TK: the top-k histogram of C_{t+1}'s keys, counted as they are written
+  __shared__ unsigned int s_kh[TK ? KH_BINS : 1];
+  if (TK) {
+    for (int b = threadIdx.x; b < KH_BINS; b += BLOCK) s_kh[b] = 0u;
+    __syncthreads();
+  }
   const Tot tot = read_totals(cur, &sh_tot);
   const int n = d.n;
   const double off = tot.T / (double)n;  // uniform restart share of eq. (6)
@@ -1178,6 +1237,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_complete(Dev d, long long s, int i
           const T y = (T)x;
           C[i] = y;
           fold_stats<RP>((double)y, r, l1, cs, sr, mx);
+          if (TK) atomicAdd(&s_kh[kh_bin(y)], 1u);
         }
       }
     }
@@ -1197,7 +1257,11 @@ __global__ __launch_bounds__(BLOCK, 4) void k_complete(Dev d, long long s, int i
     };
     // what the sources send was written by select (zero off the green set;
     // links outside [0, N) are ignored)
-    wave_pull<T, T, VAL, true, RP, true>(d, (const T *)d.src, Cc, keep, off, Cn, nxt);
+    wave_pull<T, T, VAL, true, RP, true, TK>(d, (const T *)d.src, Cc, keep, off, Cn, nxt, s_kh);
+  }
+  if (TK) {
+    __syncthreads();
+    kh_flush(khist_of(d, s + 1), s_kh);
   }
 
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1246,95 +1310,255 @@ __global__ __launch_bounds__(BLOCK) void k_refresh_long(Dev d, long long t, int 
 // The k-th largest |C| of the snapshot C_t (tau) and the largest node id that
 // still fits among the nodes with |C| = tau, so that green = |C| > tau or
 // (|C| = tau and id <= tie_id) selects exactly k nodes ordered by |C|
-// descending, then id ascending.  A radix select over the bit pattern of |C|
-// (non-negative floats order as their bits): each 8-bit digit, from the top,
-// is one k_topk_hist launch (per-workgroup LDS histograms of the digit among
-// the keys that match the prefix fixed so far, added into one global
-// histogram) and one single-workgroup k_topk_pick that fixes the digit.  Then
-// the same over the 32-bit ids of the nodes whose key equals tau, ascending.
+// descending, then id ascending.  Non-negative floats order as their bits
+// (the key).
+//
+//  1. The pass that writes C_t (k_complete of step t-1) also counts the top
+//     KH_BITS bits of every key in a per-workgroup LDS histogram, added into
+//     KH_STRIPES global copies (same-address atomics serialise).  After a
+//     refresh or an import, k_topk_hist_full counts them instead.
+//  2. k_topk_collect (one pass over C_t): every workgroup finds the bin B that
+//     holds the k-th key from the histogram, and the keys of bin B go to a
+//     candidate list (one atomic per wave).
+//  3. k_topk_pass (a few short passes over the candidates only): an 11-bit
+//     radix select fixes the rest of tau's bits, then the id bound among the
+//     keys equal to tau.
 
-template <class T>
-__device__ __forceinline__ unsigned long long topk_key(T v) {
-  if (sizeof(T) == 4) return (unsigned long long)__float_as_uint(fabsf((float)v));
-  return (unsigned long long)__double_as_longlong(fabs((double)v));
+__global__ void k_topk_hist_zero(Dev d, long long s) {
+  unsigned int *kh = khist_of(d, s);
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < KH_STRIPES * KH_BINS; q += gridDim.x * blockDim.x)
+    kh[q] = 0u;
 }
 
-__global__ void k_topk_init(Dev d) {
-  Glob *g = d.glob;
-  if (g->status != 0) return;
-  for (int q = threadIdx.x; q < 256; q += blockDim.x) g->tk_hist[q] = 0u;
-  if (threadIdx.x == 0) {
-    g->tk_prefix = 0ull;
-    g->tk_key = 0ull;
-    g->tk_rem = d.k < (long long)d.n ? d.k : (long long)d.n;
-  }
-}
-
-// ids = 0: digit `shift` of the keys whose bits above it equal the prefix;
-// ids = 1: digit `shift` of the ids of the nodes whose key is tk_key and
-// whose id bits above it equal the prefix.
 template <class T>
-__global__ __launch_bounds__(BLOCK) void k_topk_hist(Dev d, long long s, int shift, int ids) {
-  Glob *g = d.glob;
-  if (g->status != 0) return;
+__global__ __launch_bounds__(BLOCK) void k_topk_hist_full(Dev d, long long s) {
+  if (d.glob->status != 0) return;
+  __shared__ unsigned int s_kh[KH_BINS];
+  for (int b = threadIdx.x; b < KH_BINS; b += BLOCK) s_kh[b] = 0u;
+  __syncthreads();
   const T *C = (const T *)d.cash[d.rec[s % 3].buf];
-  __shared__ unsigned int h[256];
-  for (int q = threadIdx.x; q < 256; q += BLOCK) h[q] = 0u;
-  __syncthreads();
-  const unsigned long long prefix = g->tk_prefix, tkey = g->tk_key;
-  const int hi = shift + 8;
-  const int n = d.n;
-  for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
-    const unsigned long long key = topk_key(C[i]);
-    unsigned long long x;
-    if (ids) {
-      if (key != tkey) continue;
-      x = (unsigned long long)(unsigned int)i;
-    } else {
-      x = key;
-    }
-    if (hi < 64 && (x >> hi) != (prefix >> hi)) continue;
-    atomicAdd(&h[(x >> shift) & 255ull], 1u);
+  for (int base = blockIdx.x * BLOCK; base < d.n; base += gridDim.x * BLOCK) {
+    const int i = base + threadIdx.x;
+    wave_hist_add<KH_BITS>(s_kh, i < d.n ? (unsigned int)kh_bin(C[i]) : 0u, i < d.n);
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < 256; q += BLOCK)
-    if (h[q]) atomicAdd(&g->tk_hist[q], h[q]);
+  kh_flush(khist_of(d, s), s_kh);
 }
 
-// Fixes the digit at `shift`: keys take the largest digits first, ids the
-// smallest.  `last` ends a phase: after the keys, tau is written and the id
-// phase starts from an empty prefix; after the ids, tie_id is written.
-__global__ void k_topk_pick(Dev d, long long s, int shift, int ids, int last, int key_bits) {
-  Glob *g = d.glob;
-  if (g->status != 0 || threadIdx.x != 0 || blockIdx.x != 0) return;
-  long long rem = g->tk_rem;
-  int dig = ids ? 255 : 0;
-  long long before = 0;  // entries in digits taken ahead of dig
-  for (int q = 0; q < 256; ++q) {
-    const int b = ids ? q : 255 - q;
-    const long long cnt = (long long)g->tk_hist[b];
-    if (before + cnt >= rem) {
-      dig = b;
-      break;
+// The digit of a histogram in taking order (keys: largest first; ids:
+// smallest first) at which the running count reaches rem, and the count taken
+// before it.  Every thread of a BLOCK-wide workgroup calls it and receives
+// the result; `h` holds nb <= KH_BINS counts (LDS).
+__device__ __forceinline__ void pick_digit(const unsigned int *h, int nb, bool ascending, long long rem, int *dig,
+                                           long long *before, unsigned long long *sh_scan, int *sh_dig,
+                                           long long *sh_before) {
+  constexpr int PER = KH_BINS / BLOCK;
+  unsigned int cnt[PER];
+  unsigned long long mine = 0;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int q = threadIdx.x * PER + u;  // position in taking order
+    const int b = ascending ? q : nb - 1 - q;
+    cnt[u] = (q < nb) ? h[b] : 0u;
+    mine += cnt[u];
+  }
+  unsigned long long total;
+  unsigned long long run = block_excl_scan(mine, sh_scan, &total);
+  if (threadIdx.x == 0) *sh_dig = -1;
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int q = threadIdx.x * PER + u;
+    if (q < nb && run < (unsigned long long)rem && run + cnt[u] >= (unsigned long long)rem) {
+      *sh_dig = ascending ? q : nb - 1 - q;
+      *sh_before = (long long)run;
     }
-    before += cnt;
+    run += cnt[u];
   }
-  for (int q = 0; q < 256; ++q) g->tk_hist[q] = 0u;
-  const unsigned long long prefix = g->tk_prefix | ((unsigned long long)dig << shift);
-  rem -= before;
-  Rec *cur = &d.rec[s % 3];
-  if (!last) {
-    g->tk_prefix = prefix;
-    g->tk_rem = rem;
-  } else if (!ids) {
-    g->tk_key = prefix;
-    cur->topk_tau = key_bits == 32 ? (double)__uint_as_float((unsigned int)prefix)
-                                   : __longlong_as_double((long long)prefix);
-    g->tk_prefix = 0ull;
-    g->tk_rem = rem;  // ties of tau still to take, >= 1
-  } else {
-    cur->topk_tie_id = (int)prefix;
+  __syncthreads();
+  *dig = *sh_dig;
+  *before = *sh_before;
+  __syncthreads();
+}
+
+// Finds the bin B of the k-th key from the histogram the complete pass
+// counted and appends every node of bin B (key, id) to the candidate list;
+// leaves the radix state (prefix, rem) for the first pass over them.
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_topk_collect(Dev d, long long s) {
+  Glob *g = d.glob;
+  if (g->status != 0) return;
+  constexpr int KB = sizeof(T) == 4 ? 31 : 63;  // key bits
+  __shared__ unsigned int s_h[KH_BINS];
+  __shared__ unsigned long long sh_scan[NWAVE];
+  __shared__ int sh_dig;
+  __shared__ long long sh_before;
+  const unsigned int *kh = khist_of(d, s);
+  const long long want = d.k < (long long)d.n ? d.k : (long long)d.n;
+  for (int b = threadIdx.x; b < KH_BINS; b += BLOCK) {
+    unsigned int c = 0;
+#pragma unroll
+    for (int q = 0; q < KH_STRIPES; ++q) c += kh[q * KH_BINS + b];
+    s_h[b] = c;
   }
+  // the pass histograms: the first pass counts into buffer 0
+  for (int q = blockIdx.x * BLOCK + threadIdx.x; q < KH_BINS; q += gridDim.x * BLOCK) d.tk_hist[q] = 0u;
+  __syncthreads();
+  int B;
+  long long above;
+  pick_digit(s_h, KH_BINS, false, want, &B, &above, sh_scan, &sh_dig, &sh_before);
+  if (B < 0) {
+    // the histogram does not describe C_t (it counts fewer than k keys)
+    if (blockIdx.x == 0 && threadIdx.x == 0) g->bad = 1;
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    g->tk_pref[0] = (unsigned long long)B << (KB - KH_BITS);
+    g->tk_rem[0] = want - above;  // keys of bin B still to take, >= 1
+    g->tk_done = 0;
+  }
+  // workgroup b owns the nodes [b S, (b + 1) S) and writes their candidates
+  // to the same positions of the list (no shared counter), in node order;
+  // tk_cnt[b] says how many
+  const T *C = (const T *)d.cash[d.rec[s % 3].buf];
+  const int S = tk_segment(d.n, gridDim.x);
+  const int b0 = blockIdx.x * S, b1 = min(d.n, b0 + S);
+  unsigned long long *ckey = d.tk_ckey + b0;
+  int *cid = d.tk_cid + b0;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __shared__ int sh_wc[NWAVE];
+  int filled = 0;
+  for (int base = b0; base < b1; base += BLOCK) {
+    const int i = base + threadIdx.x;
+    const T v = (i < b1) ? C[i] : T(0);
+    const bool hit = i < b1 && kh_bin(v) == B;
+    const unsigned long long bal = __ballot(hit);
+    if (lane == 0) sh_wc[wv] = __popcll(bal);
+    __syncthreads();
+    int off = filled;
+    for (int w = 0; w < wv; ++w) off += sh_wc[w];
+    int tot = 0;
+    for (int w = 0; w < NWAVE; ++w) tot += sh_wc[w];
+    if (hit) {
+      const int slot = off + __popcll(bal & ((1ull << lane) - 1ull));
+      ckey[slot] = topk_key(v);
+      cid[slot] = i;
+    }
+    filled += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) d.tk_cnt[blockIdx.x] = filled;
+}
+
+// One digit of the radix select over the candidates: the digits of the key
+// below bin B from the top (largest first), then the digits of the node ids
+// among the keys equal to tau (smallest first).  Pass p first picks digit
+// p - 1 from the histogram pass p - 1 counted (every workgroup the same way),
+// then counts digit p among the candidates that match the digits fixed so
+// far.  `prev` / `cur`: {is_id, lo, width} of those digits (cur.width = 0:
+// the last pass, which only picks and writes tau and the id bound).
+struct TkDigit {
+  int is_id, lo, width;
+};
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_topk_pass(Dev d, long long s, int p, TkDigit prev, TkDigit cur) {
+  Glob *g = d.glob;
+  if (g->status != 0) return;
+  if (g->tk_done) return;  // tau and the id bound are written already
+  __shared__ unsigned int s_h[KH_BINS];
+  __shared__ unsigned long long sh_scan[NWAVE];
+  __shared__ int sh_dig;
+  __shared__ long long sh_before;
+  __shared__ int s_pre[SEL_GRID + 1];
+  unsigned long long pref = g->tk_pref[p & 1];
+  long long rem = g->tk_rem[p & 1];
+  unsigned long long tau = g->tk_tau;
+  if (p == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+    g->tk_pref[1] = pref;  // the state pass 1 starts from, before its pick
+    g->tk_rem[1] = rem;
+  }
+  if (p > 0) {
+    const unsigned int *hp = d.tk_hist + (size_t)((p - 1) % 3) * KH_BINS;
+    for (int b = threadIdx.x; b < KH_BINS; b += BLOCK) s_h[b] = hp[b];
+    __syncthreads();
+    int dig;
+    long long before;
+    pick_digit(s_h, 1 << prev.width, prev.is_id != 0, rem, &dig, &before, sh_scan, &sh_dig, &sh_before);
+    pref |= (unsigned long long)dig << prev.lo;
+    rem -= before;
+    if (!prev.is_id && cur.is_id) {
+      // the key is complete: tau; the ids come next, unless every key equal
+      // to tau is taken (then no id bound is needed)
+      tau = pref;
+      pref = 0ull;
+      if ((long long)s_h[dig] == rem) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+          Rec *r = &d.rec[s % 3];
+          r->topk_tau = sizeof(T) == 4 ? (double)__uint_as_float((unsigned int)tau)
+                                       : __longlong_as_double((long long)tau);
+          r->topk_tie_id = 0x7fffffff;
+          g->tk_done = 1;
+        }
+        return;
+      }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      g->tk_pref[(p + 1) & 1] = pref;
+      g->tk_rem[(p + 1) & 1] = rem;
+      g->tk_tau = tau;
+    }
+  }
+  if (cur.width == 0) {
+    // the last pass: pref is the id bound among the ties of tau
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      Rec *r = &d.rec[s % 3];
+      r->topk_tau = sizeof(T) == 4 ? (double)__uint_as_float((unsigned int)tau) : __longlong_as_double((long long)tau);
+      r->topk_tie_id = (int)pref;
+    }
+    return;
+  }
+  // the buffer pass p + 1 counts into (pass p - 2's, read by pass p - 1)
+  unsigned int *hz = d.tk_hist + (size_t)((p + 1) % 3) * KH_BINS;
+  for (int q = blockIdx.x * BLOCK + threadIdx.x; q < KH_BINS; q += gridDim.x * BLOCK) hz[q] = 0u;
+  for (int b = threadIdx.x; b < KH_BINS; b += BLOCK) s_h[b] = 0u;
+  __syncthreads();
+  const int hi = cur.lo + cur.width;
+  const unsigned long long dmask = (1ull << cur.width) - 1ull;
+  // the candidates sit in segments of S positions, tk_cnt[b] of them filled:
+  // candidate number q is in the segment whose prefix count covers it
+  const int S = tk_segment(d.n, d.tk_grid);
+  const int G = d.tk_grid;
+  for (int b = threadIdx.x; b < G; b += BLOCK) s_pre[b + 1] = d.tk_cnt[b];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s_pre[0] = 0;
+    for (int b = 1; b <= G; ++b) s_pre[b] += s_pre[b - 1];
+  }
+  __syncthreads();
+  const int m = s_pre[G];
+  for (int base = blockIdx.x * BLOCK; base < m; base += gridDim.x * BLOCK) {
+    const int q = base + threadIdx.x;
+    bool take = q < m;
+    unsigned long long x = 0ull;
+    if (take) {
+      int lo = 0, up = G;  // s_pre[lo] <= q < s_pre[up]
+      while (up - lo > 1) {
+        const int mid = (lo + up) >> 1;
+        if (s_pre[mid] <= q) lo = mid;
+        else up = mid;
+      }
+      const int e = lo * S + (q - s_pre[lo]);
+      const unsigned long long key = d.tk_ckey[e];
+      x = cur.is_id ? (unsigned long long)(unsigned int)d.tk_cid[e] : key;
+      take = (!cur.is_id || key == tau) && (x >> hi) == (pref >> hi);
+    }
+    wave_hist_add<KH_BITS>(s_h, (unsigned int)((x >> cur.lo) & dmask), take);
+  }
+  __syncthreads();
+  unsigned int *hc = d.tk_hist + (size_t)(p % 3) * KH_BINS;
+  for (int b = threadIdx.x; b < KH_BINS; b += BLOCK)
+    if (s_h[b]) atomicAdd(&hc[b], s_h[b]);
 }
 
 // ------------------------------------------------------------------ refresh
@@ -1435,6 +1659,7 @@ __global__ __launch_bounds__(BLOCK) void k_reset(Dev d) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     d.glob->status = 0;
     d.glob->bad = 0;
+    d.glob->tk_tau = 0ull;
     d.glob->t = 0;
     d.glob->ticket = 0u;
     d.glob->rpool = 0.0;
@@ -1586,19 +1811,31 @@ template __global__ void k_select<float, 1>(Dev, long long, double, long long, i
 template __global__ void k_select<double, 0>(Dev, long long, double, long long, int);
 template __global__ void k_push<float>(Dev, long long);
 template __global__ void k_push<double>(Dev, long long);
-template __global__ void k_complete<float, false, false>(Dev, long long, int);
-template __global__ void k_complete<float, false, true>(Dev, long long, int);
-template __global__ void k_complete<float, true, false>(Dev, long long, int);
-template __global__ void k_complete<float, true, true>(Dev, long long, int);
-template __global__ void k_complete<double, false, false>(Dev, long long, int);
-template __global__ void k_complete<double, false, true>(Dev, long long, int);
-template __global__ void k_complete<double, true, false>(Dev, long long, int);
-template __global__ void k_complete<double, true, true>(Dev, long long, int);
+template __global__ void k_complete<float, false, false, false>(Dev, long long, int);
+template __global__ void k_complete<float, false, false, true>(Dev, long long, int);
+template __global__ void k_complete<float, false, true, false>(Dev, long long, int);
+template __global__ void k_complete<float, false, true, true>(Dev, long long, int);
+template __global__ void k_complete<float, true, false, false>(Dev, long long, int);
+template __global__ void k_complete<float, true, false, true>(Dev, long long, int);
+template __global__ void k_complete<float, true, true, false>(Dev, long long, int);
+template __global__ void k_complete<float, true, true, true>(Dev, long long, int);
+template __global__ void k_complete<double, false, false, false>(Dev, long long, int);
+template __global__ void k_complete<double, false, false, true>(Dev, long long, int);
+template __global__ void k_complete<double, false, true, false>(Dev, long long, int);
+template __global__ void k_complete<double, false, true, true>(Dev, long long, int);
+template __global__ void k_complete<double, true, false, false>(Dev, long long, int);
+template __global__ void k_complete<double, true, false, true>(Dev, long long, int);
+template __global__ void k_complete<double, true, true, false>(Dev, long long, int);
+template __global__ void k_complete<double, true, true, true>(Dev, long long, int);
 template __global__ void k_refresh_long<float, 0>(Dev, long long, int);
 template __global__ void k_refresh_long<float, 1>(Dev, long long, int);
 template __global__ void k_refresh_long<double, 0>(Dev, long long, int);
-template __global__ void k_topk_hist<float>(Dev, long long, int, int);
-template __global__ void k_topk_hist<double>(Dev, long long, int, int);
+template __global__ void k_topk_hist_full<float>(Dev, long long);
+template __global__ void k_topk_hist_full<double>(Dev, long long);
+template __global__ void k_topk_collect<float>(Dev, long long);
+template __global__ void k_topk_collect<double>(Dev, long long);
+template __global__ void k_topk_pass<float>(Dev, long long, int, TkDigit, TkDigit);
+template __global__ void k_topk_pass<double>(Dev, long long, int, TkDigit, TkDigit);
 template __global__ void k_refresh_pool<0>(Dev);
 template __global__ void k_refresh_pool<1>(Dev);
 template __global__ void k_refresh<float, 0, false, false>(Dev, long long, int);
