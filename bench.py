@@ -185,9 +185,10 @@ def batched_leg(args, rl, torch, oracle):
     """Independent chains: n log-uniform in [1e3, 2e5], Chung-Lu exponent 2.3,
     mean degree 10, damping uniform in [0.8, 0.95]; FP32 cash with compensated
     history; each chain stops at ||C||_1/|H.1| < tol (1 - c_k), tol = 1e-6.
-    Both batch engines are timed; the autotuner picks the launch shape.  The
-    plain single-chain path solving the same chains one after another is
-    reported beside them."""
+    The step-synchronous engine runs with the launch shape the autotuner
+    picks (and one route workgroup per plan item beside it).  The plain
+    single-chain path solving the same chains one after another is reported
+    beside them."""
     import numpy as np
     import workloads
     t0 = time.time()
@@ -200,14 +201,13 @@ def batched_leg(args, rl, torch, oracle):
     db = rl.DeviceBatch(gs, precision=rl.FP32C_KAHANH, tol_l1=tol)
     bs = rl.BatchSolver(db, max_steps=100000)
     tuned = bs.autotune()
-    engines = {}
-    for name, eng, shape in (("lockstep", rl.BATCH_LOCKSTEP, None), ("persistent", rl.BATCH_PERSISTENT, None)):
-        if tuned["engine"] == eng:
-            opt = dict(engine=eng, wg_size=tuned["wg_size"], wg_per_cu=tuned["wg_per_cu"])
-        else:
-            opt = dict(engine=eng, wg_size=256 if eng == rl.BATCH_LOCKSTEP else 512,
-                       wg_per_cu=0 if eng == rl.BATCH_LOCKSTEP else 1)
-        b2 = rl.BatchSolver(db, max_steps=100000, **opt)
+    shapes = {}
+    # the tuned launch shape, and one route workgroup per plan item beside it
+    cands = [("tuned", tuned["wg_size"], tuned["wg_per_cu"])]
+    if (tuned["wg_size"], tuned["wg_per_cu"]) != (256, 0):
+        cands.append(("per_item_256", 256, 0))
+    for name, wg, per_cu in cands:
+        b2 = rl.BatchSolver(db, max_steps=100000, wg_size=wg, wg_per_cu=per_cu)
         b2.solve()  # warm-up
         runs = []
         for _ in range(max(1, min(args.steps, 5))):
@@ -216,6 +216,10 @@ def batched_leg(args, rl, torch, oracle):
         ms_best, res = min(runs, key=lambda x: x[0])
         lat = np.array([r["end_us"] for r in res]) / 1000.0
         pushes = sum(r["edges_pushed"] for r in res)
+        # algorithmic bytes (per link of a green node that moved cash: source
+        # index and gathered send value, 8 B with implied weights; per node and
+        # step: column pointer, cash read and write, send value, 16 B)
+        alg = sum(8.0 * r["edges_pushed"] + 16.0 * g.n * r["t"] for r, g in zip(res, gs))
         worst = 0.0
         pi = b2.pi.detach().cpu().numpy()
         for k, g in enumerate(gs):
@@ -223,14 +227,16 @@ def batched_leg(args, rl, torch, oracle):
             r = oracle.residual(ch, pi[db.node_off[k]:db.node_off[k + 1]])
             worst = max(worst, r / (1.0 - g.c))
         b2.close()
-        engines[name] = {"solves_per_s": round(len(gs) / (ms_best / 1000.0), 1), "launch_ms": round(ms_best, 3),
-                         "p50_ms": round(float(np.percentile(lat, 50)), 3),
-                         "p99_ms": round(float(np.percentile(lat, 99)), 3),
-                         "gteps": round(pushes / (ms_best / 1000.0) / 1e9, 2), "worst_certified_l1": worst,
-                         "wg_size": opt["wg_size"], "wg_per_cu": opt["wg_per_cu"],
-                         "mean_steps": round(float(np.mean([r["t"] for r in res])), 1),
-                         "max_steps": int(max(r["t"] for r in res))}
-        print(f"# batched {name}: {json.dumps(engines[name])}", file=sys.stderr, flush=True)
+        gbps = alg / (ms_best * 1e-3) / 1e9
+        shapes[name] = {"solves_per_s": round(len(gs) / (ms_best / 1000.0), 1), "batch_ms": round(ms_best, 3),
+                        "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                        "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                        "gteps": round(pushes / (ms_best / 1000.0) / 1e9, 2), "worst_certified_l1": worst,
+                        "algorithmic_GBps": round(gbps, 1), "hbm_frac": round(gbps / HBM_PEAK_GBS, 4),
+                        "wg_size": wg, "wg_per_cu": per_cu,
+                        "mean_steps": round(float(np.mean([r["t"] for r in res])), 1),
+                        "max_steps": int(max(r["t"] for r in res))}
+        log(f"batched {name}: {json.dumps(shapes[name])}")
     bs.close()
     # the plain single-chain path on the same chains, one after another
     plain = []
@@ -253,13 +259,12 @@ def batched_leg(args, rl, torch, oracle):
     plain = np.array(plain)
     seq_lat = np.cumsum(plain)
     print(f"# plain path: {plain.sum():.1f} ms for {len(gs)} solves back to back", file=sys.stderr, flush=True)
-    best = engines["lockstep"] if tuned["engine"] == rl.BATCH_LOCKSTEP else engines["persistent"]
+    best = shapes["tuned"]
     return {"workload": f"chung_lu_batch{len(gs)}", "chains": len(gs), "nodes": tot_n, "links": tot_e,
             "precision": "fp32c_kahanh", "tol_l1": tol, "stop": "resid < tol_l1 * (1 - c_k)",
-            "tuned": {"engine": "lockstep" if tuned["engine"] == rl.BATCH_LOCKSTEP else "persistent",
-                      "wg_size": tuned["wg_size"], "wg_per_cu": tuned["wg_per_cu"]},
+            "tuned": {"engine": "lockstep", "wg_size": tuned["wg_size"], "wg_per_cu": tuned["wg_per_cu"]},
             "solves_per_s": best["solves_per_s"], "p50_ms": best["p50_ms"], "p99_ms": best["p99_ms"],
-            "gteps": best["gteps"], "engines": engines,
+            "gteps": best["gteps"], "hbm_frac": best["hbm_frac"], "launch_shapes": shapes,
             "plain_single_chain": {"solves_per_s": round(len(gs) / (plain.sum() / 1000.0), 1),
                                    "solve_ms_p50": round(float(np.percentile(plain, 50)), 3),
                                    "solve_ms_p99": round(float(np.percentile(plain, 99)), 3),

@@ -309,15 +309,14 @@ int32_t rlgl_profile_read(rlgl_ctx *ctx, rlgl_kernel_stat *out, int32_t max_entr
  * belong to the caller and must outlive the batch; the library allocates no
  * device memory.
  *
- * Two engines:
- *   RLGL_BATCH_PERSISTENT - one launch for the whole batch; each workgroup
- *     takes the next chain from a device queue (largest first) and runs its
- *     whole solve with workgroup barriers only;
- *   RLGL_BATCH_LOCKSTEP - every unfinished chain advances one step per
- *     iteration of three launches (select, route, control) that span all of
- *     them, so a large chain is spread over the whole GPU; link weights are
- *     implicit (1/outdeg in FP64) and csr_val/csc_val are not read. */
-typedef enum { RLGL_BATCH_PERSISTENT = 0, RLGL_BATCH_LOCKSTEP = 1 } rlgl_batch_engine;
+ * The engine (RLGL_BATCH_LOCKSTEP): every unfinished chain advances one step
+ * per iteration of three launches (select, route, control) that span all of
+ * them, so a large chain is spread over the whole GPU; link weights are
+ * implicit (1/outdeg in FP64) and csr_val/csc_val are not read.  (Value 0,
+ * an engine that ran each chain's whole solve in one workgroup, is no
+ * longer offered: one CU per chain made the large chains of a batch slower
+ * than solving the chains one after another.) */
+typedef enum { RLGL_BATCH_LOCKSTEP = 1 } rlgl_batch_engine;
 typedef struct rlgl_batch rlgl_batch;
 
 typedef struct {
@@ -344,13 +343,11 @@ typedef struct {
   double eps;                 /* stop test on ||C_t||_1 / |H_t 1| */
   int64_t max_steps;          /* per chain */
   int32_t refresh;            /* confirm the stop on the cash rebuilt from the history (0/1) */
-  int32_t wg_size;            /* persistent: threads per workgroup, 256, 512 or 1024; lockstep: threads per
-                                 route workgroup, 256 or 512 */
-  int32_t wg_per_cu;          /* persistent: resident workgroups per CU, 1..8 (0 means 1); lockstep: route
-                                 workgroups per CU the plan items are strided over, 1..16, or 0 for one
+  int32_t wg_size;            /* threads per route workgroup, 256 or 512 */
+  int32_t wg_per_cu;          /* route workgroups per CU the plan items are strided over, 1..16, or 0 for one
                                  workgroup per item */
-  int32_t engine;             /* rlgl_batch_engine */
-  int32_t check_period;       /* lockstep: iterations between host checks of the finished count (>= 1) */
+  int32_t engine;             /* rlgl_batch_engine: RLGL_BATCH_LOCKSTEP (anything else is RLGL_EINVAL) */
+  int32_t check_period;       /* iterations between host checks of the finished count (>= 1) */
 } rlgl_batch_options;
 
 /* Outcome of one chain. */
@@ -384,12 +381,9 @@ rlgl_status rlgl_batch_create(const rlgl_batch_graphs *g, const rlgl_batch_optio
  * the first failing chain's status. */
 rlgl_status rlgl_batch_solve(rlgl_batch *b, double *dev_pi, rlgl_chain_result *results, double *elapsed_ms);
 
-/* Autotuner: times one batch solve for every candidate (persistent: wg_size
- * in {256, 512} x wg_per_cu in {1, 2}; lockstep: route wg_size in {256, 512}
- * x wg_per_cu in {0, 4, 8})
- * with HIP events and keeps the fastest in the batch; *best (may be NULL)
- * receives the chosen options.  Candidates whose LDS or register needs do not
- * fit are skipped. */
+/* Autotuner: times one batch solve for every candidate launch shape (route
+ * wg_size in {256, 512} x wg_per_cu in {0, 4, 8}) with HIP events and keeps
+ * the fastest in the batch; *best (may be NULL) receives the chosen options. */
 rlgl_status rlgl_batch_autotune(rlgl_batch *b, double *dev_pi, rlgl_batch_options *best);
 
 void rlgl_batch_destroy(rlgl_batch *b);

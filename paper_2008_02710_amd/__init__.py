@@ -56,7 +56,7 @@ class rlgl_kernel_stat(ctypes.Structure):
                 ("bytes", ctypes.c_double), ("bytes_touched", ctypes.c_double), ("green_links", ctypes.c_int64)]
 
 
-BATCH_PERSISTENT, BATCH_LOCKSTEP = 0, 1
+BATCH_LOCKSTEP = 1
 
 
 class rlgl_batch_graphs(ctypes.Structure):

@@ -21,7 +21,6 @@
 #include "../../include/rlgl.h"
 #include "rlgl_device.h"
 #include "rlgl_kernels.hip"
-#include "rlgl_batch.hip"
 #include "rlgl_lockstep.hip"
 #include "rlgl_validate.hip"
 #include "rlgl_small.hip"
@@ -1216,12 +1215,11 @@ rlgl_status ls_iterate(LsEngine &E, int count) {
   return RLGL_OK;
 }
 
-// Chain plan: the long columns (> CH links) first - as one whole item each
-// (persistent engine) or as pieces of at most LS_PIECE links that add into
-// long_acc[q] of the column's position q in long_cols (lockstep engine) -
-// then runs of at most CH links and RUN_MAX_COLS columns.  Returns false on
-// a bad colptr.
-bool chain_plan(const int *c, int n, int m, bool pieces, std::vector<int4> &items, std::vector<int> &long_cols,
+// Chain plan: the long columns (> CH links) first, as pieces of at most
+// LS_PIECE links that add into long_acc[q] of the column's position q in
+// long_cols, then runs of at most CH links and RUN_MAX_COLS columns.
+// Returns false on a bad colptr.
+bool chain_plan(const int *c, int n, int m, std::vector<int4> &items, std::vector<int> &long_cols,
                 int &n_first, int &n_run, std::string &why) {
   if (c[0] != 0 || c[n] != m) {
     why = "csc_colptr must run from 0 to the link count";
@@ -1236,10 +1234,6 @@ bool chain_plan(const int *c, int n, int m, bool pieces, std::vector<int4> &item
       return false;
     }
     if (dg <= CH) continue;
-    if (!pieces) {
-      items.push_back(make_int4(ITEM_WHOLE, q, c[q], c[q + 1]));
-      continue;
-    }
     const int slot = (int)(long_cols.size() - lfirst);
     long_cols.push_back(q);
     for (int p = c[q]; p < c[q + 1]; p += LS_PIECE)
@@ -1270,15 +1264,21 @@ bool chain_plan(const int *c, int n, int m, bool pieces, std::vector<int4> &item
 size_t long_col_bound(long long nnz) { return (size_t)(nnz / (CH + 1) + 1); }
 
 size_t batch_item_bound(long long n, long long nnz) {
-  // runs (see build_plan) plus, per column longer than CH, one whole item or
-  // its pieces
+  // runs (see build_plan) plus the pieces of the columns longer than CH
   return 3 * (size_t)(nnz / CH + 2) + (size_t)(n / RUN_MAX_COLS + 2) + (size_t)(nnz / LS_PIECE + 1) +
          2 * long_col_bound(nnz);
 }
 
+// Per-chain outcome of a batched solve, gathered on the host.
+struct ChainOut {
+  long long t, edges;
+  double resid, hsum;
+  int status, green_steps;
+  long long t0, t1;  // device wall clock at start and end of the chain's solve
+};
+
 struct BatchLayout {
-  size_t cash0, cash1, src, hist, hist_lo, items, ls_items, long_cols, long_acc, chains, order, out, queue, engine,
-      total;
+  size_t cash0, cash1, src, hist, hist_lo, ls_items, long_cols, long_acc, order, queue, engine, total;
   size_t max_items, max_long;
 };
 
@@ -1308,13 +1308,10 @@ bool batch_layout(const rlgl_batch_graphs *g, const rlgl_batch_options *o, Batch
   L.hist_lo = (o->precision == RLGL_FP32C_KAHANH) ? take(4 * tn) : 0;
   L.max_items = items;
   L.max_long = longs;
-  L.items = take(sizeof(int4) * items);
   L.ls_items = take(sizeof(int4) * items);
   L.long_cols = take(4 * longs);
   L.long_acc = take(8 * longs);
-  L.chains = take(sizeof(ChainDesc) * g->n_chains);
   L.order = take(4 * (size_t)g->n_chains);
-  L.out = take(sizeof(ChainOut) * g->n_chains);
   L.queue = take(256);
   L.engine = take(ls_device_bytes(g->n_chains));
   L.total = off + 256;
@@ -1324,10 +1321,12 @@ bool batch_layout(const rlgl_batch_graphs *g, const rlgl_batch_options *o, Batch
 }  // namespace
 
 struct rlgl_batch {
-  BatchDev bd;
   hipStream_t stream;
-  int prec, hk, nt, per_cu, cus, grid;
-  int engine, ls_nt, ls_per_cu, check_period;
+  int prec, hk, cus;
+  int sched, refresh;
+  double r;
+  long long max_steps;
+  int ls_nt, ls_per_cu, check_period;
   double eps;
   double clock_khz;
   int n_chains;
@@ -1335,6 +1334,7 @@ struct rlgl_batch {
   ChainOut *host_out;
   long long *host_t0;
   long long *dev_t0;
+  unsigned int *dev_queue;
   std::vector<long long> node_off;
   std::vector<int> order;  // largest chain first
   int *dev_order;          // the same order on the device
@@ -1344,53 +1344,17 @@ struct rlgl_batch {
 
 namespace {
 
-template <class T, int HK>
-const void *batch_kernel(int nt) {
-  if (nt == 256) return (const void *)k_batch<T, HK, 256>;
-  if (nt == 512) return (const void *)k_batch<T, HK, 512>;
-  return (const void *)k_batch<T, HK, 1024>;
-}
-
-const void *batch_kernel_for(int prec, int nt) {
-  if (prec == RLGL_FP64) return batch_kernel<double, 0>(nt);
-  if (prec == RLGL_FP32C_KAHANH) return batch_kernel<float, 1>(nt);
-  return batch_kernel<float, 0>(nt);
-}
-
 rlgl_status batch_configure(rlgl_batch *b, const rlgl_batch_options &o) {
-  if (o.engine != RLGL_BATCH_PERSISTENT && o.engine != RLGL_BATCH_LOCKSTEP)
-    return fail(RLGL_EINVAL, "engine must be RLGL_BATCH_PERSISTENT or RLGL_BATCH_LOCKSTEP");
+  if (o.engine != RLGL_BATCH_LOCKSTEP) return fail(RLGL_EINVAL, "engine must be RLGL_BATCH_LOCKSTEP");
   if (o.check_period < 1) return fail(RLGL_EINVAL, "check_period must be >= 1");
-  if (o.engine == RLGL_BATCH_LOCKSTEP) {
-    if (o.wg_size != 256 && o.wg_size != 512) return fail(RLGL_EINVAL, "lockstep wg_size must be 256 or 512");
-    if (o.wg_per_cu < 0 || o.wg_per_cu > 16) return fail(RLGL_EINVAL, "lockstep wg_per_cu must be in 0..16");
-    b->engine = RLGL_BATCH_LOCKSTEP;
-    b->ls_nt = o.wg_size;
-    b->ls_per_cu = o.wg_per_cu;
-    b->E.nt = o.wg_size;
-    b->E.route_grid = b->cus * o.wg_per_cu;
-    b->check_period = o.check_period;
-    return RLGL_OK;
-  }
-  const int nt = o.wg_size, per_cu = o.wg_per_cu == 0 ? 1 : o.wg_per_cu;
-  if (nt != 256 && nt != 512 && nt != 1024) return fail(RLGL_EINVAL, "wg_size must be 256, 512 or 1024");
-  if (per_cu < 1 || per_cu > 8) return fail(RLGL_EINVAL, "wg_per_cu must be in 1..8");
-  int fit = 0;
-  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, batch_kernel_for(b->prec, nt), nt, 0));
-  if (fit < 1) return fail(RLGL_EINVAL, "a %d-thread batch workgroup does not fit on a CU", nt);
-  b->engine = RLGL_BATCH_PERSISTENT;
-  b->nt = nt;
-  b->per_cu = std::min(per_cu, fit);
-  b->grid = b->cus * b->per_cu;
+  if (o.wg_size != 256 && o.wg_size != 512) return fail(RLGL_EINVAL, "lockstep wg_size must be 256 or 512");
+  if (o.wg_per_cu < 0 || o.wg_per_cu > 16) return fail(RLGL_EINVAL, "lockstep wg_per_cu must be in 0..16");
+  b->ls_nt = o.wg_size;
+  b->ls_per_cu = o.wg_per_cu;
+  b->E.nt = o.wg_size;
+  b->E.route_grid = b->cus * o.wg_per_cu;
   b->check_period = o.check_period;
   return RLGL_OK;
-}
-
-template <class T, int HK>
-void launch_batch(rlgl_batch *b) {
-  if (b->nt == 256) k_batch<T, HK, 256><<<b->grid, 256, 0, b->stream>>>(b->bd);
-  else if (b->nt == 512) k_batch<T, HK, 512><<<b->grid, 512, 0, b->stream>>>(b->bd);
-  else k_batch<T, HK, 1024><<<b->grid, 1024, 0, b->stream>>>(b->bd);
 }
 
 __global__ void k_batch_start(unsigned int *queue, long long *t0) {
@@ -1398,17 +1362,6 @@ __global__ void k_batch_start(unsigned int *queue, long long *t0) {
     *queue = 0u;
     *t0 = wall_clock64();
   }
-}
-
-rlgl_status persistent_run(rlgl_batch *b, double *dev_pi) {
-  b->bd.pi = dev_pi;
-  k_batch_start<<<1, 64, 0, b->stream>>>(b->bd.queue, b->dev_t0);
-  if (b->prec == RLGL_FP64) launch_batch<double, 0>(b);
-  else if (b->hk) launch_batch<float, 1>(b);
-  else launch_batch<float, 0>(b);
-  const hipError_t le = hipGetLastError();
-  if (le != hipSuccess) return fail(RLGL_EHIP, "batch launch: %s", hipGetErrorString(le));
-  return RLGL_OK;
 }
 
 rlgl_status lockstep_run(rlgl_batch *b, double *dev_pi) {
@@ -1422,7 +1375,7 @@ rlgl_status lockstep_run(rlgl_batch *b, double *dev_pi) {
   }
   rlgl_status st = ls_set_active(E, b->order);
   if (st != RLGL_OK) return st;
-  k_batch_start<<<1, 64, 0, b->stream>>>(b->bd.queue, b->dev_t0);
+  k_batch_start<<<1, 64, 0, b->stream>>>(b->dev_queue, b->dev_t0);
   k_ls_start<<<(b->n_chains + 255) / 256, 256, 0, b->stream>>>(E.d_chains, E.args.ctl, E.args.stats, b->dev_order,
                                                                b->n_chains, E.args.done);
   long long max_steps = 0;
@@ -1466,7 +1419,7 @@ rlgl_status batch_run(rlgl_batch *b, double *dev_pi, float *ms) {
   HIP_TRY(hipEventCreate(&e1));
   rlgl_status st = RLGL_OK;
   if (hipEventRecord(e0, b->stream) != hipSuccess) st = fail(RLGL_EHIP, "event record failed");
-  if (st == RLGL_OK) st = (b->engine == RLGL_BATCH_LOCKSTEP) ? lockstep_run(b, dev_pi) : persistent_run(b, dev_pi);
+  if (st == RLGL_OK) st = lockstep_run(b, dev_pi);
   if (st == RLGL_OK && (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
     st = fail(RLGL_EHIP, "event wait failed");
   float t = 0.f;
@@ -1477,28 +1430,22 @@ rlgl_status batch_run(rlgl_batch *b, double *dev_pi, float *ms) {
   return st;
 }
 
-// Per-chain outcomes of the last solve, in the persistent kernel's format.
+// Per-chain outcomes of the last solve, from the chains' control records.
 rlgl_status batch_outcomes(rlgl_batch *b) {
-  if (b->engine == RLGL_BATCH_PERSISTENT) {
-    HIP_TRY(hipMemcpyAsync(b->host_out, b->bd.out, sizeof(ChainOut) * b->n_chains, hipMemcpyDeviceToHost, b->stream));
-  } else {
-    HIP_TRY(hipMemcpyAsync(b->E.h_ctl, b->E.args.ctl, sizeof(LsCtl) * b->n_chains, hipMemcpyDeviceToHost, b->stream));
-  }
+  HIP_TRY(hipMemcpyAsync(b->E.h_ctl, b->E.args.ctl, sizeof(LsCtl) * b->n_chains, hipMemcpyDeviceToHost, b->stream));
   HIP_TRY(hipMemcpyAsync(b->host_t0, b->dev_t0, sizeof(long long), hipMemcpyDeviceToHost, b->stream));
   HIP_TRY(hipStreamSynchronize(b->stream));
-  if (b->engine == RLGL_BATCH_LOCKSTEP) {
-    for (int k = 0; k < b->n_chains; ++k) {
-      const LsCtl &c = b->E.h_ctl[k];
-      ChainOut &o = b->host_out[k];
-      o.t = c.t;
-      o.edges = c.edges;
-      o.resid = c.resid;
-      o.hsum = c.hsum;
-      o.status = c.status;
-      o.green_steps = c.green_steps;
-      o.t0 = c.t0;
-      o.t1 = c.t1;
-    }
+  for (int k = 0; k < b->n_chains; ++k) {
+    const LsCtl &c = b->E.h_ctl[k];
+    ChainOut &o = b->host_out[k];
+    o.t = c.t;
+    o.edges = c.edges;
+    o.resid = c.resid;
+    o.hsum = c.hsum;
+    o.status = c.status;
+    o.green_steps = c.green_steps;
+    o.t0 = c.t0;
+    o.t1 = c.t1;
   }
   return RLGL_OK;
 }
@@ -1562,30 +1509,13 @@ rlgl_status rlgl_batch_create(const rlgl_batch_graphs *g, const rlgl_batch_optio
   b->ls_pi = nullptr;
   b->eps = o->eps;
   char *w = (char *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
-  BatchDev &d = b->bd;
-  d.n_chains = nc;
-  d.sched = o->sched;
-  d.r = o->r;
-  d.max_steps = o->max_steps;
-  d.refresh = o->refresh ? 1 : 0;
-  d.rowptr = g->csr_rowptr;
-  d.col = g->csr_col;
-  d.val = g->csr_val;
-  d.colptr = g->csc_colptr;
-  d.crow = g->csc_row;
-  d.cval = g->csc_val;
-  d.cash0 = w + L.cash0;
-  d.cash1 = w + L.cash1;
-  d.hist = w + L.hist;
-  d.hist_lo = b->hk ? (float *)(w + L.hist_lo) : nullptr;
-  d.items = (const int4 *)(w + L.items);
-  d.chains = (const ChainDesc *)(w + L.chains);
-  d.order = (const int *)(w + L.order);
-  d.out = (ChainOut *)(w + L.out);
-  d.queue = (unsigned int *)(w + L.queue);
+  b->sched = o->sched;
+  b->r = o->r;
+  b->max_steps = o->max_steps;
+  b->refresh = o->refresh ? 1 : 0;
+  b->dev_queue = (unsigned int *)(w + L.queue);
   b->dev_t0 = (long long *)(w + L.queue + 64);
   b->dev_order = (int *)(w + L.order);
-  d.pi = nullptr;
 
   auto bail = [&](rlgl_status s) {
     rlgl_batch_destroy(b);
@@ -1603,36 +1533,25 @@ rlgl_status rlgl_batch_create(const rlgl_batch_graphs *g, const rlgl_batch_optio
   rlgl_status st = ls_init(b->E, w + L.engine, nc, o->precision, o->sched, o->r, o->refresh, b->stream);
   if (st != RLGL_OK) return bail(st);
 
-  // static plans: long columns whole, then runs of at most CH in-links
+  // static plans: pieces of the long columns, then runs of at most CH in-links
   const long long rp_total = b->total_n + nc;
   std::vector<int> cp((size_t)rp_total);
   if (hipMemcpyAsync(cp.data(), g->csc_colptr, sizeof(int) * (size_t)rp_total, hipMemcpyDeviceToHost, b->stream) !=
           hipSuccess ||
       hipStreamSynchronize(b->stream) != hipSuccess)
     return bail(fail(RLGL_EHIP, "reading the column pointers failed"));
-  std::vector<int4> items, ls_items;
-  std::vector<int> long_cols, no_longs;
-  std::vector<ChainDesc> cds((size_t)nc);
+  std::vector<int4> ls_items;
+  std::vector<int> long_cols;
+  std::vector<long long> size_of((size_t)nc);
   const size_t cs = (o->precision == RLGL_FP64) ? 8 : 4;
   for (int k = 0; k < nc; ++k) {
     const long long no = g->node_off[k], rp = no + k;
     const int n = (int)(g->node_off[k + 1] - no);
     const int m = (int)(g->edge_off[k + 1] - g->edge_off[k]);
-    ChainDesc &cd = cds[k];
-    cd.node_off = no;
-    cd.rp_off = rp;
-    cd.edge_off = g->edge_off[k];
-    cd.n = n;
-    cd.nnz = m;
-    cd.c = g->damping[k];
-    cd.eps = g->tol_l1 ? g->tol_l1[k] * (1.0 - g->damping[k]) : o->eps;
-    cd.item_off = (int)items.size();
-    int nw = 0, nr = 0, np = 0, nr2 = 0;
-    if (!chain_plan(cp.data() + rp, n, m, false, items, no_longs, nw, nr, why))
-      return bail(fail(RLGL_EINVAL, "chain %d: %s", k, why.c_str()));
-    cd.n_items = nw + nr;
+    size_of[k] = (long long)m + n;
+    int np = 0, nr2 = 0;
     const size_t li = ls_items.size(), lo = long_cols.size();
-    if (!chain_plan(cp.data() + rp, n, m, true, ls_items, long_cols, np, nr2, why))
+    if (!chain_plan(cp.data() + rp, n, m, ls_items, long_cols, np, nr2, why))
       return bail(fail(RLGL_EINVAL, "chain %d: %s", k, why.c_str()));
     LsChain &lc = b->E.host[k];
     lc.rowptr = g->csr_rowptr + rp;
@@ -1650,26 +1569,21 @@ rlgl_status rlgl_batch_create(const rlgl_batch_graphs *g, const rlgl_batch_optio
     lc.pi = nullptr;
     lc.nnz = m;
     lc.max_steps = o->max_steps;
-    lc.c = cd.c;
-    lc.eps = cd.eps;
+    lc.c = g->damping[k];
+    lc.eps = g->tol_l1 ? g->tol_l1[k] * (1.0 - g->damping[k]) : o->eps;
     lc.n = n;
     lc.n_piece = np;
     lc.n_run = nr2;
   }
-  if (items.size() > L.max_items || ls_items.size() > L.max_items || long_cols.size() > L.max_long)
+  if (ls_items.size() > L.max_items || long_cols.size() > L.max_long)
     return bail(fail(RLGL_EINVAL, "batch plan exceeds its bound (internal)"));
   b->order.resize((size_t)nc);
   for (int k = 0; k < nc; ++k) b->order[k] = k;
-  std::stable_sort(b->order.begin(), b->order.end(), [&](int a, int c2) {
-    return (long long)cds[a].nnz + cds[a].n > (long long)cds[c2].nnz + cds[c2].n;
-  });
-  if ((!items.empty() &&
-       hipMemcpyAsync(w + L.items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, b->stream)) ||
-      (!ls_items.empty() && hipMemcpyAsync(w + L.ls_items, ls_items.data(), sizeof(int4) * ls_items.size(),
+  std::stable_sort(b->order.begin(), b->order.end(), [&](int a, int c2) { return size_of[a] > size_of[c2]; });
+  if ((!ls_items.empty() && hipMemcpyAsync(w + L.ls_items, ls_items.data(), sizeof(int4) * ls_items.size(),
                                            hipMemcpyHostToDevice, b->stream)) ||
       (!long_cols.empty() && hipMemcpyAsync(w + L.long_cols, long_cols.data(), 4 * long_cols.size(),
                                             hipMemcpyHostToDevice, b->stream)) ||
-      hipMemcpyAsync(w + L.chains, cds.data(), sizeof(ChainDesc) * nc, hipMemcpyHostToDevice, b->stream) ||
       hipMemcpyAsync(w + L.order, b->order.data(), sizeof(int) * nc, hipMemcpyHostToDevice, b->stream) ||
       hipStreamSynchronize(b->stream))
     return bail(fail(RLGL_EHIP, "uploading the batch plan failed"));
@@ -1712,16 +1626,16 @@ rlgl_status rlgl_batch_autotune(rlgl_batch *b, double *dev_pi, rlgl_batch_option
   if (!b || !dev_pi) return fail(RLGL_EINVAL, "bad argument");
   rlgl_batch_options cur;
   rlgl_batch_default_options(&cur);
-  cur.sched = b->bd.sched;
-  cur.r = b->bd.r;
+  cur.sched = b->sched;
+  cur.r = b->r;
   cur.precision = b->prec;
   cur.eps = b->eps;
-  cur.max_steps = b->bd.max_steps;
-  cur.refresh = b->bd.refresh;
+  cur.max_steps = b->max_steps;
+  cur.refresh = b->refresh;
   cur.check_period = b->check_period;
-  cur.engine = b->engine;
-  cur.wg_size = b->engine == RLGL_BATCH_LOCKSTEP ? b->ls_nt : b->nt;
-  cur.wg_per_cu = b->engine == RLGL_BATCH_LOCKSTEP ? b->ls_per_cu : b->per_cu;
+  cur.engine = RLGL_BATCH_LOCKSTEP;
+  cur.wg_size = b->ls_nt;
+  cur.wg_per_cu = b->ls_per_cu;
   std::vector<rlgl_batch_options> cands;
   for (int nt : {256, 512})
     for (int pc : {0, 4, 8}) {
@@ -1731,19 +1645,10 @@ rlgl_status rlgl_batch_autotune(rlgl_batch *b, double *dev_pi, rlgl_batch_option
       c.wg_per_cu = pc;
       cands.push_back(c);
     }
-  for (int nt : {256, 512})
-    for (int pc : {1, 2}) {
-      rlgl_batch_options c = cur;
-      c.engine = RLGL_BATCH_PERSISTENT;
-      c.wg_size = nt;
-      c.wg_per_cu = pc;
-      cands.push_back(c);
-    }
   double best_ms = 1e300;
   rlgl_batch_options pick = cur;
   for (const rlgl_batch_options &c : cands) {
     if (batch_configure(b, c) != RLGL_OK) continue;
-    if (c.engine == RLGL_BATCH_PERSISTENT && b->per_cu != c.wg_per_cu) continue;
     float ms = 0.f;
     const rlgl_status st = batch_run(b, dev_pi, &ms);
     if (st != RLGL_OK) return st;
@@ -1976,7 +1881,7 @@ rlgl_status rlgl_pool_admit(rlgl_pool *p, const rlgl_request *q, int32_t *slot) 
   longs.reserve(long_col_bound(m));
   int np = 0, nr = 0;
   std::string why;
-  if (!chain_plan(q->csc_colptr, (int)n, (int)m, true, items, longs, np, nr, why))
+  if (!chain_plan(q->csc_colptr, (int)n, (int)m, items, longs, np, nr, why))
     return fail(RLGL_EINVAL, "%s", why.c_str());
   const int prec = p->opt.precision;
   const size_t bytes = pool_chain_bytes(prec, n, m, items.size(), longs.size());

@@ -1,5 +1,5 @@
-"""Batched solves (one persistent launch over many chains) vs the oracle and vs
-the single-chain path, through the C ABI."""
+"""Batched solves (the step-synchronous engine over many chains) vs the
+oracle and vs the single-chain path, through the C ABI."""
 import numpy as np
 import pytest
 
@@ -50,7 +50,7 @@ def reference(g):
     return _cache[key]
 
 
-ENGINES = {"persistent": rl.BATCH_PERSISTENT, "lockstep": rl.BATCH_LOCKSTEP}
+ENGINES = {"lockstep": rl.BATCH_LOCKSTEP}
 
 
 @pytest.mark.parametrize("engine", list(ENGINES))
@@ -108,7 +108,8 @@ def test_batch_autotune_and_repeat():
     db = rl.DeviceBatch(gs, precision=rl.FP32C_KAHANH)
     bs = rl.BatchSolver(db, eps=1e-7, max_steps=20000)
     best = bs.autotune()
-    assert best["wg_size"] in (256, 512, 1024) and 0 <= best["wg_per_cu"] <= 16
+    assert best["wg_size"] in (256, 512) and best["wg_per_cu"] in (0, 4, 8)
+    assert best["engine"] == rl.BATCH_LOCKSTEP
     st, res, ms = bs.solve()
     assert st == rl.RLGL_OK
     pa = to_np(bs.pi).copy()
@@ -123,7 +124,7 @@ def test_batch_maxc_small_chains(engine):
     gs = [workloads.chung_lu(n, 2.3, 6.0, 0.0, 0.85, seed=n, name=f"s{n}") for n in (40, 120, 333)]
     say("case batch_maxc", engine)
     db = rl.DeviceBatch(gs, precision=rl.FP64)
-    bs = rl.BatchSolver(db, sched=rl.SCHED_MAXC, eps=0.15e-10, wg_size=256, wg_per_cu=1, max_steps=200000,
+    bs = rl.BatchSolver(db, sched=rl.SCHED_MAXC, eps=0.15e-10, wg_size=256, wg_per_cu=0, max_steps=200000,
                         engine=ENGINES[engine])
     st, res, ms = bs.solve()
     assert st == rl.RLGL_OK
@@ -144,27 +145,29 @@ def test_batch_not_converged_reports_chain_status(engine):
     bs.close()
 
 
-def test_batch_engines_agree_and_tol_l1_certifies():
+def test_batch_route_shapes_agree_and_tol_l1_certifies():
     """Per-chain L1 targets: each chain stops at ||C||_1/|H.1| < tol (1 - c_k),
-    and the FP64 residual of its pi_hat certifies L1 <= tol.  Both engines
-    take the same number of steps up to the refresh and rounding order."""
+    and the FP64 residual of its pi_hat certifies L1 <= tol.  The route
+    launched one workgroup per plan item and strided over 8 workgroups per CU
+    take the same number of steps up to the rounding order."""
     gs = chains()
     say("case batch_tol_l1")
     tols = [1e-6 if k % 2 else 3e-7 for k in range(len(gs))]
     db = rl.DeviceBatch(gs, precision=rl.FP32C_KAHANH, tol_l1=tols)
     out = {}
-    for name, eng in ENGINES.items():
-        bs = rl.BatchSolver(db, engine=eng, max_steps=20000)
+    shapes = {"per_item": 0, "strided": 8}
+    for name, per_cu in shapes.items():
+        bs = rl.BatchSolver(db, engine=rl.BATCH_LOCKSTEP, wg_per_cu=per_cu, max_steps=20000)
         st, res, ms = bs.solve()
         assert st == rl.RLGL_OK
         pis = [to_np(bs.chain_pi(k)).copy() for k in range(len(gs))]
         out[name] = (res, pis)
         bs.close()
     for k, g in enumerate(gs):
-        for name in ENGINES:
+        for name in shapes:
             res, pis = out[name]
             cert = oracle.residual(oracle_chain(g), pis[k]) / (1 - g.c)
             assert cert <= tols[k], (name, k, cert)
             assert l1(pis[k], reference(g)) <= tols[k], (name, k)
-        ta, tb = out["persistent"][0][k]["t"], out["lockstep"][0][k]["t"]
+        ta, tb = out["per_item"][0][k]["t"], out["strided"][0][k]["t"]
         assert abs(ta - tb) <= 2, (k, ta, tb)

@@ -176,17 +176,16 @@ def test_small_solver_reports_links_out_of_range():
         assert st == rl.RLGL_EINVAL and "out of range" in rl.rlgl_last_error()
 
 
-@pytest.mark.parametrize("engine", [rl.BATCH_LOCKSTEP, rl.BATCH_PERSISTENT])
-def test_batch_reports_links_out_of_range(engine):
+@pytest.mark.parametrize("per_cu", [0, 8])
+def test_batch_reports_links_out_of_range(per_cu):
     gs = [workloads.chung_lu(n, 2.3, 6.0, 0.0, 0.85, seed=60 + k, name=f"b{k}")
           for k, n in enumerate((3000, 1200, 5000))]
-    say("case broken_batch", engine)
+    say("case broken_batch", per_cu)
     db = rl.DeviceBatch(gs, precision=rl.FP32C_KAHANH, tol_l1=1e-6)
     # one source of chain 1 points past its last state
     db.row[int(db.edge_off[1]) + 5] = gs[1].n + 2
     torch.cuda.synchronize()
-    bs = rl.BatchSolver(db, engine=engine, max_steps=1000,
-                        wg_size=256 if engine == rl.BATCH_LOCKSTEP else 512)
+    bs = rl.BatchSolver(db, max_steps=1000, wg_size=256, wg_per_cu=per_cu)
     st, res, _ = bs.solve(raise_on_error=False)
     assert res[1]["status"] == rl.RLGL_EINVAL
     assert res[0]["status"] == rl.RLGL_OK and res[2]["status"] == rl.RLGL_OK
