@@ -350,6 +350,69 @@ def serving_leg(args, rl, torch, oracle):
             "largest_footprint_bytes": int(max(foot)), "iterations_per_poll": args.serve_iters, "budgets": out}
 
 
+def _csv_rows(folder, suffix):
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(folder, "**", f"*{suffix}"), recursive=True)):
+        rows.extend(csv.DictReader(open(f)))
+    return rows
+
+
+def pmc_summary(folder: str, workload: str, kernel: str, commands: list) -> str:
+    """Summary text of the rocprofv3 runs under `folder` (trace/, pmc_FETCH_SIZE/,
+    pmc_WRITE_SIZE/, copy_FETCH_SIZE/, copy_WRITE_SIZE/): the dominant kernel's
+    mean launch duration and its HBM bytes per launch, the counters scaled by
+    what they read for a plain 1 GiB device copy."""
+    def per_dispatch(sub, name_part):
+        vals = {}
+        for r in _csv_rows(os.path.join(folder, sub), "counter_collection.csv"):
+            if name_part in r["Kernel_Name"]:
+                vals[r["Dispatch_Id"]] = vals.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+        return list(vals.values())
+
+    fetch = per_dispatch("pmc_FETCH_SIZE", f"k_{kernel}")
+    write = per_dispatch("pmc_WRITE_SIZE", f"k_{kernel}")
+    cf = max(per_dispatch("copy_FETCH_SIZE", "copyBuffer"))
+    cw = max(per_dispatch("copy_WRITE_SIZE", "copyBuffer"))
+    gib_kib = float(1 << 20)  # a 1 GiB copy moves 2^20 KiB each way
+    ff, wf = gib_kib / cf, gib_kib / cw
+    durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1000.0
+            for r in _csv_rows(os.path.join(folder, "trace"), "kernel_trace.csv") if f"k_{kernel}" in r["Kernel_Name"]]
+    # launches of steps that ran (those enqueued after the stop return at once)
+    durs = [x for x in durs if x >= 0.25 * max(durs)]
+    pairs = [(f, w) for f, w in zip(fetch, write) if f >= 0.25 * max(fetch)]
+    fetch, write = [f for f, _ in pairs], [w for _, w in pairs]
+    hbm = [1024.0 * (f * ff + w * wf) for f, w in zip(fetch, write)]
+    lines = [f"# rocprofv3 summary of k_{kernel} on the {workload} workload (MI355X)", "# commands, from the repository root:"]
+    lines += [f"#   {c}" for c in commands]
+    lines += [f"# calibration: a plain 1 GiB device copy reads {cf:.0f} KiB (FETCH_SIZE) and writes {cw:.0f} KiB "
+              f"(WRITE_SIZE) per launch for {gib_kib:.0f} KiB each way",
+              f"kernel = {kernel}", f"workload = {workload}", f"source_hash = {source_hash()}",
+              f"fetch_factor = {ff:.4f}", f"write_factor = {wf:.4f}",
+              "# launches of steps that ran (a launch enqueued after the stop returns at once and is left out)",
+              f"launches_counted = {len(hbm)}",
+              f"fetch_size_kib_mean = {sum(fetch) / max(len(fetch), 1):.1f}",
+              f"write_size_kib_mean = {sum(write) / max(len(write), 1):.1f}",
+              f"hbm_bytes_per_launch = {sum(hbm) / max(len(hbm), 1):.0f}",
+              f"trace_launches = {len(durs)}",
+              f"trace_avg_duration_us = {sum(durs) / max(len(durs), 1):.2f}"]
+    return "\n".join(lines) + "\n"
+
+
+def trace_summary(folder: str, workload: str, commands: list) -> str:
+    """Markdown table of rocprofv3 --stats kernel statistics under `folder`."""
+    rows = _csv_rows(folder, "kernel_stats.csv")
+    out = [f"# rocprofv3 kernel statistics: bench.py on the {workload} workload (MI355X)", "",
+           "Commands (from the repository root):", "", "```"] + commands + ["```", "",
+           "| kernel | calls | total ms | avg us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
+    for r in rows[:16]:
+        out.append(f"| `{r['Name'][:72]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                   f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                   f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    return "\n".join(out) + "\n"
+
+
 SCHED_IDS = {}
 
 
@@ -380,6 +443,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
+    ap.add_argument("--pmc-summary", default=None, metavar="FOLDER",
+                    help="print the summary of the rocprofv3 runs under FOLDER (no GPU) and exit")
+    ap.add_argument("--kernel", default="complete", help="kernel of --pmc-summary")
+    ap.add_argument("--trace-summary", default=None, metavar="FOLDER",
+                    help="print the kernel statistics of the rocprofv3 trace under FOLDER (no GPU) and exit")
+    ap.add_argument("--commands", default="", help="--pmc-summary: the commands that made the runs, ';'-separated")
     ap.add_argument("--batch", type=int, default=512,
                     help="chains of the batched workload (0 skips the batched leg)")
     ap.add_argument("--serve-requests", type=int, default=20000,
@@ -389,6 +458,16 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=512, help="pre-generated chains requests draw from")
     ap.add_argument("--serve-iters", type=int, default=4, help="lockstep iterations between host polls")
     args = ap.parse_args()
+
+    if args.trace_summary:
+        print(trace_summary(args.trace_summary, args.workload,
+                            [c.strip() for c in args.commands.split(";") if c.strip()]), end="")
+        return
+
+    if args.pmc_summary:
+        print(pmc_summary(args.pmc_summary, args.workload, args.kernel,
+                          [c.strip() for c in args.commands.split(";") if c.strip()]), end="")
+        return
 
     if args.calibrate_copy:
         import torch

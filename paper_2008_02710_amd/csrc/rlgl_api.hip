@@ -298,7 +298,10 @@ hipError_t enqueue_step(rlgl_ctx *c, long long s, double eps, long long s_limit,
     else k_select<float, 0><<<c->grid_sel, blk, 0, c->stream>>>(d, s, eps, s_limit, force_all);
   });
   if (e != hipSuccess) return e;
-  if (!(d.route == ROUTE_PULL && d.colptr)) {
+  // the select pulls every step of the all-green rule (and step 0) when the
+  // CSC is given, so the push pass is not launched for them
+  const bool pulls = d.colptr && (d.route == ROUTE_PULL || (d.route == ROUTE_AUTO && (force_all || d.sched == SCHED_ALL)));
+  if (!pulls) {
     e = timed(c, KS_PUSH, s, [&] {
       if (c->prec == RLGL_FP64) k_push<double><<<c->grid_push, blk, 0, c->stream>>>(d, s);
       else k_push<float><<<c->grid_push, blk, 0, c->stream>>>(d, s);
