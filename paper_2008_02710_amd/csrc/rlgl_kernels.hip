@@ -905,6 +905,8 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
   constexpr int NCP = (WCOLS + 1 + 63) / 64;                 // column pointers per lane
   constexpr int NK = STAGEK ? (WCOLS * KW + 63) / 64 : 1;    // staged raw dwords per lane
   __shared__ int s_row[NWAVE][WL];
+  // stored link values of the item, parked like its sources
+  __shared__ T s_val[VAL ? NWAVE : 1][VAL ? WL : 1];
   __shared__ int s_cp[NWAVE][NCP * 64];
   __shared__ unsigned int s_kr[NWAVE][NK * 64];
   __shared__ double s_sum[NWAVE][WCOLS + 64];
@@ -912,9 +914,9 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
   // What the HOTK lowest-numbered sources send, staged once per workgroup:
   // in the relabelled layout they are the states of largest out-degree, so
   // their gathers (about a fifth of the links on R-MAT, half on the
-  // Chung-Lu graphs) read LDS instead of L2.  FP32 send values only (24 KB,
-  // four workgroups per CU still fit).
-  constexpr int HOTK = sizeof(S) == 4 ? (KH ? HOT_SRC_TK : HOT_SRC) : 1;
+  // Chung-Lu graphs) read LDS instead of L2.  FP32 send values only, as many
+  // as leave room for four workgroups per CU next to the other LDS arrays.
+  constexpr int HOTK = sizeof(S) != 4 ? 1 : (VAL && KH) ? HOT_SRC_VAL_TK : (VAL || KH) ? HOT_SRC_TK : HOT_SRC;
   __shared__ S s_hot[HOTK];
   const int hk = sizeof(S) == 4 ? min(HOTK, d.n) : 0;
   for (int q = threadIdx.x; q < hk; q += BLOCK) s_hot[q] = src[q];
@@ -922,6 +924,7 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   int *row = s_row[wv];
+  T *valw = s_val[VAL ? wv : 0];
   int *cp = s_cp[wv];
   unsigned int *kr = s_kr[wv];
   double *sum = s_sum[wv];
@@ -938,6 +941,7 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
 
   // registers of the item fetched ahead
   int pr[WU] = {}, pc[NCP] = {};
+  T pv[VAL ? WU : 1] = {};
   unsigned int pk[NK] = {};
   // The item is the same for the whole wave (scalar registers); every lane
   // loads at an index clamped into the item, so no load sits behind a
@@ -954,6 +958,13 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
     const int elast = max(ne - 1, 0);
 #pragma unroll
     for (int u = 0; u < WU; ++u) pr[u] = rows[(unsigned int)min(u * 64 + lane, elast)];
+    if (VAL) {
+      // the item's link values, coalesced like its sources (an empty item
+      // reads the first column pointer's bytes, which every graph has)
+      const T *__restrict__ vs = (ne > 0) ? cval + item.z : (const T *)colptr;
+#pragma unroll
+      for (int u = 0; u < WU; ++u) pv[u] = vs[(unsigned int)min(u * 64 + lane, elast)];
+    }
     const bool run = item.x >= 0;  // a run: 1 <= ncol <= WCOLS
     const int k0 = run ? item.x : 0, ncol = run ? item.y - item.x : 0;
     const int *__restrict__ cps = colptr + k0;
@@ -1046,6 +1057,10 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
       const bool run = item.x >= 0;
 #pragma unroll
       for (int u = 0; u < WU; ++u) row[u * 64 + lane] = (u * 64 + lane < ne) ? pr[u] : -1;
+      if (VAL) {
+#pragma unroll
+        for (int u = 0; u < WU; ++u) valw[u * 64 + lane] = pv[u];
+      }
 #pragma unroll
       for (int q = 0; q < NCP; ++q) cp[q * 64 + lane] = (run && q * 64 + lane <= ncol) ? pc[q] - p0 : 0;
       if (STAGEK) {
@@ -1062,9 +1077,9 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
       const int4 a = *(const int4 *)&row[e0 + h];
       jj[h] = a.x; jj[h + 1] = a.y; jj[h + 2] = a.z; jj[h + 3] = a.w;
     }
-    // The item's gathers (and stored link values) are sent before the next
-    // item's loads: loads complete in the order they were sent, so waiting
-    // for the gathers then never waits for the next item's stream.
+    // The item's gathers are sent before the next item's loads: loads
+    // complete in the order they were sent, so waiting for the gathers then
+    // never waits for the next item's stream.
     S xr[WU];
     bool ok[WU];
 #pragma unroll
@@ -1076,11 +1091,11 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
       badl |= (e0 + u < item.w - item.z && !ok[u]) ? 1 : 0;
       xr[u] = (j < (unsigned int)hk) ? s_hot[j] : src[ok[u] ? j : 0u];
     }
+    // this lane's link values, parked with the item
     T wr[WU];
-    const T *__restrict__ vals = cval + (VAL ? item.z : 0);
-    if (VAL && ne > 0) {
+    if (VAL) {
 #pragma unroll
-      for (int u = 0; u < WU; ++u) wr[u] = vals[(unsigned int)min(e0 + u, ne - 1)];
+      for (int u = 0; u < WU; ++u) wr[u] = valw[e0 + u];
     }
     asm volatile("" ::: "memory");
     // the next round's item (none past the end: its loads read element 0)
@@ -1093,10 +1108,7 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
       asm volatile("" : "+v"(xr[u]));  // the wait for the gather stays here
       x[u] = ok[u] ? xr[u] : S(0);
       w[u] = 1.0;
-      if (VAL && ne > 0) {
-        asm volatile("" : "+v"(wr[u]));
-        w[u] = (e0 + u < ne) ? (double)wr[u] : 1.0;
-      }
+      if (VAL) w[u] = (e0 + u < ne) ? (double)wr[u] : 1.0;
     }
     if (item.x >= 0) {
       const int k0 = item.x, ncol = item.y - item.x;
