@@ -55,7 +55,7 @@ size_t record_span() { return records_bytes() + sizeof(Glob); }
 struct Layout {
   size_t cash0, cash1, hist, hist_lo, fr_rowstart, fr_eoff, fr_id, fr_scale, chunk_first, green_mask, delta, colt,
       hot_nodes, rec, glob,
-      log, items, long_cols, long_acc, long_cnt, khist, tk_ckey, tk_cid, tk_hist, tk_cnt, total;
+      log, items, long_cols, long_acc, long_cnt, khist, tk_ckey, tk_cid, tk_hist, tk_cnt, tk_seg, total;
   size_t max_items, max_long;
   // relabelled layout
   size_t perm, old2new, nrowptr, ncol, nval, ncolptr, nrow, ncval;
@@ -103,8 +103,9 @@ Layout make_layout(long long n, long long nnz, int prec, bool has_csc, bool rela
     L.khist = take(4 * (size_t)3 * KH_STRIPES * KH_BINS);
     L.tk_ckey = take(8 * (size_t)n);
     L.tk_cid = take(4 * (size_t)n);
-    L.tk_hist = take(4 * (size_t)3 * KH_BINS);
+    L.tk_hist = take(4 * (size_t)TK_HIST_WORDS);
     L.tk_cnt = take(4 * (size_t)SEL_GRID);
+    L.tk_seg = (prec == RLGL_FP64) ? 0 : take(4 * (size_t)TK_GRID * TK_LOW_BINS);
   }
   if (relabel) {
     const size_t vs = (prec == RLGL_FP64) ? 8 : 4;
@@ -259,7 +260,7 @@ hipError_t enqueue_step(rlgl_ctx *c, long long s, double eps, long long s_limit,
     e = timed(c, KS_TOPK, s, [&] {
       // the k-th largest |C| and the id bound among its ties: the bin of the
       // histogram the previous complete pass counted, its candidates, then a
-      // one-workgroup radix select over them
+      // radix select over them
       const bool dbl = c->prec == RLGL_FP64;
       if (c->khist_stale) {
         k_topk_hist_zero<<<8, 256, 0, c->stream>>>(d, s);
@@ -267,10 +268,18 @@ hipError_t enqueue_step(rlgl_ctx *c, long long s, double eps, long long s_limit,
         else k_topk_hist_full<float><<<c->grid_sel, BLOCK, 0, c->stream>>>(d, s);
         c->khist_stale = false;
       }
-      // the digits below bin B, then those of the ids (ids < 2^31)
+      if (!dbl) {
+        // FP32 keys: the collecting pass counts the middle digit, one more
+        // pass the low digit, and one workgroup fixes tau and the id bound
+        k_topk_collect<float><<<d.tk_grid, BLOCK, 0, c->stream>>>(d, s);
+        k_topk_narrow<<<d.tk_grid, BLOCK, 0, c->stream>>>(d, s);
+        k_topk_finish<<<1, BLOCK, 0, c->stream>>>(d, s, d.tk_grid);
+        return;
+      }
+      // FP64 keys: the digits below bin B, then those of the ids (ids < 2^31)
       TkDigit dg[8];
       int nd = 0;
-      for (int lo = (dbl ? 63 : 31) - KH_BITS; lo > 0;) {
+      for (int lo = 63 - KH_BITS; lo > 0;) {
         const int w = std::min(lo, KH_BITS);
         lo -= w;
         dg[nd++] = TkDigit{0, lo, w};
@@ -281,13 +290,11 @@ hipError_t enqueue_step(rlgl_ctx *c, long long s, double eps, long long s_limit,
         dg[nd++] = TkDigit{1, lo, w};
       }
       const int pg = std::max(1, std::min(c->grid_sel, 256));
-      if (dbl) k_topk_collect<double><<<d.tk_grid, BLOCK, 0, c->stream>>>(d, s);
-      else k_topk_collect<float><<<d.tk_grid, BLOCK, 0, c->stream>>>(d, s);
+      k_topk_collect<double><<<d.tk_grid, BLOCK, 0, c->stream>>>(d, s);
       for (int p = 0; p <= nd; ++p) {
         const TkDigit prev = p > 0 ? dg[p - 1] : TkDigit{0, 0, 0};
         const TkDigit cur = p < nd ? dg[p] : TkDigit{1, 0, 0};
-        if (dbl) k_topk_pass<double><<<p < nd ? pg : 1, BLOCK, 0, c->stream>>>(d, s, p, prev, cur);
-        else k_topk_pass<float><<<p < nd ? pg : 1, BLOCK, 0, c->stream>>>(d, s, p, prev, cur);
+        k_topk_pass<double><<<p < nd ? pg : 1, BLOCK, 0, c->stream>>>(d, s, p, prev, cur);
       }
     });
     if (e != hipSuccess) return e;
@@ -788,11 +795,12 @@ rlgl_status rlgl_create(const rlgl_graph *g, const rlgl_options *o, void *ws, si
   d.tk_cid = topk ? (int *)(w + L.tk_cid) : nullptr;
   d.tk_hist = topk ? (unsigned int *)(w + L.tk_hist) : nullptr;
   d.tk_cnt = topk ? (int *)(w + L.tk_cnt) : nullptr;
+  d.tk_seg = (topk && c->prec != RLGL_FP64) ? (unsigned int *)(w + L.tk_seg) : nullptr;
   c->khist_stale = false;
 
   const int tiles = (g->n + TILE - 1) / TILE;
   c->grid_sel = std::max(1, std::min(tiles, SEL_GRID));
-  d.tk_grid = std::min(c->grid_sel, 256);  // workgroups of the collecting pass
+  d.tk_grid = std::min(c->grid_sel, TK_GRID);  // workgroups of the collecting pass
   c->grid_push = (int)std::max<long long>(1, std::min<long long>((g->nnz + CH - 1) / CH, PUSH_GRID));
   c->grid_misc = std::max(1, std::min((g->n + BLOCK - 1) / BLOCK, NODE_GRID));
 

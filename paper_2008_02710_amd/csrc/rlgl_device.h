@@ -21,6 +21,12 @@ constexpr int HOT_SRC_VAL_TK = 2048;  // ... when it does both
 constexpr int KH_BITS = 11;         // top-k: bits of the |C| key counted by the pass that writes C
 constexpr int KH_BINS = 1 << KH_BITS;
 constexpr int KH_STRIPES = 4;       // global copies of the top-k histogram
+constexpr int TK_GRID = 256;        // top-k: workgroups of the collecting pass at most (one segment each)
+constexpr int TK_LOW_BITS = 31 - 2 * KH_BITS;  // FP32 keys: bits below the histogram's and the next digit's
+constexpr int TK_LOW_BINS = 1 << TK_LOW_BITS;
+// top-k pass histograms: FP64 keys, three digit buffers; FP32 keys, the
+// middle digit in KH_STRIPES copies and the low digit
+constexpr int TK_HIST_WORDS = (3 > KH_STRIPES ? 3 : KH_STRIPES) * KH_BINS + TK_LOW_BINS;
 constexpr int LOG_STEPS = 4096;     // ring of per-step records kept for profiling
 constexpr int MAX_GRID = 2048;      // edge-parallel launches
 constexpr int NODE_GRID = 512;      // node-parallel launches (2 workgroups per CU)
@@ -154,8 +160,9 @@ struct Dev {
   unsigned int *khist;         // [3][KH_STRIPES][KH_BINS]
   unsigned long long *tk_ckey;  // [n]
   int *tk_cid;                  // [n]
-  unsigned int *tk_hist;        // [3][KH_BINS] digit histograms of the passes over the candidates
+  unsigned int *tk_hist;        // [TK_HIST_WORDS] digit histograms of the passes over the candidates
   int *tk_cnt;                  // [tk_grid] candidates each collecting workgroup found
+  unsigned int *tk_seg;         // FP32 keys: [tk_grid][TK_LOW_BINS] low-digit histograms per segment
   int tk_grid;                  // workgroups of the collecting pass
 };
 

@@ -675,6 +675,20 @@ __device__ __forceinline__ void kh_flush(unsigned int *kh, const unsigned int *s
   for (int b = threadIdx.x; b < KH_BINS; b += blockDim.x)
     if (s_kh[b]) atomicAdd(&dst[b], s_kh[b]);
 }
+// The sum of the KH_STRIPES copies of a histogram into LDS (BLOCK threads):
+// every load is sent before the first one is waited for.
+__device__ __forceinline__ void kh_load(const unsigned int *kh, unsigned int *s_h) {
+  constexpr int PB = KH_BINS / BLOCK;
+  unsigned int c[PB];
+#pragma unroll
+  for (int u = 0; u < PB; ++u) c[u] = 0u;
+#pragma unroll
+  for (int q = 0; q < KH_STRIPES; ++q)
+#pragma unroll
+    for (int u = 0; u < PB; ++u) c[u] += kh[q * KH_BINS + u * BLOCK + threadIdx.x];
+#pragma unroll
+  for (int u = 0; u < PB; ++u) s_h[u * BLOCK + threadIdx.x] = c[u];
+}
 
 // ------------------------------------------------------- column gather pass
 //
@@ -1330,11 +1344,13 @@ __global__ __launch_bounds__(BLOCK) void k_refresh_long(Dev d, long long t, int 
 //     KH_STRIPES global copies (same-address atomics serialise).  After a
 //     refresh or an import, k_topk_hist_full counts them instead.
 //  2. k_topk_collect (one pass over C_t): every workgroup finds the bin B that
-//     holds the k-th key from the histogram, and the keys of bin B go to a
-//     candidate list (one atomic per wave).
-//  3. k_topk_pass (a few short passes over the candidates only): an 11-bit
-//     radix select fixes the rest of tau's bits, then the id bound among the
-//     keys equal to tau.
+//     holds the k-th key from the histogram and copies the keys of bin B and
+//     their ids into its own segment of the candidate list, in node order.
+//     With FP32 keys it also counts their next KH_BITS bits.
+//  3. FP32 keys: k_topk_narrow fixes the last bits of tau and the id bound in
+//     one more pass over the candidates (below).  FP64 keys: k_topk_pass, a
+//     few short radix passes over the candidates, KH_BITS bits of the key at a
+//     time, then of the ids among the keys equal to tau.
 
 __global__ void k_topk_hist_zero(Dev d, long long s) {
   unsigned int *kh = khist_of(d, s);
@@ -1407,22 +1423,28 @@ __global__ __launch_bounds__(BLOCK) void k_topk_collect(Dev d, long long s) {
   __shared__ long long sh_before;
   const unsigned int *kh = khist_of(d, s);
   const long long want = d.k < (long long)d.n ? d.k : (long long)d.n;
-  for (int b = threadIdx.x; b < KH_BINS; b += BLOCK) {
-    unsigned int c = 0;
-#pragma unroll
-    for (int q = 0; q < KH_STRIPES; ++q) c += kh[q * KH_BINS + b];
-    s_h[b] = c;
-  }
-  // the pass histograms: the first pass counts into buffer 0
-  for (int q = blockIdx.x * BLOCK + threadIdx.x; q < KH_BINS; q += gridDim.x * BLOCK) d.tk_hist[q] = 0u;
+  kh_load(kh, s_h);
+  // FP64 keys: the first pass counts into buffer 0.  FP32 keys: this pass
+  // counts the next digit into the KH_STRIPES copies at tk_hist itself, which
+  // the previous step's k_topk_finish (or the reset) left at zero.
+  constexpr bool NEXT = sizeof(T) == 4;
+  if (!NEXT)
+    for (int q = blockIdx.x * BLOCK + threadIdx.x; q < KH_BINS; q += gridDim.x * BLOCK) d.tk_hist[q] = 0u;
   __syncthreads();
   int B;
   long long above;
   pick_digit(s_h, KH_BINS, false, want, &B, &above, sh_scan, &sh_dig, &sh_before);
   if (B < 0) {
     // the histogram does not describe C_t (it counts fewer than k keys)
-    if (blockIdx.x == 0 && threadIdx.x == 0) g->bad = 1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      g->bad = 1;
+      g->tk_rem[0] = 0;
+    }
     return;
+  }
+  if (NEXT) {
+    for (int b = threadIdx.x; b < KH_BINS; b += BLOCK) s_h[b] = 0u;
+    __syncthreads();
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     g->tk_pref[0] = (unsigned long long)B << (KB - KH_BITS);
@@ -1438,28 +1460,208 @@ __global__ __launch_bounds__(BLOCK) void k_topk_collect(Dev d, long long s) {
   unsigned long long *ckey = d.tk_ckey + b0;
   int *cid = d.tk_cid + b0;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  __shared__ int sh_wc[NWAVE];
+  const unsigned long long below = (1ull << lane) - 1ull;
+  // VPT nodes per thread between two barriers, listed in node order
+  __shared__ int sh_wc[VPT][NWAVE];
   int filled = 0;
-  for (int base = b0; base < b1; base += BLOCK) {
-    const int i = base + threadIdx.x;
-    const T v = (i < b1) ? C[i] : T(0);
-    const bool hit = i < b1 && kh_bin(v) == B;
-    const unsigned long long bal = __ballot(hit);
-    if (lane == 0) sh_wc[wv] = __popcll(bal);
-    __syncthreads();
-    int off = filled;
-    for (int w = 0; w < wv; ++w) off += sh_wc[w];
-    int tot = 0;
-    for (int w = 0; w < NWAVE; ++w) tot += sh_wc[w];
-    if (hit) {
-      const int slot = off + __popcll(bal & ((1ull << lane) - 1ull));
-      ckey[slot] = topk_key(v);
-      cid[slot] = i;
+  for (int base = b0; base < b1; base += TILE) {
+    T v[VPT];
+    bool hit[VPT];
+    unsigned long long bal[VPT];
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      const int i = base + u * BLOCK + threadIdx.x;
+      v[u] = (i < b1) ? C[i] : T(0);
     }
-    filled += tot;
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      const int i = base + u * BLOCK + threadIdx.x;
+      hit[u] = i < b1 && kh_bin(v[u]) == B;
+      bal[u] = __ballot(hit[u]);
+      if (lane == 0) sh_wc[u][wv] = __popcll(bal[u]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      int off = filled, tot = 0;
+      for (int w = 0; w < NWAVE; ++w) {
+        off += (w < wv) ? sh_wc[u][w] : 0;
+        tot += sh_wc[u][w];
+      }
+      const unsigned long long key = topk_key(v[u]);
+      if (hit[u]) {
+        const int slot = off + __popcll(bal[u] & below);
+        ckey[slot] = key;
+        cid[slot] = base + u * BLOCK + threadIdx.x;
+      }
+      // (bal is the same on every lane: the whole wave enters or none)
+      if (NEXT && bal[u]) wave_hist_add<KH_BITS>(s_h, (unsigned int)(key >> TK_LOW_BITS) & (KH_BINS - 1u), hit[u]);
+      filled += tot;
+    }
     __syncthreads();
   }
   if (threadIdx.x == 0) d.tk_cnt[blockIdx.x] = filled;
+  if (NEXT) kh_flush(d.tk_hist, s_h);  // stripe blockIdx mod KH_STRIPES
+}
+
+// FP32 keys (31 bits: the histogram's KH_BITS, a middle digit of KH_BITS, a
+// low digit of TK_LOW_BITS).  k_topk_narrow: every workgroup picks the middle
+// digit from the counts k_topk_collect made, then compacts the candidates of
+// its own segment that match the key so far (in place and in node order) and
+// counts their low digit, into the global low-digit histogram and into its
+// segment's row of tk_seg.  k_topk_finish (one workgroup) picks the low digit,
+// which completes tau; if only some of the keys equal to tau are taken, the
+// segment rows say which segment holds the last one taken, and a scan of that
+// segment's compacted list in node order finds its id.  It leaves the pass
+// histograms at zero for the next step.  (A last-workgroup ticket in place of
+// the second launch would need a device-scope fence in every workgroup, which
+// writes back the XCD's whole L2.)
+__device__ __forceinline__ unsigned int *tk_low_hist(const Dev &d) { return d.tk_hist + KH_STRIPES * KH_BINS; }
+
+__global__ __launch_bounds__(BLOCK) void k_topk_narrow(Dev d, long long s) {
+  Glob *g = d.glob;
+  if (g->status != 0) return;
+  __shared__ unsigned int s_h[KH_BINS];
+  __shared__ unsigned long long sh_scan[NWAVE];
+  __shared__ int sh_dig;
+  __shared__ long long sh_before;
+  __shared__ int sh_wc[NWAVE];
+  const unsigned long long pref0 = g->tk_pref[0];
+  const long long rem0 = g->tk_rem[0];
+  if (rem0 <= 0) return;  // k_topk_collect found no bin (reported there)
+  kh_load(d.tk_hist, s_h);
+  __syncthreads();
+  int A;
+  long long beforeA;
+  pick_digit(s_h, KH_BINS, false, rem0, &A, &beforeA, sh_scan, &sh_dig, &sh_before);
+  if (A < 0) {
+    // fewer candidates than the histogram of C_t promised
+    if (threadIdx.x == 0) g->bad = 1;
+    return;
+  }
+  const long long remA = rem0 - beforeA;
+  const unsigned long long prefA = pref0 | ((unsigned long long)A << TK_LOW_BITS);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    g->tk_pref[1] = prefA;
+    g->tk_rem[1] = remA;
+  }
+  for (int b = threadIdx.x; b < TK_LOW_BINS; b += BLOCK) s_h[b] = 0u;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int S = tk_segment(d.n, gridDim.x);
+  const int cnt = d.tk_cnt[blockIdx.x];
+  unsigned long long *ckey = d.tk_ckey + (size_t)blockIdx.x * S;
+  int *cid = d.tk_cid + (size_t)blockIdx.x * S;
+  int filled = 0;
+  // Every thread holds its entry before the barrier below, and an entry moves
+  // only to a position at or before its own, so no entry is overwritten
+  // before it is read.
+  for (int c0 = 0; c0 < cnt; c0 += BLOCK) {
+    const int q = c0 + threadIdx.x;
+    const bool in = q < cnt;
+    const unsigned long long key = in ? ckey[q] : 0ull;
+    const int id = in ? cid[q] : 0;
+    const bool hit = in && (key >> TK_LOW_BITS) == (prefA >> TK_LOW_BITS);
+    const unsigned long long bal = __ballot(hit);
+    if (lane == 0) sh_wc[wv] = __popcll(bal);
+    __syncthreads();
+    int off = filled, tot = 0;
+    for (int w = 0; w < NWAVE; ++w) {
+      off += (w < wv) ? sh_wc[w] : 0;
+      tot += sh_wc[w];
+    }
+    if (hit) {
+      const int slot = off + __popcll(bal & ((1ull << lane) - 1ull));
+      ckey[slot] = key;
+      cid[slot] = id;
+    }
+    wave_hist_add<TK_LOW_BITS>(s_h, (unsigned int)key & (TK_LOW_BINS - 1u), hit);
+    filled += tot;
+    __syncthreads();
+  }
+  unsigned int *hlow = tk_low_hist(d);
+  unsigned int *seg = d.tk_seg + (size_t)blockIdx.x * TK_LOW_BINS;
+  for (int b = threadIdx.x; b < TK_LOW_BINS; b += BLOCK) {
+    seg[b] = s_h[b];
+    if (s_h[b]) atomicAdd(&hlow[b], s_h[b]);
+  }
+  if (threadIdx.x == 0) d.tk_cnt[blockIdx.x] = filled;
+}
+
+static_assert(TK_GRID <= BLOCK, "k_topk_finish reads one segment row per thread");
+__global__ __launch_bounds__(BLOCK) void k_topk_finish(Dev d, long long s, int G) {
+  Glob *g = d.glob;
+  if (g->status != 0) return;
+  __shared__ unsigned int s_h[TK_LOW_BINS];
+  __shared__ unsigned long long sh_scan[NWAVE];
+  __shared__ int sh_dig, sh_seg, sh_id;
+  __shared__ long long sh_before, sh_r;
+  unsigned int *hlow = tk_low_hist(d);
+  if (g->tk_rem[0] > 0 && !g->bad) {
+    const unsigned long long prefA = g->tk_pref[1];
+    const long long remA = g->tk_rem[1];
+    for (int b = threadIdx.x; b < TK_LOW_BINS; b += BLOCK) s_h[b] = hlow[b];
+    __syncthreads();
+    int Bl;
+    long long beforeB;
+    pick_digit(s_h, TK_LOW_BINS, false, remA, &Bl, &beforeB, sh_scan, &sh_dig, &sh_before);
+    const unsigned long long tau = prefA | (unsigned long long)(Bl < 0 ? 0 : Bl);
+    const long long remB = remA - beforeB;  // keys equal to tau still to take, >= 1
+    int tie = 0x7fffffff;                    // every key equal to tau is taken
+    if (Bl < 0) {
+      if (threadIdx.x == 0) g->bad = 1;
+    } else if (remB < (long long)s_h[Bl]) {
+      // the segment that holds the remB-th key equal to tau, in node order
+      const unsigned long long mine =
+          (int)threadIdx.x < G ? (unsigned long long)d.tk_seg[(size_t)threadIdx.x * TK_LOW_BINS + Bl] : 0ull;
+      unsigned long long total;
+      const unsigned long long run = block_excl_scan(mine, sh_scan, &total);
+      if (threadIdx.x == 0) sh_seg = -1;
+      __syncthreads();
+      if ((int)threadIdx.x < G && run < (unsigned long long)remB && run + mine >= (unsigned long long)remB) {
+        sh_seg = threadIdx.x;
+        sh_r = remB - (long long)run;
+      }
+      __syncthreads();
+      const int sb = sh_seg;
+      if (sb < 0) {
+        if (threadIdx.x == 0) g->bad = 1;
+      } else {
+        // thread t scans the strip [t L, (t + 1) L) of the segment's list
+        const long long r = sh_r;
+        const int S = tk_segment(d.n, G);
+        const int m = d.tk_cnt[sb];
+        const unsigned long long *kk = d.tk_ckey + (size_t)sb * S;
+        const int *ii = d.tk_cid + (size_t)sb * S;
+        const int L = (m + BLOCK - 1) / BLOCK;
+        const int q0 = min(m, (int)threadIdx.x * L), q1 = min(m, q0 + L);
+        unsigned long long own = 0;
+        for (int q = q0; q < q1; ++q) own += (kk[q] == tau) ? 1ull : 0ull;
+        unsigned long long tot2;
+        const unsigned long long before = block_excl_scan(own, sh_scan, &tot2);
+        if (threadIdx.x == 0) sh_id = -1;
+        __syncthreads();
+        if (before < (unsigned long long)r && before + own >= (unsigned long long)r) {
+          long long left = r - (long long)before;
+          for (int q = q0; q < q1; ++q)
+            if (kk[q] == tau && --left == 0) {
+              sh_id = ii[q];
+              break;
+            }
+        }
+        __syncthreads();
+        tie = sh_id;
+        if (tie < 0 && threadIdx.x == 0) g->bad = 1;
+      }
+    }
+    if (threadIdx.x == 0) {
+      Rec *rc = &d.rec[s % 3];
+      rc->topk_tau = (double)__uint_as_float((unsigned int)tau);
+      rc->topk_tie_id = tie;
+    }
+  }
+  // the pass histograms start the next step at zero
+  for (int b = threadIdx.x; b < KH_STRIPES * KH_BINS + TK_LOW_BINS; b += BLOCK) d.tk_hist[b] = 0u;
 }
 
 // One digit of the radix select over the candidates: the digits of the key
@@ -1676,6 +1878,8 @@ __global__ __launch_bounds__(BLOCK) void k_reset(Dev d) {
     d.glob->ticket = 0u;
     d.glob->rpool = 0.0;
   }
+  if (d.tk_hist)
+    for (int q = blockIdx.x * BLOCK + threadIdx.x; q < TK_HIST_WORDS; q += gridDim.x * BLOCK) d.tk_hist[q] = 0u;
   for (int q = blockIdx.x * BLOCK + threadIdx.x; q < d.n_long; q += gridDim.x * BLOCK) {
     d.long_acc[q] = 0.0;
     if (d.long_cnt) d.long_cnt[q] = 0;
@@ -1846,7 +2050,6 @@ template __global__ void k_topk_hist_full<float>(Dev, long long);
 template __global__ void k_topk_hist_full<double>(Dev, long long);
 template __global__ void k_topk_collect<float>(Dev, long long);
 template __global__ void k_topk_collect<double>(Dev, long long);
-template __global__ void k_topk_pass<float>(Dev, long long, int, TkDigit, TkDigit);
 template __global__ void k_topk_pass<double>(Dev, long long, int, TkDigit, TkDigit);
 template __global__ void k_refresh_pool<0>(Dev);
 template __global__ void k_refresh_pool<1>(Dev);

@@ -537,6 +537,44 @@ def test_topk_with_heavy_ties(prec, k):
     s.close()
 
 
+
+_topk_big = {}
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=PREC_NAMES.get)
+@pytest.mark.parametrize("case,k", [("levels", 1), ("levels", 777), ("levels", 150001), ("levels", 299999),
+                                    ("low", 1000), ("low", 123457), ("equal", 1), ("equal", 200000),
+                                    ("distinct", 50000), ("distinct", 400000)])
+def test_topk_many_segments(prec, case, k):
+    """Top-k on 300,000 nodes (256 candidate segments of 1,280 nodes): a few
+    magnitudes (ties across many segments), keys that differ only in their
+    last 9 bits, all magnitudes equal, all distinct, and k above N.  The
+    green set is the oracle's bit for bit."""
+    if "g" not in _topk_big:
+        _topk_big["g"] = workloads.poisson_uniform(300000, 4.0, 0.85, seed=3)
+    g = _topk_big["g"]
+    say("case topk_segments", PREC_NAMES[prec], case, k)
+    rng = np.random.default_rng(k)
+    sign = rng.choice([-1.0, 1.0], g.n)
+    if case == "levels":
+        mag = np.array([0.0, 2.0 ** -12, 2.0 ** -11, 2.0 ** -10, 2.0 ** -9])[rng.integers(0, 5, g.n)]
+    elif case == "low":
+        mag = 1.0 + rng.integers(0, 512, g.n) * 2.0 ** -23  # the same top 22 key bits
+    elif case == "equal":
+        mag = np.full(g.n, 2.0 ** -18)
+    else:
+        mag = rng.integers(1, 2 ** 23, g.n) * 2.0 ** -40  # exact in FP32
+    C0 = sign * mag
+    H0 = np.full(g.n, 1.0 / g.n)
+    s = solver(g, prec, sched=rl.SCHED_TOPK, k=k, record_green=1, route=rl.ROUTE_PULL)
+    s.set_state(torch.from_numpy(C0).cuda(), torch.from_numpy(H0).cuda(), float(H0.sum()), t=4)
+    s.step(1)
+    mask = to_np(s.green()).astype(bool)
+    s.close()
+    want = oracle.select(C0, oracle.TOPK, 0.0, k)
+    assert int(mask.sum()) == min(k, g.n)
+    assert np.array_equal(mask, want)
+
 # ------------------------------------------------------- pull plan edges
 
 def _boundary_graph():
