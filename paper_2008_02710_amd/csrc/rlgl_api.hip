@@ -2125,13 +2125,18 @@ const void *small_kernel(int prec) {
 
 // Largest n whose cash fits in the LDS one workgroup may take on the current
 // device, next to the kernel's own static LDS; 0 when the query fails.
-int small_capacity(int prec) {
+// LDS bytes left to the one-workgroup kernel after its static arrays.
+long long small_lds_budget(int prec) {
   int dev = 0, lds = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
   hipFuncAttributes fa{};
   if (hipFuncGetAttributes(&fa, small_kernel(prec)) != hipSuccess) return 0;
-  const long long dyn = (long long)lds - (long long)fa.sharedSizeBytes - 16;
+  return (long long)lds - (long long)fa.sharedSizeBytes - 16;
+}
+
+int small_capacity(int prec) {
+  const long long dyn = small_lds_budget(prec);
   const int cs = prec == RLGL_FP64 ? 8 : 4;
   return dyn > 0 ? (int)(dyn / cs) : 0;
 }
@@ -2214,7 +2219,11 @@ rlgl_status small_solve(const rlgl_graph *g, const rlgl_options *o, double eps, 
   a.rec = (SmallRec *)(w + L.rec);
   a.pi = dev_pi;
   const int cs = o->precision == RLGL_FP64 ? 8 : 4;
-  const size_t dyn = align_up((size_t)g->n * cs, 16);
+  size_t dyn = align_up((size_t)g->n * cs, 16);
+  // the row pointers go into LDS after the cash when both fit
+  const size_t with_rp = dyn + align_up(4 * ((size_t)g->n + 1), 16);
+  a.rp_lds = (long long)with_rp <= small_lds_budget(o->precision) ? 1 : 0;
+  if (a.rp_lds) dyn = with_rp;
   HIP_TRY(hipFuncSetAttribute(small_kernel(o->precision), hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
   if (o->precision == RLGL_FP64) k_small<double><<<1, SM_BLOCK, dyn, stream>>>(a);
   else k_small<float><<<1, SM_BLOCK, dyn, stream>>>(a);

@@ -26,6 +26,8 @@
 // its list route rounds once per link, and a stop is accepted only on the
 // cash rebuilt from the history, C_t = H_t P - H_t (eq. (7)), when refresh is
 // set.
+#include <type_traits>
+
 #include "rlgl_device.h"
 
 namespace rlgl {
@@ -34,6 +36,7 @@ constexpr int SM_BLOCK = 512;             // threads of the one workgroup (8 wav
 constexpr int SM_NW = SM_BLOCK / 64;
 constexpr int SM_LIST = 512;              // green nodes the list route takes
 constexpr int SM_BATCH = 8;               // in-links of a column whose loads are sent together
+constexpr int SM_UNROLL = 8;              // nodes per thread whose LDS loads are sent together
 
 // Result record of a small solve (in the workspace).
 struct SmallRec {
@@ -53,6 +56,7 @@ struct SmallArgs {
   int theta_period;
   unsigned long long seed;
   int refresh;  // FP32 cash: accept a stop only on the cash rebuilt from H
+  int rp_lds;   // the CSR row pointers are copied into LDS after the cash (they fit)
   double eps;
   long long max_steps;
   double *H;  // [n] history
@@ -103,6 +107,14 @@ __device__ __forceinline__ long long small_sum_ll(long long v, long long *sh) {
   return r;
 }
 
+// A double of lane q (uniform q) on every lane.
+__device__ __forceinline__ double rd_lane(double v, int q) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned int)(b & 0xffffffffll), q);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), q);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
 template <class T>
 __global__ __launch_bounds__(SM_BLOCK) void k_small(SmallArgs a) {
 #pragma clang fp contract(off)
@@ -111,7 +123,11 @@ __global__ __launch_bounds__(SM_BLOCK) void k_small(SmallArgs a) {
   __shared__ double s_red[4 * SM_NW];
   __shared__ long long s_ll[SM_NW];
   __shared__ int s_list[SM_LIST];
+  // list route: each green node's moved cash, out-degree and first link
+  __shared__ double s_lm[SM_LIST];
+  __shared__ int s_ld[SM_LIST], s_lr[SM_LIST];
   __shared__ int s_cnt;
+  __shared__ int s_ovf;  // a thread holds more than two maximisers
   __shared__ double s_out[4];  // list route: moved sum, restart pool, change of ||H||_1
   __shared__ long long s_edges;
   __shared__ int s_bad;  // a pointer or link index outside its range was met
@@ -152,11 +168,12 @@ __global__ __launch_bounds__(SM_BLOCK) void k_small(SmallArgs a) {
   // the in-links in CSC order (increasing source); Q holds what each source
   // sends.  Folds the statistics of the new cash.
   double l1p, csp, srp, mxp;
+  const bool rp = a.r != 1.0;
   auto fold = [&](double x) {
     const double ax = fabs(x);
     l1p += ax;
     csp += x;
-    if (a.r != 1.0) srp += pow(ax, a.r);
+    if (rp) srp += pow(ax, a.r);
     mxp = fmax(mxp, ax);
   };
   auto column_pass = [&](auto kept, double share) {
@@ -204,7 +221,15 @@ __global__ __launch_bounds__(SM_BLOCK) void k_small(SmallArgs a) {
   };
 
   // ---- step 0 (eq. (3), then eqs. (5)-(6) with G_0 = [N], M_0 = (1/N) 1)
-  if (tid == 0) s_bad = 0;
+  if (tid == 0) {
+    s_bad = 0;
+    s_ovf = 0;
+    s_cnt = 0;
+  }
+  // the list route reads each green node's row pointers from this copy
+  int *s_rp = (int *)(sm_dyn + (((size_t)n * sizeof(T) + 15) & ~(size_t)15));
+  if (a.rp_lds)
+    for (int i = tid; i <= n; i += SM_BLOCK) s_rp[i] = rowptr[i];
   __syncthreads();
   const double m0 = 1.0 / (double)n;
   long long edges = 0;
@@ -231,10 +256,38 @@ __global__ __launch_bounds__(SM_BLOCK) void k_small(SmallArgs a) {
   column_pass([&](int) { return -m0; }, s_out[1] / (double)n);
 
   long long t = 1, green = 0, green_total = 0, refreshed_at = -1;
+  // MaxC: the pass that adds the restart share also keeps, per thread, its
+  // largest |C| and the nodes that hold it (up to two); `tracked` says they
+  // describe the cash the next step selects from
+  bool tracked = false;
+  double tmax = -1.0;
+  int tidx0 = -1, tidx1 = -1, tcnt = 0;
   int status = ST_RUNNING, last_route = ROUTE_PULL;
   double theta = 0.0, l1 = 0.0, csum = 0.0;
+  // l1 and max after a list-route step with FP64 cash and r = 1 (the other
+  // sums are zero there): one exchange and one barrier; the exchange buffer
+  // alternates with the step, and the route's barrier lies between a read of
+  // one buffer and the next write of it
+  __shared__ double s_r2[2][2 * SM_NW];
   for (;;) {
-    const Red3M st = small_reduce(Red3M{l1p, csp, srp, mxp}, s_red);
+    Red3M st;
+    if (tracked && !fp32 && !rp) {
+      const double lw = wave_sum(l1p), mw = wave_max(mxp);
+      double *b2 = s_r2[t & 1];
+      if ((tid & 63) == 0) {
+        b2[tid >> 6] = lw;
+        b2[SM_NW + (tid >> 6)] = mw;
+      }
+      __syncthreads();
+      st = Red3M{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int i = 0; i < SM_NW; ++i) {
+        st.a += b2[i];
+        st.m = fmax(st.m, b2[SM_NW + i]);
+      }
+    } else {
+      st = small_reduce(Red3M{l1p, csp, srp, mxp}, s_red);
+    }
     l1 = st.a;
     csum = st.b;
     const double maxabs = st.m;
@@ -263,6 +316,7 @@ __global__ __launch_bounds__(SM_BLOCK) void k_small(SmallArgs a) {
       }
       pool = small_reduce(Red3M{pool, 0.0, 0.0, 0.0}, s_red).a;
       column_pass([&](int k) { return -H[k]; }, pool / (double)n);
+      tracked = false;
       refreshed_at = t;
       continue;
     }
@@ -280,73 +334,148 @@ __global__ __launch_bounds__(SM_BLOCK) void k_small(SmallArgs a) {
     // ---- list route (RLGL_MaxC)
     bool listed = false;
     if (a.sched == SCHED_MAXC) {
-      if (tid == 0) s_cnt = 0;
-      __syncthreads();
-      for (int i = tid; i < n; i += SM_BLOCK) {
-        if (fabs((double)C[i]) == maxabs) {
-          const int q = atomicAdd(&s_cnt, 1);
-          if (q < SM_LIST) s_list[q] = i;
+      if (tracked) {
+        // the maximisers from the per-thread records (s_cnt was cleared by
+        // the pass that made them); a thread that holds more than two falls
+        // back to the scan below
+        if (tmax == maxabs) {
+          if (tcnt > 2) {
+            s_ovf = 1;
+          } else {
+            const int q = atomicAdd(&s_cnt, tcnt);
+            if (q < SM_LIST) s_list[q] = tidx0;
+            if (tcnt == 2 && q + 1 < SM_LIST) s_list[q + 1] = tidx1;
+          }
+        }
+        __syncthreads();
+      }
+      const bool scan = !tracked || s_ovf;
+      if (scan) {
+        __syncthreads();  // every thread has read s_ovf
+        if (tid == 0) {
+          s_cnt = 0;
+          s_ovf = 0;
+        }
+        __syncthreads();
+      }
+      // SM_UNROLL independent LDS loads per thread before the first is used
+      for (int base = 0; scan && base < n; base += SM_BLOCK * SM_UNROLL) {
+        double v[SM_UNROLL];
+#pragma unroll
+        for (int u = 0; u < SM_UNROLL; ++u) {
+          // an index clamped into [0, n): no load waits behind a branch
+          const int i = base + u * SM_BLOCK + tid;
+          const double x = fabs((double)C[min(i, n - 1)]);
+          v[u] = (i < n) ? x : -1.0;
+        }
+#pragma unroll
+        for (int u = 0; u < SM_UNROLL; ++u) {
+          if (v[u] == maxabs) {
+            const int q = atomicAdd(&s_cnt, 1);
+            if (q < SM_LIST) s_list[q] = base + u * SM_BLOCK + tid;
+          }
         }
       }
-      __syncthreads();
+      if (scan) __syncthreads();
       const int ng = s_cnt;
       if (ng <= SM_LIST) {
         listed = true;
-        if (tid == 0) {
-          // increasing node order (insertion sort; the list is usually one node)
-          for (int q = 1; q < ng; ++q) {
-            const int v = s_list[q];
-            int p = q - 1;
-            while (p >= 0 && s_list[p] > v) {
-              s_list[p + 1] = s_list[p];
-              --p;
+        if (tid < 64) {
+          // Wave 0 routes the list.  Loads are made by the lanes together;
+          // every update of the cash and of the sums is made one at a time in
+          // the serial order, from values read out of the lanes.
+          const int lane = tid;
+          if (lane == 0) {
+            // increasing node order (insertion sort; the list is usually one node)
+            for (int q = 1; q < ng; ++q) {
+              const int v = s_list[q];
+              int p = q - 1;
+              while (p >= 0 && s_list[p] > v) {
+                s_list[p + 1] = s_list[p];
+                --p;
+              }
+              s_list[p + 1] = v;
             }
-            s_list[p + 1] = v;
           }
+          wave_lds_fence();
           double msum = 0.0, pool = 0.0, dh = 0.0;
           long long e = 0;
           // M_t from the snapshot: every green node's cash leaves before any
-          // arrives; each node's M parks in Q until its links are walked
-          for (int q = 0; q < ng; ++q) {
-            const int i = s_list[q];
-            const double m = (double)C[i];
-            const double h0 = H[i];
-            const double h1 = h0 + m;
-            H[i] = h1;
-            dh += fabs(h1) - fabs(h0);
-            msum += m;
-            C[i] = (T)((double)C[i] - m);
-            Q[i] = m;  // parked until routed below
+          // arrives (the nodes of the list are distinct)
+          for (int q0 = 0; q0 < ng; q0 += 64) {
+            const int nq = min(64, ng - q0);
+            double lm = 0.0, ldh = 0.0;
+            if (lane < nq) {
+              const int li = s_list[q0 + lane];
+              lm = (double)C[li];
+              const double h0 = H[li];
+              const double h1 = h0 + lm;
+              H[li] = h1;
+              ldh = fabs(h1) - fabs(h0);
+              C[li] = (T)((double)C[li] - lm);
+              s_lm[q0 + lane] = lm;
+              const int r0 = a.rp_lds ? s_rp[li] : rowptr[li];
+              const int r1 = a.rp_lds ? s_rp[li + 1] : rowptr[li + 1];
+              const bool okr = r0 >= 0 && r1 >= r0 && (long long)r1 <= nnz;
+              if (!okr) s_bad = 1;
+              s_ld[q0 + lane] = okr ? r1 - r0 : 0;
+              s_lr[q0 + lane] = r0;
+            }
+            for (int q = 0; q < nq; ++q) {
+              msum += rd_lane(lm, q);
+              dh += rd_lane(ldh, q);
+            }
           }
+          wave_lds_fence();
           for (int q = 0; q < ng; ++q) {
-            const int i = s_list[q];
-            const double m = Q[i];
-            Q[i] = 0.0;
+            const double m = s_lm[q];
             if (m == 0.0) continue;
-            const int d = deg(i);
-            const int r0 = rowptr[i], r1 = r0 + d;
+            const int d = s_ld[q];
+            const int r0 = s_lr[q];
             if (d == 0) {
               pool += m;
               continue;
             }
             e += d;
-            for (int p = r0; p < r1; ++p) {
-              const double w = a.val ? (double)((const T *)a.val)[p] : 1.0 / (double)d;
-              const double cw = c * w;
-              const double add = cw * m;
-              const int k = a.col[p];
-              if ((unsigned)k >= (unsigned)n) {
-                s_bad = 1;
-                continue;
+            for (int b = 0; b < d; b += 64) {
+              const int nb = min(64, d - b);
+              int lk = -1;
+              double ladd = 0.0;
+              if (lane < nb) {
+                const int p = r0 + b + lane;
+                const double w = a.val ? (double)((const T *)a.val)[p] : 1.0 / (double)d;
+                const double cw = c * w;
+                ladd = cw * m;
+                lk = a.col[p];
+                if ((unsigned)lk >= (unsigned)n) {
+                  s_bad = 1;
+                  lk = -1;
+                }
               }
-              C[k] = (T)((double)C[k] + add);
+              // FP64 cash and one value on every link of the chunk: the adds
+              // are equal, so the lanes may make them in any order (an LDS
+              // atomic for a node linked twice); otherwise one at a time in
+              // link order
+              const double a0 = rd_lane(ladd, 0);
+              if (!fp32 && __ballot(lane < nb && ladd != a0) == 0ull) {
+                if (lk >= 0) atomicAdd((double *)&C[lk], ladd);
+              } else {
+                for (int u = 0; u < nb; ++u) {
+                  const int k = __builtin_amdgcn_readlane(lk, u);
+                  const double add = rd_lane(ladd, u);
+                  if (k >= 0 && lane == 0) C[k] = (T)((double)C[k] + add);
+                }
+              }
+              wave_lds_fence();
             }
             pool += (1.0 - c) * m;
           }
-          s_out[0] = msum;
-          s_out[1] = pool;
-          s_out[2] = dh;
-          s_edges = e;
+          if (lane == 0) {
+            s_out[0] = msum;
+            s_out[1] = pool;
+            s_out[2] = dh;
+            s_edges = e;
+          }
         }
         __syncthreads();
         const double share = s_out[1] / (double)n;
@@ -355,11 +484,43 @@ __global__ __launch_bounds__(SM_BLOCK) void k_small(SmallArgs a) {
         edges += s_edges;
         green = ng;
         l1p = csp = srp = mxp = 0.0;
-        for (int k = tid; k < n; k += SM_BLOCK) {
-          const T y = (T)((double)C[k] + share);
-          C[k] = y;
-          fold((double)y);
-        }
+        tmax = -1.0;
+        tcnt = 0;
+        if (tid == 0) s_cnt = 0;  // every thread read it before the barrier above
+        // C_k + share for every node, with the statistics of fold() (the sum
+        // of C only where the drift test needs it, FP32 cash; the maximum is
+        // tmax) and the per-thread maximisers.  Whole chunks of SM_UNROLL
+        // nodes per thread carry no bounds test, so their loads are all sent
+        // before the first is used; the power sum is a separate instance.
+        auto share_pass = [&](auto rpow) {
+          constexpr bool RPW = decltype(rpow)::value;
+          auto one = [&](double v, int k) {
+            const T y = (T)(v + share);
+            C[k] = y;
+            const double ay = fabs((double)y);
+            l1p += ay;
+            if (fp32) csp += (double)y;
+            if (RPW) srp += pow(ay, a.r);
+            const bool gt = ay > tmax, eq = ay == tmax;
+            tidx1 = (eq && tcnt == 1) ? k : tidx1;
+            tcnt = gt ? 1 : (eq ? tcnt + 1 : tcnt);
+            tidx0 = gt ? k : tidx0;
+            tmax = gt ? ay : tmax;
+          };
+          int base = 0;
+          for (; base + SM_BLOCK * SM_UNROLL <= n; base += SM_BLOCK * SM_UNROLL) {
+            double v[SM_UNROLL];
+#pragma unroll
+            for (int u = 0; u < SM_UNROLL; ++u) v[u] = (double)C[base + u * SM_BLOCK + tid];
+#pragma unroll
+            for (int u = 0; u < SM_UNROLL; ++u) one(v[u], base + u * SM_BLOCK + tid);
+          }
+          for (int k = base + tid; k < n; k += SM_BLOCK) one((double)C[k], k);
+        };
+        if (rp) share_pass(std::true_type{});
+        else share_pass(std::false_type{});
+        mxp = fmax(tmax, 0.0);
+        tracked = true;
         last_route = ROUTE_PUSH;
       }
     }
@@ -394,13 +555,21 @@ __global__ __launch_bounds__(SM_BLOCK) void k_small(SmallArgs a) {
       edges += e;
       green = g;
       column_pass([&](int k) { return (double)C[k]; }, r.b / (double)n);
+      tracked = false;
       last_route = ROUTE_PULL;
     }
     green_total += green;
     ++t;
-    __syncthreads();
+    // no barrier here: the reduction that opens the next step has one before
+    // any thread reads what this step wrote
   }
 
+  if (!fp32 && tracked) {
+    // the last pass was the list route's, which leaves out the sum of C
+    double cs = 0.0;
+    for (int k = tid; k < n; k += SM_BLOCK) cs += (double)C[k];
+    csum = small_reduce(Red3M{cs, 0.0, 0.0, 0.0}, s_red).a;
+  }
   if (a.pi && (status == ST_CONVERGED || status == ST_LIMIT)) {
     for (int i = tid; i < n; i += SM_BLOCK) a.pi[i] = H[i] / hsum;  // pi_hat_t = H_t / (H_t 1), eq. (2)
   }
