@@ -425,8 +425,9 @@ def main():
     ap.add_argument("--route", default="auto", choices=["auto", "push", "pull"])
     ap.add_argument("--precision", default="fp32c_fp64h", choices=["fp64", "fp32c_fp64h", "fp32c_kahanh"])
     ap.add_argument("--tol", type=float, default=1e-6, help="certified L1 target")
-    ap.add_argument("--sched", default=None, choices=["all", "threshold", "maxc", "pc"],
+    ap.add_argument("--sched", default=None, choices=["all", "threshold", "topk", "maxc", "pc"],
                     help="green-light schedule (default: the workload's)")
+    ap.add_argument("--k", type=int, default=262144, help="green nodes per step of the top-k schedule")
     ap.add_argument("--r", type=float, default=None, help="threshold power-mean order (default 1)")
     ap.add_argument("--theta-period", type=int, default=1, help="steps between threshold refreshes")
     ap.add_argument("--seed", type=int, default=1, help="seed of the PC draws")
@@ -491,7 +492,7 @@ def main():
     import paper_2008_02710_amd as rl
 
     SCHED_IDS.update({"threshold": rl.SCHED_THRESHOLD, "all": rl.SCHED_ALL, "maxc": rl.SCHED_MAXC,
-                      "pc": rl.SCHED_PC})
+                      "pc": rl.SCHED_PC, "topk": rl.SCHED_TOPK})
     prec = {"fp64": rl.FP64, "fp32c_fp64h": rl.FP32C_FP64H, "fp32c_kahanh": rl.FP32C_KAHANH}[args.precision]
     route = {"auto": rl.ROUTE_AUTO, "push": rl.ROUTE_PUSH, "pull": rl.ROUTE_PULL}[args.route]
     wl = dict(WORKLOADS[args.workload])
@@ -504,8 +505,8 @@ def main():
     t0 = time.time()
     g = make_workload(args.workload)
     sched = SCHED_IDS[wl["sched"]]
-    if sched == rl.SCHED_PC and args.relabel:
-        args.relabel = 0  # the PC draws are keyed by the caller's node ids
+    if sched in (rl.SCHED_PC, rl.SCHED_TOPK) and args.relabel:
+        args.relabel = 0  # the PC draws and the top-k ties are keyed by the caller's node ids
     log(f"workload {g.name}: n={g.n} nnz={g.nnz} dangling={g.n_dangling} gen={time.time() - t0:.1f}s")
 
     dev = torch.device("cuda:0")
@@ -524,7 +525,7 @@ def main():
         s.reset = lambda: None  # every one-workgroup solve starts from step 0
     else:
         s = rl.Solver(dg, stream=stream, sched=sched, r=r, route=route, precision=prec, relabel=args.relabel,
-                      theta_period=args.theta_period, seed=args.seed)
+                      theta_period=args.theta_period, seed=args.seed, k=args.k)
     infos, wall, t_total, ev_ms = time_solves(rl, torch, s, eps, max_steps, args.steps, args.warmup, stream)
     pushes = sum(i["edges_pushed"] for i in infos)
     gteps = pushes / t_total / 1e9
@@ -609,16 +610,17 @@ def main():
     cpu = None
     if not args.no_cpu:
         osched = {rl.SCHED_THRESHOLD: oracle.THRESHOLD, rl.SCHED_ALL: oracle.ALL, rl.SCHED_MAXC: oracle.MAXC,
-                  rl.SCHED_PC: oracle.PC}[sched]
+                  rl.SCHED_PC: oracle.PC, rl.SCHED_TOPK: oracle.TOPK}[sched]
+        ok = {"r": r, "seed": args.seed, "k": args.k}
         a = time.perf_counter()
-        ost, _, oinfo = oracle.solve(ch, osched, eps=eps, max_steps=1, r=r, seed=args.seed)
+        ost, _, oinfo = oracle.solve(ch, osched, eps=eps, max_steps=1, **ok)
         probe = time.perf_counter() - a
         per_step = probe / 2.0
         if ost == oracle.OK:
             solves, opushes, tcpu = 0, 0, 0.0
             while tcpu < args.cpu_seconds:
                 a = time.perf_counter()
-                ost, _, oinfo = oracle.solve(ch, osched, eps=eps, max_steps=10_000_000, r=r, seed=args.seed)
+                ost, _, oinfo = oracle.solve(ch, osched, eps=eps, max_steps=10_000_000, **ok)
                 tcpu += time.perf_counter() - a
                 opushes += oinfo["edges_pushed"]
                 solves += 1
@@ -626,7 +628,7 @@ def main():
         else:
             k = max(1, int(args.cpu_seconds / max(per_step, 1e-9)) - 1)
             a = time.perf_counter()
-            ost, _, oinfo = oracle.solve(ch, osched, eps=eps, max_steps=k, r=r, seed=args.seed)
+            ost, _, oinfo = oracle.solve(ch, osched, eps=eps, max_steps=k, **ok)
             tcpu = time.perf_counter() - a
             opushes = oinfo["edges_pushed"]
             sample = (f"{'a full solve' if ost == oracle.OK else 'the first ' + str(oinfo['steps']) + ' steps'} "
@@ -667,6 +669,7 @@ def main():
                    "schedule": wl["sched"], "r": r, "precision": args.precision, "route": args.route,
                    "relabel": args.relabel, "link_values": wl["link_values"], "theta_period": args.theta_period,
                    "solver": "one-workgroup" if args.small else "multi-launch",
+                   **({"k": args.k} if wl["sched"] == "topk" else {}),
                    "eps_resid": eps, "tol_l1": args.tol, "generator": g.params.get("generator"),
                    "seed": g.params.get("seed")},
         "time_to_solution_ms": round(ms_per_solve, 4),

@@ -11,12 +11,15 @@
 //
 // Two routes per step (eq. (6), C_{t+1} = C_t - M_t + M_t P):
 //   * list route, for RLGL_MaxC (Sec. 6): the maximisers are collected in LDS
-//     and one lane moves their cash in increasing node order, link by link
-//     along the CSR rows, then the restart share is added to every node.
-//     With FP64 cash this is the operation order of the plain serial method
-//     (C -= M for every green node, then the links of each green node in turn,
-//     then the uniform share), so the cash vector equals the serial one bit
-//     for bit and so does the green set of every step.
+//     (from per-thread records the previous step's share pass kept, or by a
+//     scan) and wave 0 moves their cash in increasing node order, link by
+//     link along the CSR rows (the lanes load a green node's links together;
+//     the adds are made in link order, or all at once when they are equal),
+//     then the restart share is added to every node.  With FP64 cash this is
+//     the operation order of the plain serial method (C -= M for every green
+//     node, then the links of each green node in turn, then the uniform
+//     share), so the cash vector equals the serial one bit for bit and so
+//     does the green set of every step.
 //   * column route, for every other rule (and MaxC ties beyond the list's
 //     capacity): every green node publishes c P'_ij M_i (or M_i with stored
 //     values), and each column k sums C_k - M_k plus its in-links in
@@ -32,7 +35,7 @@
 
 namespace rlgl {
 
-constexpr int SM_BLOCK = 512;             // threads of the one workgroup (8 waves; 170 VGPRs, no spills)
+constexpr int SM_BLOCK = 512;             // threads of the one workgroup (8 waves; about 215 VGPRs, no spills)
 constexpr int SM_NW = SM_BLOCK / 64;
 constexpr int SM_LIST = 512;              // green nodes the list route takes
 constexpr int SM_BATCH = 8;               // in-links of a column whose loads are sent together
