@@ -400,10 +400,11 @@ def pmc_summary(folder: str, workload: str, kernel: str, commands: list) -> str:
     return "\n".join(lines) + "\n"
 
 
-def trace_summary(folder: str, workload: str, commands: list) -> str:
+def trace_summary(folder: str, workload: str, commands: list, label: str = None) -> str:
     """Markdown table of rocprofv3 --stats kernel statistics under `folder`."""
     rows = _csv_rows(folder, "kernel_stats.csv")
-    out = [f"# rocprofv3 kernel statistics: bench.py on the {workload} workload (MI355X)", "",
+    what = label or f"the {workload} workload"
+    out = [f"# rocprofv3 kernel statistics: bench.py on {what} (MI355X)", "",
            "Commands (from the repository root):", "", "```"] + commands + ["```", "",
            "| kernel | calls | total ms | avg us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
     for r in rows[:16]:
@@ -450,6 +451,7 @@ def main():
     ap.add_argument("--trace-summary", default=None, metavar="FOLDER",
                     help="print the kernel statistics of the rocprofv3 trace under FOLDER (no GPU) and exit")
     ap.add_argument("--commands", default="", help="--pmc-summary: the commands that made the runs, ';'-separated")
+    ap.add_argument("--label", default=None, help="--trace-summary: what the run measured (title of the table)")
     ap.add_argument("--batch", type=int, default=512,
                     help="chains of the batched workload (0 skips the batched leg)")
     ap.add_argument("--serve-requests", type=int, default=20000,
@@ -462,7 +464,7 @@ def main():
 
     if args.trace_summary:
         print(trace_summary(args.trace_summary, args.workload,
-                            [c.strip() for c in args.commands.split(";") if c.strip()]), end="")
+                            [c.strip() for c in args.commands.split(";") if c.strip()], args.label), end="")
         return
 
     if args.pmc_summary:

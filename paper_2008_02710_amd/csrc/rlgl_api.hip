@@ -159,6 +159,8 @@ struct rlgl_ctx {
   int hk;  // compensated history
   long long t;
   int grid_sel, grid_push, grid_cmp, grid_misc;
+  int pull_wide;  // k_complete runs one workgroup of PULL_WIDE waves per CU (FP32 cash)
+  int grid_pull;  // its grid: the workgroups that stay resident together
   Glob *host_glob;  // pinned
   Rec *host_rec;    // pinned, 3 records
   StepLog *host_log;
@@ -203,14 +205,20 @@ hipError_t timed(rlgl_ctx *c, int kind, long long s, F launch) {
 
 // k_complete and k_refresh come in variants by stored or implied link values
 // and by whether the threshold's power mean needs sum |C|^r (r != 1).
-template <class T, bool TK>
-void launch_complete_tk(rlgl_ctx *c, long long s, int force_all) {
+template <class T, bool TK, int PW>
+void launch_complete_w(rlgl_ctx *c, long long s, int force_all) {
   const Dev &d = c->d;
   const bool v = d.cval != nullptr, rp = d.r != 1.0;
-  if (v && rp) k_complete<T, true, true, TK><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, s, force_all);
-  else if (v) k_complete<T, true, false, TK><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, s, force_all);
-  else if (rp) k_complete<T, false, true, TK><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, s, force_all);
-  else k_complete<T, false, false, TK><<<c->grid_cmp, BLOCK, 0, c->stream>>>(d, s, force_all);
+  const int grid = c->grid_pull;
+  if (v && rp) k_complete<T, true, true, TK, PW><<<grid, PW * 64, 0, c->stream>>>(d, s, force_all);
+  else if (v) k_complete<T, true, false, TK, PW><<<grid, PW * 64, 0, c->stream>>>(d, s, force_all);
+  else if (rp) k_complete<T, false, true, TK, PW><<<grid, PW * 64, 0, c->stream>>>(d, s, force_all);
+  else k_complete<T, false, false, TK, PW><<<grid, PW * 64, 0, c->stream>>>(d, s, force_all);
+}
+template <class T, bool TK>
+void launch_complete_tk(rlgl_ctx *c, long long s, int force_all) {
+  if (sizeof(T) == 4 && c->pull_wide) launch_complete_w<float, TK, PULL_WIDE>(c, s, force_all);
+  else launch_complete_w<T, TK, NWAVE>(c, s, force_all);
 }
 // The top-k rule needs the histogram of the keys the pass writes.
 template <class T>
@@ -220,9 +228,20 @@ void launch_complete(rlgl_ctx *c, long long s, int force_all) {
 }
 
 // Workgroups of the k_complete variant launch_complete picks that fit one CU together.
+template <bool TK>
+const void *complete_wide_kernel(bool v, bool rp) {
+  return v ? (rp ? (const void *)k_complete<float, true, true, TK, PULL_WIDE>
+                 : (const void *)k_complete<float, true, false, TK, PULL_WIDE>)
+           : (rp ? (const void *)k_complete<float, false, true, TK, PULL_WIDE>
+                 : (const void *)k_complete<float, false, false, TK, PULL_WIDE>);
+}
 hipError_t complete_occupancy(const rlgl_ctx *c, int *per_cu) {
   const Dev &d = c->d;
   const bool v = d.cval != nullptr, rp = d.r != 1.0;
+  if (c->pull_wide) {
+    const void *w = d.sched == SCHED_TOPK ? complete_wide_kernel<true>(v, rp) : complete_wide_kernel<false>(v, rp);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, w, PULL_WIDE * 64, 0);
+  }
   const void *f;
   if (d.sched == SCHED_TOPK) {
     if (c->prec == RLGL_FP64)
@@ -830,12 +849,25 @@ rlgl_status rlgl_create(const rlgl_graph *g, const rlgl_options *o, void *ws, si
     // the pull's waves take items until the plan is done: one round of
     // workgroups, as many as stay resident together, keeps every wave's
     // one-item-ahead loads flowing from start to end
-    int dev = 0, cus = 0, per_cu = 0;
+    // (FP32 cash: one workgroup of PULL_WIDE waves per CU, whose LDS stages
+    // the send values of four times as many sources; the refresh keeps
+    // four workgroups of NWAVE waves)
+    int dev = 0, cus = 0, per_cu = 0, per_cu_w = 0;
+    c->pull_wide = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) ||
-        complete_occupancy(c, &per_cu) != hipSuccess || cus < 1 || per_cu < 1)
+        complete_occupancy(c, &per_cu) != hipSuccess || cus < 1 || per_cu < 1) {
       st = fail(RLGL_EHIP, "occupancy query failed");
-    else
+    } else {
       c->grid_cmp = std::max({1, std::min(tiles, NODE_GRID), std::min(d.n_items, cus * per_cu)});
+      c->grid_pull = c->grid_cmp;
+      if (c->prec != RLGL_FP64 && gi.csc_colptr) {
+        c->pull_wide = 1;
+        if (complete_occupancy(c, &per_cu_w) != hipSuccess || per_cu_w < 1)
+          st = fail(RLGL_EHIP, "occupancy query failed");
+        else
+          c->grid_pull = std::max(1, std::min(d.n_items > 0 ? d.n_items : 1, cus * per_cu_w));
+      }
+    }
   }
   if (st == RLGL_OK) st = reset_device(c);
   if (st != RLGL_OK) {

@@ -250,16 +250,37 @@ __device__ __forceinline__ void clear_stripes(Rec *r) {
 
 // Adds a block's statistics of a cash vector to its stripe of record r.
 template <int NW = NWAVE>
+// The waves' partials meet in LDS and wave 0 folds them with lane moves, so
+// no thread holds the NW partials of all four sums at once.
 __device__ __forceinline__ void fold_block_stats(Rec *r, double l1, double cs, double sr, double mx, double *sh) {
-  const Red4 t4 = block_sum4<NW>(Red4{l1, cs, sr, 0.0}, sh);
-  const double bm = block_max<NW>(mx, sh);
-  if (threadIdx.x == 0) {
-    Acc *a = my_stripe(r);
-    if (t4.a != 0.0) atomic_add_f64(&a->l1, t4.a);
-    if (t4.b != 0.0) atomic_add_f64(&a->csum, t4.b);
-    if (t4.c != 0.0) atomic_add_f64(&a->sumr, t4.c);
-    if (bm > 0.0) atomic_max_nonneg(&a->maxabs_bits, bm);
+  static_assert(NW <= 64, "one lane of wave 0 per wave");
+  l1 = wave_sum(l1);
+  cs = wave_sum(cs);
+  sr = wave_sum(sr);
+  mx = wave_max(mx);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) {
+    sh[w] = l1;
+    sh[NW + w] = cs;
+    sh[2 * NW + w] = sr;
+    sh[3 * NW + w] = mx;
   }
+  __syncthreads();
+  if (w == 0) {
+    const bool in = l < NW;
+    const double a = wave_sum(in ? sh[l] : 0.0);
+    const double b = wave_sum(in ? sh[NW + l] : 0.0);
+    const double c = wave_sum(in ? sh[2 * NW + l] : 0.0);
+    const double m = wave_max(in ? sh[3 * NW + l] : 0.0);
+    if (l == 0) {
+      Acc *acc = my_stripe(r);
+      if (a != 0.0) atomic_add_f64(&acc->l1, a);
+      if (b != 0.0) atomic_add_f64(&acc->csum, b);
+      if (c != 0.0) atomic_add_f64(&acc->sumr, c);
+      if (m > 0.0) atomic_max_nonneg(&acc->maxabs_bits, m);
+    }
+  }
+  __syncthreads();
 }
 
 // RP = false: the caller knows r = 1 (no power sum, which keeps pow out of
@@ -909,7 +930,7 @@ __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_wave_barrier();
 }
 
-template <class T, class S, bool VAL, bool STAGEK, bool RP, bool FUSE, bool KH = false, class Keep>
+template <class T, class S, bool VAL, bool STAGEK, bool RP, bool FUSE, bool KH = false, int PW = NWAVE, class Keep>
 __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ src, const T *__restrict__ kraw,
                                           Keep keep, double off, T *__restrict__ out, Rec *r,
                                           unsigned int *s_kh = nullptr) {
@@ -918,22 +939,26 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
   constexpr int KW = STAGEK ? (int)(sizeof(T) / 4) : 0;      // dwords per staged raw value
   constexpr int NCP = (WCOLS + 1 + 63) / 64;                 // column pointers per lane
   constexpr int NK = STAGEK ? (WCOLS * KW + 63) / 64 : 1;    // staged raw dwords per lane
-  __shared__ int s_row[NWAVE][WL];
+  __shared__ int s_row[PW][WL];
   // stored link values of the item, parked like its sources
-  __shared__ T s_val[VAL ? NWAVE : 1][VAL ? WL : 1];
-  __shared__ int s_cp[NWAVE][NCP * 64];
-  __shared__ unsigned int s_kr[NWAVE][NK * 64];
-  __shared__ double s_sum[NWAVE][WCOLS + 64];
-  __shared__ double sh_red[4 * NWAVE];
+  __shared__ T s_val[VAL ? PW : 1][VAL ? WL : 1];
+  __shared__ int s_cp[PW][NCP * 64];
+  __shared__ unsigned int s_kr[PW][NK * 64];
+  __shared__ double s_sum[PW][WCOLS + 64];
+  __shared__ double sh_red[4 * PW];
   // What the HOTK lowest-numbered sources send, staged once per workgroup:
   // in the relabelled layout they are the states of largest out-degree, so
   // their gathers (about a fifth of the links on R-MAT, half on the
   // Chung-Lu graphs) read LDS instead of L2.  FP32 send values only, as many
-  // as leave room for four workgroups per CU next to the other LDS arrays.
-  constexpr int HOTK = sizeof(S) != 4 ? 1 : (VAL && KH) ? HOT_SRC_VAL_TK : (VAL || KH) ? HOT_SRC_TK : HOT_SRC;
+  // as leave room for the other LDS arrays of four workgroups of NWAVE waves
+  // per CU, or of one of PULL_WIDE waves.
+  static_assert(PW == NWAVE || PW == PULL_WIDE, "two workgroup widths");
+  constexpr int HOTK = sizeof(S) != 4 ? 1
+                       : PW == NWAVE ? ((VAL && KH) ? HOT_SRC_VAL_TK : (VAL || KH) ? HOT_SRC_TK : HOT_SRC)
+                                     : ((VAL && KH) ? HOT_WIDE_VAL_TK : VAL ? HOT_WIDE_VAL : KH ? HOT_WIDE_TK : HOT_WIDE);
   __shared__ S s_hot[HOTK];
   const int hk = sizeof(S) == 4 ? min(HOTK, d.n) : 0;
-  for (int q = threadIdx.x; q < hk; q += BLOCK) s_hot[q] = src[q];
+  for (int q = threadIdx.x; q < hk; q += PW * 64) s_hot[q] = src[q];
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
@@ -950,7 +975,7 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
   const unsigned int *__restrict__ kw = (const unsigned int *)kraw;
   double l1 = 0.0, cs = 0.0, sr = 0.0, mx = 0.0;
   const int e0 = lane * WU;
-  const int stride = (int)gridDim.x * NWAVE;
+  const int stride = (int)gridDim.x * PW;
   const int4 none = make_int4(-1, 0, 0, 0);
 
   // registers of the item fetched ahead
@@ -995,7 +1020,7 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
   // holding round base + r, and each round's item is read out of its lane
   // into scalar registers: no round waits for an item load (a per-round load
   // would have to be waited for together with the vector loads before it).
-  const int it0 = (int)blockIdx.x * NWAVE + wv;
+  const int it0 = (int)blockIdx.x * PW + wv;
   int4 ilist = none;
   int ibase = 0;
   auto load_items = [&](int round0) {
@@ -1220,23 +1245,27 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
     advance();
   }
   if (badl) d.glob->bad = 1;
-  fold_block_stats(r, l1, cs, sr, mx, sh_red);
+  fold_block_stats<PW>(r, l1, cs, sr, mx, sh_red);
 }
 
 // ----------------------------------------------------------------- complete
 
-template <class T, bool VAL, bool RP, bool TK>
-__global__ __launch_bounds__(BLOCK, 4) void k_complete(Dev d, long long s, int init) {
+// PW waves per workgroup: NWAVE (four workgroups per CU) or PULL_WIDE (one
+// workgroup per CU, whose pull stages the send values of four times as many
+// sources in LDS).
+template <class T, bool VAL, bool RP, bool TK, int PW = NWAVE>
+__global__ __launch_bounds__(PW * 64, PW == NWAVE ? 4 : 1) void k_complete(Dev d, long long s, int init) {
+  constexpr int NT = PW * 64;
   Glob *g = d.glob;
   if (g->status != 0) return;
   Rec *cur = &d.rec[s % 3];
   Rec *nxt = &d.rec[(s + 1) % 3];
   __shared__ Tot sh_tot;
-  __shared__ double sh_red[4 * NWAVE];
+  __shared__ double sh_red[4 * PW];
   // TK: the top-k histogram of C_{t+1}'s keys, counted as they are written
   __shared__ unsigned int s_kh[TK ? KH_BINS : 1];
   if (TK) {
-    for (int b = threadIdx.x; b < KH_BINS; b += BLOCK) s_kh[b] = 0u;
+    for (int b = threadIdx.x; b < KH_BINS; b += NT) s_kh[b] = 0u;
     __syncthreads();
   }
   const Tot tot = read_totals(cur, &sh_tot);
@@ -1249,11 +1278,11 @@ __global__ __launch_bounds__(BLOCK, 4) void k_complete(Dev d, long long s, int i
     double l1 = 0.0, cs = 0.0, sr = 0.0, mx = 0.0;
     T *C = (T *)d.cash[cur->buf];
     double *D = d.delta;
-    const int ntiles = (n + TILE - 1) / TILE;
+    const int ntiles = (n + NT * VPT - 1) / (NT * VPT);
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
 #pragma unroll
       for (int q = 0; q < VPT; ++q) {
-        const int i = tile * TILE + q * BLOCK + threadIdx.x;
+        const int i = tile * NT * VPT + q * NT + threadIdx.x;
         if (i < n) {
           double x = (double)C[i] + off;
           if (D) {
@@ -1267,7 +1296,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_complete(Dev d, long long s, int i
         }
       }
     }
-    fold_block_stats(nxt, l1, cs, sr, mx, sh_red);
+    fold_block_stats<PW>(nxt, l1, cs, sr, mx, sh_red);
   } else {
     const int sched = init ? SCHED_ALL : d.sched;
     const double theta = cur->theta;
@@ -1283,7 +1312,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_complete(Dev d, long long s, int i
     };
     // what the sources send was written by select (zero off the green set;
     // links outside [0, N) are ignored)
-    wave_pull<T, T, VAL, true, RP, true, TK>(d, (const T *)d.src, Cc, keep, off, Cn, nxt, s_kh);
+    wave_pull<T, T, VAL, true, RP, true, TK, PW>(d, (const T *)d.src, Cc, keep, off, Cn, nxt, s_kh);
   }
   if (TK) {
     __syncthreads();
@@ -2035,6 +2064,14 @@ template __global__ void k_complete<float, true, false, false>(Dev, long long, i
 template __global__ void k_complete<float, true, false, true>(Dev, long long, int);
 template __global__ void k_complete<float, true, true, false>(Dev, long long, int);
 template __global__ void k_complete<float, true, true, true>(Dev, long long, int);
+template __global__ void k_complete<float, false, false, false, PULL_WIDE>(Dev, long long, int);
+template __global__ void k_complete<float, false, false, true, PULL_WIDE>(Dev, long long, int);
+template __global__ void k_complete<float, false, true, false, PULL_WIDE>(Dev, long long, int);
+template __global__ void k_complete<float, false, true, true, PULL_WIDE>(Dev, long long, int);
+template __global__ void k_complete<float, true, false, false, PULL_WIDE>(Dev, long long, int);
+template __global__ void k_complete<float, true, false, true, PULL_WIDE>(Dev, long long, int);
+template __global__ void k_complete<float, true, true, false, PULL_WIDE>(Dev, long long, int);
+template __global__ void k_complete<float, true, true, true, PULL_WIDE>(Dev, long long, int);
 template __global__ void k_complete<double, false, false, false>(Dev, long long, int);
 template __global__ void k_complete<double, false, false, true>(Dev, long long, int);
 template __global__ void k_complete<double, false, true, false>(Dev, long long, int);
