@@ -241,6 +241,39 @@ rlgl_status rlgl_solve_small(const rlgl_graph *g, const rlgl_options *opt, doubl
 rlgl_status rlgl_solve_small_static(const rlgl_graph *g, const rlgl_options *opt, double eps, int64_t max_steps,
                                     double *dev_pi, void *stream, rlgl_step_info *info);
 
+/* ---- pull plans (host only; no GPU is used) ---------------------------
+ *
+ * The static work partition of the column sums of eq. (6) (the pull route,
+ * C_{t+1,k} = (C_t - M_t)_k + sum over the in-links j -> k of c P'_jk M_j +
+ * the restart share), built from CSC column pointers held in HOST memory.
+ * rlgl_create builds the same plan for a single chain and rlgl_batch_create /
+ * rlgl_pool_admit the batched one for each chain; these calls return it so it
+ * can be inspected.
+ *
+ * Item i is items[4i .. 4i+3] = {x, y, p0, p1}, links [p0, p1) of the CSC:
+ *   x >= 0: a run of the whole columns [x, y);
+ *   x <  0: a piece of column y, whose in-links exceed one run; its partial sum
+ *           goes to long-column slot -1 - x, and long_cols[slot] = y.
+ * Single chain (rlgl_pull_plan): runs hold at most 512 links and 64 columns,
+ * pieces 512 links, and the pieces are spread over the first three quarters
+ * of the runs.  Batched (rlgl_batch_chain_plan): all pieces first (*n_pieces
+ * of them, at most 4096 links each, for columns of more than 2048 in-links),
+ * then runs of at most 2048 links and 1024 columns.  Every column lies in
+ * exactly one run or is a long column; every link lies in exactly one item.
+ *
+ * host_colptr: n + 1 non-decreasing ints from 0 to nnz (caller-owned host
+ * memory, read only).  items / long_cols: caller-owned host arrays of
+ * 4 * max_items and max_long ints (may be NULL when the max is 0).  Returns
+ * the number of items (>= 0), RLGL_EINVAL for bad pointers or column
+ * pointers, RLGL_ENOMEM when max_items or max_long is too small (the counts
+ * are still returned through n_long and n_pieces).  *item_bound (may be NULL)
+ * receives the item count the device workspace is sized for. */
+int64_t rlgl_pull_plan(const int32_t *host_colptr, int32_t n, int64_t nnz, int32_t *items, int64_t max_items,
+                       int32_t *long_cols, int64_t max_long, int64_t *n_long, int64_t *item_bound);
+int64_t rlgl_batch_chain_plan(const int32_t *host_colptr, int32_t n, int64_t nnz, int32_t *items, int64_t max_items,
+                              int32_t *long_cols, int64_t max_long, int64_t *n_long, int64_t *n_pieces,
+                              int64_t *item_bound);
+
 /* Releases the host context.  Does not touch the caller's device memory. */
 void rlgl_destroy(rlgl_ctx *ctx);
 

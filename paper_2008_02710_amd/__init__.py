@@ -103,7 +103,7 @@ EXPORTED = ["rlgl_default_options", "rlgl_workspace_bytes", "rlgl_create", "rlgl
             "rlgl_pool_admit", "rlgl_pool_advance", "rlgl_pool_launch", "rlgl_pool_wait", "rlgl_pool_poll",
             "rlgl_pool_result", "rlgl_pool_release", "rlgl_pool_destroy", "rlgl_validate_scratch_bytes",
             "rlgl_validate", "rlgl_step_mask", "rlgl_small_max_n", "rlgl_small_workspace_bytes",
-            "rlgl_solve_small", "rlgl_solve_small_static"]
+            "rlgl_solve_small", "rlgl_solve_small_static", "rlgl_pull_plan", "rlgl_batch_chain_plan"]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -136,6 +136,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rlgl_solve_small.restype = i32
     lib.rlgl_solve_small_static.argtypes = [G, O, f64, i64, vp, vp, I]
     lib.rlgl_solve_small_static.restype = i32
+    P64 = ctypes.POINTER(i64)
+    lib.rlgl_pull_plan.argtypes = [vp, i32, i64, vp, i64, vp, i64, P64, P64]
+    lib.rlgl_pull_plan.restype = i64
+    lib.rlgl_batch_chain_plan.argtypes = [vp, i32, i64, vp, i64, vp, i64, P64, P64, P64]
+    lib.rlgl_batch_chain_plan.restype = i64
     lib.rlgl_destroy.argtypes = [vp]
     lib.rlgl_destroy.restype = None
     lib.rlgl_last_error.argtypes = []
@@ -276,6 +281,41 @@ def rlgl_solve(ctx, eps: float, max_steps: int, pi_out=None, raise_on_error: boo
     if raise_on_error:
         _check(st, "rlgl_solve")
     return st, info
+
+
+def _plan(fn, colptr, batched: bool):
+    """Runs a host-only plan builder on int32 column pointers (numpy)."""
+    import numpy as np
+    cp = np.ascontiguousarray(colptr, dtype=np.int32)
+    n = cp.size - 1
+    nnz = int(cp[-1]) if cp.size else 0
+    n_long, n_pieces, bound = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    extra = [ctypes.byref(n_pieces)] if batched else []
+    # first call sizes the output (RLGL_ENOMEM with zero capacity unless the plan is empty)
+    cnt = fn(cp.ctypes.data, n, nnz, None, 0, None, 0, ctypes.byref(n_long), *extra, ctypes.byref(bound))
+    if cnt < 0 and cnt != RLGL_ENOMEM:
+        raise RlglError(int(cnt), "plan")
+    cap_items = int(bound.value)
+    items = np.zeros((max(cap_items, 1), 4), dtype=np.int32)
+    longs = np.zeros(max(int(n_long.value), 1), dtype=np.int32)
+    cnt = fn(cp.ctypes.data, n, nnz, items.ctypes.data, cap_items, longs.ctypes.data, int(n_long.value),
+             ctypes.byref(n_long), *extra, ctypes.byref(bound))
+    if cnt < 0:
+        raise RlglError(int(cnt), "plan")
+    out = {"items": items[:cnt], "long_cols": longs[:int(n_long.value)], "item_bound": int(bound.value)}
+    if batched:
+        out["n_pieces"] = int(n_pieces.value)
+    return out
+
+
+def rlgl_pull_plan(colptr) -> dict:
+    """The single-chain pull plan of CSC column pointers (host numpy array)."""
+    return _plan(_lib.rlgl_pull_plan, colptr, False)
+
+
+def rlgl_batch_chain_plan(colptr) -> dict:
+    """The batched engine's plan of one chain's CSC column pointers (host numpy array)."""
+    return _plan(_lib.rlgl_batch_chain_plan, colptr, True)
 
 
 def rlgl_small_max_n(precision: int) -> int:

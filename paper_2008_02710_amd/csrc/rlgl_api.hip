@@ -61,6 +61,15 @@ struct Layout {
   size_t perm, old2new, nrowptr, ncol, nval, ncolptr, nrow, ncval;
 };
 
+// Upper bounds of the single-chain pull plan (pull_plan_host): a run ends
+// because it is full (WL links or WCOLS columns) or because a long column
+// follows; two consecutive runs hold more than WL links unless a column-count
+// or long-column break separates them; pieces: nnz / WL + one per long column.
+size_t pull_long_bound(long long nnz) { return (size_t)(nnz / (WL + 1) + 1); }
+size_t pull_item_bound(long long n, long long nnz) {
+  return 3 * (size_t)(nnz / WL + 2) + (size_t)(n / WCOLS + 2) + 2 * pull_long_bound(nnz) + 2;
+}
+
 Layout make_layout(long long n, long long nnz, int prec, bool has_csc, bool relabel = false, bool has_val = false,
                    bool topk = false) {
   Layout L{};
@@ -90,10 +99,10 @@ Layout make_layout(long long n, long long nnz, int prec, bool has_csc, bool rela
   if (has_csc) {
     // upper bounds of the plan built in rlgl_create: a run ends because it is
     // full (WL links or WCOLS columns) or because a long column follows
-    L.max_long = (size_t)(nnz / (WL + 1) + 1);
+    L.max_long = pull_long_bound(nnz);
     // runs: two consecutive runs hold more than WL links unless a column-count
     // or long-column break separates them; pieces: nnz / WL + one per long column
-    L.max_items = 3 * (size_t)(nnz / WL + 2) + (size_t)(n / WCOLS + 2) + 2 * L.max_long + 2;
+    L.max_items = pull_item_bound(n, nnz);
     L.items = take(sizeof(int4) * L.max_items);
     L.long_cols = take(4 * L.max_long);
     L.long_acc = take(8 * L.max_long);
@@ -534,17 +543,20 @@ rlgl_status relabel_graph(rlgl_ctx *c, const rlgl_graph *g, const Layout &L, cha
   return RLGL_OK;
 }
 
-// Host-side construction of the static pull plan from the CSC column pointers.
-rlgl_status build_plan(rlgl_ctx *c, const rlgl_graph *g, const Layout &L, char *ws) {
-  const int n = g->n;
-  std::vector<int> cp((size_t)n + 1);
-  HIP_TRY(hipMemcpyAsync(cp.data(), g->csc_colptr, sizeof(int) * ((size_t)n + 1), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  if (cp[0] != 0 || (long long)cp[n] != g->nnz) return fail(RLGL_EINVAL, "csc_colptr[0] must be 0 and csc_colptr[n] = nnz");
-  std::vector<int4> items;
-  std::vector<int> lng;
+// The static plan of the single-chain pull from the CSC column pointers
+// (host memory): RUN {k0, k1, p0, p1} (k0 >= 0) of whole columns with at most
+// WL links and WCOLS columns, PIECE {-1 - slot, k, p0, p1} of at most WL links
+// of a column with more than WL in-links (lng[slot] = k).  Every column is in
+// exactly one run or is a long column, and every link in exactly one item.
+bool pull_plan_host(const int *cp, int n, long long nnz, std::vector<int4> &items, std::vector<int> &lng,
+                    std::string &why) {
+  items.clear();
+  lng.clear();
+  if (n < 1 || cp[0] != 0 || (long long)cp[n] != nnz) {
+    why = "csc_colptr[0] must be 0 and csc_colptr[n] = nnz";
+    return false;
+  }
   int run0 = -1, run_e = 0;
-  // RUN {k0, k1, p0, p1} with k0 >= 0; PIECE {-1 - slot, k, p0, p1}
   auto flush = [&](int end) {
     if (run0 >= 0 && end > run0) items.push_back(make_int4(run0, end, cp[run0], cp[end]));
     run0 = -1;
@@ -552,7 +564,10 @@ rlgl_status build_plan(rlgl_ctx *c, const rlgl_graph *g, const Layout &L, char *
   };
   for (int k = 0; k < n; ++k) {
     const int dg = cp[k + 1] - cp[k];
-    if (dg < 0) return fail(RLGL_EINVAL, "csc_colptr is not non-decreasing at %d", k);
+    if (dg < 0) {
+      why = "csc_colptr is not non-decreasing at " + std::to_string(k);
+      return false;
+    }
     if (dg > WL) {
       // a long column: pieces of WL links; the last one summed writes the column
       flush(k);
@@ -572,19 +587,30 @@ rlgl_status build_plan(rlgl_ctx *c, const rlgl_graph *g, const Layout &L, char *
   // costs little while the other waves keep their gathers going, but stalls
   // the pass when every wave takes a piece at once; the last column finished
   // leaves a quarter of the pass to hide behind.
-  {
-    std::vector<int4> runs, pieces;
-    for (const int4 &it : items) (it.x < 0 ? pieces : runs).push_back(it);
-    const size_t span = (runs.size() * 3) / 4;
-    items.clear();
-    size_t r = 0;
-    for (size_t j = 0; j < pieces.size(); ++j) {
-      const size_t upto = span * (j + 1) / (pieces.size() + 1);
-      while (r < upto) items.push_back(runs[r++]);
-      items.push_back(pieces[j]);
-    }
-    while (r < runs.size()) items.push_back(runs[r++]);
+  std::vector<int4> runs, pieces;
+  for (const int4 &it : items) (it.x < 0 ? pieces : runs).push_back(it);
+  const size_t span = (runs.size() * 3) / 4;
+  items.clear();
+  size_t r = 0;
+  for (size_t q = 0; q < pieces.size(); ++q) {
+    const size_t upto = span * (q + 1) / (pieces.size() + 1);
+    while (r < upto) items.push_back(runs[r++]);
+    items.push_back(pieces[q]);
   }
+  while (r < runs.size()) items.push_back(runs[r++]);
+  return true;
+}
+
+// Host-side construction of the static pull plan from the CSC column pointers.
+rlgl_status build_plan(rlgl_ctx *c, const rlgl_graph *g, const Layout &L, char *ws) {
+  const int n = g->n;
+  std::vector<int> cp((size_t)n + 1);
+  HIP_TRY(hipMemcpyAsync(cp.data(), g->csc_colptr, sizeof(int) * ((size_t)n + 1), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  std::vector<int4> items;
+  std::vector<int> lng;
+  std::string why;
+  if (!pull_plan_host(cp.data(), n, g->nnz, items, lng, why)) return fail(RLGL_EINVAL, "%s", why.c_str());
   if (items.size() > L.max_items || lng.size() > L.max_long)
     return fail(RLGL_EINVAL, "pull plan exceeds its bound (internal)");
   if (!items.empty())
@@ -1495,7 +1521,60 @@ rlgl_status batch_outcomes(rlgl_batch *b) {
 
 }  // namespace
 
+namespace {
+// Copies a plan out to the caller's host arrays (4 ints per item).
+int64_t plan_out(const std::vector<int4> &items, const std::vector<int> &lng, int32_t *items_out, int64_t max_items,
+                 int32_t *long_out, int64_t max_long) {
+  if ((int64_t)items.size() > max_items || (int64_t)lng.size() > max_long) {
+    fail(RLGL_ENOMEM, "plan needs %zu items and %zu long columns", items.size(), lng.size());
+    return RLGL_ENOMEM;
+  }
+  if (items_out)
+    for (size_t q = 0; q < items.size(); ++q) {
+      items_out[4 * q] = items[q].x;
+      items_out[4 * q + 1] = items[q].y;
+      items_out[4 * q + 2] = items[q].z;
+      items_out[4 * q + 3] = items[q].w;
+    }
+  if (long_out)
+    for (size_t q = 0; q < lng.size(); ++q) long_out[q] = lng[q];
+  return (int64_t)items.size();
+}
+}  // namespace
+
 extern "C" {
+
+int64_t rlgl_pull_plan(const int32_t *host_colptr, int32_t n, int64_t nnz, int32_t *items, int64_t max_items,
+                       int32_t *long_cols, int64_t max_long, int64_t *n_long, int64_t *item_bound) {
+  if (!host_colptr || n < 1 || nnz < 0 || nnz >= (1ll << 31) || max_items < 0 || max_long < 0 ||
+      (max_items > 0 && !items) || (max_long > 0 && !long_cols))
+    return fail(RLGL_EINVAL, "bad arguments to rlgl_pull_plan");
+  std::vector<int4> it;
+  std::vector<int> lng;
+  std::string why;
+  if (!pull_plan_host(host_colptr, n, nnz, it, lng, why)) return fail(RLGL_EINVAL, "%s", why.c_str());
+  if (n_long) *n_long = (int64_t)lng.size();
+  if (item_bound) *item_bound = (int64_t)pull_item_bound(n, nnz);
+  return plan_out(it, lng, items, max_items, long_cols, max_long);
+}
+
+int64_t rlgl_batch_chain_plan(const int32_t *host_colptr, int32_t n, int64_t nnz, int32_t *items, int64_t max_items,
+                              int32_t *long_cols, int64_t max_long, int64_t *n_long, int64_t *n_pieces,
+                              int64_t *item_bound) {
+  if (!host_colptr || n < 1 || nnz < 0 || nnz >= (1ll << 31) || max_items < 0 || max_long < 0 ||
+      (max_items > 0 && !items) || (max_long > 0 && !long_cols))
+    return fail(RLGL_EINVAL, "bad arguments to rlgl_batch_chain_plan");
+  std::vector<int4> it;
+  std::vector<int> lng;
+  std::string why;
+  int np = 0, nr = 0;
+  if (!chain_plan(host_colptr, n, (int)nnz, it, lng, np, nr, why)) return fail(RLGL_EINVAL, "%s", why.c_str());
+  if (n_long) *n_long = (int64_t)lng.size();
+  if (n_pieces) *n_pieces = np;
+  if (item_bound) *item_bound = (int64_t)batch_item_bound(n, nnz);
+  return plan_out(it, lng, items, max_items, long_cols, max_long);
+}
+
 
 void rlgl_batch_default_options(rlgl_batch_options *o) {
   if (!o) return;
