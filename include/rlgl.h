@@ -366,7 +366,9 @@ typedef struct {
   const void *csc_val;        /* device or NULL, as csr_val */
   const double *tol_l1;       /* host [n_chains] or NULL: chain k stops at ||C_t||_1 / |H_t 1| < tol_l1[k] (1 - c_k),
                                  which bounds the L1 error of pi_hat by tol_l1[k] (Lemma 1 with
-                                 ||sum_k (P^k - 1 pi)||_1 <= 1 / (1 - c)); NULL: options.eps for every chain */
+                                 ||sum_k (P^k - 1 pi)||_1 <= 1 / (1 - c)); NULL: options.eps for every chain.
+                                 With tol_l1 given, every damping must be below 1 (at c = 1 there is no such
+                                 bound and the target would be 0): RLGL_EINVAL otherwise */
 } rlgl_batch_graphs;
 
 typedef struct {
@@ -458,7 +460,8 @@ typedef struct {
   const int32_t *csr_rowptr;  /* host [n+1], 0 .. nnz, non-decreasing: the out-degrees */
   const int32_t *csc_colptr;  /* host [n+1], 0 .. nnz, non-decreasing */
   const int32_t *csc_row;     /* host [nnz], local source ids (NULL allowed when nnz = 0) */
-  double damping;             /* c in (0, 1] */
+  double damping;             /* c in (0, 1): a request stops on an L1 certificate, which c = 1 does not
+                                 have (RLGL_EINVAL) */
   double tol_l1;              /* stop at ||C_t||_1 / |H_t 1| < tol_l1 (1 - c), which bounds the L1 error of
                                  pi_hat by tol_l1 (Lemma 1); >= 0 */
 } rlgl_request;

@@ -1618,6 +1618,8 @@ rlgl_status rlgl_batch_create(const rlgl_batch_graphs *g, const rlgl_batch_optio
   for (int k = 0; k < nc; ++k) {
     if (!(g->damping[k] > 0.0 && g->damping[k] <= 1.0)) return fail(RLGL_EINVAL, "damping of chain %d out of (0,1]", k);
     if (g->tol_l1 && !(g->tol_l1[k] >= 0.0)) return fail(RLGL_EINVAL, "tol_l1 of chain %d is negative", k);
+    if (g->tol_l1 && g->damping[k] >= 1.0)
+      return fail(RLGL_EINVAL, "chain %d: damping 1 has no L1 certificate for tol_l1 (give options.eps instead)", k);
   }
 
   rlgl_batch *b = new (std::nothrow) rlgl_batch();
@@ -1982,7 +1984,8 @@ rlgl_status rlgl_pool_admit(rlgl_pool *p, const rlgl_request *q, int32_t *slot) 
   const long long n = q->n, m = q->nnz;
   if (n < 1 || m < 0 || m >= (1ll << 31)) return fail(RLGL_EINVAL, "request sizes out of range");
   if (!q->csr_rowptr || !q->csc_colptr || (m > 0 && !q->csc_row)) return fail(RLGL_EINVAL, "request arrays are NULL");
-  if (!(q->damping > 0.0 && q->damping <= 1.0)) return fail(RLGL_EINVAL, "damping out of (0,1]");
+  if (!(q->damping > 0.0 && q->damping < 1.0))
+    return fail(RLGL_EINVAL, "damping must be in (0, 1): a request stops on an L1 certificate, which c = 1 lacks");
   if (!(q->tol_l1 >= 0.0)) return fail(RLGL_EINVAL, "tol_l1 must be >= 0");
   const int32_t *rp = q->csr_rowptr;
   if (rp[0] != 0 || rp[n] != m) return fail(RLGL_EINVAL, "csr_rowptr must run from 0 to nnz");

@@ -171,3 +171,21 @@ def test_batch_route_shapes_agree_and_tol_l1_certifies():
             assert l1(pis[k], reference(g)) <= tols[k], (name, k)
         ta, tb = out["per_item"][0][k]["t"], out["strided"][0][k]["t"]
         assert abs(ta - tb) <= 2, (k, ta, tb)
+
+
+def test_batch_rejects_l1_target_without_damping():
+    """A per-chain L1 target certifies through 1/(1 - c): a chain with c = 1
+    has no such bound (its residual target would be 0), so a batch that
+    gives both is rejected before any work; without tol_l1 it runs on the
+    residual target of the options."""
+    g = workloads.largest_scc(workloads.chung_lu(3000, 2.3, 10.0, 0.0, 1.0, seed=3), c=1.0)
+    say("case batch_damping_1", g.n, g.nnz)
+    db = rl.DeviceBatch([g], precision=rl.FP32C_KAHANH, tol_l1=[1e-6])
+    with pytest.raises(rl.RlglError) as e:
+        rl.BatchSolver(db, engine=rl.BATCH_LOCKSTEP)
+    assert e.value.status == rl.RLGL_EINVAL
+    db = rl.DeviceBatch([g], precision=rl.FP32C_KAHANH)
+    bs = rl.BatchSolver(db, engine=rl.BATCH_LOCKSTEP, eps=1e-8, max_steps=20000)
+    st, res, _ = bs.solve()
+    assert st == rl.RLGL_OK and res[0]["status"] == rl.RLGL_OK
+    bs.close()

@@ -144,6 +144,12 @@ def test_pool_rejects_bad_requests():
     req.damping = 1.5
     with pytest.raises(rl.RlglError):
         rl.rlgl_pool_admit(pool.handle, req)
+    # c = 1: the L1 target tol (1 - c) would be 0, and no certificate exists
+    req = h.request()
+    req.damping = 1.0
+    with pytest.raises(rl.RlglError) as e:
+        rl.rlgl_pool_admit(pool.handle, req)
+    assert e.value.status == rl.RLGL_EINVAL
     req = h.request()
     req.nnz = g.nnz + 1  # disagrees with rowptr[n]
     with pytest.raises(rl.RlglError):
