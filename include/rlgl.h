@@ -383,6 +383,11 @@ typedef struct {
                                  workgroup per item */
   int32_t engine;             /* rlgl_batch_engine: RLGL_BATCH_LOCKSTEP (anything else is RLGL_EINVAL) */
   int32_t check_period;       /* iterations between host checks of the finished count (>= 1) */
+  int32_t relabel;            /* non-zero: every chain is solved in a relabelled copy of its graph (states
+                                 renumbered by decreasing out-degree, ties by id) kept in the workspace, so
+                                 the sources that send on most links share cache lines; pi_hat comes back in
+                                 the caller's numbering.  Costs 4 (2 n + 2 + nnz) + 4 n bytes of workspace
+                                 per chain */
 } rlgl_batch_options;
 
 /* Outcome of one chain. */
@@ -398,13 +403,18 @@ typedef struct {
 
 /* Defaults: THRESHOLD, r = 1, FP32C_KAHANH, eps = 1e-7, max_steps = 100000,
  * refresh = 1, wg_size = 256, wg_per_cu = 0, engine = LOCKSTEP,
- * check_period = 8. */
+ * check_period = 8, relabel = 1. */
 void rlgl_batch_default_options(rlgl_batch_options *opt);
 
 size_t rlgl_batch_workspace_bytes(const rlgl_batch_graphs *g, const rlgl_batch_options *opt);
 
 /* Checks the arguments, copies the column pointers to the host once to build
- * each chain's static plan, and orders the chains by decreasing link count. */
+ * each chain's static plan, and orders the chains by decreasing link count.
+ * With opt->relabel it also copies the row pointers, renumbers every chain
+ * and writes the relabelled row pointers and CSC into the workspace (the
+ * caller's arrays are only read); RLGL_EINVAL when a chain's row or column
+ * pointers decrease or its column pointers do not run from 0 to its link
+ * count. */
 rlgl_status rlgl_batch_create(const rlgl_batch_graphs *g, const rlgl_batch_options *opt, void *dev_workspace,
                               size_t ws_bytes, void *stream, rlgl_batch **out);
 

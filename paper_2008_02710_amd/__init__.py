@@ -70,7 +70,7 @@ class rlgl_batch_options(ctypes.Structure):
     _fields_ = [("sched", ctypes.c_int32), ("r", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("eps", ctypes.c_double), ("max_steps", ctypes.c_int64), ("refresh", ctypes.c_int32),
                 ("wg_size", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32), ("engine", ctypes.c_int32),
-                ("check_period", ctypes.c_int32)]
+                ("check_period", ctypes.c_int32), ("relabel", ctypes.c_int32)]
 
 
 class rlgl_chain_result(ctypes.Structure):

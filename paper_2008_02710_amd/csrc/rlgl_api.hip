@@ -1349,6 +1349,7 @@ struct ChainOut {
 struct BatchLayout {
   size_t cash0, cash1, src, hist, hist_lo, ls_items, long_cols, long_acc, order, queue, engine, total;
   size_t max_items, max_long;
+  size_t nrowptr, ncolptr, nrow, perm;  // relabelled layout (0 without)
 };
 
 bool batch_layout(const rlgl_batch_graphs *g, const rlgl_batch_options *o, BatchLayout &L, std::string &why) {
@@ -1383,6 +1384,14 @@ bool batch_layout(const rlgl_batch_graphs *g, const rlgl_batch_options *o, Batch
   L.order = take(4 * (size_t)g->n_chains);
   L.queue = take(256);
   L.engine = take(ls_device_bytes(g->n_chains));
+  L.nrowptr = L.ncolptr = L.nrow = L.perm = 0;
+  if (o->relabel) {
+    const size_t rp_total = (size_t)tn + (size_t)g->n_chains;
+    L.nrowptr = take(4 * rp_total);
+    L.ncolptr = take(4 * rp_total);
+    L.nrow = take(4 * (size_t)g->edge_off[g->n_chains]);
+    L.perm = take(4 * (size_t)tn);
+  }
   L.total = off + 256;
   return true;
 }
@@ -1396,6 +1405,7 @@ struct rlgl_batch {
   double r;
   long long max_steps;
   int ls_nt, ls_per_cu, check_period;
+  int relabel;
   double eps;
   double clock_khz;
   int n_chains;
@@ -1423,6 +1433,91 @@ rlgl_status batch_configure(rlgl_batch *b, const rlgl_batch_options &o) {
   b->E.nt = o.wg_size;
   b->E.route_grid = b->cus * o.wg_per_cu;
   b->check_period = o.check_period;
+  return RLGL_OK;
+}
+
+// Relabelled layout of every chain of a batch (a1): each chain's states
+// renumbered by decreasing out-degree, ties by id (a stable counting sort on
+// the host, from the row pointers), its row pointers rebuilt and its CSC
+// rewritten by k_relabel_side into the workspace.  cp (host, the caller's
+// column pointers of every chain) receives the new ones; the chain's new ->
+// caller map stays in the workspace for the final pass.  The map the other
+// way is only needed here and is kept in the send-value buffer, which no
+// solve has used yet.
+rlgl_status batch_relabel(rlgl_batch *b, const rlgl_batch_graphs *g, const BatchLayout &L, char *w,
+                          std::vector<int> &cp, std::string &why) {
+  const int nc = g->n_chains;
+  const long long rp_total = b->total_n + nc;
+  std::vector<int> rp((size_t)rp_total);
+  HIP_TRY(hipMemcpyAsync(rp.data(), g->csr_rowptr, sizeof(int) * (size_t)rp_total, hipMemcpyDeviceToHost,
+                         b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  std::vector<int> new2old((size_t)b->total_n), old2new((size_t)b->total_n), nrp((size_t)rp_total),
+      ncp((size_t)rp_total);
+  std::vector<long long> start;
+  for (int k = 0; k < nc; ++k) {
+    const long long no = g->node_off[k], ro = no + k;
+    const int n = (int)(g->node_off[k + 1] - no);
+    const int m = (int)(g->edge_off[k + 1] - g->edge_off[k]);
+    const int *r = rp.data() + ro, *c = cp.data() + ro;
+    if (c[0] != 0 || c[n] != m) {
+      why = "chain " + std::to_string(k) + ": csc_colptr must run from 0 to the link count";
+      return RLGL_EINVAL;
+    }
+    int maxdeg = 0;
+    for (int i = 0; i < n; ++i) {
+      const int dg = r[i + 1] - r[i];
+      if (dg < 0 || c[i + 1] < c[i]) {
+        why = "chain " + std::to_string(k) + ": csr_rowptr or csc_colptr decreases";
+        return RLGL_EINVAL;
+      }
+      maxdeg = std::max(maxdeg, dg);
+    }
+    int *n2o = new2old.data() + no, *o2n = old2new.data() + no;
+    if ((long long)maxdeg <= 4ll * n + 1024) {
+      start.assign((size_t)maxdeg + 2, 0);
+      for (int i = 0; i < n; ++i) ++start[(size_t)(maxdeg - (r[i + 1] - r[i]))];
+      long long acc = 0;
+      for (auto &x : start) {
+        const long long cnt = x;
+        x = acc;
+        acc += cnt;
+      }
+      for (int i = 0; i < n; ++i) n2o[start[(size_t)(maxdeg - (r[i + 1] - r[i]))]++] = i;
+    } else {
+      for (int i = 0; i < n; ++i) n2o[i] = i;
+      std::stable_sort(n2o, n2o + n, [&](int a, int c2) { return r[a + 1] - r[a] > r[c2 + 1] - r[c2]; });
+    }
+    for (int i = 0; i < n; ++i) o2n[n2o[i]] = i;
+    int *nr = nrp.data() + ro, *nc2 = ncp.data() + ro;
+    nr[0] = 0;
+    nc2[0] = 0;
+    for (int i = 0; i < n; ++i) {
+      nr[i + 1] = nr[i] + (r[n2o[i] + 1] - r[n2o[i]]);
+      nc2[i + 1] = nc2[i] + (c[n2o[i] + 1] - c[n2o[i]]);
+    }
+  }
+  int *d_perm = (int *)(w + L.perm), *d_o2n = (int *)(w + L.src), *d_nrp = (int *)(w + L.nrowptr),
+      *d_ncp = (int *)(w + L.ncolptr), *d_nrow = (int *)(w + L.nrow);
+  HIP_TRY(hipMemcpyAsync(d_perm, new2old.data(), sizeof(int) * (size_t)b->total_n, hipMemcpyHostToDevice,
+                         b->stream));
+  HIP_TRY(hipMemcpyAsync(d_o2n, old2new.data(), sizeof(int) * (size_t)b->total_n, hipMemcpyHostToDevice,
+                         b->stream));
+  HIP_TRY(hipMemcpyAsync(d_nrp, nrp.data(), sizeof(int) * (size_t)rp_total, hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipMemcpyAsync(d_ncp, ncp.data(), sizeof(int) * (size_t)rp_total, hipMemcpyHostToDevice, b->stream));
+  for (int k = 0; k < nc; ++k) {
+    const long long no = g->node_off[k], ro = no + k, eo = g->edge_off[k];
+    const int n = (int)(g->node_off[k + 1] - no);
+    const long long m = g->edge_off[k + 1] - eo;
+    if (m == 0) continue;
+    const int grid = (int)std::max<long long>(1, std::min<long long>((m + BLOCK - 1) / BLOCK, 16384));
+    k_relabel_side<float><<<grid, BLOCK, 0, b->stream>>>(n, g->csc_colptr + ro, g->csc_row + eo, (const float *)nullptr,
+                                                         d_perm + no, d_o2n + no, d_ncp + ro, d_nrow + eo,
+                                                         (float *)nullptr);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  cp.swap(ncp);
   return RLGL_OK;
 }
 
@@ -1589,6 +1684,7 @@ void rlgl_batch_default_options(rlgl_batch_options *o) {
   o->wg_per_cu = 0;
   o->engine = RLGL_BATCH_LOCKSTEP;
   o->check_period = 8;
+  o->relabel = 1;
 }
 
 size_t rlgl_batch_workspace_bytes(const rlgl_batch_graphs *g, const rlgl_batch_options *o) {
@@ -1664,6 +1760,11 @@ rlgl_status rlgl_batch_create(const rlgl_batch_graphs *g, const rlgl_batch_optio
           hipSuccess ||
       hipStreamSynchronize(b->stream) != hipSuccess)
     return bail(fail(RLGL_EHIP, "reading the column pointers failed"));
+  b->relabel = o->relabel ? 1 : 0;
+  if (b->relabel) {
+    st = batch_relabel(b, g, L, w, cp, why);
+    if (st != RLGL_OK) return bail(st == RLGL_EINVAL ? fail(st, "%s", why.c_str()) : st);
+  }
   std::vector<int4> ls_items;
   std::vector<int> long_cols;
   std::vector<long long> size_of((size_t)nc);
@@ -1678,9 +1779,17 @@ rlgl_status rlgl_batch_create(const rlgl_batch_graphs *g, const rlgl_batch_optio
     if (!chain_plan(cp.data() + rp, n, m, ls_items, long_cols, np, nr2, why))
       return bail(fail(RLGL_EINVAL, "chain %d: %s", k, why.c_str()));
     LsChain &lc = b->E.host[k];
-    lc.rowptr = g->csr_rowptr + rp;
-    lc.colptr = g->csc_colptr + rp;
-    lc.crow = g->csc_row + g->edge_off[k];
+    if (b->relabel) {
+      lc.rowptr = (const int *)(w + L.nrowptr) + rp;
+      lc.colptr = (const int *)(w + L.ncolptr) + rp;
+      lc.crow = (const int *)(w + L.nrow) + g->edge_off[k];
+      lc.perm = (const int *)(w + L.perm) + no;
+    } else {
+      lc.rowptr = g->csr_rowptr + rp;
+      lc.colptr = g->csc_colptr + rp;
+      lc.crow = g->csc_row + g->edge_off[k];
+      lc.perm = nullptr;
+    }
     lc.items = (const int4 *)(w + L.ls_items) + li;
     lc.long_cols = (const int *)(w + L.long_cols) + lo;
     lc.long_acc = (double *)(w + L.long_acc) + lo;
@@ -1757,6 +1866,7 @@ rlgl_status rlgl_batch_autotune(rlgl_batch *b, double *dev_pi, rlgl_batch_option
   cur.max_steps = b->max_steps;
   cur.refresh = b->refresh;
   cur.check_period = b->check_period;
+  cur.relabel = b->relabel;
   cur.engine = RLGL_BATCH_LOCKSTEP;
   cur.wg_size = b->ls_nt;
   cur.wg_per_cu = b->ls_per_cu;

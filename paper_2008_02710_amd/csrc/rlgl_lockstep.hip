@@ -26,7 +26,10 @@
 // that have stopped cost one record load per workgroup until the host drops
 // them from the active list.  The link weights are implicit, 1/outdeg(j) in
 // FP64, so the refresh that confirms a stop is exact to FP64 rounding (its
-// scaled history H_j / outdeg(j) is gathered in FP64).
+// scaled history H_j / outdeg(j) is gathered in FP64).  A batch may keep
+// each chain in a relabelled layout (states renumbered by decreasing
+// out-degree): every pass works in that numbering and only the final pass
+// writes pi_hat back in the caller's.
 #include "rlgl_device.h"
 
 namespace rlgl {
@@ -50,6 +53,7 @@ struct LsChain {
   void *hist;
   float *hist_lo;
   double *pi;
+  const int *perm;  // relabelled layout: [n] caller id of each state, else null
   long long nnz, max_steps;
   double c, eps;
   int n, n_piece, n_run, n_long;
@@ -128,7 +132,7 @@ __global__ __launch_bounds__(BLOCK) void k_ls_select(LsArgs a) {
     if (i >= n) continue;
     const int dg = rowptr[i + 1] - rowptr[i];
     if (mode == LS_FINISH) {
-      ch.pi[i] = ls_hist<HK>(ch, i) / hsum;  // eq. (2)
+      ch.pi[ch.perm ? ch.perm[i] : i] = ls_hist<HK>(ch, i) / hsum;  // eq. (2), in the caller's numbering
     } else if (mode == LS_REFRESH) {
       // the FP64 scaled history H_j / outdeg(j) for the route, parked in the
       // output vector, which is not written before the final pass

@@ -46,12 +46,13 @@ def test_struct_sizes_match_header(tmp_path):
     exe = str(tmp_path / "sizes_probe")
     open(src, "w").write(
         '#include <stdio.h>\n#include <stddef.h>\n#include "rlgl.h"\n'
-        'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(rlgl_graph),'
+        'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(rlgl_graph),'
         ' sizeof(rlgl_options), sizeof(rlgl_step_info), sizeof(rlgl_kernel_stat),'
         ' offsetof(rlgl_options, record_green), offsetof(rlgl_step_info, last_route),'
         ' sizeof(rlgl_batch_graphs), sizeof(rlgl_batch_options), offsetof(rlgl_batch_options, check_period),'
         ' sizeof(rlgl_chain_result), sizeof(rlgl_pool_options), sizeof(rlgl_request),'
-        ' offsetof(rlgl_request, tol_l1), offsetof(rlgl_options, relabel), offsetof(rlgl_options, seed));'
+        ' offsetof(rlgl_request, tol_l1), offsetof(rlgl_options, relabel), offsetof(rlgl_options, seed),'
+        ' offsetof(rlgl_batch_options, relabel));'
         'return 0;}\n')
     import subprocess
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", exe, src])
@@ -61,7 +62,8 @@ def test_struct_sizes_match_header(tmp_path):
            rl.rlgl_step_info.last_route.offset, ctypes.sizeof(rl.rlgl_batch_graphs),
            ctypes.sizeof(rl.rlgl_batch_options), rl.rlgl_batch_options.check_period.offset,
            ctypes.sizeof(rl.rlgl_chain_result), ctypes.sizeof(rl.rlgl_pool_options), ctypes.sizeof(rl.rlgl_request),
-           rl.rlgl_request.tol_l1.offset, rl.rlgl_options.relabel.offset, rl.rlgl_options.seed.offset]
+           rl.rlgl_request.tol_l1.offset, rl.rlgl_options.relabel.offset, rl.rlgl_options.seed.offset,
+           rl.rlgl_batch_options.relabel.offset]
     assert [int(x) for x in out] == got
 
 

@@ -189,3 +189,27 @@ def test_batch_rejects_l1_target_without_damping():
     st, res, _ = bs.solve()
     assert st == rl.RLGL_OK and res[0]["status"] == rl.RLGL_OK
     bs.close()
+
+
+@pytest.mark.parametrize("sched", ["threshold", "all"])
+def test_batch_relabelled_layout_matches_caller_layout(sched):
+    """The relabelled layout (states renumbered by decreasing out-degree
+    inside the library) gives each chain's pi_hat in the caller's numbering:
+    in FP64 the column sums add the same links in the same order, so the two
+    layouts agree to rounding in the statistics, and both match the oracle."""
+    gs = chains()
+    say("case batch_relabel", sched)
+    eps = 0.05 * 1e-10
+    s = {"threshold": rl.SCHED_THRESHOLD, "all": rl.SCHED_ALL}[sched]
+    db = rl.DeviceBatch(gs, precision=rl.FP64)
+    out = {}
+    for relabel in (0, 1):
+        bs = rl.BatchSolver(db, sched=s, eps=eps, max_steps=20000, relabel=relabel)
+        st, res, _ = bs.solve()
+        assert st == rl.RLGL_OK
+        out[relabel] = ([to_np(bs.chain_pi(k)).copy() for k in range(len(gs))], [r["t"] for r in res])
+        bs.close()
+    for k, g in enumerate(gs):
+        assert l1(out[0][0][k], out[1][0][k]) <= 1e-12, k
+        assert abs(out[0][1][k] - out[1][1][k]) <= 1, k
+        assert l1(out[1][0][k], reference(g)) <= 1e-10, k
