@@ -420,7 +420,52 @@ def trace_summary(folder: str, workload: str, commands: list, label: str = None)
         out.append(f"| `{r['Name'][:72]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
                    f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
                    f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    out += lockstep_iterations(folder)
     return "\n".join(out) + "\n"
+
+
+def lockstep_iterations(folder: str) -> list:
+    """Per batched (lockstep) solve in the trace: its iterations (one select,
+    route and control launch each), the mean kernel times of the iterations
+    in which every chain is still in the launch grids, and the time of the
+    later ones (from the per-dispatch timestamps)."""
+    try:
+        rows = _csv_rows(folder, "kernel_trace.csv")
+    except (OSError, StopIteration, IndexError):
+        return []
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    starts = [i for i, r in enumerate(rows) if "k_batch_start" in r["Kernel_Name"]]
+    if not starts:
+        return []
+    out = ["", "Lockstep solves in the trace (per-dispatch timestamps; a full iteration has every chain in the "
+           "launch grids):", "",
+           "| solve | ms | iterations | full iterations | select / route / control per full iteration, us | "
+           "later iterations: kernel ms | later iterations: idle ms |", "|---|---|---|---|---|---|---|"]
+    for q, a in enumerate(starts):
+        b = starts[q + 1] if q + 1 < len(starts) else len(rows)
+        its = []
+        for r in rows[a:b]:
+            name = r["Kernel_Name"]
+            dur = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+            if "k_ls_select" in name:
+                its.append({"start": int(r["Start_Timestamp"]), "grid": int(r["Grid_Size_X"]), "k": {}, "busy": 0})
+            if its and "k_ls_" in name:
+                kind = "select" if "select" in name else "route" if "route" in name else "control"
+                its[-1]["k"][kind] = its[-1]["k"].get(kind, 0) + dur
+                its[-1]["busy"] += dur
+        if not its:
+            continue
+        # the solve ends at the last lockstep launch
+        end = max(int(r["End_Timestamp"]) for r in rows[a:b] if "k_ls_" in r["Kernel_Name"])
+        full = [it for it in its if it["grid"] == its[0]["grid"]]
+        later = its[len(full):]
+        mean = lambda kind: sum(it["k"].get(kind, 0) for it in full) / len(full) / 1e3
+        span_later = (end - later[0]["start"]) / 1e6 if later else 0.0
+        busy_later = sum(it["busy"] for it in later) / 1e6
+        out.append(f"| {q} | {(end - int(rows[a]['Start_Timestamp'])) / 1e6:.2f} | {len(its)} | {len(full)} | "
+                   f"{mean('select'):.1f} / {mean('route'):.1f} / {mean('control'):.1f} | {busy_later:.2f} | "
+                   f"{span_later - busy_later:.2f} |")
+    return out
 
 
 SCHED_IDS = {}
