@@ -748,11 +748,13 @@ struct ColView {
 };
 
 // LDS of the column pass over items of at most IC links and IK columns.
+// Column starts as bits and column pointers as 16-bit offsets into the item.
 template <int NT, int IC = CH, int IK = RUN_MAX_COLS>
 struct ColLds {
+  static_assert(IC <= 65535, "16-bit item offsets");
   double con[IC];              // contributions, then inclusive segmented sums
-  unsigned char head[IC];
-  int cp[IK + 1];              // column pointers of the run, relative to p0
+  unsigned int head[IC / 32];  // bit e: a column of the run starts at element e
+  unsigned short cp[IK + 1];   // column pointers of the run, relative to p0, clamped into [0, ne]
   Seg wave[NT / 64];
   double red[4 * (NT / 64)];
 };
@@ -768,6 +770,7 @@ __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved m
   constexpr int U = IC / NT;                 // links per thread
   constexpr int KC = IK / NT;                // columns per thread
   static_assert(U >= 1 && KC >= 1 && U * NT == IC && KC * NT == IK, "item shape");
+  static_assert(32 % U == 0 && IC % 32 == 0, "a thread's column-start bits lie in one word");
   const int *__restrict__ colptr = g.colptr;
   const int *__restrict__ crow = g.crow;
   const T *__restrict__ cval = (const T *)g.cval;
@@ -811,31 +814,32 @@ __device__ __forceinline__ void column_item(const ColView &g, int4 item, Moved m
       const int q = m * NT + tid;
       kv[m] = (q < ncol) ? kept(k0 + q) : 0.0;
     }
-    for (int q = tid; q <= ncol; q += NT) L.cp[q] = colptr[k0 + q] - p0;
+    for (int q = tid; q <= ncol; q += NT) L.cp[q] = (unsigned short)min(max(colptr[k0 + q] - p0, 0), ne);
+    for (int q = tid; q < IC / 32; q += NT) L.head[q] = 0u;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = u * NT + tid;
       if (e < ne) {
         const double w = unit ? 1.0 : (cval ? ww[u] : inv_outdeg(g.rowptr, g.n, jj[u]));
         L.con[e] = moved(jj[u]) * w;
-        L.head[e] = 0;
       }
     }
     __syncthreads();
     for (int q = tid; q < ncol; q += NT) {
       const int a = L.cp[q];
-      if (a < L.cp[q + 1]) L.head[a] = 1;
+      if (a < L.cp[q + 1]) atomicOr(&L.head[a >> 5], 1u << (a & 31));  // a < ne <= IC
     }
     __syncthreads();
     // segmented inclusive scan: thread t owns elements [t*U, t*U+U)
     double loc[U];
     int first_head = U;
     Seg run{0.0, 0};
+    const unsigned int hbits = L.head[(tid * U) >> 5] >> ((tid * U) & 31);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = tid * U + u;
       const double x = (e < ne) ? L.con[e] : 0.0;
-      const int h = (e < ne) ? L.head[e] : 0;
+      const int h = (e < ne) ? (int)((hbits >> u) & 1u) : 0;
       if (h && first_head == U) first_head = u;
       run = h ? Seg{x, 1} : Seg{run.v + x, run.f};
       loc[u] = run.v;

@@ -10,7 +10,8 @@
 //   k_ls_route   - plan items (the pieces of the long columns of every
 //                  chain first, then runs of at most CH links), one per
 //                  workgroup or strided over a machine-sized grid: the CSC gather of eq. (6), C_{t+1}[k] = kept(k) +
-//                  c sum_j src[j] + T/N, and the statistics of C_{t+1}; a
+//                  c sum_j src[j] + T/N (what the LS_HUB lowest-numbered
+//                  states send is read from LDS, staged per item), and the statistics of C_{t+1}; a
 //                  piece of a column with more than CH in-links adds its
 //                  partial sum into the chain's FP64 long-column accumulator;
 //   k_ls_control - one wave per active chain: finishes the long columns,
@@ -37,6 +38,7 @@ namespace rlgl {
 constexpr int LS_NS = 16;       // stat stripes per chain
 constexpr int LS_TILE = 1024;   // nodes per select workgroup (BLOCK threads x VPT)
 constexpr int LS_PIECE = 4096;  // links per piece of a long column
+constexpr int LS_HUB = 1024;    // FP32 send values staged per route item
 static_assert(LS_TILE == BLOCK * VPT, "select tile");
 
 enum : int { LS_IDLE = 0, LS_INIT = 1, LS_STEP = 2, LS_REFRESH = 3, LS_FINISH = 4, LS_DONE = 5 };
@@ -194,9 +196,9 @@ __global__ __launch_bounds__(BLOCK) void k_ls_select(LsArgs a) {
 // (C_1 = 0 - M_0 + M_0 P), a green-light step, or the refresh C_t = H_t P -
 // H_t (eq. (7) with C_0 = 0) from the FP64 scaled history.  Adds the
 // statistics of the written values to l1..mx.
-template <class T, int HK, int NT>
+template <class T, int HK, int NT, bool FRESH>
 __device__ __forceinline__ void ls_item(const LsArgs &a, int k, int mode, int local, double off, ColLds<NT> &L,
-                                        double &l1, double &cs, double &sr, double &mx) {
+                                        T *hub, double &l1, double &cs, double &sr, double &mx) {
   const LsChain ch = a.chains[k];
   const LsCtl *ctl = &a.ctl[k];
   const int n = ch.n;
@@ -212,6 +214,12 @@ __device__ __forceinline__ void ls_item(const LsArgs &a, int k, int mode, int lo
   const double m0 = (double)(T)(1.0 / (double)n);
   const double theta = ctl->theta, maxabs = ctl->maxabs;
   const int sched = a.sched;
+  // What the LS_HUB lowest-numbered states send, staged in LDS for the item:
+  // in the relabelled layout they are the chain's largest out-degrees
+  const int hn = (!refresh && sizeof(T) == 4) ? min(LS_HUB, n) : 0;
+  if (!FRESH) __syncthreads();  // the previous item's reads of the table are done
+  for (int q = threadIdx.x; q < hn; q += NT) hub[q] = src[q];
+  __syncthreads();
   column_item<T, NT>(
       g, item,
       [&](int j) -> double {
@@ -220,7 +228,7 @@ __device__ __forceinline__ void ls_item(const LsArgs &a, int k, int mode, int lo
         const bool ok = (unsigned)j < (unsigned)n;
         if (!ok) *bad = 1;
         const unsigned int jc = ok ? (unsigned int)j : 0u;
-        const double v = refresh ? hs[jc] : (double)src[jc];
+        const double v = refresh ? hs[jc] : (double)(jc < (unsigned int)hn ? hub[jc] : src[jc]);
         return ok ? v : 0.0;
       },
       [&](int kk) -> double {
@@ -267,6 +275,7 @@ template <class T, int HK, int NT>
 __global__ __launch_bounds__(NT) void k_ls_route(LsArgs a) {
   __shared__ ColLds<NT> L;
   __shared__ double sh_T;
+  __shared__ T s_hub[sizeof(T) == 4 ? LS_HUB : 1];
   const bool piece = (int)blockIdx.x < a.w_total;
   const int b = piece ? (int)blockIdx.x : (int)blockIdx.x - a.w_total;
   const int ai = ls_find(piece ? a.wpre : a.rpre, a.n_act, b);
@@ -276,7 +285,7 @@ __global__ __launch_bounds__(NT) void k_ls_route(LsArgs a) {
   const int local = piece ? b - a.wpre[ai] : a.chains[k].n_piece + (b - a.rpre[ai]);
   const double off = ls_offset<NT>(a, k, &sh_T);
   double l1 = 0.0, cs = 0.0, sr = 0.0, mx = 0.0;
-  ls_item<T, HK, NT>(a, k, mode, local, off, L, l1, cs, sr, mx);
+  ls_item<T, HK, NT, true>(a, k, mode, local, off, L, s_hub, l1, cs, sr, mx);
   ls_fold<NT>(a, k, local % LS_NS, l1, cs, sr, mx, L);
 }
 
@@ -286,6 +295,7 @@ template <class T, int HK, int NT>
 __global__ __launch_bounds__(NT) void k_ls_route_strided(LsArgs a) {
   __shared__ ColLds<NT> L;
   __shared__ double sh_T;
+  __shared__ T s_hub[sizeof(T) == 4 ? LS_HUB : 1];
   const int total = a.w_total + a.r_total;
   const int stripe = blockIdx.x % LS_NS;
   int kc = -1, mode = LS_IDLE;  // chain of the previous item, its mode
@@ -307,7 +317,7 @@ __global__ __launch_bounds__(NT) void k_ls_route_strided(LsArgs a) {
     }
     if (!ls_routes(mode)) continue;
     const int local = piece ? b - a.wpre[ai] : a.chains[k].n_piece + (b - a.rpre[ai]);
-    ls_item<T, HK, NT>(a, k, mode, local, off, L, l1, cs, sr, mx);
+    ls_item<T, HK, NT, false>(a, k, mode, local, off, L, s_hub, l1, cs, sr, mx);
   }
   if (kc >= 0) ls_fold<NT>(a, kc, stripe, l1, cs, sr, mx, L);
 }
