@@ -298,10 +298,9 @@ hipError_t enqueue_step(rlgl_ctx *c, long long s, double eps, long long s_limit,
       }
       if (!dbl) {
         // FP32 keys: the collecting pass counts the middle digit, one more
-        // pass the low digit, and one workgroup fixes tau and the id bound
+        // pass the low digit; the select pass fixes tau and the id bound
         k_topk_collect<float><<<d.tk_grid, BLOCK, 0, c->stream>>>(d, s);
         k_topk_narrow<<<d.tk_grid, BLOCK, 0, c->stream>>>(d, s);
-        k_topk_finish<<<1, BLOCK, 0, c->stream>>>(d, s, d.tk_grid);
         return;
       }
       // FP64 keys: the digits below bin B, then those of the ids (ids < 2^31)

@@ -339,6 +339,16 @@ __device__ __forceinline__ double hist_at(const Dev &d, int j) {
 
 // ------------------------------------------------------------------ select
 
+// LDS of topk_fix_tau (defined with the top-k search below), which the select
+// pass of a top-k step with FP32 keys calls to fix tau and the id bound.
+struct TkFix {
+  unsigned int h[TK_LOW_BINS];
+  unsigned long long scan[NWAVE];
+  int dig, seg, id;
+  long long before, r;
+};
+__device__ __forceinline__ bool topk_fix_tau(const Dev &d, int G, TkFix &L, double *tau_out, int *tie_out);
+
 template <class T, int HK>
 __global__ __launch_bounds__(BLOCK) void k_select(Dev d, long long s, double eps, long long s_limit, int init) {
   Glob *g = d.glob;
@@ -379,6 +389,13 @@ __global__ __launch_bounds__(BLOCK) void k_select(Dev d, long long s, double eps
     }
   };
   if ((int)blockIdx.x < ntiles) load_tile(blockIdx.x);
+  if (sizeof(T) == 4 && !init && d.sched == SCHED_TOPK) {
+    // the middle-digit counts of this step's top-k search, read only by
+    // k_topk_narrow, start the next step at zero whatever this pass decides
+    // (the low-digit ones, which it reads, are cleared by the next collect)
+    for (int q = blockIdx.x * BLOCK + threadIdx.x; q < KH_STRIPES * KH_BINS; q += gridDim.x * BLOCK)
+      d.tk_hist[q] = 0u;
+  }
   if (g->status != 0) return;
   if (g->bad) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -414,8 +431,28 @@ __global__ __launch_bounds__(BLOCK) void k_select(Dev d, long long s, double eps
       theta = prv->theta;
   }
   const double maxabs = tot.maxabs;
-  const double tau = cur->topk_tau;
-  const int tie_id = cur->topk_tie_id;
+  double tau = cur->topk_tau;
+  int tie_id = cur->topk_tie_id;
+  if constexpr (sizeof(T) == 4) {
+    if (sched == SCHED_TOPK) {
+      // FP32 keys: every workgroup fixes tau and the id bound from what
+      // k_topk_narrow counted (no launch of its own for one workgroup's work)
+      __shared__ TkFix sh_fix;
+      if (!topk_fix_tau(d, d.tk_grid, sh_fix, &tau, &tie_id)) {
+        // the candidate lists do not hold what the histograms counted
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+          g->bad = 1;
+          g->status = ST_BAD_GRAPH;
+          g->t = s;
+        }
+        return;
+      }
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        cur->topk_tau = tau;
+        cur->topk_tie_id = tie_id;
+      }
+    }
+  }
   // route: AUTO pulls when the previous step moved cash along at least
   // pull_alpha * nnz links (the log entry of step s-1)
   int mode;
@@ -1380,10 +1417,11 @@ __global__ __launch_bounds__(BLOCK) void k_refresh_long(Dev d, long long t, int 
 //     holds the k-th key from the histogram and copies the keys of bin B and
 //     their ids into its own segment of the candidate list, in node order.
 //     With FP32 keys it also counts their next KH_BITS bits.
-//  3. FP32 keys: k_topk_narrow fixes the last bits of tau and the id bound in
-//     one more pass over the candidates (below).  FP64 keys: k_topk_pass, a
-//     few short radix passes over the candidates, KH_BITS bits of the key at a
-//     time, then of the ids among the keys equal to tau.
+//  3. FP32 keys: k_topk_narrow counts the last bits of the keys in one more
+//     pass over the candidates, and every workgroup of the select pass fixes
+//     tau and the id bound from those counts (below).  FP64 keys: k_topk_pass,
+//     a few short radix passes over the candidates, KH_BITS bits of the key at
+//     a time, then of the ids among the keys equal to tau.
 
 __global__ void k_topk_hist_zero(Dev d, long long s) {
   unsigned int *kh = khist_of(d, s);
@@ -1456,13 +1494,34 @@ __global__ __launch_bounds__(BLOCK) void k_topk_collect(Dev d, long long s) {
   __shared__ long long sh_before;
   const unsigned int *kh = khist_of(d, s);
   const long long want = d.k < (long long)d.n ? d.k : (long long)d.n;
+  // workgroup b owns the nodes [b S, (b + 1) S) and writes their candidates
+  // to the same positions of the list (no shared counter), in node order;
+  // tk_cnt[b] says how many.  The values of its first TK_PRE tiles are
+  // loaded before the bin is known, so they travel with the histogram.
+  const T *C = (const T *)d.cash[d.rec[s % 3].buf];
+  const int S = tk_segment(d.n, gridDim.x);
+  const int b0 = blockIdx.x * S, b1 = min(d.n, b0 + S);
+  constexpr int TK_PRE = 4;
+  T pre[TK_PRE][VPT];
+#pragma unroll
+  for (int r = 0; r < TK_PRE; ++r)
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      // a load at an index clamped into [0, n) and a select, no branch
+      const int i = b0 + r * TILE + u * BLOCK + threadIdx.x;
+      const T x = C[(unsigned int)min(i, b1 - 1)];
+      pre[r][u] = (i < b1) ? x : T(0);
+    }
   kh_load(kh, s_h);
   // FP64 keys: the first pass counts into buffer 0.  FP32 keys: this pass
   // counts the next digit into the KH_STRIPES copies at tk_hist itself, which
-  // the previous step's k_topk_finish (or the reset) left at zero.
+  // the previous step's select pass (or the reset) left at zero, and clears
+  // the low-digit counts that select pass read, for k_topk_narrow.
   constexpr bool NEXT = sizeof(T) == 4;
   if (!NEXT)
     for (int q = blockIdx.x * BLOCK + threadIdx.x; q < KH_BINS; q += gridDim.x * BLOCK) d.tk_hist[q] = 0u;
+  else if (blockIdx.x == 0)
+    for (int q = threadIdx.x; q < TK_LOW_BINS; q += BLOCK) d.tk_hist[KH_STRIPES * KH_BINS + q] = 0u;
   __syncthreads();
   int B;
   long long above;
@@ -1484,12 +1543,6 @@ __global__ __launch_bounds__(BLOCK) void k_topk_collect(Dev d, long long s) {
     g->tk_rem[0] = want - above;  // keys of bin B still to take, >= 1
     g->tk_done = 0;
   }
-  // workgroup b owns the nodes [b S, (b + 1) S) and writes their candidates
-  // to the same positions of the list (no shared counter), in node order;
-  // tk_cnt[b] says how many
-  const T *C = (const T *)d.cash[d.rec[s % 3].buf];
-  const int S = tk_segment(d.n, gridDim.x);
-  const int b0 = blockIdx.x * S, b1 = min(d.n, b0 + S);
   unsigned long long *ckey = d.tk_ckey + b0;
   int *cid = d.tk_cid + b0;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1497,15 +1550,10 @@ __global__ __launch_bounds__(BLOCK) void k_topk_collect(Dev d, long long s) {
   // VPT nodes per thread between two barriers, listed in node order
   __shared__ int sh_wc[VPT][NWAVE];
   int filled = 0;
-  for (int base = b0; base < b1; base += TILE) {
-    T v[VPT];
+  // one tile of VPT nodes per thread (a uniform call: it holds barriers)
+  auto tile = [&](int base, const T (&v)[VPT]) {
     bool hit[VPT];
     unsigned long long bal[VPT];
-#pragma unroll
-    for (int u = 0; u < VPT; ++u) {
-      const int i = base + u * BLOCK + threadIdx.x;
-      v[u] = (i < b1) ? C[i] : T(0);
-    }
 #pragma unroll
     for (int u = 0; u < VPT; ++u) {
       const int i = base + u * BLOCK + threadIdx.x;
@@ -1532,6 +1580,18 @@ __global__ __launch_bounds__(BLOCK) void k_topk_collect(Dev d, long long s) {
       filled += tot;
     }
     __syncthreads();
+  };
+#pragma unroll
+  for (int r = 0; r < TK_PRE; ++r)
+    if (b0 + r * TILE < b1) tile(b0 + r * TILE, pre[r]);
+  for (int base = b0 + TK_PRE * TILE; base < b1; base += TILE) {
+    T v[VPT];
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      const int i = base + u * BLOCK + threadIdx.x;
+      v[u] = (i < b1) ? C[i] : T(0);
+    }
+    tile(base, v);
   }
   if (threadIdx.x == 0) d.tk_cnt[blockIdx.x] = filled;
   if (NEXT) kh_flush(d.tk_hist, s_h);  // stripe blockIdx mod KH_STRIPES
@@ -1542,13 +1602,13 @@ __global__ __launch_bounds__(BLOCK) void k_topk_collect(Dev d, long long s) {
 // digit from the counts k_topk_collect made, then compacts the candidates of
 // its own segment that match the key so far (in place and in node order) and
 // counts their low digit, into the global low-digit histogram and into its
-// segment's row of tk_seg.  k_topk_finish (one workgroup) picks the low digit,
-// which completes tau; if only some of the keys equal to tau are taken, the
-// segment rows say which segment holds the last one taken, and a scan of that
-// segment's compacted list in node order finds its id.  It leaves the pass
-// histograms at zero for the next step.  (A last-workgroup ticket in place of
-// the second launch would need a device-scope fence in every workgroup, which
-// writes back the XCD's whole L2.)
+// segment's row of tk_seg.  topk_fix_tau, in every workgroup of the select
+// pass, picks the low digit, which completes tau; if only some of the keys
+// equal to tau are taken, the segment rows say which segment holds the last
+// one taken, and a scan of that segment's compacted list in node order finds
+// its id.  (A last-workgroup ticket in place of that redundant work would need
+// a device-scope fence in every workgroup of k_topk_narrow, which writes back
+// the XCD's whole L2.)
 __device__ __forceinline__ unsigned int *tk_low_hist(const Dev &d) { return d.tk_hist + KH_STRIPES * KH_BINS; }
 
 __global__ __launch_bounds__(BLOCK) void k_topk_narrow(Dev d, long long s) {
@@ -1562,6 +1622,17 @@ __global__ __launch_bounds__(BLOCK) void k_topk_narrow(Dev d, long long s) {
   const unsigned long long pref0 = g->tk_pref[0];
   const long long rem0 = g->tk_rem[0];
   if (rem0 <= 0) return;  // k_topk_collect found no bin (reported there)
+  // the segment's first BLOCK entries are loaded before the digit is known,
+  // so they travel with the histogram (at an index clamped into the list:
+  // the last segments may start past its end; only entries below cnt are
+  // used)
+  const int S = tk_segment(d.n, gridDim.x);
+  const int cnt = d.tk_cnt[blockIdx.x];
+  unsigned long long *ckey = d.tk_ckey + (size_t)blockIdx.x * S;
+  int *cid = d.tk_cid + (size_t)blockIdx.x * S;
+  const size_t q0 = min((size_t)blockIdx.x * S + threadIdx.x, (size_t)d.n - 1);
+  const unsigned long long key0 = d.tk_ckey[q0];
+  const int id0 = d.tk_cid[q0];
   kh_load(d.tk_hist, s_h);
   __syncthreads();
   int A;
@@ -1581,10 +1652,6 @@ __global__ __launch_bounds__(BLOCK) void k_topk_narrow(Dev d, long long s) {
   for (int b = threadIdx.x; b < TK_LOW_BINS; b += BLOCK) s_h[b] = 0u;
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int S = tk_segment(d.n, gridDim.x);
-  const int cnt = d.tk_cnt[blockIdx.x];
-  unsigned long long *ckey = d.tk_ckey + (size_t)blockIdx.x * S;
-  int *cid = d.tk_cid + (size_t)blockIdx.x * S;
   int filled = 0;
   // Every thread holds its entry before the barrier below, and an entry moves
   // only to a position at or before its own, so no entry is overwritten
@@ -1592,8 +1659,8 @@ __global__ __launch_bounds__(BLOCK) void k_topk_narrow(Dev d, long long s) {
   for (int c0 = 0; c0 < cnt; c0 += BLOCK) {
     const int q = c0 + threadIdx.x;
     const bool in = q < cnt;
-    const unsigned long long key = in ? ckey[q] : 0ull;
-    const int id = in ? cid[q] : 0;
+    const unsigned long long key = in ? (c0 == 0 ? key0 : ckey[q]) : 0ull;
+    const int id = in ? (c0 == 0 ? id0 : cid[q]) : 0;
     const bool hit = in && (key >> TK_LOW_BITS) == (prefA >> TK_LOW_BITS);
     const unsigned long long bal = __ballot(hit);
     if (lane == 0) sh_wc[wv] = __popcll(bal);
@@ -1621,80 +1688,70 @@ __global__ __launch_bounds__(BLOCK) void k_topk_narrow(Dev d, long long s) {
   if (threadIdx.x == 0) d.tk_cnt[blockIdx.x] = filled;
 }
 
-static_assert(TK_GRID <= BLOCK, "k_topk_finish reads one segment row per thread");
-__global__ __launch_bounds__(BLOCK) void k_topk_finish(Dev d, long long s, int G) {
-  Glob *g = d.glob;
-  if (g->status != 0) return;
-  __shared__ unsigned int s_h[TK_LOW_BINS];
-  __shared__ unsigned long long sh_scan[NWAVE];
-  __shared__ int sh_dig, sh_seg, sh_id;
-  __shared__ long long sh_before, sh_r;
-  unsigned int *hlow = tk_low_hist(d);
-  if (g->tk_rem[0] > 0 && !g->bad) {
-    const unsigned long long prefA = g->tk_pref[1];
-    const long long remA = g->tk_rem[1];
-    for (int b = threadIdx.x; b < TK_LOW_BINS; b += BLOCK) s_h[b] = hlow[b];
+static_assert(TK_GRID <= BLOCK, "topk_fix_tau reads one segment row per thread");
+// FP32 keys, after k_topk_narrow: picks the low digit from the low-digit
+// histogram, which completes tau, and the id bound among the keys equal to
+// tau (segment rows, then a scan of the segment's compacted list in node
+// order).  Every thread of the BLOCK-wide workgroup calls it and receives
+// the result; false when the lists do not hold what the histograms counted.
+__device__ __forceinline__ bool topk_fix_tau(const Dev &d, int G, TkFix &L, double *tau_out, int *tie_out) {
+  const Glob *g = d.glob;
+  const unsigned long long prefA = g->tk_pref[1];
+  const long long remA = g->tk_rem[1];
+  const unsigned int *hlow = tk_low_hist(d);
+  for (int b = threadIdx.x; b < TK_LOW_BINS; b += BLOCK) L.h[b] = hlow[b];
+  __syncthreads();
+  int Bl;
+  long long beforeB;
+  pick_digit(L.h, TK_LOW_BINS, false, remA, &Bl, &beforeB, L.scan, &L.dig, &L.before);
+  if (Bl < 0) return false;
+  const unsigned long long tau = prefA | (unsigned long long)Bl;
+  const long long remB = remA - beforeB;  // keys equal to tau still to take, >= 1
+  int tie = 0x7fffffff;                    // every key equal to tau is taken
+  if (remB < (long long)L.h[Bl]) {
+    // the segment that holds the remB-th key equal to tau, in node order
+    const unsigned long long mine =
+        (int)threadIdx.x < G ? (unsigned long long)d.tk_seg[(size_t)threadIdx.x * TK_LOW_BINS + Bl] : 0ull;
+    unsigned long long total;
+    const unsigned long long run = block_excl_scan(mine, L.scan, &total);
+    if (threadIdx.x == 0) L.seg = -1;
     __syncthreads();
-    int Bl;
-    long long beforeB;
-    pick_digit(s_h, TK_LOW_BINS, false, remA, &Bl, &beforeB, sh_scan, &sh_dig, &sh_before);
-    const unsigned long long tau = prefA | (unsigned long long)(Bl < 0 ? 0 : Bl);
-    const long long remB = remA - beforeB;  // keys equal to tau still to take, >= 1
-    int tie = 0x7fffffff;                    // every key equal to tau is taken
-    if (Bl < 0) {
-      if (threadIdx.x == 0) g->bad = 1;
-    } else if (remB < (long long)s_h[Bl]) {
-      // the segment that holds the remB-th key equal to tau, in node order
-      const unsigned long long mine =
-          (int)threadIdx.x < G ? (unsigned long long)d.tk_seg[(size_t)threadIdx.x * TK_LOW_BINS + Bl] : 0ull;
-      unsigned long long total;
-      const unsigned long long run = block_excl_scan(mine, sh_scan, &total);
-      if (threadIdx.x == 0) sh_seg = -1;
-      __syncthreads();
-      if ((int)threadIdx.x < G && run < (unsigned long long)remB && run + mine >= (unsigned long long)remB) {
-        sh_seg = threadIdx.x;
-        sh_r = remB - (long long)run;
-      }
-      __syncthreads();
-      const int sb = sh_seg;
-      if (sb < 0) {
-        if (threadIdx.x == 0) g->bad = 1;
-      } else {
-        // thread t scans the strip [t L, (t + 1) L) of the segment's list
-        const long long r = sh_r;
-        const int S = tk_segment(d.n, G);
-        const int m = d.tk_cnt[sb];
-        const unsigned long long *kk = d.tk_ckey + (size_t)sb * S;
-        const int *ii = d.tk_cid + (size_t)sb * S;
-        const int L = (m + BLOCK - 1) / BLOCK;
-        const int q0 = min(m, (int)threadIdx.x * L), q1 = min(m, q0 + L);
-        unsigned long long own = 0;
-        for (int q = q0; q < q1; ++q) own += (kk[q] == tau) ? 1ull : 0ull;
-        unsigned long long tot2;
-        const unsigned long long before = block_excl_scan(own, sh_scan, &tot2);
-        if (threadIdx.x == 0) sh_id = -1;
-        __syncthreads();
-        if (before < (unsigned long long)r && before + own >= (unsigned long long)r) {
-          long long left = r - (long long)before;
-          for (int q = q0; q < q1; ++q)
-            if (kk[q] == tau && --left == 0) {
-              sh_id = ii[q];
-              break;
-            }
+    if ((int)threadIdx.x < G && run < (unsigned long long)remB && run + mine >= (unsigned long long)remB) {
+      L.seg = threadIdx.x;
+      L.r = remB - (long long)run;
+    }
+    __syncthreads();
+    const int sb = L.seg;
+    if (sb < 0) return false;
+    // thread t scans the strip [t L, (t + 1) L) of the segment's list
+    const long long r = L.r;
+    const int S = tk_segment(d.n, G);
+    const int m = d.tk_cnt[sb];
+    const unsigned long long *kk = d.tk_ckey + (size_t)sb * S;
+    const int *ii = d.tk_cid + (size_t)sb * S;
+    const int strip = (m + BLOCK - 1) / BLOCK;
+    const int q0 = min(m, (int)threadIdx.x * strip), q1 = min(m, q0 + strip);
+    unsigned long long own = 0;
+    for (int q = q0; q < q1; ++q) own += (kk[q] == tau) ? 1ull : 0ull;
+    unsigned long long tot2;
+    const unsigned long long before = block_excl_scan(own, L.scan, &tot2);
+    if (threadIdx.x == 0) L.id = -1;
+    __syncthreads();
+    if (before < (unsigned long long)r && before + own >= (unsigned long long)r) {
+      long long left = r - (long long)before;
+      for (int q = q0; q < q1; ++q)
+        if (kk[q] == tau && --left == 0) {
+          L.id = ii[q];
+          break;
         }
-        __syncthreads();
-        tie = sh_id;
-        if (tie < 0 && threadIdx.x == 0) g->bad = 1;
-      }
     }
-    if (threadIdx.x == 0) {
-      Rec *rc = &d.rec[s % 3];
-      rc->topk_tau = (double)__uint_as_float((unsigned int)tau);
-      rc->topk_tie_id = tie;
-    }
+    __syncthreads();
+    tie = L.id;
+    if (tie < 0) return false;
   }
-  // the pass histograms start the next step at zero
-  for (int b = threadIdx.x; b < KH_STRIPES * KH_BINS + TK_LOW_BINS; b += BLOCK) d.tk_hist[b] = 0u;
+  *tau_out = (double)__uint_as_float((unsigned int)tau);
+  *tie_out = tie;
+  return true;
 }
 
 // One digit of the radix select over the candidates: the digits of the key
