@@ -409,6 +409,39 @@ def pmc_summary(folder: str, workload: str, kernel: str, commands: list) -> str:
     return "\n".join(lines) + "\n"
 
 
+def fixed_step_leg(rl, torch, dg, args, prec, route, stream, nsteps: int = 20, reps: int = 7):
+    """A top-k step beside a threshold step (with about as many green nodes:
+    k = N/4 on the Chung-Lu graphs) in the same, the caller's, numbering:
+    nsteps steps from step 0, best of reps, and the per-kernel event times
+    of one more run (rlgl_profile)."""
+    out = {}
+    for name, opts in (("threshold", dict(sched=rl.SCHED_THRESHOLD)), ("topk", dict(sched=rl.SCHED_TOPK, k=args.k))):
+        s = rl.Solver(dg, stream=stream, route=route, precision=prec, relabel=0, **opts)
+        s.reset()
+        s.step(nsteps)
+        best = 1e30
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            s.reset()
+            info = s.step(nsteps)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - a)
+        rl.rlgl_profile_enable(s.ctx, True)
+        s.reset()
+        s.step(nsteps)
+        torch.cuda.synchronize()
+        prof = rl.rlgl_profile_read(s.ctx)
+        rl.rlgl_profile_enable(s.ctx, False)
+        out[name] = {"us_per_step": round(best / nsteps * 1e6, 1), "green_last_step": info["green"],
+                     "kernel_us_per_step": {k: round(1000.0 * v["ms"] / nsteps, 1) for k, v in prof.items()}}
+        s.close()
+    out["ratio"] = round(out["topk"]["us_per_step"] / out["threshold"]["us_per_step"], 3)
+    out["steps"] = nsteps
+    log(f"top-k beside threshold, {nsteps} steps from step 0: {json.dumps(out)}")
+    return out
+
+
 def trace_summary(folder: str, workload: str, commands: list, label: str = None) -> str:
     """Markdown table of rocprofv3 --stats kernel statistics under `folder`."""
     rows = _csv_rows(folder, "kernel_stats.csv")
@@ -660,6 +693,11 @@ def main():
             del dg2, g2
             torch.cuda.empty_cache()
 
+    # ---- top-k: fixed steps beside the threshold rule in the same numbering
+    topk_steps = None
+    if sched == rl.SCHED_TOPK and not args.small:
+        topk_steps = fixed_step_leg(rl, torch, dg, args, prec, route, stream)
+
     # ---- CPU baseline: the oracle's own serial solve loop (C, FP64, one core)
     # on the same graph, schedule and eps: whole solves while they fit the time
     # budget, else its first steps (step 0 included)
@@ -739,6 +777,7 @@ def main():
         "l1_certified_bound": l1_bound,
         "schedules": schedules,
         "chung_lu_2p20": chung_lu,
+        "topk_vs_threshold": topk_steps,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched": batched,
