@@ -215,11 +215,14 @@ __device__ __forceinline__ void ls_item(const LsArgs &a, int k, int mode, int lo
   const double theta = ctl->theta, maxabs = ctl->maxabs;
   const int sched = a.sched;
   // What the LS_HUB lowest-numbered states send, staged in LDS for the item:
-  // in the relabelled layout they are the chain's largest out-degrees
-  const int hn = (!refresh && sizeof(T) == 4) ? min(LS_HUB, n) : 0;
-  if (!FRESH) __syncthreads();  // the previous item's reads of the table are done
-  for (int q = threadIdx.x; q < hn; q += NT) hub[q] = src[q];
-  __syncthreads();
+  // in the relabelled layout they are the chain's largest out-degrees (in the
+  // caller's numbering they are no one in particular, and nothing is staged)
+  const int hn = (!refresh && sizeof(T) == 4 && ch.perm) ? min(LS_HUB, n) : 0;
+  if (hn > 0) {  // the same for the whole workgroup
+    if (!FRESH) __syncthreads();  // the previous item's reads of the table are done
+    for (int q = threadIdx.x; q < hn; q += NT) hub[q] = src[q];
+    __syncthreads();
+  }
   column_item<T, NT>(
       g, item,
       [&](int j) -> double {
