@@ -9,11 +9,13 @@
 //                  chain's source buffer;
 //   k_ls_route   - plan items (the pieces of the long columns of every
 //                  chain first, then runs of at most CH links), one per
-//                  workgroup or strided over a machine-sized grid: the CSC gather of eq. (6), C_{t+1}[k] = kept(k) +
-//                  c sum_j src[j] + T/N (what the LS_HUB lowest-numbered
-//                  states send is read from LDS, staged per item), and the statistics of C_{t+1}; a
-//                  piece of a column with more than CH in-links adds its
-//                  partial sum into the chain's FP64 long-column accumulator;
+//                  workgroup or strided over a machine-sized grid: the CSC
+//                  gather of eq. (6), C_{t+1}[k] = kept(k) + c sum_j src[j]
+//                  + T/N, and the statistics of C_{t+1} (in the relabelled
+//                  layout what the LS_HUB lowest-numbered states send is
+//                  staged in LDS per item); a piece of a column with more
+//                  than CH in-links adds its partial sum into the chain's
+//                  FP64 long-column accumulator;
 //   k_ls_control - one wave per active chain: finishes the long columns,
 //                  adds up the chain's statistics,
 //                  applies the stop test of Algorithm 1 step (7), the drift

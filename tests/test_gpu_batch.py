@@ -213,3 +213,18 @@ def test_batch_relabelled_layout_matches_caller_layout(sched):
         assert l1(out[0][0][k], out[1][0][k]) <= 1e-12, k
         assert abs(out[0][1][k] - out[1][1][k]) <= 1, k
         assert l1(out[1][0][k], reference(g)) <= 1e-10, k
+
+
+def test_batch_relabel_rejects_decreasing_row_pointers():
+    """The relabelled layout sorts each chain's states by out-degree from its
+    row pointers: a chain whose row pointers decrease is rejected at create
+    (RLGL_EINVAL) before any work, and the other chains are not touched."""
+    gs = [workloads.chung_lu(n, 2.3, 6.0, 0.0, 0.85, seed=n, name=f"r{n}") for n in (300, 500)]
+    say("case batch_relabel_bad_rowptr")
+    db = rl.DeviceBatch(gs, precision=rl.FP32C_KAHANH)
+    off = int(db.node_off[1]) + 1  # chain 1's row pointers start after chain 0's n + 1
+    rp = db.rowptr[off + 10:off + 12].clone()
+    db.rowptr[off + 10] = rp[1] + 1  # row pointer 10 of chain 1 above row pointer 11
+    with pytest.raises(rl.RlglError) as e:
+        rl.BatchSolver(db, relabel=1)
+    assert e.value.status == rl.RLGL_EINVAL
