@@ -403,18 +403,20 @@ __global__ __launch_bounds__(SM_BLOCK) void k_small(SmallArgs a) {
           wave_lds_fence();
           double msum = 0.0, pool = 0.0, dh = 0.0;
           long long e = 0;
+          // The history of the first 64 listed nodes is loaded here and
+          // updated after the links are routed (H takes no part in moving the
+          // cash), so its round trip overlaps theirs.
+          const int nq0 = min(64, ng);
+          const int li0 = min(max(s_list[min(lane, max(nq0 - 1, 0))], 0), n - 1);  // in [0, n) whatever the list
+          const double h00 = H[li0];
           // M_t from the snapshot: every green node's cash leaves before any
           // arrives (the nodes of the list are distinct)
           for (int q0 = 0; q0 < ng; q0 += 64) {
             const int nq = min(64, ng - q0);
-            double lm = 0.0, ldh = 0.0;
+            double lm = 0.0;
             if (lane < nq) {
               const int li = s_list[q0 + lane];
               lm = (double)C[li];
-              const double h0 = H[li];
-              const double h1 = h0 + lm;
-              H[li] = h1;
-              ldh = fabs(h1) - fabs(h0);
               C[li] = (T)((double)C[li] - lm);
               s_lm[q0 + lane] = lm;
               const int r0 = a.rp_lds ? s_rp[li] : rowptr[li];
@@ -424,10 +426,7 @@ __global__ __launch_bounds__(SM_BLOCK) void k_small(SmallArgs a) {
               s_ld[q0 + lane] = okr ? r1 - r0 : 0;
               s_lr[q0 + lane] = r0;
             }
-            for (int q = 0; q < nq; ++q) {
-              msum += rd_lane(lm, q);
-              dh += rd_lane(ldh, q);
-            }
+            for (int q = 0; q < nq; ++q) msum += rd_lane(lm, q);
           }
           wave_lds_fence();
           for (int q = 0; q < ng; ++q) {
@@ -472,6 +471,20 @@ __global__ __launch_bounds__(SM_BLOCK) void k_small(SmallArgs a) {
               wave_lds_fence();
             }
             pool += (1.0 - c) * m;
+          }
+          // H_{t+1} = H_t + M_t on the listed nodes (eq. (5)), and the change
+          // of ||H||_1 summed in list order
+          for (int q0 = 0; q0 < ng; q0 += 64) {
+            const int nq = min(64, ng - q0);
+            double ldh = 0.0;
+            if (lane < nq) {
+              const int li = s_list[q0 + lane];
+              const double h0 = (q0 == 0) ? h00 : H[li];
+              const double h1 = h0 + s_lm[q0 + lane];
+              H[li] = h1;
+              ldh = fabs(h1) - fabs(h0);
+            }
+            for (int q = 0; q < nq; ++q) dh += rd_lane(ldh, q);
           }
           if (lane == 0) {
             s_out[0] = msum;
