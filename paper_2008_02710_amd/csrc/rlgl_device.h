@@ -15,12 +15,11 @@ constexpr int WU = 8;               // single-chain pull: links per lane of a wa
 constexpr int WL = 64 * WU;         // single-chain pull: links per run item and per long-column piece
 constexpr int WCOLS = 64;           // single-chain pull: columns per run item
 constexpr int HOT_SRC = 6144;       // single-chain pull: send values of the lowest-numbered sources held in LDS
-constexpr int HOT_SRC_TK = 4096;    // the same when the pull also counts the top-k histogram or parks
-                                    // stored link values (LDS budget of four workgroups per CU)
-constexpr int HOT_SRC_VAL_TK = 2048;  // ... when it does both
+constexpr int HOT_SRC_VAL = 4096;   // the same when the pull parks stored link values (LDS budget of four
+                                    // workgroups per CU)
 // The same with one workgroup of PULL_WIDE waves per CU (the LDS of a whole CU):
 constexpr int PULL_WIDE = 16;
-constexpr int HOT_WIDE = 24576, HOT_WIDE_TK = 20480, HOT_WIDE_VAL = 16384, HOT_WIDE_VAL_TK = 14336;
+constexpr int HOT_WIDE = 24576, HOT_WIDE_VAL = 16384;
 constexpr int KH_BITS = 11;         // top-k: bits of the |C| key counted by the pass that writes C
 constexpr int KH_BINS = 1 << KH_BITS;
 constexpr int KH_STRIPES = 4;       // global copies of the top-k histogram

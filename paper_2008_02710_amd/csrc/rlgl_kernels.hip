@@ -987,18 +987,20 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
   __shared__ unsigned int s_kr[PW][NK * 64];
   __shared__ double s_sum[PW][WCOLS + 64];
   __shared__ double sh_red[4 * PW];
-  // What the HOTK lowest-numbered sources send, staged once per workgroup:
-  // in the relabelled layout they are the states of largest out-degree, so
-  // their gathers (about a fifth of the links on R-MAT, half on the
-  // Chung-Lu graphs) read LDS instead of L2.  FP32 send values only, as many
-  // as leave room for the other LDS arrays of four workgroups of NWAVE waves
-  // per CU, or of one of PULL_WIDE waves.
+  // What the HOTK lowest-numbered sources send, staged once per workgroup
+  // in the relabelled layout, where they are the states of largest
+  // out-degree: their gathers (about a fifth of the links on R-MAT, half on
+  // the Chung-Lu graphs) read LDS instead of L2.  In the caller's numbering
+  // (always so under top-k) the lowest ids are no one in particular, and
+  // nothing is staged.  FP32 send values only, as many as leave room for the
+  // other LDS arrays of four workgroups of NWAVE waves per CU, or of one of
+  // PULL_WIDE waves.
   static_assert(PW == NWAVE || PW == PULL_WIDE, "two workgroup widths");
-  constexpr int HOTK = sizeof(S) != 4 ? 1
-                       : PW == NWAVE ? ((VAL && KH) ? HOT_SRC_VAL_TK : (VAL || KH) ? HOT_SRC_TK : HOT_SRC)
-                                     : ((VAL && KH) ? HOT_WIDE_VAL_TK : VAL ? HOT_WIDE_VAL : KH ? HOT_WIDE_TK : HOT_WIDE);
+  constexpr int HOTK = (sizeof(S) != 4 || KH) ? 1
+                       : PW == NWAVE ? (VAL ? HOT_SRC_VAL : HOT_SRC)
+                                     : (VAL ? HOT_WIDE_VAL : HOT_WIDE);
   __shared__ S s_hot[HOTK];
-  const int hk = sizeof(S) == 4 ? min(HOTK, d.n) : 0;
+  const int hk = (sizeof(S) == 4 && !KH && d.perm) ? min(HOTK, d.n) : 0;
   for (int q = threadIdx.x; q < hk; q += PW * 64) s_hot[q] = src[q];
   __syncthreads();
   const int lane = threadIdx.x & 63;
