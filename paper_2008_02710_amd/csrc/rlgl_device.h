@@ -19,7 +19,7 @@ constexpr int HOT_SRC_VAL = 4096;   // the same when the pull parks stored link 
                                     // workgroups per CU)
 // The same with one workgroup of PULL_WIDE waves per CU (the LDS of a whole CU):
 constexpr int PULL_WIDE = 16;
-constexpr int HOT_WIDE = 24576, HOT_WIDE_VAL = 16384;
+constexpr int HOT_WIDE = 24576, HOT_WIDE_VAL = 20480;
 constexpr int KH_BITS = 11;         // top-k: bits of the |C| key counted by the pass that writes C
 constexpr int KH_BINS = 1 << KH_BITS;
 constexpr int KH_STRIPES = 4;       // global copies of the top-k histogram

@@ -982,10 +982,14 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
   constexpr int NK = STAGEK ? (WCOLS * KW + 63) / 64 : 1;    // staged raw dwords per lane
   __shared__ int s_row[PW][WL];
   // stored link values of the item, parked like its sources
-  __shared__ T s_val[VAL ? PW : 1][VAL ? WL : 1];
+  // (with stored values a wave's column sums share its value buffer: the
+  // values are read out of it before the first sum is written, and the next
+  // item is parked only after the last sum is read)
+  __shared__ __align__(16) T s_val[VAL ? PW : 1][VAL ? WL : 1];
   __shared__ int s_cp[PW][NCP * 64];
   __shared__ unsigned int s_kr[PW][NK * 64];
-  __shared__ double s_sum[PW][WCOLS + 64];
+  __shared__ double s_sum[VAL ? 1 : PW][WCOLS + 64];
+  static_assert(!VAL || WL * sizeof(T) >= (WCOLS + 64) * sizeof(double), "sums fit the value buffer");
   __shared__ double sh_red[4 * PW];
   // What the HOTK lowest-numbered sources send, staged once per workgroup
   // in the relabelled layout, where they are the states of largest
@@ -1009,7 +1013,7 @@ __device__ __forceinline__ void wave_pull(const Dev &d, const S *__restrict__ sr
   T *valw = s_val[VAL ? wv : 0];
   int *cp = s_cp[wv];
   unsigned int *kr = s_kr[wv];
-  double *sum = s_sum[wv];
+  double *sum = VAL ? (double *)s_val[wv] : s_sum[wv];
   const int n = d.n, n_items = d.n_items;
   const double c = d.c, rr = d.r;
   const int *__restrict__ colptr = d.colptr;
